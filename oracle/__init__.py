@@ -1,0 +1,234 @@
+"""FP64 CPU oracle for the Gaussian rasterization hot path (test infrastructure).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. It shares no code with the HIP library
+(``paper_2312_10070_amd``) and never imports it.
+
+The native part (``gsr_oracle.cpp``, ``cnn_oracle.cpp``) is plain C++17 in
+double precision; :func:`build` compiles it with g++ into ``liboracle.so``
+beside the sources. Every function here only marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SOURCES = ["gsr_oracle.cpp", "cnn_oracle.cpp"]
+_LIB_PATH = os.environ.get("GSR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ORC_REC = 24
+REC_FIELDS = ["valid", "x", "y", "z_cam", "u", "v", "Sxx", "Sxy", "Syy", "a", "b", "c", "z", "o",
+              "px0", "px1", "py0", "py1", "tx0", "tx1", "ty0", "ty1", "margin", "smax"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (FP64, no fast-math, no FMA contraction)."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    if not force and os.path.exists(_LIB_PATH):
+        newest = max(os.path.getmtime(s) for s in srcs)
+        if os.path.getmtime(_LIB_PATH) >= newest:
+            return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
+           "-o", tmp] + srcs
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    lib.orc_project.argtypes = [i64] + [P] * 9
+    lib.orc_render.argtypes = [i64] + [P] * 8 + [ctypes.c_int, i64, P, ctypes.c_int] + [P] * 10
+    lib.orc_backward.argtypes = [i64] + [P] * 8 + [ctypes.c_int, i64, P, ctypes.c_int] + [P] * 7
+    lib.orc_backward.restype = i64
+    lib.orc_tile_lists.argtypes = [i64] + [P] * 8 + [P, P, P, P, i64]
+    lib.orc_loss_l1.argtypes = [i64, P, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
+    lib.orc_loss_track.argtypes = [i64, P, P, P, P, P, ctypes.c_double, ctypes.c_float, P, P, P, P, P]
+    lib.orc_adam.argtypes = [i64, P, P, P, P, i64] + [ctypes.c_double] * 4
+    if hasattr(lib, "orc_conv2d_fwd"):
+        _bind_cnn(lib)
+    _lib = lib
+    return lib
+
+
+def _bind_cnn(lib):
+    P = ctypes.c_void_p
+    i = ctypes.c_int
+    lib.orc_conv2d_fwd.argtypes = [i, i, i, i, i, i, i, i, P, P, P, P]
+    lib.orc_conv2d_bwd.argtypes = [i, i, i, i, i, i, i, i, P, P, P, P, P, P]
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+@dataclass
+class Camera:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    near_z: float = 0.2
+    bg: tuple = (0.0, 0.0, 0.0)
+
+    def packed(self) -> np.ndarray:
+        return _d([self.width, self.height, self.fx, self.fy, self.cx, self.cy, self.near_z, *self.bg])
+
+
+@dataclass
+class Opts:
+    lowpass: float = 0.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    guard: float = 1.3
+    tile_w: int = 16
+    tile_h: int = 16
+    amb_rel: float = 1e-5
+    amb_z: float = 1e-6
+
+    def packed(self) -> np.ndarray:
+        return _d([self.lowpass, self.alpha_min, self.alpha_max, self.T_min, self.guard, self.tile_w,
+                   self.tile_h, self.amb_rel, self.amb_z])
+
+
+def _params(g):
+    """(means, scales, quats, opacities, colors) as contiguous float64 arrays."""
+    return [_d(g[k]) for k in ("means", "scales", "quats", "opacities", "colors")]
+
+
+def project(g: dict, pose7, cam: Camera, opts: Opts) -> dict:
+    """Per-Gaussian projection record (O2/O3) as a dict of arrays."""
+    lib = _load()
+    m, s, q, o, c = _params(g)
+    n = m.shape[0]
+    out = np.zeros((n, ORC_REC), np.float64)
+    lib.orc_project(n, _p(m), _p(s), _p(q), _p(o), _p(c), _p(_d(pose7)), _p(cam.packed()),
+                    _p(opts.packed()), _p(out))
+    rec = {name: out[:, i] for i, name in enumerate(REC_FIELDS)}
+    rec["valid"] = rec["valid"] > 0.5
+    return rec
+
+
+def render(g: dict, pose7, cam: Camera, opts: Opts, mode: int = 1, pixels=None, nthreads: int | None = None):
+    """Brute-force FP64 render; returns dict of color [3,H,W], depth, alpha, T, ncomp, amb, alt_*."""
+    lib = _load()
+    m, s, q, o, c = _params(g)
+    n = m.shape[0]
+    H, W = cam.height, cam.width
+    P = H * W
+    color = np.zeros((3, H, W)); depth = np.zeros((H, W)); alpha = np.zeros((H, W))
+    T = np.ones((H, W)); ncomp = np.zeros((H, W), np.int32); amb = np.zeros((H, W), np.int32)
+    ac = np.zeros((3, H, W)); ad = np.zeros((H, W)); aa = np.zeros((H, W))
+    hsh = np.zeros((H, W), np.uint64)
+    pix = None if pixels is None else np.ascontiguousarray(np.asarray(pixels, np.int64))
+    npix = 0 if pix is None else pix.shape[0]
+    nt = nthreads or os.cpu_count() or 1
+    lib.orc_render(n, _p(m), _p(s), _p(q), _p(o), _p(c), _p(_d(pose7)), _p(cam.packed()), _p(opts.packed()),
+                   mode, npix, _p(pix), nt, _p(color), _p(depth), _p(alpha), _p(T), _p(ncomp), _p(amb),
+                   _p(ac), _p(ad), _p(aa), _p(hsh))
+    return dict(color=color, depth=depth, alpha=alpha, T=T, ncomp=ncomp, amb=amb, alt_color=ac,
+                alt_depth=ad, alt_alpha=aa, hash=hsh)
+
+
+def split_flat(flat: np.ndarray, n: int) -> dict:
+    o = 0
+    out = {}
+    for name, shape in (("means", (n, 3)), ("scales", (n, 3)), ("quats", (n, 4)), ("opacities", (n,)),
+                        ("colors", (n, 3)), ("pose7", (7,)), ("twist6", (6,))):
+        size = int(np.prod(shape))
+        out[name] = flat[o:o + size].reshape(shape)
+        o += size
+    return out
+
+
+def backward(g: dict, pose7, cam: Camera, opts: Opts, gC, gD, gA=None, mode: int = 1, pixels=None,
+             nthreads: int | None = None, with_g2d: bool = False) -> dict:
+    """Analytic FP64 backward; returns grads, aref, slack (dicts) and n_unverifiable."""
+    lib = _load()
+    m, s, q, o, c = _params(g)
+    n = m.shape[0]
+    total = 14 * n + 13
+    gflat = np.zeros(total); aref = np.zeros(total); slack = np.zeros(total)
+    g2d = np.zeros((n, 10)) if with_g2d else None
+    pix = None if pixels is None else np.ascontiguousarray(np.asarray(pixels, np.int64))
+    npix = 0 if pix is None else pix.shape[0]
+    nt = nthreads or os.cpu_count() or 1
+    gCd = _d(gC); gDd = _d(gD); gAd = None if gA is None else _d(gA)
+    nu = lib.orc_backward(n, _p(m), _p(s), _p(q), _p(o), _p(c), _p(_d(pose7)), _p(cam.packed()),
+                          _p(opts.packed()), mode, npix, _p(pix), nt, _p(gCd), _p(gDd), _p(gAd), _p(gflat),
+                          _p(aref), _p(slack), _p(g2d))
+    out = dict(grads=split_flat(gflat, n), aref=split_flat(aref, n), slack=split_flat(slack, n),
+               n_unverifiable=int(nu))
+    if with_g2d:
+        out["g2d"] = g2d
+    return out
+
+
+def tile_lists(g: dict, pose7, cam: Camera, opts: Opts) -> dict:
+    """Per-tile depth-ordered Gaussian id lists (O6)."""
+    lib = _load()
+    m, s, q, o, c = _params(g)
+    n = m.shape[0]
+    ntx = -(-cam.width // opts.tile_w)
+    nty = -(-cam.height // opts.tile_h)
+    K = np.zeros(1, np.int64)
+    counts = np.zeros(n, np.int64)
+    ranges = np.zeros((ntx * nty, 2), np.int64)
+    args = [n, _p(m), _p(s), _p(q), _p(o), _p(c), _p(_d(pose7)), _p(cam.packed()), _p(opts.packed())]
+    lib.orc_tile_lists(*args, _p(K), _p(counts), _p(ranges), None, 0)
+    ids = np.zeros(max(int(K[0]), 1), np.int32)
+    rc = lib.orc_tile_lists(*args, _p(K), None, None, _p(ids), ids.shape[0])
+    assert rc == 0
+    return dict(K=int(K[0]), counts=counts, ranges=ranges, ids=ids[:int(K[0])], n_tiles_x=ntx, n_tiles_y=nty)
+
+
+def loss_l1(C, D, Ct, Dt, w_color=1.0, w_depth=1.0):
+    lib = _load()
+    C = np.ascontiguousarray(C, np.float32); D = np.ascontiguousarray(D, np.float32)
+    Ct = np.ascontiguousarray(Ct, np.float32); Dt = np.ascontiguousarray(Dt, np.float32)
+    P = D.size
+    loss = np.zeros(1); gC = np.zeros(C.shape); gD = np.zeros(D.shape)
+    lib.orc_loss_l1(P, _p(C), _p(D), _p(Ct), _p(Dt), w_color, w_depth, _p(loss), _p(gC), _p(gD))
+    return float(loss[0]), gC, gD
+
+
+def loss_track(C, D, A, Ct, Dt, lambda_c=0.5, inlier_mult=50.0):
+    lib = _load()
+    C = np.ascontiguousarray(C, np.float32); D = np.ascontiguousarray(D, np.float32)
+    A = np.ascontiguousarray(A, np.float32)
+    Ct = np.ascontiguousarray(Ct, np.float32); Dt = np.ascontiguousarray(Dt, np.float32)
+    P = D.size
+    loss = np.zeros(1); gC = np.zeros(C.shape); gD = np.zeros(D.shape)
+    med = np.zeros(1, np.float32); ni = np.zeros(1, np.int64)
+    lib.orc_loss_track(P, _p(C), _p(D), _p(A), _p(Ct), _p(Dt), lambda_c, inlier_mult, _p(loss), _p(gC),
+                       _p(gD), _p(med), _p(ni))
+    return dict(loss=float(loss[0]), gC=gC, gD=gD, median=float(med[0]), n_inlier=int(ni[0]))
+
+
+def adam(param, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays."""
+    lib = _load()
+    for a in (param, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    gd = _d(g)
+    lib.orc_adam(param.size, _p(param), _p(m), _p(v), _p(gd), step, lr, b1, b2, eps)

@@ -1,0 +1,151 @@
+"""Pins of the oracle's analytic backward: FP64 central finite differences on
+every parameter kind, the pose (quaternion, translation and twist), and exact
+identities between gradient blocks."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import helpers as H
+
+
+def scene(seed=0, n=60):
+    rng = np.random.default_rng(seed)
+    g = dict(means=np.stack([rng.uniform(-0.7, 0.7, n), rng.uniform(-0.5, 0.5, n), rng.uniform(1.2, 3.5, n)], 1),
+             scales=np.exp(rng.normal(-2.6, 0.4, (n, 3))), quats=rng.normal(size=(n, 4)),
+             opacities=rng.uniform(0.2, 0.95, n), colors=rng.uniform(0, 1, (n, 3)))
+    # one nearly opaque Gaussian whose centre pixels clamp at alpha_max
+    g["opacities"][0] = 0.99995
+    g["means"][0] = [0.05, 0.02, 1.6]
+    g["scales"][0] = [0.5, 0.4, 0.05]
+    # one large Gaussian beyond the guard band: its Jacobian clamps
+    g["means"][1] = [1.8, 0.1, 2.0]
+    g["scales"][1] = [0.35, 0.3, 0.3]
+    g["opacities"][1] = 0.8
+    cam = oracle.Camera(32, 24, 30.0, 31.0, 16.0, 12.0, 0.2, (0.2, 0.1, 0.3))
+    pose = np.array([0.98, 0.06, -0.04, 0.03, 0.04, -0.03, 0.15])
+    return g, cam, pose
+
+
+def upstream(cam, seed=1):
+    rng = np.random.default_rng(seed)
+    H_, W_ = cam.height, cam.width
+    return rng.normal(size=(3, H_, W_)), rng.normal(size=(H_, W_)), rng.normal(size=(H_, W_))
+
+
+def functional(g, pose, cam, opts, gC, gD, gA):
+    out = oracle.render(g, pose, cam, opts, mode=1, nthreads=4)
+    L = float((gC * out["color"]).sum() + (gD * out["depth"]).sum() + (gA * out["alpha"]).sum())
+    return L, out["hash"]
+
+
+def fd_check(g, pose, cam, opts, gC, gD, gA, which, idxs, analytic, aref):
+    base_hash = functional(g, pose, cam, opts, gC, gD, gA)[1]
+    n_ok = 0
+    for idx in idxs:
+        if which == "pose7":
+            theta = pose[idx]
+        else:
+            theta = g[which][idx]
+        h = 1e-6 * max(1.0, abs(theta))
+        vals = []
+        hashes = []
+        for sgn in (+1, -1):
+            gg = {k: v.copy() for k, v in g.items()}
+            pp = pose.copy()
+            if which == "pose7":
+                pp[idx] = theta + sgn * h
+            else:
+                gg[which][idx] = theta + sgn * h
+            L, hs = functional(gg, pp, cam, opts, gC, gD, gA)
+            vals.append(L)
+            hashes.append(hs)
+        if not (np.array_equal(hashes[0], base_hash) and np.array_equal(hashes[1], base_hash)):
+            continue  # a discrete decision changed inside the stencil: resample
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = analytic[idx]
+        tol = 1e-5 * abs(fd) + 1e-7 * aref[idx] + 1e-8
+        assert abs(fd - an) <= tol, f"{which}{idx}: fd {fd!r} analytic {an!r} (tol {tol:.3g})"
+        n_ok += 1
+    return n_ok
+
+
+@pytest.mark.parametrize("which,shape", [("means", 3), ("scales", 3), ("quats", 4), ("opacities", 1), ("colors", 3)])
+def test_fd_gaussian_params(which, shape):
+    g, cam, pose = scene()
+    opts = oracle.Opts()
+    gC, gD, gA = upstream(cam)
+    b = oracle.backward(g, pose, cam, opts, gC, gD, gA, nthreads=4)
+    an = b["grads"][which]
+    ar = b["aref"][which]
+    # Gaussians 0 (clamped alpha) and 1 (clamped Jacobian) plus a spread of others
+    ks = [0, 1] + list(range(2, 60, 5))
+    idxs = [(k,) if shape == 1 else (k, j) for k in ks for j in range(shape)] if shape > 1 else [(k,) for k in ks]
+    n_ok = fd_check(g, pose, cam, opts, gC, gD, gA, which, idxs, an, ar)
+    assert n_ok >= 0.8 * len(idxs)
+    assert np.abs(an).max() > 0
+
+
+def test_fd_pose_quaternion_and_translation():
+    g, cam, pose = scene(2)
+    opts = oracle.Opts()
+    gC, gD, gA = upstream(cam, 3)
+    b = oracle.backward(g, pose, cam, opts, gC, gD, gA, nthreads=4)
+    n_ok = fd_check(g, pose, cam, opts, gC, gD, gA, "pose7", [(i,) for i in range(7)], b["grads"]["pose7"],
+                    b["aref"]["pose7"])
+    assert n_ok == 7
+
+
+def test_fd_twist_left_perturbation():
+    g, cam, pose = scene(4)
+    opts = oracle.Opts()
+    gC, gD, gA = upstream(cam, 5)
+    b = oracle.backward(g, pose, cam, opts, gC, gD, gA, nthreads=4)
+    tw = b["grads"]["twist6"]
+    base_hash = functional(g, pose, cam, opts, gC, gD, gA)[1]
+    for i in range(6):
+        h = 1e-6
+        xi = np.zeros(6); xi[i] = h
+        Lp, hp = functional(g, H.left_perturb_pose(pose, xi), cam, opts, gC, gD, gA)
+        Lm, hm = functional(g, H.left_perturb_pose(pose, -xi), cam, opts, gC, gD, gA)
+        assert np.array_equal(hp, base_hash) and np.array_equal(hm, base_hash)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - tw[i]) <= 1e-5 * abs(fd) + 1e-7 * b["aref"]["twist6"][i] + 1e-8, (i, fd, tw[i])
+
+
+def test_translation_gradient_identities():
+    """dL/dt equals the sum over Gaussians of dL/dx_cam = R_p dL/dmu, and equals
+    the rho part of the twist (both follow from x = R_p mu + t)."""
+    g, cam, pose = scene(6)
+    opts = oracle.Opts()
+    gC, gD, gA = upstream(cam, 7)
+    b = oracle.backward(g, pose, cam, opts, gC, gD, gA, nthreads=4)
+    Rp = H.scipy_R(pose[:4] / np.linalg.norm(pose[:4]))
+    s = (b["grads"]["means"] @ Rp.T).sum(0)
+    np.testing.assert_allclose(b["grads"]["pose7"][4:7], s, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(b["grads"]["twist6"][:3], s, rtol=1e-10, atol=1e-12)
+
+
+def test_quaternion_sign_symmetry():
+    """q and -q give the same image, so their gradients are negatives."""
+    g, cam, pose = scene(8)
+    opts = oracle.Opts()
+    gC, gD, gA = upstream(cam, 9)
+    b1 = oracle.backward(g, pose, cam, opts, gC, gD, gA, nthreads=4)
+    g2 = dict(g)
+    g2["quats"] = -g["quats"]
+    b2 = oracle.backward(g2, pose, cam, opts, gC, gD, gA, nthreads=4)
+    np.testing.assert_allclose(b2["grads"]["quats"], -b1["grads"]["quats"], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(b2["grads"]["means"], b1["grads"]["means"], rtol=1e-12, atol=1e-14)
+
+
+def test_zero_upstream_gives_zero_gradient_and_ground_truth_pose_is_stationary():
+    """At the pose that rendered the target, every L1 residual is 0, sign(0) = 0,
+    so the tracking and mapping gradients vanish exactly."""
+    g, cam, pose = scene(10)
+    opts = oracle.Opts()
+    out = oracle.render(g, pose, cam, opts)
+    Ct = out["color"].astype(np.float32); Dt = out["depth"].astype(np.float32)
+    L, gC, gD = oracle.loss_l1(Ct, Dt, Ct, Dt)
+    assert L == 0 and not gC.any() and not gD.any()
+    b = oracle.backward(g, pose, cam, opts, gC, gD, nthreads=4)
+    assert all(not v.any() for v in b["grads"].values())
