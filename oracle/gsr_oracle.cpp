@@ -353,7 +353,6 @@ void composite_pixel(const Scene& S, int px, int py, bool pruned, int flip, bool
     if (pruned && (px < g.px0 || px > g.px1 || py < g.py0 || py > g.py1)) continue;
     const double dx = px - g.u, dy = py - g.v;
     const double sigma = 0.5 * (g.a * dx * dx + g.c * dy * dy) + g.b * dx * dy;
-    if (sigma < 0) continue;
     const double e = std::exp(-sigma);
     const double raw = g.o * e;
     bool clamped = raw > opt.amax;

@@ -93,8 +93,6 @@ def brute_force_render(g: dict, pose7, cam: oracle.Camera, opts: oracle.Opts):
             for z, k, uv, Ainv, o, col in recs:
                 delta = np.array([px, py], np.float64) - uv
                 sigma = 0.5 * delta @ Ainv @ delta
-                if sigma < 0:
-                    continue
                 a = min(opts.alpha_max, o * np.exp(-sigma))
                 if a < opts.alpha_min:
                     continue
