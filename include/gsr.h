@@ -1,0 +1,157 @@
+/*
+ * gsr.h — C ABI of libgsr.so, a differentiable tile-based rasterizer of 3D
+ * Gaussians into colour, depth and alpha for AMD Instinct MI355X (gfx950).
+ *
+ * It implements the rendering hot path of Gaussian-SLAM (Yugay et al., arXiv
+ * 2312.10070): projection of Gaussians (Sec. 3.1, Eq. 1) with the EWA 2D
+ * covariance (Eq. 2), front-to-back alpha compositing of colour (Eq. 3, 4)
+ * and depth (Eq. 6), their explicit gradients (Sec. 3.3, Eq. 7-8 and the
+ * colour/opacity/covariance analogues), the L1 mapping losses (Eq. 9, Eq. 10
+ * without SSIM) and the masked tracking loss (Eq. 15) with the pose gradient
+ * the tracking optimisation (Eq. 14) needs.
+ *
+ * Conventions shared by every call
+ *  - All array arguments are DEVICE pointers to contiguous float32 (unless
+ *    stated), owned by the caller, 4-byte aligned (quats: 16-byte aligned),
+ *    never aliased with an output of the same call.
+ *  - Gaussians: means [n,3], scales [n,3] (the positive per-axis standard
+ *    deviations s of Sigma = R diag(s)^2 R^T), quats [n,4] (w,x,y,z, any
+ *    non-zero norm; normalised inside), opacities [n] (in (0,1]), colors [n,3]
+ *    (RGB, no spherical harmonics, as the paper optimises RGB directly).
+ *  - pose7 (device, 7 floats): (qw,qx,qy,qz,tx,ty,tz) of the world-to-camera
+ *    transform x_cam = R(q/|q|) mu + t. Camera axes: +x right, +y down, +z
+ *    forward; pixel (px,py) is sampled at the continuous point (px,py).
+ *  - Images are planar: color [3,H,W], depth [H,W], alpha [H,W].
+ *  - Every call enqueues work on the context's HIP stream and returns without
+ *    waiting, except where noted ("synchronises"). Inputs must stay alive and
+ *    unmodified until the stream has passed the call; the backward re-reads
+ *    the forward's Gaussian and pose inputs.
+ *  - Errors: every call returns GSR_OK (0) or a negative code; no exception
+ *    crosses the ABI. gsr_last_error() gives a message for the last failure
+ *    on that context. A degenerate Gaussian (non-finite parameters, zero
+ *    quaternion, depth <= near_z, singular 2D covariance, opacity below
+ *    alpha_min, support box off the image) is not an error: it is culled and
+ *    receives zero gradient.
+ */
+#ifndef GSR_H_
+#define GSR_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GSR_OK = 0,
+  GSR_EINVAL = -1,    /* bad argument: NULL required pointer, n < 0, W/H <= 0,
+                         non-finite intrinsics, unsupported tile shape */
+  GSR_ENOMEM = -2,    /* device allocation failed */
+  GSR_EHIP = -3,      /* a HIP runtime call failed (text in gsr_last_error) */
+  GSR_EOVERFLOW = -4  /* a fixed-capacity (graph) buffer was too small */
+};
+
+typedef struct gsr_ctx gsr_ctx;     /* opaque: stream, workspaces, graphs */
+typedef struct gsr_state gsr_state; /* opaque: what one forward leaves for its backward */
+
+/* Pinhole camera (host struct, passed by pointer and copied). */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float near_z; /* Gaussians with camera depth <= near_z are culled */
+  float bg[3];  /* background colour composited behind the last Gaussian */
+} gsr_camera;
+
+/* Rasterizer constants (host struct). Defaults: lowpass 0.3 px^2, alpha_min
+ * 1/255, alpha_max 0.99, T_min 1e-4, guard 1.3, tile 16x16. */
+typedef struct {
+  float lowpass;   /* h added to both diagonal entries of Sigma' */
+  float alpha_min; /* pairs with alpha < alpha_min are skipped */
+  float alpha_max; /* alpha = min(alpha_max, o exp(-sigma)) */
+  float T_min;     /* a pixel stops before the Gaussian that would take T below it */
+  float guard;     /* lateral clamp of x/z, y/z inside J: guard * max(c, size-c) / f */
+  int32_t tile_w, tile_h; /* 16x16, 8x32 or 32x8 */
+} gsr_opts;
+
+typedef struct {
+  int64_t n;
+  const float *means, *scales, *quats, *opacities, *colors;
+} gsr_gaussians;
+
+/* Gradient outputs of the backward (device). NULL = not wanted. Overwritten. */
+typedef struct {
+  float *means, *scales, *quats, *opacities, *colors;
+} gsr_grads;
+
+/* Library / context ---------------------------------------------------- */
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). */
+int gsr_ctx_create(gsr_ctx **out, int device, void *hip_stream);
+int gsr_ctx_destroy(gsr_ctx *ctx);
+/* Change the stream later calls enqueue on. */
+int gsr_set_stream(gsr_ctx *ctx, void *hip_stream);
+const char *gsr_strerror(int code);
+const char *gsr_last_error(gsr_ctx *ctx);
+void gsr_default_opts(gsr_opts *out);
+
+/* Forward render (Eq. 1-4, 6) ------------------------------------------ */
+
+/* Render colour (+ background), depth (sum z alpha T, background depth 0) and
+ * accumulated alpha 1 - T_final. Projection, tile binning, (tile, depth)
+ * radix sort and compositing all run on the device. The call synchronises
+ * once, after the tile-overlap count is known, to size its buffers.
+ * *state receives a handle the backward needs; release it with
+ * gsr_state_release (it owns the sorted tile lists and per-pixel state). */
+int gsr_render_fwd(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cam, const gsr_opts *opts,
+                   const float *pose7, float *color, float *depth, float *alpha, gsr_state **state);
+
+/* Backward of gsr_render_fwd for upstream gradients dL/dcolor [3,H,W],
+ * dL/ddepth [H,W] and dL/dalpha [H,W] (NULL = zero). Writes the gradients
+ * w.r.t. the activated parameters (Sec. 3.3; Eq. 8 for the depth-alpha term,
+ * plus the direct depth term dD/dz_j = alpha_j T_j), and, if non-NULL,
+ * dL/dpose7 (7 floats: quaternion through its normalisation, translation)
+ * and dL/dtwist6 (6 floats: (rho, phi) of the left perturbation
+ * T <- exp(xi^) T). Transmittance is recomputed back to front, not stored. */
+int gsr_render_bwd(gsr_ctx *ctx, gsr_state *state, const float *dL_dcolor, const float *dL_ddepth,
+                   const float *dL_dalpha, const gsr_grads *grads, float *dL_dpose7, float *dL_dtwist6);
+
+int gsr_state_release(gsr_ctx *ctx, gsr_state *state);
+
+/* Introspection of a forward's tile lists (O(K) copy; synchronises).
+ * *K = number of (tile, Gaussian) overlaps; ranges (device int32 [n_tiles,2],
+ * [start,end) into ids) and ids (device int32 [K]) may be NULL. Tiles are
+ * numbered row-major with ceil(W/tile_w) tiles per row. */
+int gsr_tile_lists(gsr_ctx *ctx, const gsr_state *state, int64_t *K, int32_t *ranges, int32_t *ids);
+
+/* Losses (device outputs) ----------------------------------------------- */
+
+/* Mapping L1 (Eq. 9 and the L1 part of Eq. 10):
+ * L = w_color mean_{3P}|C - C*| + w_depth mean_P|D - D*|, sign(0) = 0.
+ * loss: device float[1] (overwritten); gradients [3,P] and [P]. */
+int gsr_loss_l1(gsr_ctx *ctx, const float *color, const float *depth, const float *tgt_color,
+                const float *tgt_depth, int64_t n_pixels, float w_color, float w_depth, float *loss,
+                float *dL_dcolor, float *dL_ddepth);
+
+/* Tracking loss (Eq. 15 with the supplement's masks): valid = observed depth
+ * > 0; e = |D - D*|; m = lower median of e over valid pixels (exact, radix
+ * select on the device); inlier = valid and e <= inlier_mult * m; weight =
+ * inlier * alpha^3 (treated as constant, so dL/dalpha = 0);
+ * L = sum_p weight (lambda_c sum_ch |C - C*| + (1 - lambda_c) |D - D*|).
+ * loss, median: device float[1]; median may be NULL. */
+int gsr_loss_track(gsr_ctx *ctx, const float *color, const float *depth, const float *alpha,
+                   const float *tgt_color, const float *tgt_depth, int64_t n_pixels, float lambda_c,
+                   float inlier_mult, float *loss, float *dL_dcolor, float *dL_ddepth, float *median);
+
+/* Optimiser --------------------------------------------------------------- */
+
+/* One bias-corrected Adam step (Kingma & Ba) on n device floats, in place;
+ * step >= 1 is the 1-based step count. */
+int gsr_adam(gsr_ctx *ctx, float *param, float *exp_avg, float *exp_avg_sq, const float *grad, int64_t n,
+             int64_t step, float lr, float beta1, float beta2, float eps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H_ */

@@ -1,0 +1,218 @@
+// Internal declarations of libgsr: launch-constant structs, device helpers
+// shared by the forward and backward kernels, and the host-side launchers.
+// gfx950 (CDNA4) only: wave64, 256-thread workgroups for the tile kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsr.h"
+
+namespace gsr {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+constexpr int kTileThreads = 256;  // one pixel per lane, 4 waves per tile
+constexpr int kWave = 64;
+
+// Launch constants of one render (by value into every kernel).
+struct Raster {
+  int W, H;
+  int tw, th;         // tile shape (tw * th == 256)
+  int tw_log2;        // log2(tw)
+  int ntx, nty;       // tiles per row / column
+  int n_tiles;        // ntx * nty (per view)
+  float fx, fy, cx, cy, near_z;
+  float lowpass, amin, amax, tmin;
+  float limx, limy;   // guard band on x/z and y/z inside the Jacobian
+  float bg0, bg1, bg2;
+};
+
+// Per-Gaussian record written by the projection kernel. The quadratic form of
+// Eq. 4 is stored pre-scaled so that one pair costs three FMAs:
+//   p = pa dx^2 + pb dx dy + pc dy^2 = -sigma * log2(e),   alpha = o * 2^p.
+//   rec_uvab = (u, v, pa, pb), rec_co = (pc, o), rec_rgbz = (r, g, b, z_cam).
+struct PairEval {
+  float alpha;   // min(alpha_max, o 2^p)
+  float e;       // 2^p = exp(-sigma)
+  bool use;      // alpha >= alpha_min
+  bool clamped;  // o 2^p > alpha_max (alpha does not depend on o, sigma)
+};
+
+// The single definition of every per-pair discrete decision. The forward and
+// the backward both call it, so skip / clamp decisions agree bit for bit. FP
+// contraction is pinned: only the explicit fmaf calls fuse.
+__device__ __forceinline__ PairEval eval_pair(float dx, float dy, float pa, float pb, float pc, float o,
+                                              float amin, float amax) {
+#pragma clang fp contract(off)
+  const float t = pc * dy;
+  const float p = fmaf(pa * dx, dx, fmaf(pb * dx, dy, t * dy));
+  PairEval r;
+  r.e = __builtin_amdgcn_exp2f(p);
+  const float raw = o * r.e;
+  r.clamped = raw > amax;
+  r.alpha = r.clamped ? amax : raw;
+  r.use = r.alpha >= amin;
+  return r;
+}
+
+// Tile index of a workgroup. Workgroups are dealt round-robin to the 8 XCDs
+// (each with its own L2); this gives each XCD a contiguous run of row-major
+// tiles so neighbouring tiles, which share most Gaussians, hit the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// Sum over the 64 lanes with DPP row operations; the total lands in lane 63.
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+  int x = __float_as_int(v);
+#define GSR_DPP_ADD(ctrl)                                                                  \
+  x = __float_as_int(__int_as_float(x) +                                                   \
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, ctrl, 0xf, 0xf, false)))
+  GSR_DPP_ADD(0xb1);   // quad_perm [1,0,3,2]
+  GSR_DPP_ADD(0x4e);   // quad_perm [2,3,0,1]
+  GSR_DPP_ADD(0x124);  // row_ror:4
+  GSR_DPP_ADD(0x128);  // row_ror:8
+  GSR_DPP_ADD(0x142);  // row_bcast:15
+  GSR_DPP_ADD(0x143);  // row_bcast:31
+#undef GSR_DPP_ADD
+  return __int_as_float(x);
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_all(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Rotation matrix of a unit quaternion (w, x, y, z), row-major.
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float R[9]) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+  R[0] = 1.f - 2.f * (yy + zz);
+  R[1] = 2.f * (xy - wz);
+  R[2] = 2.f * (xz + wy);
+  R[3] = 2.f * (xy + wz);
+  R[4] = 1.f - 2.f * (xx + zz);
+  R[5] = 2.f * (yz - wx);
+  R[6] = 2.f * (xz - wy);
+  R[7] = 2.f * (yz + wx);
+  R[8] = 1.f - 2.f * (xx + yy);
+}
+
+// Gradient of <G, R(q)> w.r.t. a unit quaternion, then through q / |q|.
+__device__ __forceinline__ void quat_rot_vjp(const float qh[4], float inv_norm, const float G[9], float gq[4]) {
+  const float w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+  float gw = 2.f * (x * (G[7] - G[5]) + y * (G[2] - G[6]) + z * (G[3] - G[1]));
+  float gx = 2.f * (y * (G[1] + G[3]) + z * (G[2] + G[6]) + w * (G[7] - G[5])) - 4.f * x * (G[4] + G[8]);
+  float gy = 2.f * (x * (G[1] + G[3]) + w * (G[2] - G[6]) + z * (G[5] + G[7])) - 4.f * y * (G[0] + G[8]);
+  float gz = 2.f * (w * (G[3] - G[1]) + x * (G[2] + G[6]) + y * (G[5] + G[7])) - 4.f * z * (G[0] + G[4]);
+  const float d = w * gw + x * gx + y * gy + z * gz;
+  gq[0] = (gw - w * d) * inv_norm;
+  gq[1] = (gx - x * d) * inv_norm;
+  gq[2] = (gy - y * d) * inv_norm;
+  gq[3] = (gz - z * d) * inv_norm;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (defined in the .hip files, called by gsr_api.cpp).
+// ---------------------------------------------------------------------------
+
+struct ProjectArgs {
+  int64_t n;
+  const float *means, *scales, *quats, *opacities, *colors;
+  const float* pose7;  // device
+  float4* rec_uvab;
+  float2* rec_co;
+  float4* rec_rgbz;
+  int4* rect;          // tile rectangle (tx0, ty0, tx1, ty1)
+  uint32_t* counts;    // tiles per Gaussian (0 = culled)
+};
+void launch_project(const Raster& R, const ProjectArgs& a, hipStream_t s);
+
+// Exclusive scan of n uint32 values; writes the total to *total (device).
+// temp must hold scan_temp_words(n) uint32.
+int64_t scan_temp_words(int64_t n);
+void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* temp,
+                           hipStream_t s);
+
+struct BinArgs {
+  int64_t n;
+  const float4* rec_rgbz;
+  const int4* rect;
+  const uint32_t* counts;
+  const uint32_t* offsets;
+  const uint32_t* d_K;
+  int64_t K_cap;
+  uint32_t tile_base;  // view * n_tiles for multi-view lists
+  uint64_t* keys;
+  uint32_t* vals;
+  int* overflow;
+};
+void launch_duplicate(const Raster& R, const BinArgs& a, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs over the low `bits` bits.
+// Returns the index (0/1) of the buffer pair holding the result.
+int64_t radix_temp_words(int64_t cap);
+int launch_radix_sort(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* d_K, int64_t cap, int bits,
+                      uint32_t* temp, hipStream_t s);
+void launch_tile_ranges(const uint64_t* keys, const uint32_t* d_K, int64_t cap, int2* ranges, int64_t n_ranges,
+                        hipStream_t s);
+
+struct FwdArgs {
+  const int2* ranges;
+  const uint32_t* ids;
+  const float4* rec_uvab;
+  const float2* rec_co;
+  const float4* rec_rgbz;
+  float *color, *depth, *alpha, *Tfin;
+  int* last;
+};
+void launch_render_fwd(const Raster& R, const FwdArgs& a, hipStream_t s);
+
+struct BwdArgs {
+  const int2* ranges;
+  const uint32_t* ids;
+  const float4* rec_uvab;
+  const float2* rec_co;
+  const float4* rec_rgbz;
+  const float* Tfin;
+  const int* last;
+  const float *gC, *gD, *gA;
+  float* g2d;  // [n, 10]: u, v, pa, pb, pc, o, r, g, b, z
+};
+void launch_render_bwd(const Raster& R, const BwdArgs& a, hipStream_t s);
+
+struct ProjectBwdArgs {
+  int64_t n;
+  const float *means, *scales, *quats, *opacities, *colors;
+  const float* pose7;
+  const uint32_t* counts;
+  const float* g2d;
+  float *g_means, *g_scales, *g_quats, *g_opacities, *g_colors;  // may be NULL
+  float* pose_acc;  // [12]: dL/dR_p (9, row-major), dL/dt (3); NULL = skip
+};
+void launch_project_bwd(const Raster& R, const ProjectBwdArgs& a, hipStream_t s);
+void launch_pose_finalize(const float* pose7, const float* pose_acc, float* dL_dpose7, float* dL_dtwist6,
+                          hipStream_t s);
+
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+
+void launch_loss_l1(const float* C, const float* D, const float* Ct, const float* Dt, int64_t P, float wc, float wd,
+                    float* loss, float* gC, float* gD, hipStream_t s);
+// temp: track_temp_words() uint32
+int64_t track_temp_words();
+void launch_loss_track(const float* C, const float* D, const float* A, const float* Ct, const float* Dt, int64_t P,
+                       float lambda_c, float inlier_mult, float* loss, float* gC, float* gD, float* median,
+                       uint32_t* temp, hipStream_t s);
+void launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
+                 float bc1, float bc2, hipStream_t s);
+
+}  // namespace gsr

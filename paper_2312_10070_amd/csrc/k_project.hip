@@ -1,0 +1,379 @@
+// Projection of Gaussians (Eq. 1), EWA 2D covariance (Eq. 2), support box and
+// tile rectangle; and the backward of that chain to the 3D parameters and the
+// camera pose. One thread per Gaussian; memory bound (56 B in, 60 B out).
+#include "gsr_internal.h"
+
+namespace gsr {
+
+namespace {
+
+struct PoseF {
+  float qh[4];
+  float inv_norm;
+  float R[9];
+  float t[3];
+  bool ok;
+};
+
+__device__ __forceinline__ PoseF load_pose(const float* __restrict__ p7) {
+  PoseF P;
+  const float w = p7[0], x = p7[1], y = p7[2], z = p7[3];
+  const float n2 = w * w + x * x + y * y + z * z;
+  P.ok = n2 > 0.f && isfinite(n2);
+  const float inv = P.ok ? 1.f / sqrtf(n2) : 0.f;
+  P.inv_norm = inv;
+  P.qh[0] = w * inv;
+  P.qh[1] = x * inv;
+  P.qh[2] = y * inv;
+  P.qh[3] = z * inv;
+  quat_rot(P.qh[0], P.qh[1], P.qh[2], P.qh[3], P.R);
+  P.t[0] = p7[4];
+  P.t[1] = p7[5];
+  P.t[2] = p7[6];
+  return P;
+}
+
+// Everything about one Gaussian that both passes recompute.
+struct Geo {
+  float qh[4], inv_qn;
+  float R[9];
+  float s[3];
+  float Sig[6];   // Sigma (xx, xy, xz, yy, yz, zz)
+  float x[3];     // camera-space mean
+  float Sc[6];    // Sigma_c = R_p Sigma R_p^T (xx, xy, xz, yy, yz, zz)
+  float J00, J02, J11, J12;
+  bool clx, cly;
+  float Xc, Yc;
+  float Sxx, Sxy, Syy;  // Sigma' with low-pass
+  float det;
+  float u, v;
+};
+
+// Returns false if the Gaussian is culled before the support box.
+__device__ __forceinline__ bool project_geo(const Raster& Rr, const PoseF& P, const float* __restrict__ means,
+                                            const float* __restrict__ scales, const float* __restrict__ quats,
+                                            int64_t k, Geo& g) {
+  if (!P.ok) return false;
+  const float4 q = reinterpret_cast<const float4*>(quats)[k];
+  const float n2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
+  if (!(n2 > 0.f) || !isfinite(n2)) return false;
+  g.inv_qn = 1.f / sqrtf(n2);
+  g.qh[0] = q.x * g.inv_qn;
+  g.qh[1] = q.y * g.inv_qn;
+  g.qh[2] = q.z * g.inv_qn;
+  g.qh[3] = q.w * g.inv_qn;
+  quat_rot(g.qh[0], g.qh[1], g.qh[2], g.qh[3], g.R);
+  g.s[0] = scales[3 * k + 0];
+  g.s[1] = scales[3 * k + 1];
+  g.s[2] = scales[3 * k + 2];
+  // M = R diag(s); Sigma = M M^T
+  float M[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[3 * i + j] = g.R[3 * i + j] * g.s[j];
+  g.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  g.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+  g.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+  g.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+  g.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+  g.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+  const float mx = means[3 * k + 0], my = means[3 * k + 1], mz = means[3 * k + 2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) g.x[i] = P.R[3 * i] * mx + P.R[3 * i + 1] * my + P.R[3 * i + 2] * mz + P.t[i];
+  if (!isfinite(g.x[0]) || !isfinite(g.x[1]) || !isfinite(g.x[2])) return false;
+  const float z = g.x[2];
+  if (!(z > Rr.near_z)) return false;
+  const float iz = 1.f / z;
+  g.u = Rr.fx * g.x[0] * iz + Rr.cx;
+  g.v = Rr.fy * g.x[1] * iz + Rr.cy;
+  const float X = g.x[0] * iz, Y = g.x[1] * iz;
+  g.clx = (X < -Rr.limx) || (X > Rr.limx);
+  g.cly = (Y < -Rr.limy) || (Y > Rr.limy);
+  g.Xc = fminf(Rr.limx, fmaxf(-Rr.limx, X));
+  g.Yc = fminf(Rr.limy, fmaxf(-Rr.limy, Y));
+  g.J00 = Rr.fx * iz;
+  g.J02 = -Rr.fx * g.Xc * iz;
+  g.J11 = Rr.fy * iz;
+  g.J12 = -Rr.fy * g.Yc * iz;
+  // Sigma_c = R_p Sigma R_p^T
+  const float S[9] = {g.Sig[0], g.Sig[1], g.Sig[2], g.Sig[1], g.Sig[3], g.Sig[4], g.Sig[2], g.Sig[4], g.Sig[5]};
+  float T[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      T[3 * i + j] = P.R[3 * i] * S[j] + P.R[3 * i + 1] * S[3 + j] + P.R[3 * i + 2] * S[6 + j];
+  float Sc[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Sc[3 * i + j] = T[3 * i] * P.R[3 * j] + T[3 * i + 1] * P.R[3 * j + 1] + T[3 * i + 2] * P.R[3 * j + 2];
+  g.Sc[0] = Sc[0];
+  g.Sc[1] = 0.5f * (Sc[1] + Sc[3]);
+  g.Sc[2] = 0.5f * (Sc[2] + Sc[6]);
+  g.Sc[3] = Sc[4];
+  g.Sc[4] = 0.5f * (Sc[5] + Sc[7]);
+  g.Sc[5] = Sc[8];
+  // Sigma' = J Sigma_c J^T + h I with J = [[J00, 0, J02], [0, J11, J12]]
+  const float a0 = g.J00 * g.Sc[0] + g.J02 * g.Sc[2];  // row 0 of J Sigma_c: (a0, a1, a2)
+  const float a1 = g.J00 * g.Sc[1] + g.J02 * g.Sc[4];
+  const float a2 = g.J00 * g.Sc[2] + g.J02 * g.Sc[5];
+  const float b1 = g.J11 * g.Sc[3] + g.J12 * g.Sc[4];  // row 1: (b0, b1, b2)
+  const float b2 = g.J11 * g.Sc[4] + g.J12 * g.Sc[5];
+  g.Sxx = a0 * g.J00 + a2 * g.J02 + Rr.lowpass;
+  g.Sxy = a1 * g.J11 + a2 * g.J12;
+  g.Syy = b1 * g.J11 + b2 * g.J12 + Rr.lowpass;
+  g.det = g.Sxx * g.Syy - g.Sxy * g.Sxy;
+  if (!(g.det > 0.f) || !isfinite(g.det)) return false;
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_project(Raster Rr, ProjectArgs a) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.n) return;
+  const PoseF P = load_pose(a.pose7);
+  Geo g;
+  uint32_t count = 0;
+  int4 rect = make_int4(0, 0, -1, -1);
+  if (project_geo(Rr, P, a.means, a.scales, a.quats, k, g)) {
+    const float o = a.opacities[k];
+    if (o >= Rr.amin && isfinite(o)) {
+      const float idet = 1.f / g.det;
+      const float ca = g.Syy * idet, cb = -g.Sxy * idet, cc = g.Sxx * idet;
+      // support: o exp(-sigma) >= alpha_min needs sigma <= ln(o / alpha_min)
+      const float smax = logf(o / Rr.amin);
+      const float rx = sqrtf(2.f * smax * g.Sxx), ry = sqrtf(2.f * smax * g.Syy);
+      const float ex0 = g.u - rx, ex1 = g.u + rx, ey0 = g.v - ry, ey1 = g.v + ry;
+      if (isfinite(ex0) && isfinite(ex1) && isfinite(ey0) && isfinite(ey1)) {
+        const float fx0 = fmaxf(0.f, ceilf(ex0)), fx1 = fminf((float)(Rr.W - 1), floorf(ex1));
+        const float fy0 = fmaxf(0.f, ceilf(ey0)), fy1 = fminf((float)(Rr.H - 1), floorf(ey1));
+        if (fx0 <= fx1 && fy0 <= fy1) {
+          const int px0 = (int)fx0, px1 = (int)fx1, py0 = (int)fy0, py1 = (int)fy1;
+          rect = make_int4(px0 >> Rr.tw_log2, py0 / Rr.th, px1 >> Rr.tw_log2, py1 / Rr.th);
+          count = (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1));
+          const float s = -0.5f * kLog2e;
+          a.rec_uvab[k] = make_float4(g.u, g.v, s * ca, -kLog2e * cb);
+          a.rec_co[k] = make_float2(s * cc, o);
+          a.rec_rgbz[k] = make_float4(a.colors[3 * k], a.colors[3 * k + 1], a.colors[3 * k + 2], g.x[2]);
+        }
+      }
+    }
+  }
+  a.rect[k] = rect;
+  a.counts[k] = count;
+}
+
+// Backward of the projection for one Gaussian. g2d holds dL/d(u, v, pa, pb,
+// pc, o, r, g, b, z) accumulated by the compositing backward.
+__global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const PoseF P = load_pose(a.pose7);
+  float pacc[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) pacc[i] = 0.f;
+  if (k < a.n) {
+    float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
+    Geo g;
+    if (a.counts[k] > 0 && project_geo(Rr, P, a.means, a.scales, a.quats, k, g)) {
+      const float* G2 = a.g2d + 10 * k;
+      const float g_u = G2[0], g_v = G2[1];
+      // stored (pa, pb, pc) = -log2(e) (a/2, b, c/2) for the conic (a, b, c)
+      const float g_a = -0.5f * kLog2e * G2[2];
+      const float g_b = -kLog2e * G2[3];
+      const float g_c = -0.5f * kLog2e * G2[4];
+      go = G2[5];
+      gc[0] = G2[6];
+      gc[1] = G2[7];
+      gc[2] = G2[8];
+      const float g_zd = G2[9];
+      const float idet = 1.f / g.det;
+      const float A00 = g.Syy * idet, A01 = -g.Sxy * idet, A11 = g.Sxx * idet;
+      // dL/dSigma' = -A Mg A with Mg = [[g_a, g_b/2], [g_b/2, g_c]]
+      const float m01 = 0.5f * g_b;
+      const float t00 = A00 * g_a + A01 * m01, t01 = A00 * m01 + A01 * g_c;
+      const float t10 = A01 * g_a + A11 * m01, t11 = A01 * m01 + A11 * g_c;
+      const float G00 = -(t00 * A00 + t01 * A01);
+      const float G01 = -(t00 * A01 + t01 * A11);
+      const float G11 = -(t10 * A01 + t11 * A11);
+      // Sigma' = J Sc J^T:  dL/dSc = J^T G J,  dL/dJ = 2 G J Sc
+      const float J00 = g.J00, J02 = g.J02, J11 = g.J11, J12 = g.J12;
+      // rows of J Sc
+      const float r0[3] = {J00 * g.Sc[0] + J02 * g.Sc[2], J00 * g.Sc[1] + J02 * g.Sc[4], J00 * g.Sc[2] + J02 * g.Sc[5]};
+      const float r1[3] = {J11 * g.Sc[1] + J12 * g.Sc[2], J11 * g.Sc[3] + J12 * g.Sc[4], J11 * g.Sc[4] + J12 * g.Sc[5]};
+      const float dJ00 = 2.f * (G00 * r0[0] + G01 * r1[0]);
+      const float dJ02 = 2.f * (G00 * r0[2] + G01 * r1[2]);
+      const float dJ11 = 2.f * (G01 * r0[1] + G11 * r1[1]);
+      const float dJ12 = 2.f * (G01 * r0[2] + G11 * r1[2]);
+      // J^T G J for J columns c0 = (J00, 0), c1 = (0, J11), c2 = (J02, J12)
+      float GSc[9];
+      {
+        const float c[3][2] = {{J00, 0.f}, {0.f, J11}, {J02, J12}};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            GSc[3 * i + j] = c[i][0] * (G00 * c[j][0] + G01 * c[j][1]) + c[i][1] * (G01 * c[j][0] + G11 * c[j][1]);
+      }
+      const float z = g.x[2], iz = 1.f / z, iz2 = iz * iz;
+      float gx = 0.f, gy = 0.f, gz = 0.f;
+      gz += dJ00 * (-Rr.fx * iz2) + dJ11 * (-Rr.fy * iz2);
+      if (!g.clx) {
+        gx += dJ02 * (-Rr.fx * iz2);
+        gz += dJ02 * (2.f * Rr.fx * g.x[0] * iz2 * iz);
+      } else {
+        gz += dJ02 * (Rr.fx * g.Xc * iz2);
+      }
+      if (!g.cly) {
+        gy += dJ12 * (-Rr.fy * iz2);
+        gz += dJ12 * (2.f * Rr.fy * g.x[1] * iz2 * iz);
+      } else {
+        gz += dJ12 * (Rr.fy * g.Yc * iz2);
+      }
+      gx += g_u * Rr.fx * iz;
+      gz += -g_u * Rr.fx * g.x[0] * iz2;
+      gy += g_v * Rr.fy * iz;
+      gz += -g_v * Rr.fy * g.x[1] * iz2;
+      gz += g_zd;
+      // mean: x = R_p mu + t
+#pragma unroll
+      for (int i = 0; i < 3; ++i) gm[i] = P.R[i] * gx + P.R[3 + i] * gy + P.R[6 + i] * gz;
+      // dL/dSigma = R_p^T GSc R_p
+      float U[9], GS[9];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) U[3 * i + j] = P.R[i] * GSc[j] + P.R[3 + i] * GSc[3 + j] + P.R[6 + i] * GSc[6 + j];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) GS[3 * i + j] = U[3 * i] * P.R[j] + U[3 * i + 1] * P.R[3 + j] + U[3 * i + 2] * P.R[6 + j];
+      // Sigma = M M^T, M = R diag(s): dL/dM = 2 GS M
+      float M[9], GM[9];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) M[3 * i + j] = g.R[3 * i + j] * g.s[j];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          GM[3 * i + j] = 2.f * (GS[3 * i] * M[j] + GS[3 * i + 1] * M[3 + j] + GS[3 * i + 2] * M[6 + j]);
+      float GR[9];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        gs[j] = GM[j] * g.R[j] + GM[3 + j] * g.R[3 + j] + GM[6 + j] * g.R[6 + j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) GR[3 * i + j] = GM[3 * i + j] * g.s[j];
+      }
+      quat_rot_vjp(g.qh, g.inv_qn, GR, gq);
+      if (a.pose_acc) {
+        // dL/dR_p = gx mu^T + 2 GSc R_p Sigma ;  dL/dt = gx
+        const float mu[3] = {a.means[3 * k], a.means[3 * k + 1], a.means[3 * k + 2]};
+        const float S[9] = {g.Sig[0], g.Sig[1], g.Sig[2], g.Sig[1], g.Sig[3], g.Sig[4], g.Sig[2], g.Sig[4], g.Sig[5]};
+        float RS[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) RS[3 * i + j] = P.R[3 * i] * S[j] + P.R[3 * i + 1] * S[3 + j] + P.R[3 * i + 2] * S[6 + j];
+        const float gxv[3] = {gx, gy, gz};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            pacc[3 * i + j] = gxv[i] * mu[j] +
+                              2.f * (GSc[3 * i] * RS[j] + GSc[3 * i + 1] * RS[3 + j] + GSc[3 * i + 2] * RS[6 + j]);
+        pacc[9] = gx;
+        pacc[10] = gy;
+        pacc[11] = gz;
+      }
+    }
+    if (a.g_means) {
+      a.g_means[3 * k] = gm[0];
+      a.g_means[3 * k + 1] = gm[1];
+      a.g_means[3 * k + 2] = gm[2];
+    }
+    if (a.g_scales) {
+      a.g_scales[3 * k] = gs[0];
+      a.g_scales[3 * k + 1] = gs[1];
+      a.g_scales[3 * k + 2] = gs[2];
+    }
+    if (a.g_quats) reinterpret_cast<float4*>(a.g_quats)[k] = make_float4(gq[0], gq[1], gq[2], gq[3]);
+    if (a.g_opacities) a.g_opacities[k] = go;
+    if (a.g_colors) {
+      a.g_colors[3 * k] = gc[0];
+      a.g_colors[3 * k + 1] = gc[1];
+      a.g_colors[3 * k + 2] = gc[2];
+    }
+  }
+  if (a.pose_acc) {
+    // workgroup reduction of the 12 pose partials, one atomic per value
+    __shared__ float red[4][12];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const float s = wave_sum_all(pacc[i]);
+      if (lane == 0) red[w][i] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+      const int nw = (blockDim.x + 63) >> 6;
+      float s = 0.f;
+      for (int i = 0; i < nw; ++i) s += red[i][threadIdx.x];
+      atomicAdd(&a.pose_acc[threadIdx.x], s);
+    }
+  }
+}
+
+// From dL/dR_p and dL/dt to the quaternion/translation gradient and the twist
+// of the left perturbation (R <- Exp(phi) R, t <- Exp(phi) t + rho):
+//   dL/drho = dL/dt,   dL/dphi = sum_j R[:, j] x G[:, j] + t x dL/dt.
+__global__ void k_pose_finalize(const float* __restrict__ pose7, const float* __restrict__ acc,
+                                float* __restrict__ dpose7, float* __restrict__ dtwist6) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const PoseF P = load_pose(pose7);
+  float G[9];
+  for (int i = 0; i < 9; ++i) G[i] = acc[i];
+  const float gt[3] = {acc[9], acc[10], acc[11]};
+  if (dpose7) {
+    float gq[4] = {0, 0, 0, 0};
+    if (P.ok) quat_rot_vjp(P.qh, P.inv_norm, G, gq);
+    for (int i = 0; i < 4; ++i) dpose7[i] = gq[i];
+    for (int i = 0; i < 3; ++i) dpose7[4 + i] = gt[i];
+  }
+  if (dtwist6) {
+    float phi[3] = {P.t[1] * gt[2] - P.t[2] * gt[1], P.t[2] * gt[0] - P.t[0] * gt[2], P.t[0] * gt[1] - P.t[1] * gt[0]};
+    for (int j = 0; j < 3; ++j) {
+      const float r0 = P.R[j], r1 = P.R[3 + j], r2 = P.R[6 + j];
+      const float g0 = G[j], g1 = G[3 + j], g2 = G[6 + j];
+      phi[0] += r1 * g2 - r2 * g1;
+      phi[1] += r2 * g0 - r0 * g2;
+      phi[2] += r0 * g1 - r1 * g0;
+    }
+    for (int i = 0; i < 3; ++i) {
+      dtwist6[i] = gt[i];
+      dtwist6[3 + i] = phi[i];
+    }
+  }
+}
+
+}  // namespace
+
+void launch_project(const Raster& R, const ProjectArgs& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  const int64_t blocks = (a.n + 255) / 256;
+  hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, R, a);
+}
+
+void launch_project_bwd(const Raster& R, const ProjectBwdArgs& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  const int64_t blocks = (a.n + 255) / 256;
+  hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, R, a);
+}
+
+void launch_pose_finalize(const float* pose7, const float* acc, float* dpose7, float* dtwist6, hipStream_t s) {
+  hipLaunchKernelGGL(k_pose_finalize, dim3(1), dim3(64), 0, s, pose7, acc, dpose7, dtwist6);
+}
+
+}  // namespace gsr

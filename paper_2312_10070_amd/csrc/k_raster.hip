@@ -1,0 +1,211 @@
+// Per-tile compositing. One 256-thread workgroup per tile, one pixel per lane.
+// Gaussian records of the tile's depth-sorted list are staged through LDS in
+// batches of 256 (one coalesced fetch per record per workgroup); each wave
+// walks the batch with the records broadcast from LDS.
+//
+// Forward: front to back (Eq. 3 colour, Eq. 4 alpha, Eq. 6 depth). A lane
+// stops before the Gaussian that would take its transmittance below T_min; a
+// wave leaves the batch loop as soon as all its lanes have stopped, and the
+// workgroup stops fetching batches once all four waves have.
+//
+// Backward: back to front from each pixel's last composited Gaussian. The
+// transmittance in front of Gaussian j is recomputed as T_j = T_{j+1} /
+// (1 - alpha_j) instead of being stored; suffix sums of c alpha T and z alpha T
+// give the second terms of dC/dalpha and Eq. 8. Per-Gaussian partials are
+// reduced across the wave with DPP and added to a [n, 10] gradient buffer with
+// one 10-lane atomic per (Gaussian, wave).
+#include "gsr_internal.h"
+
+namespace gsr {
+
+namespace {
+
+__global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs a) {
+  __shared__ float4 s_uvab[kTileThreads];
+  __shared__ float2 s_co[kTileThreads];
+  __shared__ float4 s_rgbz[kTileThreads];
+
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tyi = tile / Rr.ntx, txi = tile - tyi * Rr.ntx;
+  const int tid = threadIdx.x;
+  const int px = txi * Rr.tw + (tid & (Rr.tw - 1));
+  const int py = tyi * Rr.th + (tid >> Rr.tw_log2);
+  const bool inside = px < Rr.W && py < Rr.H;
+  const float fpx = (float)px, fpy = (float)py;
+
+  const int2 rg = a.ranges[tile];
+  const int start = rg.x, end = rg.y;
+  bool done = !inside;
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
+  int last = 0;
+
+  for (int base = start; base < end; base += kTileThreads) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int i = base + tid;
+    if (i < end) {
+      const uint32_t gid = a.ids[i];
+      s_uvab[tid] = a.rec_uvab[gid];
+      s_co[tid] = a.rec_co[gid];
+      s_rgbz[tid] = a.rec_rgbz[gid];
+    }
+    __syncthreads();
+    if (!__any(!done)) continue;
+    const int cnt = min(kTileThreads, end - base);
+    for (int j = 0; j < cnt; ++j) {
+      if (!done) {
+        const float4 g = s_uvab[j];
+        const float2 co = s_co[j];
+        const PairEval pe = eval_pair(fpx - g.x, fpy - g.y, g.z, g.w, co.x, co.y, Rr.amin, Rr.amax);
+        if (pe.use) {
+          const float Tn = T * (1.f - pe.alpha);
+          if (Tn < Rr.tmin) {
+            done = true;
+          } else {
+            const float4 cz = s_rgbz[j];
+            const float w = pe.alpha * T;
+            C0 = fmaf(cz.x, w, C0);
+            C1 = fmaf(cz.y, w, C1);
+            C2 = fmaf(cz.z, w, C2);
+            D = fmaf(cz.w, w, D);
+            T = Tn;
+            last = base - start + j + 1;
+          }
+        }
+      }
+      if (!__any(!done)) break;
+    }
+  }
+  if (inside) {
+    const int64_t P = (int64_t)Rr.W * Rr.H;
+    const int64_t p = (int64_t)py * Rr.W + px;
+    a.color[p] = fmaf(T, Rr.bg0, C0);
+    a.color[P + p] = fmaf(T, Rr.bg1, C1);
+    a.color[2 * P + p] = fmaf(T, Rr.bg2, C2);
+    a.depth[p] = D;
+    a.alpha[p] = 1.f - T;
+    a.Tfin[p] = T;
+    a.last[p] = last;
+  }
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs a) {
+  __shared__ float4 s_uvab[kTileThreads];
+  __shared__ float2 s_co[kTileThreads];
+  __shared__ float4 s_rgbz[kTileThreads];
+  __shared__ uint32_t s_gid[kTileThreads];
+  __shared__ int s_max;
+
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tyi = tile / Rr.ntx, txi = tile - tyi * Rr.ntx;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int px = txi * Rr.tw + (tid & (Rr.tw - 1));
+  const int py = tyi * Rr.th + (tid >> Rr.tw_log2);
+  const bool inside = px < Rr.W && py < Rr.H;
+  const float fpx = (float)px, fpy = (float)py;
+  const int64_t P = (int64_t)Rr.W * Rr.H;
+  const int64_t p = (int64_t)py * Rr.W + px;
+
+  float T = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gd = 0.f, ga = 0.f;
+  int last = 0;
+  if (inside) {
+    T = a.Tfin[p];
+    last = a.last[p];
+    g0 = a.gC[p];
+    g1 = a.gC[P + p];
+    g2 = a.gC[2 * P + p];
+    gd = a.gD[p];
+    ga = a.gA ? a.gA[p] : 0.f;
+  }
+  const float Tfin = T;
+  // suffix sums: background enters dC/dalpha through T_final * bg
+  float S0 = T * Rr.bg0, S1 = T * Rr.bg1, S2 = T * Rr.bg2, SD = 0.f;
+
+  if (tid == 0) s_max = 0;
+  __syncthreads();
+  if (last > 0) atomicMax(&s_max, last);
+  const int wmax = wave_max_int(last);
+  __syncthreads();
+  const int bmax = s_max;
+  const int2 rg = a.ranges[tile];
+  const int start = rg.x;
+
+  for (int bend = start + bmax; bend > start; bend -= kTileThreads) {
+    const int bstart = max(start, bend - kTileThreads);
+    __syncthreads();
+    const int i = bstart + tid;
+    if (i < bend) {
+      const uint32_t gid = a.ids[i];
+      s_gid[tid] = gid;
+      s_uvab[tid] = a.rec_uvab[gid];
+      s_co[tid] = a.rec_co[gid];
+      s_rgbz[tid] = a.rec_rgbz[gid];
+    }
+    __syncthreads();
+    const int jtop = min(bend, start + wmax) - 1;
+    for (int j = jtop; j >= bstart; --j) {
+      const int li = j - bstart;
+      const int pos = j - start;
+      float v[10];
+#pragma unroll
+      for (int f = 0; f < 10; ++f) v[f] = 0.f;
+      bool hit = false;
+      if (pos < last) {
+        const float4 g = s_uvab[li];
+        const float2 co = s_co[li];
+        const float dx = fpx - g.x, dy = fpy - g.y;
+        const PairEval pe = eval_pair(dx, dy, g.z, g.w, co.x, co.y, Rr.amin, Rr.amax);
+        if (pe.use) {
+          hit = true;
+          const float4 cz = s_rgbz[li];
+          const float inv = 1.f / (1.f - pe.alpha);
+          const float Tj = T * inv;
+          const float w = pe.alpha * Tj;
+          v[6] = w * g0;
+          v[7] = w * g1;
+          v[8] = w * g2;
+          v[9] = w * gd;
+          float dA = g0 * (cz.x * Tj - S0 * inv) + g1 * (cz.y * Tj - S1 * inv) + g2 * (cz.z * Tj - S2 * inv);
+          dA += gd * (cz.w * Tj - SD * inv);
+          dA += ga * Tfin * inv;
+          S0 = fmaf(cz.x, w, S0);
+          S1 = fmaf(cz.y, w, S1);
+          S2 = fmaf(cz.z, w, S2);
+          SD = fmaf(cz.w, w, SD);
+          T = Tj;
+          if (!pe.clamped) {
+            v[5] = dA * pe.e;                    // d alpha / d o = exp(-sigma)
+            const float gp = dA * pe.alpha * kLn2;  // dL/dp, alpha = o 2^p
+            const float gpx = gp * dx, gpy = gp * dy;
+            v[2] = gpx * dx;
+            v[3] = gpx * dy;
+            v[4] = gpy * dy;
+            v[0] = -(2.f * g.z * gpx + g.w * gpy);
+            v[1] = -(g.w * gpx + 2.f * co.x * gpy);
+          }
+        }
+      }
+      if (__any(hit)) {
+        float tot[10];
+#pragma unroll
+        for (int f = 0; f < 10; ++f)
+          tot[f] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(v[f])), 63));
+        float mine = 0.f;
+#pragma unroll
+        for (int f = 0; f < 10; ++f) mine = (lane == f) ? tot[f] : mine;
+        if (lane < 10) atomicAdd(&a.g2d[10 * (int64_t)s_gid[li] + lane], mine);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void launch_render_fwd(const Raster& R, const FwdArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_render_fwd, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
+}
+
+void launch_render_bwd(const Raster& R, const BwdArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
+}
+
+}  // namespace gsr

@@ -1,0 +1,301 @@
+"""ctypes binding of libgsr.so (the C ABI in include/gsr.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream; every step of the rendering path runs in the library's kernels. The
+library is loaded from this package directory; if it is missing, or no HIP
+device is present, calls raise instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsr.so")
+
+GSR_OK, GSR_EINVAL, GSR_ENOMEM, GSR_EHIP, GSR_EOVERFLOW = 0, -1, -2, -3, -4
+
+
+class GsrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libgsr error {code}: {msg}")
+        self.code = code
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("near_z", ctypes.c_float), ("bg", ctypes.c_float * 3)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("lowpass", ctypes.c_float), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
+                ("T_min", ctypes.c_float), ("guard", ctypes.c_float), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32)]
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("means", ctypes.c_void_p), ("scales", ctypes.c_void_p),
+                ("quats", ctypes.c_void_p), ("opacities", ctypes.c_void_p), ("colors", ctypes.c_void_p)]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("opacities", ctypes.c_void_p), ("colors", ctypes.c_void_p)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+# name -> (restype, argtypes)
+P = ctypes.c_void_p
+_SIGS = {
+    "gsr_ctx_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, P]),
+    "gsr_ctx_destroy": (ctypes.c_int, [P]),
+    "gsr_set_stream": (ctypes.c_int, [P, P]),
+    "gsr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "gsr_last_error": (ctypes.c_char_p, [P]),
+    "gsr_default_opts": (None, [ctypes.POINTER(Opts)]),
+    "gsr_render_fwd": (ctypes.c_int, [P, ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), ctypes.POINTER(Opts), P,
+                                      P, P, P, ctypes.POINTER(P)]),
+    "gsr_render_bwd": (ctypes.c_int, [P, P, P, P, P, ctypes.POINTER(Grads), P, P]),
+    "gsr_state_release": (ctypes.c_int, [P, P]),
+    "gsr_tile_lists": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_int64), P, P]),
+    "gsr_loss_l1": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P]),
+    "gsr_loss_track": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P, P]),
+    "gsr_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float]),
+}
+OPTIONAL_SIGS = {}
+
+
+def declared_symbols() -> list[str]:
+    return list(_SIGS) + list(OPTIONAL_SIGS)
+
+
+def load(path: str = LIB_PATH):
+    """Load libgsr.so (without touching the GPU) and bind its signatures."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise FileNotFoundError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                                    f"g.build()'` (hipcc, gfx950)")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in {**_SIGS, **OPTIONAL_SIGS}.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libgsr takes device tensors only")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f32(t, name, shape=None):
+    if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+@dataclass
+class RasterOpts:
+    lowpass: float = 0.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    guard: float = 1.3
+    tile_w: int = 16
+    tile_h: int = 16
+
+    def c(self) -> Opts:
+        return Opts(self.lowpass, self.alpha_min, self.alpha_max, self.T_min, self.guard, self.tile_w, self.tile_h)
+
+
+def make_camera(width, height, fx, fy, cx, cy, near_z=0.2, bg=(0.0, 0.0, 0.0)) -> Camera:
+    return Camera(int(width), int(height), float(fx), float(fy), float(cx), float(cy), float(near_z),
+                  (ctypes.c_float * 3)(*[float(b) for b in bg]))
+
+
+def camera_from(intr, bg=(0.0, 0.0, 0.0)) -> Camera:
+    return make_camera(intr.width, intr.height, intr.fx, intr.fy, intr.cx, intr.cy, intr.near_z, bg)
+
+
+class Context:
+    """One libgsr context per device; enqueues on torch's current stream."""
+
+    _per_device: dict[int, "Context"] = {}
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libgsr needs a HIP device; none is available")
+        self.lib = lib
+        self.device = device
+        h = P()
+        with torch.cuda.device(device):
+            stream = torch.cuda.current_stream(device).cuda_stream
+        rc = lib.gsr_ctx_create(ctypes.byref(h), device, P(stream))
+        if rc != GSR_OK:
+            raise GsrError(rc, lib.gsr_strerror(rc).decode())
+        self.h = h
+
+    @classmethod
+    def get(cls, device: int = 0) -> "Context":
+        if device not in cls._per_device:
+            cls._per_device[device] = Context(device)
+        return cls._per_device[device]
+
+    def check(self, rc):
+        if rc != GSR_OK:
+            msg = self.lib.gsr_last_error(self.h).decode()
+            raise GsrError(rc, msg)
+
+    def sync_stream(self):
+        self.check(self.lib.gsr_set_stream(self.h, P(torch.cuda.current_stream(self.device).cuda_stream)))
+
+
+class State:
+    """Handle of one forward's saved state; released when garbage-collected."""
+
+    def __init__(self, ctx: Context, h, keep):
+        self.ctx = ctx
+        self.h = h
+        self.keep = keep  # tensors the backward re-reads
+
+    def release(self):
+        if self.h is not None:
+            self.ctx.lib.gsr_state_release(self.ctx.h, self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def _gaussians(means, scales, quats, opacities, colors) -> Gaussians:
+    n = means.shape[0]
+    _f32(means, "means", (n, 3)); _f32(scales, "scales", (n, 3)); _f32(quats, "quats", (n, 4))
+    _f32(opacities, "opacities", (n,)); _f32(colors, "colors", (n, 3))
+    if n > 0 and quats.data_ptr() % 16:
+        raise ValueError("quats must be 16-byte aligned")
+    return Gaussians(n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opacities), _ptr(colors))
+
+
+def render_fwd(means, scales, quats, opacities, colors, pose7, camera: Camera, opts: RasterOpts | None = None,
+               ctx: Context | None = None):
+    """Forward render; returns (color [3,H,W], depth [H,W], alpha [H,W], State)."""
+    ctx = ctx or Context.get(means.device.index or 0)
+    ctx.sync_stream()
+    opts = opts or RasterOpts()
+    g = _gaussians(means, scales, quats, opacities, colors)
+    _f32(pose7, "pose7", (7,))
+    H, W = camera.height, camera.width
+    dev = means.device
+    color = torch.empty((3, H, W), device=dev, dtype=torch.float32)
+    depth = torch.empty((H, W), device=dev, dtype=torch.float32)
+    alpha = torch.empty((H, W), device=dev, dtype=torch.float32)
+    st = P()
+    oc = opts.c()
+    ctx.check(ctx.lib.gsr_render_fwd(ctx.h, ctypes.byref(g), ctypes.byref(camera), ctypes.byref(oc), _ptr(pose7),
+                                     _ptr(color), _ptr(depth), _ptr(alpha), ctypes.byref(st)))
+    state = State(ctx, st, (means, scales, quats, opacities, colors, pose7))
+    state.shape = (H, W)
+    return color, depth, alpha, state
+
+
+def render_bwd(state: State, dL_dcolor, dL_ddepth, dL_dalpha=None, want_params=True, want_pose=True):
+    """Backward; returns dict of gradients (means, scales, quats, opacities, colors, pose7, twist6)."""
+    ctx = state.ctx
+    ctx.sync_stream()
+    means, scales, quats, opacities, colors, pose7 = state.keep
+    n = means.shape[0]
+    dev = means.device
+    gC = _f32(dL_dcolor.contiguous(), "dL_dcolor")
+    gD = _f32(dL_ddepth.contiguous(), "dL_ddepth")
+    gA = None if dL_dalpha is None else _f32(dL_dalpha.contiguous(), "dL_dalpha")
+    out = {}
+    if want_params:
+        for k, shape in (("means", (n, 3)), ("scales", (n, 3)), ("quats", (n, 4)), ("opacities", (n,)),
+                         ("colors", (n, 3))):
+            out[k] = torch.empty(shape, device=dev, dtype=torch.float32)
+        gr = Grads(*[_ptr(out[k]) for k in ("means", "scales", "quats", "opacities", "colors")])
+    else:
+        gr = Grads()
+    if want_pose:
+        out["pose7"] = torch.empty(7, device=dev, dtype=torch.float32)
+        out["twist6"] = torch.empty(6, device=dev, dtype=torch.float32)
+    ctx.check(ctx.lib.gsr_render_bwd(ctx.h, state.h, _ptr(gC), _ptr(gD), _ptr(gA), ctypes.byref(gr),
+                                     _ptr(out.get("pose7")), _ptr(out.get("twist6"))))
+    return out
+
+
+def tile_lists(state: State, n_tiles: int):
+    """(K, ranges int32 [n_tiles,2], ids int32 [K]) of a forward (synchronises)."""
+    ctx = state.ctx
+    ctx.sync_stream()
+    K = ctypes.c_int64()
+    ctx.check(ctx.lib.gsr_tile_lists(ctx.h, state.h, ctypes.byref(K), None, None))
+    dev = state.keep[0].device
+    ranges = torch.empty((n_tiles, 2), device=dev, dtype=torch.int32)
+    ids = torch.empty((max(K.value, 1),), device=dev, dtype=torch.int32)
+    ctx.check(ctx.lib.gsr_tile_lists(ctx.h, state.h, ctypes.byref(K), _ptr(ranges), _ptr(ids)))
+    return K.value, ranges, ids[:K.value]
+
+
+def loss_l1(color, depth, tgt_color, tgt_depth, w_color=1.0, w_depth=1.0, ctx: Context | None = None):
+    """Mapping L1 loss; returns (loss [1] device, dL/dcolor, dL/ddepth)."""
+    ctx = ctx or Context.get(color.device.index or 0)
+    ctx.sync_stream()
+    P_ = depth.numel()
+    for t, nme in ((color, "color"), (depth, "depth"), (tgt_color, "tgt_color"), (tgt_depth, "tgt_depth")):
+        _f32(t, nme)
+    loss = torch.empty(1, device=color.device, dtype=torch.float32)
+    gC = torch.empty_like(color)
+    gD = torch.empty_like(depth)
+    ctx.check(ctx.lib.gsr_loss_l1(ctx.h, _ptr(color), _ptr(depth), _ptr(tgt_color), _ptr(tgt_depth), P_,
+                                  float(w_color), float(w_depth), _ptr(loss), _ptr(gC), _ptr(gD)))
+    return loss, gC, gD
+
+
+def loss_track(color, depth, alpha, tgt_color, tgt_depth, lambda_c=0.5, inlier_mult=50.0, ctx: Context | None = None):
+    """Tracking loss (Eq. 15); returns (loss [1], dL/dcolor, dL/ddepth, median [1])."""
+    ctx = ctx or Context.get(color.device.index or 0)
+    ctx.sync_stream()
+    P_ = depth.numel()
+    for t, nme in ((color, "color"), (depth, "depth"), (alpha, "alpha"), (tgt_color, "tgt_color"),
+                   (tgt_depth, "tgt_depth")):
+        _f32(t, nme)
+    loss = torch.empty(1, device=color.device, dtype=torch.float32)
+    med = torch.empty(1, device=color.device, dtype=torch.float32)
+    gC = torch.empty_like(color)
+    gD = torch.empty_like(depth)
+    ctx.check(ctx.lib.gsr_loss_track(ctx.h, _ptr(color), _ptr(depth), _ptr(alpha), _ptr(tgt_color), _ptr(tgt_depth),
+                                     P_, float(lambda_c), float(inlier_mult), _ptr(loss), _ptr(gC), _ptr(gD),
+                                     _ptr(med)))
+    return loss, gC, gD, med
+
+
+def adam_step(param, exp_avg, exp_avg_sq, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+              ctx: Context | None = None):
+    ctx = ctx or Context.get(param.device.index or 0)
+    ctx.sync_stream()
+    for t, nme in ((param, "param"), (exp_avg, "exp_avg"), (exp_avg_sq, "exp_avg_sq"), (grad, "grad")):
+        _f32(t, nme)
+    ctx.check(ctx.lib.gsr_adam(ctx.h, _ptr(param), _ptr(exp_avg), _ptr(exp_avg_sq), _ptr(grad), param.numel(),
+                               int(step), float(lr), float(beta1), float(beta2), float(eps)))
