@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the rasterization hot path on one MI355X.
+
+Workload (default): one mapping iteration of a 1200 x 680 view over a sub-map of
+500,000 Gaussians seeded from a procedural room (synthetic stand-in for the
+paper's Replica scans): project + EWA covariance, tile binning and (tile,
+depth) radix sort, forward compositing of colour / depth / alpha, L1 colour +
+L1 depth loss, the hand-written backward to every Gaussian parameter, and Adam
+on all 14 N parameters. `value` is iterations per second with all inputs
+resident in HBM. Prints ONE JSON line (rank 0) with a roofline entry for the
+dominant kernel (stage times from HIP events inside the timed region) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd render it/s (1200x680, 500K Gaussians); tracking ms/frame vs plain"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (256 CU x 2.4 GHz, packed FMA)
+
+# Algorithmic FP32 operations per (pixel, Gaussian) pair; FMA = 2.
+FLOPS_EVAL = 15      # offset, quadratic form, exp2, opacity, clamp and skip tests
+FLOPS_COMP_FWD = 12  # transmittance update, stop test, colour + depth accumulation
+FLOPS_COMP_BWD = 48  # T recovery, dC/dalpha, dD/dalpha (Eq. 8), dA/dalpha, suffix sums, 10 partials
+
+
+def stage_work(stage: str, st: dict, n: int, P: int, radix_passes: int) -> tuple[str, float]:
+    """(bound, algorithmic work per launch) of a stage: bytes for memory-bound
+    stages, FP32 operations for the compositing kernels."""
+    K = st["K"]
+    if stage == "render_fwd":
+        return "alu", FLOPS_EVAL * st["pairs_fwd"] + FLOPS_COMP_FWD * st["pairs_composited"]
+    if stage == "render_bwd":
+        return "alu", FLOPS_EVAL * st["pairs_bwd"] + FLOPS_COMP_BWD * st["pairs_composited"]
+    if stage == "radix_sort":
+        # per pass: keys read by the histogram (8 B) + key/value read and written by the scatter (24 B)
+        return "hbm", radix_passes * 32.0 * K
+    if stage == "project":
+        return "hbm", n * (56.0 + 64.0)
+    if stage == "project_bwd":
+        return "hbm", n * (56.0 + 40.0 + 56.0)
+    if stage == "duplicate":
+        return "hbm", n * 24.0 + K * 12.0
+    if stage == "adam":
+        return "hbm", 28.0 * 14 * n / 5.0  # per launch (5 launches per step)
+    if stage == "loss_l1":
+        return "hbm", P * 8 * 4.0 * 2
+    return "hbm", 0.0
+
+
+def source_hash(names) -> str:
+    h = hashlib.sha1()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_2312_10070_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+STAGE_SOURCES = {"render_fwd": ["k_raster.hip", "gsr_internal.h"], "render_bwd": ["k_raster.hip", "gsr_internal.h"],
+                 "radix_sort": ["k_sort.hip"], "project": ["k_project.hip", "gsr_internal.h"],
+                 "project_bwd": ["k_project.hip", "gsr_internal.h"]}
+
+
+def read_traffic(stage: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{stage}_{workload}_traffic.txt")
+    if not os.path.exists(path) or stage not in STAGE_SOURCES:
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha1") != source_hash(STAGE_SOURCES[stage]):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(inp: dict, rows_every: int, threads: int) -> dict:
+    """The FP64 oracle (box-pruned brute force) on every `rows_every`-th pixel row
+    of one fwd+bwd of the same workload, scaled to iterations per second."""
+    import oracle
+    cam = inp["camera"]
+    ocam = oracle.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near_z)
+    opts = oracle.Opts()
+    rows = np.arange(0, cam.height, rows_every)
+    pix = (rows[:, None] * cam.width + np.arange(cam.width)[None, :]).ravel()
+    g = inp["gaussians"]
+    pose = inp["pose7"].astype(np.float64)
+    t0 = time.perf_counter()
+    out = oracle.render(g, pose, ocam, opts, mode=1, pixels=pix, nthreads=threads)
+    P = cam.width * cam.height
+    gC = np.zeros((3, cam.height, cam.width))
+    gD = np.zeros((cam.height, cam.width))
+    yy, xx = pix // cam.width, pix % cam.width
+    gC[:, yy, xx] = np.sign(out["color"][:, yy, xx] - inp["target_color"][:, yy, xx]) / (3 * P)
+    gD[yy, xx] = np.sign(out["depth"][yy, xx] - inp["target_depth"][yy, xx]) / P
+    oracle.backward(g, pose, ocam, opts, gC, gD, mode=1, pixels=pix, nthreads=threads)
+    dt = time.perf_counter() - t0
+    frac = len(pix) / P
+    return {"value": round(frac / dt, 6), "unit": "it/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {rows_every}th pixel row ({len(pix)} of {P} pixels) of one fwd+bwd, FP64 "
+                      f"box-pruned brute force, {dt:.1f} s, scaled by the pixel fraction"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--gaussians", type=int, default=500_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows-every", type=int, default=68)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2312_10070_amd import gsr, synth
+
+    t_gen = time.perf_counter()
+    inp = synth.mapping_inputs(args.seed, args.gaussians)
+    t_gen = time.perf_counter() - t_gen
+    cam = inp["camera"]
+    camera = gsr.camera_from(cam)
+    dev = torch.device("cuda:0")
+    params = {k: torch.from_numpy(v).to(dev) for k, v in inp["gaussians"].items()}
+    pose = torch.from_numpy(inp["pose7"]).to(dev)
+    tgt_c = torch.from_numpy(inp["target_color"]).to(dev)
+    tgt_d = torch.from_numpy(inp["target_depth"]).to(dev)
+    lrs = {"means": 1e-4, "scales": 5e-5, "quats": 1e-3, "opacities": 1e-3, "colors": 2.5e-3}
+    adam_m = {k: torch.zeros_like(v) for k, v in params.items()}
+    adam_v = {k: torch.zeros_like(v) for k, v in params.items()}
+    opts = gsr.RasterOpts()
+    step_no = [0]
+
+    def step():
+        color, depth, alpha, st = gsr.render_fwd(params["means"], params["scales"], params["quats"],
+                                                 params["opacities"], params["colors"], pose, camera, opts)
+        loss, gC, gD = gsr.loss_l1(color, depth, tgt_c, tgt_d)
+        grads = gsr.render_bwd(st, gC, gD, None, want_params=True, want_pose=False)
+        step_no[0] += 1
+        for k in params:
+            gsr.adam_step(params[k], adam_m[k], adam_v[k], grads[k], step_no[0], lrs[k])
+        st.release()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    gsr.profile_read()  # discard warm-up records
+    gsr.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        loss = step()
+    e1.record()
+    torch.cuda.synchronize()
+    gsr.profile_enable(False)
+    ms_total = e0.elapsed_time(e1)
+    stages = gsr.profile_read()
+    ms_per_step = ms_total / args.steps
+    value = 1000.0 / ms_per_step
+
+    # work counters of the current parameters (outside the timed region)
+    color, depth, alpha, st = gsr.render_fwd(params["means"], params["scales"], params["quats"],
+                                             params["opacities"], params["colors"], pose, camera, opts)
+    stats = gsr.state_stats(st)
+    st.release()
+    n = args.gaussians
+    P = cam.width * cam.height
+    tile_bits = int(np.ceil(np.log2(max(stats["tiles"], 2))))
+    radix_passes = (32 + tile_bits + 7) // 8
+    dom = max((s for s in stages if s not in ("fill",)), key=lambda s: stages[s][0])
+    bound, work = stage_work(dom, stats, n, P, radix_passes)
+    avg_ms = stages[dom][0] / stages[dom][1]
+    if bound == "alu":
+        achieved = work / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4)}
+    else:
+        achieved = work / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    roof["traffic"] = read_traffic(dom, "H")
+    roof["kernel"] = dom
+    roof["avg_ms"] = round(avg_ms, 4)
+
+    if args.calib_copy_mib > 0:
+        nbytes = args.calib_copy_mib << 20
+        a = torch.empty(nbytes // 4, device=dev, dtype=torch.float32).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(os.cpu_count() or 1, 16)
+        cpu = cpu_baseline(inp, args.cpu_rows_every, threads)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mapping iteration (fwd + L1 loss + bwd + Adam on all params), 1200x680, "
+                               "500K Gaussians seeded from a procedural room",
+                   "width": cam.width, "height": cam.height, "gaussians": n, "tile": "16x16", "seed": args.seed},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(stages.items())},
+        "work": stats,
+        "loss": float(loss.item()),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -150,6 +150,25 @@ int gsr_loss_track(gsr_ctx *ctx, const float *color, const float *depth, const f
 int gsr_adam(gsr_ctx *ctx, float *param, float *exp_avg, float *exp_avg_sq, const float *grad, int64_t n,
              int64_t step, float lr, float beta1, float beta2, float eps);
 
+/* Measurement ------------------------------------------------------------ */
+
+/* Stage timing for benchmarks: while enabled, every stage a call enqueues
+ * (project, scan, duplicate, radix_sort, tile_ranges, render_fwd, fill,
+ * render_bwd, project_bwd, loss_l1, loss_track, adam, ...) is bracketed by a
+ * pair of HIP events on the context's stream. */
+int gsr_profile_enable(gsr_ctx *ctx, int on);
+/* Synchronises, then reports per stage name (NUL-terminated, 32 bytes each in
+ * `names`) the summed milliseconds and the number of launches since the last
+ * read, and clears the record. *n_stages receives the number of names, which
+ * may exceed max_stages (only the first max_stages are written). */
+int gsr_profile_read(gsr_ctx *ctx, int max_stages, char *names, double *total_ms, int64_t *counts, int *n_stages);
+/* Work counters of a forward (synchronises; re-runs the compositing pass in
+ * a counting mode that writes no image): out[0] K = (tile, Gaussian)
+ * overlaps, out[1] visible Gaussians, out[2] (pixel, Gaussian) pairs the
+ * forward evaluates, out[3] pairs it composites, out[4] pairs the backward
+ * evaluates (sum over pixels of the last composited position), out[5] tiles. */
+int gsr_state_stats(gsr_ctx *ctx, gsr_state *state, int64_t out[6]);
+
 #ifdef __cplusplus
 }
 #endif

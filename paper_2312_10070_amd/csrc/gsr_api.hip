@@ -52,6 +52,15 @@ struct gsr_ctx {
   std::vector<gsr_state*> pool;
   uint32_t* h_K = nullptr;  // pinned host word for the overlap count
   uint32_t* track_temp = nullptr;
+  unsigned long long* d_stats = nullptr;
+  // stage timing (gsr_profile_*): an event pair around each stage launch
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  bool prof = false;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> spare;
 };
 
 namespace {
@@ -205,6 +214,37 @@ int make_raster(gsr_ctx* c, const gsr_camera* cam, const gsr_opts* o, gsr::Raste
   return GSR_OK;
 }
 
+hipEvent_t take_event(gsr_ctx* c) {
+  if (!c->spare.empty()) {
+    hipEvent_t e = c->spare.back();
+    c->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Records an event pair around one stage when profiling is on.
+struct Stage {
+  gsr_ctx* c;
+  const char* name;
+  hipEvent_t a = nullptr;
+  Stage(gsr_ctx* ctx, const char* nm) : c(ctx), name(nm) {
+    if (c->prof && (a = take_event(c))) (void)hipEventRecord(a, c->stream);
+  }
+  ~Stage() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->recs.push_back({name, a, b});
+  }
+};
+
 gsr_state* acquire_state(gsr_ctx* c) {
   for (gsr_state* s : c->pool)
     if (!s->in_use) {
@@ -261,7 +301,8 @@ int gsr_ctx_create(gsr_ctx** out, int device, void* hip_stream) {
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   if (hipHostMalloc((void**)&c->h_K, 64, hipHostMallocDefault) != hipSuccess ||
-      hipMalloc((void**)&c->track_temp, sizeof(uint32_t) * gsr::track_temp_words()) != hipSuccess) {
+      hipMalloc((void**)&c->track_temp, sizeof(uint32_t) * gsr::track_temp_words()) != hipSuccess ||
+      hipMalloc((void**)&c->d_stats, 64) != hipSuccess) {
     (void)hipGetLastError();
     delete c;
     return GSR_ENOMEM;
@@ -281,6 +322,12 @@ int gsr_ctx_destroy(gsr_ctx* c) {
   }
   if (c->h_K) (void)hipHostFree(c->h_K);
   if (c->track_temp) (void)hipFree(c->track_temp);
+  if (c->d_stats) (void)hipFree(c->d_stats);
+  for (auto& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
   delete c;
   return GSR_OK;
 }
@@ -323,8 +370,14 @@ int gsr_render_fwd(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, co
 
   gsr::ProjectArgs pa{g->n, g->means, g->scales, g->quats, g->opacities, g->colors, pose7,
                       s->rec_uvab, s->rec_co, s->rec_rgbz, s->rect, s->counts};
-  gsr::launch_project(R, pa, st);
-  gsr::launch_exclusive_scan(s->counts, s->offsets, g->n, s->d_K, s->scan_temp, st);
+  {
+    Stage t(c, "project");
+    gsr::launch_project(R, pa, st);
+  }
+  {
+    Stage t(c, "scan");
+    gsr::launch_exclusive_scan(s->counts, s->offsets, g->n, s->d_K, s->scan_temp, st);
+  }
   GSR_HIP(c, hipMemcpyAsync(c->h_K, s->d_K, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   GSR_HIP(c, hipStreamSynchronize(st));
   const int64_t K = (int64_t)*c->h_K;
@@ -336,12 +389,24 @@ int gsr_render_fwd(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, co
   }
   gsr::BinArgs ba{g->n, s->rec_rgbz, s->rect, s->counts, s->offsets, s->d_K, K, 0u,
                   s->keys[0], s->vals[0], s->d_overflow};
-  gsr::launch_duplicate(R, ba, st);
-  s->sorted = gsr::launch_radix_sort(s->keys, s->vals, s->d_K, K, 32 + bits_for(R.n_tiles), s->sort_temp, st);
-  gsr::launch_tile_ranges(s->keys[s->sorted], s->d_K, K, s->ranges, R.n_tiles, st);
+  {
+    Stage t(c, "duplicate");
+    gsr::launch_duplicate(R, ba, st);
+  }
+  {
+    Stage t(c, "radix_sort");
+    s->sorted = gsr::launch_radix_sort(s->keys, s->vals, s->d_K, K, 32 + bits_for(R.n_tiles), s->sort_temp, st);
+  }
+  {
+    Stage t(c, "tile_ranges");
+    gsr::launch_tile_ranges(s->keys[s->sorted], s->d_K, K, s->ranges, R.n_tiles, st);
+  }
   gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_co, s->rec_rgbz,
-                  color, depth, alpha, s->Tfin, s->last};
-  gsr::launch_render_fwd(R, fa, st);
+                  color, depth, alpha, s->Tfin, s->last, nullptr};
+  {
+    Stage t(c, "render_fwd");
+    gsr::launch_render_fwd(R, fa, st);
+  }
   rc = check_launch(c, "gsr_render_fwd kernels");
   if (rc) {
     s->in_use = false;
@@ -358,12 +423,18 @@ int gsr_render_bwd(gsr_ctx* c, gsr_state* s, const float* dL_dcolor, const float
   GSR_HIP(c, hipSetDevice(c->device));
   hipStream_t st = c->stream;
   const gsr::Raster& R = s->R;
-  gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n, st);
   const bool want_pose = dL_dpose7 || dL_dtwist6;
-  if (want_pose) gsr::launch_fill_f32(s->pose_acc, 0.f, 12, st);
+  {
+    Stage t(c, "fill");
+    gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n, st);
+    if (want_pose) gsr::launch_fill_f32(s->pose_acc, 0.f, 12, st);
+  }
   gsr::BwdArgs ba{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_co, s->rec_rgbz, s->Tfin, s->last,
                   dL_dcolor, dL_ddepth, dL_dalpha, s->g2d};
-  gsr::launch_render_bwd(R, ba, st);
+  {
+    Stage t(c, "render_bwd");
+    gsr::launch_render_bwd(R, ba, st);
+  }
   gsr_grads none{};
   const gsr_grads& G = grads ? *grads : none;
   if (G.quats && (reinterpret_cast<uintptr_t>(G.quats) & 15u) != 0)
@@ -371,8 +442,11 @@ int gsr_render_bwd(gsr_ctx* c, gsr_state* s, const float* dL_dcolor, const float
   gsr::ProjectBwdArgs pb{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
                          s->counts, s->g2d, G.means, G.scales, G.quats, G.opacities, G.colors,
                          want_pose ? s->pose_acc : nullptr};
-  gsr::launch_project_bwd(R, pb, st);
-  if (want_pose) gsr::launch_pose_finalize(s->pose7, s->pose_acc, dL_dpose7, dL_dtwist6, st);
+  {
+    Stage t(c, "project_bwd");
+    gsr::launch_project_bwd(R, pb, st);
+    if (want_pose) gsr::launch_pose_finalize(s->pose7, s->pose_acc, dL_dpose7, dL_dtwist6, st);
+  }
   return check_launch(c, "gsr_render_bwd kernels");
 }
 
@@ -400,6 +474,7 @@ int gsr_loss_l1(gsr_ctx* c, const float* color, const float* depth, const float*
   if (P < 0 || !loss || (P > 0 && (!color || !depth || !tgt_color || !tgt_depth || !dL_dcolor || !dL_ddepth)))
     return fail(c, GSR_EINVAL, "bad loss arguments");
   GSR_HIP(c, hipSetDevice(c->device));
+  Stage t(c, "loss_l1");
   gsr::launch_loss_l1(color, depth, tgt_color, tgt_depth, P, w_color, w_depth, loss, dL_dcolor, dL_ddepth, c->stream);
   return check_launch(c, "gsr_loss_l1");
 }
@@ -412,6 +487,7 @@ int gsr_loss_track(gsr_ctx* c, const float* color, const float* depth, const flo
       (P > 0 && (!color || !depth || !alpha || !tgt_color || !tgt_depth || !dL_dcolor || !dL_ddepth)))
     return fail(c, GSR_EINVAL, "bad loss arguments");
   GSR_HIP(c, hipSetDevice(c->device));
+  Stage t(c, "loss_track");
   gsr::launch_loss_track(color, depth, alpha, tgt_color, tgt_depth, P, lambda_c, inlier_mult, loss, dL_dcolor,
                          dL_ddepth, median, c->track_temp, c->stream);
   return check_launch(c, "gsr_loss_track");
@@ -424,8 +500,73 @@ int gsr_adam(gsr_ctx* c, float* param, float* m, float* v, const float* grad, in
   GSR_HIP(c, hipSetDevice(c->device));
   const float bc1 = (float)(1.0 - std::pow((double)b1, (double)step));
   const float bc2 = (float)(1.0 - std::pow((double)b2, (double)step));
+  Stage t(c, "adam");
   gsr::launch_adam(param, m, v, grad, n, lr, b1, b2, eps, bc1, bc2, c->stream);
   return check_launch(c, "gsr_adam");
+}
+
+int gsr_profile_enable(gsr_ctx* c, int on) {
+  if (!c) return GSR_EINVAL;
+  c->prof = on != 0;
+  return GSR_OK;
+}
+
+int gsr_profile_read(gsr_ctx* c, int max_stages, char* names, double* total_ms, int64_t* counts, int* n_stages) {
+  if (!c || !n_stages || (max_stages > 0 && (!names || !total_ms || !counts)))
+    return fail(c, GSR_EINVAL, "bad profile arguments");
+  GSR_HIP(c, hipSetDevice(c->device));
+  GSR_HIP(c, hipStreamSynchronize(c->stream));
+  std::vector<std::string> nm;
+  std::vector<double> ms;
+  std::vector<int64_t> cnt;
+  for (auto& r : c->recs) {
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, r.a, r.b);
+    size_t i = 0;
+    while (i < nm.size() && nm[i] != r.name) ++i;
+    if (i == nm.size()) {
+      nm.push_back(r.name);
+      ms.push_back(0.0);
+      cnt.push_back(0);
+    }
+    ms[i] += t;
+    cnt[i] += 1;
+    c->spare.push_back(r.a);
+    c->spare.push_back(r.b);
+  }
+  c->recs.clear();
+  *n_stages = (int)nm.size();
+  for (int i = 0; i < (int)nm.size() && i < max_stages; ++i) {
+    std::memset(names + 32 * i, 0, 32);
+    std::strncpy(names + 32 * i, nm[i].c_str(), 31);
+    total_ms[i] = ms[i];
+    counts[i] = cnt[i];
+  }
+  return GSR_OK;
+}
+
+int gsr_state_stats(gsr_ctx* c, gsr_state* s, int64_t out[6]) {
+  if (!c || !s || !s->in_use || s->ctx != c || !out) return fail(c, GSR_EINVAL, "invalid state");
+  GSR_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  GSR_HIP(c, hipMemsetAsync(c->d_stats, 0, 64, st));
+  gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_co, s->rec_rgbz,
+                  nullptr, nullptr, nullptr, nullptr, nullptr, c->d_stats};
+  gsr::launch_render_fwd(s->R, fa, st);
+  unsigned long long h[3] = {0, 0, 0};
+  GSR_HIP(c, hipMemcpyAsync(h, c->d_stats, sizeof(h), hipMemcpyDeviceToHost, st));
+  std::vector<uint32_t> counts((size_t)std::max<int64_t>(s->n, 1));
+  if (s->n > 0) GSR_HIP(c, hipMemcpyAsync(counts.data(), s->counts, 4 * s->n, hipMemcpyDeviceToHost, st));
+  GSR_HIP(c, hipStreamSynchronize(st));
+  int64_t vis = 0;
+  for (int64_t i = 0; i < s->n; ++i) vis += counts[i] > 0;
+  out[0] = s->K;
+  out[1] = vis;
+  out[2] = (int64_t)h[0];
+  out[3] = (int64_t)h[1];
+  out[4] = (int64_t)h[2];
+  out[5] = s->R.n_tiles;
+  return check_launch(c, "gsr_state_stats");
 }
 
 }  // extern "C"

@@ -173,6 +173,7 @@ struct FwdArgs {
   const float4* rec_rgbz;
   float *color, *depth, *alpha, *Tfin;
   int* last;
+  unsigned long long* stats;  // non-NULL: count work only, write no outputs
 };
 void launch_render_fwd(const Raster& R, const FwdArgs& a, hipStream_t s);
 

@@ -20,6 +20,9 @@ namespace gsr {
 
 namespace {
 
+// STATS = true: count evaluated and composited pairs instead of writing
+// outputs (work counters for the benchmark's roofline; same control flow).
+template <bool STATS>
 __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs a) {
   __shared__ float4 s_uvab[kTileThreads];
   __shared__ float2 s_co[kTileThreads];
@@ -38,6 +41,7 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
   bool done = !inside;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   int last = 0;
+  uint32_t n_eval = 0, n_comp = 0;
 
   for (int base = start; base < end; base += kTileThreads) {
     if (__syncthreads_count(!done) == 0) break;
@@ -56,6 +60,7 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
         const float4 g = s_uvab[j];
         const float2 co = s_co[j];
         const PairEval pe = eval_pair(fpx - g.x, fpy - g.y, g.z, g.w, co.x, co.y, Rr.amin, Rr.amax);
+        if (STATS) ++n_eval;
         if (pe.use) {
           const float Tn = T * (1.f - pe.alpha);
           if (Tn < Rr.tmin) {
@@ -69,11 +74,27 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
             D = fmaf(cz.w, w, D);
             T = Tn;
             last = base - start + j + 1;
+            if (STATS) ++n_comp;
           }
         }
       }
       if (!__any(!done)) break;
     }
+  }
+  if (STATS) {
+    // counters: [0] evaluated pairs, [1] composited pairs, [2] backward pairs (sum of last)
+    unsigned long long e = n_eval, c = n_comp, b = (unsigned long long)last;
+    for (int o = 32; o > 0; o >>= 1) {
+      e += __shfl_xor(e, o, 64);
+      c += __shfl_xor(c, o, 64);
+      b += __shfl_xor(b, o, 64);
+    }
+    if ((tid & 63) == 0) {
+      atomicAdd(&a.stats[0], e);
+      atomicAdd(&a.stats[1], c);
+      atomicAdd(&a.stats[2], b);
+    }
+    return;
   }
   if (inside) {
     const int64_t P = (int64_t)Rr.W * Rr.H;
@@ -201,7 +222,10 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
 }  // namespace
 
 void launch_render_fwd(const Raster& R, const FwdArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_render_fwd, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
+  if (a.stats)
+    hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
+  else
+    hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
 }
 
 void launch_render_bwd(const Raster& R, const BwdArgs& a, hipStream_t s) {

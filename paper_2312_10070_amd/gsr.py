@@ -69,6 +69,9 @@ _SIGS = {
     "gsr_loss_track": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P, P]),
     "gsr_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float]),
+    "gsr_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
+    "gsr_profile_read": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_char_p, P, P, ctypes.POINTER(ctypes.c_int)]),
+    "gsr_state_stats": (ctypes.c_int, [P, P, P]),
 }
 OPTIONAL_SIGS = {}
 
@@ -299,3 +302,37 @@ def adam_step(param, exp_avg, exp_avg_sq, grad, step, lr, beta1=0.9, beta2=0.999
         _f32(t, nme)
     ctx.check(ctx.lib.gsr_adam(ctx.h, _ptr(param), _ptr(exp_avg), _ptr(exp_avg_sq), _ptr(grad), param.numel(),
                                int(step), float(lr), float(beta1), float(beta2), float(eps)))
+
+
+def profile_enable(on: bool = True, ctx: Context | None = None):
+    ctx = ctx or Context.get(torch.cuda.current_device())
+    ctx.check(ctx.lib.gsr_profile_enable(ctx.h, 1 if on else 0))
+
+
+def profile_read(ctx: Context | None = None) -> dict:
+    """{stage: (total_ms, launches)} since the last read (synchronises)."""
+    import numpy as np
+    ctx = ctx or Context.get(torch.cuda.current_device())
+    ctx.sync_stream()
+    maxn = 64
+    names = ctypes.create_string_buffer(32 * maxn)
+    ms = np.zeros(maxn, np.float64)
+    cnt = np.zeros(maxn, np.int64)
+    n = ctypes.c_int()
+    ctx.check(ctx.lib.gsr_profile_read(ctx.h, maxn, names, ms.ctypes.data_as(P), cnt.ctypes.data_as(P),
+                                       ctypes.byref(n)))
+    out = {}
+    for i in range(min(n.value, maxn)):
+        nm = names.raw[32 * i:32 * (i + 1)].split(b"\0")[0].decode()
+        out[nm] = (float(ms[i]), int(cnt[i]))
+    return out
+
+
+def state_stats(state: State) -> dict:
+    import numpy as np
+    ctx = state.ctx
+    ctx.sync_stream()
+    out = np.zeros(6, np.int64)
+    ctx.check(ctx.lib.gsr_state_stats(ctx.h, state.h, out.ctypes.data_as(P)))
+    return dict(K=int(out[0]), visible=int(out[1]), pairs_fwd=int(out[2]), pairs_composited=int(out[3]),
+                pairs_bwd=int(out[4]), tiles=int(out[5]))

@@ -281,6 +281,21 @@ def random_view(rng) -> np.ndarray:
     return camera_pose(center, rng.uniform(-np.pi, np.pi), np.deg2rad(rng.uniform(-15, 15)))
 
 
+def open_view(room: Room, rng, cam: Intrinsics, tries: int = 12) -> np.ndarray:
+    """A random view that looks across the room: of `tries` random views, the one
+    with the largest median depth on a coarse ray-cast (an indoor scan views
+    the room, not a wall at arm's length)."""
+    small = Intrinsics(cam.width // 16, cam.height // 16, cam.fx / 16, cam.fy / 16, cam.cx / 16, cam.cy / 16)
+    best, best_d = None, -1.0
+    for _ in range(tries):
+        v = random_view(rng)
+        d, _, _ = raycast(room, small, v)
+        med = float(np.median(d))
+        if med > best_d:
+            best, best_d = v, med
+    return best
+
+
 def _nn_distance(pts: np.ndarray) -> np.ndarray:
     from scipy.spatial import cKDTree
     tree = cKDTree(pts)
@@ -322,7 +337,7 @@ def mapping_inputs(seed: int = 0, n: int = 200_000, cam: Intrinsics = MAPPING_CA
     """C2 / headline: one view of the room, `n` Gaussians seeded from it, RGB-D target."""
     rng = np.random.default_rng(seed)
     room = make_room(seed)
-    pose = random_view(rng)
+    pose = open_view(room, rng, cam)
     g = seed_gaussians(room, cam, [pose], n, rng)
     color, depth = render_frame(room, cam, pose)
     return dict(gaussians=g, pose7=pose, camera=cam, target_color=color, target_depth=depth)
@@ -333,7 +348,7 @@ def tracking_inputs(seed: int = 0, n: int = 500_000, cam: Intrinsics = TRACKING_
     """C3: sub-map seeded from views near the ground-truth pose, GT pose, perturbed init."""
     rng = np.random.default_rng(seed)
     room = make_room(seed)
-    gt = random_view(rng)
+    gt = open_view(room, rng, cam)
     views = [gt] + [perturb_pose(gt, rng, rng.uniform(0, 0.3), rng.uniform(0, 10)) for _ in range(n_views - 1)]
     g = seed_gaussians(room, cam, views, n, rng)
     init = perturb_pose(gt, rng, trans_m, rot_deg)
