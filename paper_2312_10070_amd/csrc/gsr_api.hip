@@ -25,7 +25,7 @@ struct gsr_state {
   void* arenaB = nullptr;
   // arena A: per Gaussian / pixel / tile
   float4* rec_uvab = nullptr;
-  float2* rec_co = nullptr;
+  float4* rec_cob = nullptr;
   float4* rec_rgbz = nullptr;
   int4* rect = nullptr;
   uint32_t* counts = nullptr;
@@ -102,7 +102,7 @@ struct Carver {
 void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, size_t* bytes) {
   Carver c{base};
   s->rec_uvab = c.take<float4>(n);
-  s->rec_co = c.take<float2>(n);
+  s->rec_cob = c.take<float4>(n);
   s->rec_rgbz = c.take<float4>(n);
   s->rect = c.take<int4>(n);
   s->counts = c.take<uint32_t>(n);
@@ -176,6 +176,7 @@ int bits_for(int64_t v) {
 int make_raster(gsr_ctx* c, const gsr_camera* cam, const gsr_opts* o, gsr::Raster* R) {
   if (!cam || !o) return fail(c, GSR_EINVAL, "camera and opts are required");
   if (cam->width <= 0 || cam->height <= 0) return fail(c, GSR_EINVAL, "image size must be positive");
+  if (cam->width > 32768 || cam->height > 32768) return fail(c, GSR_EINVAL, "image sides are limited to 32768");
   const float vals[] = {cam->fx, cam->fy, cam->cx, cam->cy, cam->near_z, cam->bg[0], cam->bg[1], cam->bg[2]};
   for (float v : vals)
     if (!std::isfinite(v)) return fail(c, GSR_EINVAL, "camera intrinsics must be finite");
@@ -369,7 +370,7 @@ int gsr_render_fwd(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, co
   hipStream_t st = c->stream;
 
   gsr::ProjectArgs pa{g->n, g->means, g->scales, g->quats, g->opacities, g->colors, pose7,
-                      s->rec_uvab, s->rec_co, s->rec_rgbz, s->rect, s->counts};
+                      s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts};
   {
     Stage t(c, "project");
     gsr::launch_project(R, pa, st);
@@ -401,7 +402,7 @@ int gsr_render_fwd(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, co
     Stage t(c, "tile_ranges");
     gsr::launch_tile_ranges(s->keys[s->sorted], s->d_K, K, s->ranges, R.n_tiles, st);
   }
-  gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_co, s->rec_rgbz,
+  gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz,
                   color, depth, alpha, s->Tfin, s->last, nullptr};
   {
     Stage t(c, "render_fwd");
@@ -429,7 +430,7 @@ int gsr_render_bwd(gsr_ctx* c, gsr_state* s, const float* dL_dcolor, const float
     gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n, st);
     if (want_pose) gsr::launch_fill_f32(s->pose_acc, 0.f, 12, st);
   }
-  gsr::BwdArgs ba{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_co, s->rec_rgbz, s->Tfin, s->last,
+  gsr::BwdArgs ba{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
                   dL_dcolor, dL_ddepth, dL_dalpha, s->g2d};
   {
     Stage t(c, "render_bwd");
@@ -550,7 +551,7 @@ int gsr_state_stats(gsr_ctx* c, gsr_state* s, int64_t out[6]) {
   GSR_HIP(c, hipSetDevice(c->device));
   hipStream_t st = c->stream;
   GSR_HIP(c, hipMemsetAsync(c->d_stats, 0, 64, st));
-  gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_co, s->rec_rgbz,
+  gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz,
                   nullptr, nullptr, nullptr, nullptr, nullptr, c->d_stats};
   gsr::launch_render_fwd(s->R, fa, st);
   unsigned long long h[3] = {0, 0, 0};

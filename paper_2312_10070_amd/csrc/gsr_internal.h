@@ -31,7 +31,9 @@ struct Raster {
 // Per-Gaussian record written by the projection kernel. The quadratic form of
 // Eq. 4 is stored pre-scaled so that one pair costs three FMAs:
 //   p = pa dx^2 + pb dx dy + pc dy^2 = -sigma * log2(e),   alpha = o * 2^p.
-//   rec_uvab = (u, v, pa, pb), rec_co = (pc, o), rec_rgbz = (r, g, b, z_cam).
+//   rec_uvab = (u, v, pa, pb), rec_cob = (pc, o, bx, by), rec_rgbz = (r, g, b, z_cam)
+// where bx / by carry the pixel support box as bit patterns px0 | px1 << 16 and
+// py0 | py1 << 16 (a wave skips records whose box misses its pixels).
 struct PairEval {
   float alpha;   // min(alpha_max, o 2^p)
   float e;       // 2^p = exp(-sigma)
@@ -79,6 +81,54 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
   GSR_DPP_ADD(0x143);  // row_bcast:31
 #undef GSR_DPP_ADD
   return __int_as_float(x);
+}
+
+// Adds the wave-wide sums of ten per-lane values to dst[0..9] with one
+// 10-lane atomic. Field-splitting butterfly: at each of four exchange steps a
+// lane keeps half of its remaining fields and hands the other half to its
+// partner (v_permlane32_swap across the 32-lane halves, v_permlane16_swap
+// across rows, then DPP row_mirror / row_half_mirror inside rows), so the ten
+// sums cost ~27 VALU operations instead of ten full 64-lane reductions. After
+// the last quad reduction lane L holds field 8 b2 + 4 b3 + 2 b4 + b5 of its
+// lane bits b_i.
+__device__ __forceinline__ float perm_add32(float a, float b) {
+  auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+__device__ __forceinline__ float perm_add16(float a, float b) {
+  auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ void wave_add10(const float v[10], float* __restrict__ dst, int lane) {
+  // step 1 (lane bit 5): pairs of fields (2k, 2k+1)
+  const float r10 = perm_add32(v[0], v[1]);
+  const float r11 = perm_add32(v[2], v[3]);
+  const float r12 = perm_add32(v[4], v[5]);
+  const float r13 = perm_add32(v[6], v[7]);
+  const float r14 = perm_add32(v[8], v[9]);
+  // step 2 (lane bit 4)
+  const float r20 = perm_add16(r10, r11);
+  const float r21 = perm_add16(r12, r13);
+  const float r22 = perm_add16(r14, 0.f);
+  // step 3 (lane bit 3): partner = 15 - i inside the row
+  const bool b3 = (lane >> 3) & 1;
+  const float a0 = b3 ? r21 : r20, c0 = b3 ? r20 : r21;
+  const float r30 = a0 + dpp_f<0x140>(c0);                 // row_mirror
+  const float a1 = b3 ? 0.f : r22, c1 = b3 ? r22 : 0.f;
+  const float r31 = a1 + dpp_f<0x140>(c1);
+  // step 4 (lane bit 2): partner = 7 - i inside the half row
+  const bool b2 = (lane >> 2) & 1;
+  const float a2 = b2 ? r31 : r30, c2 = b2 ? r30 : r31;
+  float r4 = a2 + dpp_f<0x141>(c2);                        // row_half_mirror
+  // steps 5-6: sum the quad
+  r4 += dpp_f<0xb1>(r4);                                   // quad_perm [1,0,3,2]
+  r4 += dpp_f<0x4e>(r4);                                   // quad_perm [2,3,0,1]
+  const int f = 8 * ((lane >> 2) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
+  if ((lane & 3) == 0 && f < 10) atomicAdd(dst + f, r4);
 }
 
 __device__ __forceinline__ int wave_max_int(int v) {
@@ -129,7 +179,7 @@ struct ProjectArgs {
   const float *means, *scales, *quats, *opacities, *colors;
   const float* pose7;  // device
   float4* rec_uvab;
-  float2* rec_co;
+  float4* rec_cob;
   float4* rec_rgbz;
   int4* rect;          // tile rectangle (tx0, ty0, tx1, ty1)
   uint32_t* counts;    // tiles per Gaussian (0 = culled)
@@ -169,7 +219,7 @@ struct FwdArgs {
   const int2* ranges;
   const uint32_t* ids;
   const float4* rec_uvab;
-  const float2* rec_co;
+  const float4* rec_cob;
   const float4* rec_rgbz;
   float *color, *depth, *alpha, *Tfin;
   int* last;
@@ -181,7 +231,7 @@ struct BwdArgs {
   const int2* ranges;
   const uint32_t* ids;
   const float4* rec_uvab;
-  const float2* rec_co;
+  const float4* rec_cob;
   const float4* rec_rgbz;
   const float* Tfin;
   const int* last;

@@ -155,7 +155,8 @@ __global__ __launch_bounds__(256) void k_project(Raster Rr, ProjectArgs a) {
           count = (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1));
           const float s = -0.5f * kLog2e;
           a.rec_uvab[k] = make_float4(g.u, g.v, s * ca, -kLog2e * cb);
-          a.rec_co[k] = make_float2(s * cc, o);
+          a.rec_cob[k] = make_float4(s * cc, o, __uint_as_float((uint32_t)px0 | ((uint32_t)px1 << 16)),
+                                     __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16)));
           a.rec_rgbz[k] = make_float4(a.colors[3 * k], a.colors[3 * k + 1], a.colors[3 * k + 2], g.x[2]);
         }
       }

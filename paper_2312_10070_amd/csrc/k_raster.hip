@@ -1,40 +1,65 @@
 // Per-tile compositing. One 256-thread workgroup per tile, one pixel per lane.
 // Gaussian records of the tile's depth-sorted list are staged through LDS in
-// batches of 256 (one coalesced fetch per record per workgroup); each wave
-// walks the batch with the records broadcast from LDS.
+// batches of 256 (one coalesced fetch per record per workgroup). Each wave
+// then ballots, 64 records at a time, which records' support boxes overlap its
+// own pixel strip, and visits only those, in list order, with the record
+// broadcast from LDS. Skipping a record whose box misses the strip cannot
+// change the result: outside its box a Gaussian has alpha < alpha_min.
 //
 // Forward: front to back (Eq. 3 colour, Eq. 4 alpha, Eq. 6 depth). A lane
 // stops before the Gaussian that would take its transmittance below T_min; a
-// wave leaves the batch loop as soon as all its lanes have stopped, and the
+// wave leaves the batch as soon as all its lanes have stopped, and the
 // workgroup stops fetching batches once all four waves have.
 //
 // Backward: back to front from each pixel's last composited Gaussian. The
 // transmittance in front of Gaussian j is recomputed as T_j = T_{j+1} /
 // (1 - alpha_j) instead of being stored; suffix sums of c alpha T and z alpha T
-// give the second terms of dC/dalpha and Eq. 8. Per-Gaussian partials are
-// reduced across the wave with DPP and added to a [n, 10] gradient buffer with
-// one 10-lane atomic per (Gaussian, wave).
+// give the second terms of dC/dalpha and Eq. 8. The ten per-Gaussian partials
+// of a wave are summed with a field-splitting butterfly and added to the
+// [n, 10] gradient buffer with one 10-lane atomic per (Gaussian, wave).
 #include "gsr_internal.h"
 
 namespace gsr {
 
 namespace {
 
+struct Strip {
+  int x0, x1, y0, y1;  // inclusive pixel rectangle of a wave
+};
+
+__device__ __forceinline__ Strip wave_strip(const Raster& Rr, int txi, int tyi, int wave) {
+  const int rows = kWave >> Rr.tw_log2;  // pixel rows per wave
+  Strip s;
+  s.x0 = txi * Rr.tw;
+  s.x1 = s.x0 + Rr.tw - 1;
+  s.y0 = tyi * Rr.th + wave * rows;
+  s.y1 = s.y0 + rows - 1;
+  return s;
+}
+
+// Does the packed support box (bx = x0 | x1 << 16, by = y0 | y1 << 16) meet the strip?
+__device__ __forceinline__ bool box_meets(float fbx, float fby, const Strip& s) {
+  const uint32_t bx = __float_as_uint(fbx), by = __float_as_uint(fby);
+  const int x0 = (int)(bx & 0xffffu), x1 = (int)(bx >> 16), y0 = (int)(by & 0xffffu), y1 = (int)(by >> 16);
+  return x0 <= s.x1 && x1 >= s.x0 && y0 <= s.y1 && y1 >= s.y0;
+}
+
 // STATS = true: count evaluated and composited pairs instead of writing
 // outputs (work counters for the benchmark's roofline; same control flow).
 template <bool STATS>
 __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs a) {
   __shared__ float4 s_uvab[kTileThreads];
-  __shared__ float2 s_co[kTileThreads];
+  __shared__ float4 s_cob[kTileThreads];
   __shared__ float4 s_rgbz[kTileThreads];
 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tyi = tile / Rr.ntx, txi = tile - tyi * Rr.ntx;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int px = txi * Rr.tw + (tid & (Rr.tw - 1));
   const int py = tyi * Rr.th + (tid >> Rr.tw_log2);
   const bool inside = px < Rr.W && py < Rr.H;
   const float fpx = (float)px, fpy = (float)py;
+  const Strip strip = wave_strip(Rr, txi, tyi, tid >> 6);
 
   const int2 rg = a.ranges[tile];
   const int start = rg.x, end = rg.y;
@@ -49,49 +74,64 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
     if (i < end) {
       const uint32_t gid = a.ids[i];
       s_uvab[tid] = a.rec_uvab[gid];
-      s_co[tid] = a.rec_co[gid];
+      s_cob[tid] = a.rec_cob[gid];
       s_rgbz[tid] = a.rec_rgbz[gid];
     }
     __syncthreads();
     if (!__any(!done)) continue;
     const int cnt = min(kTileThreads, end - base);
-    for (int j = 0; j < cnt; ++j) {
-      if (!done) {
-        const float4 g = s_uvab[j];
-        const float2 co = s_co[j];
-        const PairEval pe = eval_pair(fpx - g.x, fpy - g.y, g.z, g.w, co.x, co.y, Rr.amin, Rr.amax);
-        if (STATS) ++n_eval;
-        if (pe.use) {
-          const float Tn = T * (1.f - pe.alpha);
-          if (Tn < Rr.tmin) {
-            done = true;
-          } else {
-            const float4 cz = s_rgbz[j];
-            const float w = pe.alpha * T;
-            C0 = fmaf(cz.x, w, C0);
-            C1 = fmaf(cz.y, w, C1);
-            C2 = fmaf(cz.z, w, C2);
-            D = fmaf(cz.w, w, D);
-            T = Tn;
-            last = base - start + j + 1;
-            if (STATS) ++n_comp;
+    bool wave_done = false;
+    for (int c = 0; c * kWave < cnt && !wave_done; ++c) {
+      const int r = c * kWave + lane;
+      bool meets = false;
+      if (r < cnt) {
+        const float4 cb = s_cob[r];
+        meets = box_meets(cb.z, cb.w, strip);
+      }
+      uint64_t m = __ballot(meets);
+      while (m) {
+        const int j = c * kWave + __builtin_ctzll(m);
+        m &= m - 1;
+        if (!done) {
+          const float4 g = s_uvab[j];
+          const float4 cb = s_cob[j];
+          const PairEval pe = eval_pair(fpx - g.x, fpy - g.y, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
+          if (STATS) ++n_eval;
+          if (pe.use) {
+            const float Tn = T * (1.f - pe.alpha);
+            if (Tn < Rr.tmin) {
+              done = true;
+            } else {
+              const float4 cz = s_rgbz[j];
+              const float w = pe.alpha * T;
+              C0 = fmaf(cz.x, w, C0);
+              C1 = fmaf(cz.y, w, C1);
+              C2 = fmaf(cz.z, w, C2);
+              D = fmaf(cz.w, w, D);
+              T = Tn;
+              last = base - start + j + 1;
+              if (STATS) ++n_comp;
+            }
           }
         }
+        if (!__any(!done)) {
+          wave_done = true;
+          break;
+        }
       }
-      if (!__any(!done)) break;
     }
   }
   if (STATS) {
     // counters: [0] evaluated pairs, [1] composited pairs, [2] backward pairs (sum of last)
-    unsigned long long e = n_eval, c = n_comp, b = (unsigned long long)last;
+    unsigned long long e = n_eval, cm = n_comp, b = (unsigned long long)last;
     for (int o = 32; o > 0; o >>= 1) {
       e += __shfl_xor(e, o, 64);
-      c += __shfl_xor(c, o, 64);
+      cm += __shfl_xor(cm, o, 64);
       b += __shfl_xor(b, o, 64);
     }
-    if ((tid & 63) == 0) {
+    if (lane == 0) {
       atomicAdd(&a.stats[0], e);
-      atomicAdd(&a.stats[1], c);
+      atomicAdd(&a.stats[1], cm);
       atomicAdd(&a.stats[2], b);
     }
     return;
@@ -111,7 +151,7 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
 
 __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs a) {
   __shared__ float4 s_uvab[kTileThreads];
-  __shared__ float2 s_co[kTileThreads];
+  __shared__ float4 s_cob[kTileThreads];
   __shared__ float4 s_rgbz[kTileThreads];
   __shared__ uint32_t s_gid[kTileThreads];
   __shared__ int s_max;
@@ -125,6 +165,7 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
   const float fpx = (float)px, fpy = (float)py;
   const int64_t P = (int64_t)Rr.W * Rr.H;
   const int64_t p = (int64_t)py * Rr.W + px;
+  const Strip strip = wave_strip(Rr, txi, tyi, tid >> 6);
 
   float T = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gd = 0.f, ga = 0.f;
   int last = 0;
@@ -138,7 +179,7 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
     ga = a.gA ? a.gA[p] : 0.f;
   }
   const float Tfin = T;
-  // suffix sums: background enters dC/dalpha through T_final * bg
+  // suffix sums: the background enters dC/dalpha through T_final * bg
   float S0 = T * Rr.bg0, S1 = T * Rr.bg1, S2 = T * Rr.bg2, SD = 0.f;
 
   if (tid == 0) s_max = 0;
@@ -147,8 +188,7 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
   const int wmax = wave_max_int(last);
   __syncthreads();
   const int bmax = s_max;
-  const int2 rg = a.ranges[tile];
-  const int start = rg.x;
+  const int start = a.ranges[tile].x;
 
   for (int bend = start + bmax; bend > start; bend -= kTileThreads) {
     const int bstart = max(start, bend - kTileThreads);
@@ -158,62 +198,64 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
       const uint32_t gid = a.ids[i];
       s_gid[tid] = gid;
       s_uvab[tid] = a.rec_uvab[gid];
-      s_co[tid] = a.rec_co[gid];
+      s_cob[tid] = a.rec_cob[gid];
       s_rgbz[tid] = a.rec_rgbz[gid];
     }
     __syncthreads();
-    const int jtop = min(bend, start + wmax) - 1;
-    for (int j = jtop; j >= bstart; --j) {
-      const int li = j - bstart;
-      const int pos = j - start;
-      float v[10];
+    const int cnt = min(bend, start + wmax) - bstart;  // records this wave may need
+    for (int c = (cnt - 1) >> 6; c >= 0; --c) {
+      const int r = c * kWave + lane;
+      bool meets = false;
+      if (r < cnt) {
+        const float4 cb = s_cob[r];
+        meets = box_meets(cb.z, cb.w, strip);
+      }
+      uint64_t m = __ballot(meets);
+      while (m) {
+        const int bit = 63 - __builtin_clzll(m);
+        m &= ~(1ull << bit);
+        const int li = c * kWave + bit;
+        const int pos = bstart + li - start;
+        float v[10];
 #pragma unroll
-      for (int f = 0; f < 10; ++f) v[f] = 0.f;
-      bool hit = false;
-      if (pos < last) {
-        const float4 g = s_uvab[li];
-        const float2 co = s_co[li];
-        const float dx = fpx - g.x, dy = fpy - g.y;
-        const PairEval pe = eval_pair(dx, dy, g.z, g.w, co.x, co.y, Rr.amin, Rr.amax);
-        if (pe.use) {
-          hit = true;
-          const float4 cz = s_rgbz[li];
-          const float inv = 1.f / (1.f - pe.alpha);
-          const float Tj = T * inv;
-          const float w = pe.alpha * Tj;
-          v[6] = w * g0;
-          v[7] = w * g1;
-          v[8] = w * g2;
-          v[9] = w * gd;
-          float dA = g0 * (cz.x * Tj - S0 * inv) + g1 * (cz.y * Tj - S1 * inv) + g2 * (cz.z * Tj - S2 * inv);
-          dA += gd * (cz.w * Tj - SD * inv);
-          dA += ga * Tfin * inv;
-          S0 = fmaf(cz.x, w, S0);
-          S1 = fmaf(cz.y, w, S1);
-          S2 = fmaf(cz.z, w, S2);
-          SD = fmaf(cz.w, w, SD);
-          T = Tj;
-          if (!pe.clamped) {
-            v[5] = dA * pe.e;                    // d alpha / d o = exp(-sigma)
-            const float gp = dA * pe.alpha * kLn2;  // dL/dp, alpha = o 2^p
-            const float gpx = gp * dx, gpy = gp * dy;
-            v[2] = gpx * dx;
-            v[3] = gpx * dy;
-            v[4] = gpy * dy;
-            v[0] = -(2.f * g.z * gpx + g.w * gpy);
-            v[1] = -(g.w * gpx + 2.f * co.x * gpy);
+        for (int f = 0; f < 10; ++f) v[f] = 0.f;
+        bool hit = false;
+        if (pos < last) {
+          const float4 g = s_uvab[li];
+          const float4 cb = s_cob[li];
+          const float dx = fpx - g.x, dy = fpy - g.y;
+          const PairEval pe = eval_pair(dx, dy, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
+          if (pe.use) {
+            hit = true;
+            const float4 cz = s_rgbz[li];
+            const float inv = 1.f / (1.f - pe.alpha);
+            const float Tj = T * inv;
+            const float w = pe.alpha * Tj;
+            v[6] = w * g0;
+            v[7] = w * g1;
+            v[8] = w * g2;
+            v[9] = w * gd;
+            float dA = g0 * (cz.x * Tj - S0 * inv) + g1 * (cz.y * Tj - S1 * inv) + g2 * (cz.z * Tj - S2 * inv);
+            dA += gd * (cz.w * Tj - SD * inv);
+            dA += ga * Tfin * inv;
+            S0 = fmaf(cz.x, w, S0);
+            S1 = fmaf(cz.y, w, S1);
+            S2 = fmaf(cz.z, w, S2);
+            SD = fmaf(cz.w, w, SD);
+            T = Tj;
+            if (!pe.clamped) {
+              v[5] = dA * pe.e;                       // d alpha / d o = exp(-sigma)
+              const float gp = dA * pe.alpha * kLn2;  // dL/dp with alpha = o 2^p
+              const float gpx = gp * dx, gpy = gp * dy;
+              v[2] = gpx * dx;
+              v[3] = gpx * dy;
+              v[4] = gpy * dy;
+              v[0] = -(2.f * g.z * gpx + g.w * gpy);
+              v[1] = -(g.w * gpx + 2.f * cb.x * gpy);
+            }
           }
         }
-      }
-      if (__any(hit)) {
-        float tot[10];
-#pragma unroll
-        for (int f = 0; f < 10; ++f)
-          tot[f] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(v[f])), 63));
-        float mine = 0.f;
-#pragma unroll
-        for (int f = 0; f < 10; ++f) mine = (lane == f) ? tot[f] : mine;
-        if (lane < 10) atomicAdd(&a.g2d[10 * (int64_t)s_gid[li] + lane], mine);
+        if (__any(hit)) wave_add10(v, a.g2d + 10 * (int64_t)s_gid[li], lane);
       }
     }
   }
