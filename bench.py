@@ -119,6 +119,41 @@ def cpu_baseline(inp: dict, rows_every: int, threads: int) -> dict:
                       f"box-pruned brute force, {dt:.1f} s, scaled by the pixel fraction"}
 
 
+def bench_tracking(seed: int, n: int, frames: int) -> dict:
+    """Config C3: 640x480, n Gaussians, target = the renderer's own output at the
+    ground-truth pose, init perturbed by 2 cm / 1 degree, 100 Adam iterations on
+    (q, t) captured as one hipGraph. ms/frame = wall time of one graph run."""
+    import torch
+    from paper_2312_10070_amd import gsr, synth, tracking
+    inp = synth.tracking_inputs(seed, n)
+    cam = gsr.camera_from(inp["camera"])
+    g = {k: torch.from_numpy(v).cuda() for k, v in inp["gaussians"].items()}
+    args = (g["means"], g["scales"], g["quats"], g["opacities"], g["colors"])
+    gt = torch.from_numpy(inp["gt_pose7"]).cuda()
+    color, depth, alpha, st = gsr.render_fwd(*args, gt, cam)
+    st.release()
+    init = torch.from_numpy(inp["init_pose7"]).cuda()
+    tg = gsr.TrackGraph(*args, cam, color.clone(), depth.clone(), n_iters=100,
+                        K_cap=tracking.overlap_capacity(*args, init, cam))
+    pose = init.clone()
+    tg.run(pose)  # warm-up (first launch uploads the graph)
+    times = []
+    for _ in range(frames):
+        pose = init.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tg.run(pose)
+        times.append((time.perf_counter() - t0) * 1e3)
+    e0 = synth.pose_error(inp["init_pose7"], inp["gt_pose7"])
+    e1 = synth.pose_error(pose.cpu().numpy(), inp["gt_pose7"])
+    tg.close()
+    ms = float(np.median(times))
+    return {"workload": "tracking frame, 640x480, %d Gaussians, 100 Adam iterations in one hipGraph" % n,
+            "ms_per_frame": round(ms, 3), "ms_per_iteration": round(ms / 100, 4), "frames": frames,
+            "init_error_cm_deg": [round(100 * e0[0], 3), round(e0[1], 3)],
+            "final_error_cm_deg": [round(100 * e1[0], 4), round(e1[1], 4)]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +163,8 @@ def main() -> int:
     ap.add_argument("--gaussians", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows-every", type=int, default=68)
+    ap.add_argument("--no-tracking", action="store_true")
+    ap.add_argument("--tracking-frames", type=int, default=5)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -217,6 +254,10 @@ def main() -> int:
             b.copy_(a)
         torch.cuda.synchronize()
 
+    track = None
+    if not args.no_tracking:
+        track = bench_tracking(args.seed, args.gaussians, args.tracking_frames)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, 16)
@@ -242,6 +283,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(stages.items())},
         "work": stats,
+        "tracking": track,
         "loss": float(loss.item()),
     }
     print(json.dumps(line), flush=True)

@@ -150,6 +150,49 @@ int gsr_loss_track(gsr_ctx *ctx, const float *color, const float *depth, const f
 int gsr_adam(gsr_ctx *ctx, float *param, float *exp_avg, float *exp_avg_sq, const float *grad, int64_t n,
              int64_t step, float lr, float beta1, float beta2, float eps);
 
+/* Tracking (Sec. 3.4) ------------------------------------------------------ */
+
+/* Constant-speed pose initialisation (Eq. 13) on the quaternion and the
+ * translation: t = 2 t1 - t0, q = normalise(2 q1 - q0) after flipping q0 into
+ * q1's hemisphere. All three are device pose7 buffers. */
+int gsr_pose_const_velocity(gsr_ctx *ctx, const float *pose_prev2, const float *pose_prev1, float *pose_out);
+
+/* One Adam step on a pose7 (quaternion step size lr_q, translation lr_t) with
+ * the step count kept on the device: state is a device float[20] buffer,
+ * zero before the first step (m[0..7), v[8..15), step count at [16]). */
+int gsr_pose_adam(gsr_ctx *ctx, float *pose7, float *state, const float *grad7, float lr_q, float lr_t, float beta1,
+                  float beta2, float eps);
+
+typedef struct gsr_track_graph gsr_track_graph; /* opaque: a captured tracking loop */
+
+typedef struct {
+  float lambda_c;     /* colour weight of Eq. 15 (depth weight 1 - lambda_c) */
+  float inlier_mult;  /* inlier threshold multiple of the median depth error (50) */
+  float lr_q, lr_t;   /* Adam step sizes of the quaternion and the translation */
+  float beta1, beta2, eps;
+  int32_t n_iters;    /* optimisation iterations per frame */
+} gsr_track_opts;
+
+/* Capture n_iters tracking iterations (Eq. 14): render the frozen Gaussians at
+ * the current pose, masked tracking loss (Eq. 15) against the observed frame,
+ * backward to the pose only, Adam on (q, t) -- as ONE hipGraph with fixed
+ * capacities (K_cap tile overlaps per iteration; every K-dependent kernel
+ * reads the actual K from device memory). The Gaussian pointers are captured
+ * (their contents may change between runs, their count may not); the observed
+ * colour [3,H,W] and depth [H,W] are copied into graph-owned buffers now and by
+ * gsr_track_graph_set_frame. */
+int gsr_track_graph_create(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cam, const gsr_opts *opts,
+                           const gsr_track_opts *topts, const float *obs_color, const float *obs_depth,
+                           int64_t K_cap, gsr_track_graph **out);
+int gsr_track_graph_set_frame(gsr_ctx *ctx, gsr_track_graph *tg, const float *obs_color, const float *obs_depth);
+/* Run one frame: pose7 (device, in/out) holds the initial pose and receives the
+ * optimised one; losses (device float[n_iters], may be NULL) receive the loss
+ * of every iteration. One graph launch; synchronises once to read the
+ * capacity flag and returns GSR_EOVERFLOW if an iteration had more than K_cap
+ * overlaps (the pose is then not valid: re-create with a larger K_cap). */
+int gsr_track_graph_run(gsr_ctx *ctx, gsr_track_graph *tg, float *pose7, float *losses);
+int gsr_track_graph_destroy(gsr_ctx *ctx, gsr_track_graph *tg);
+
 /* Measurement ------------------------------------------------------------ */
 
 /* Stage timing for benchmarks: while enabled, every stage a call enqueues
@@ -164,9 +207,11 @@ int gsr_profile_enable(gsr_ctx *ctx, int on);
 int gsr_profile_read(gsr_ctx *ctx, int max_stages, char *names, double *total_ms, int64_t *counts, int *n_stages);
 /* Work counters of a forward (synchronises; re-runs the compositing pass in
  * a counting mode that writes no image): out[0] K = (tile, Gaussian)
- * overlaps, out[1] visible Gaussians, out[2] (pixel, Gaussian) pairs the
- * forward evaluates, out[3] pairs it composites, out[4] pairs the backward
- * evaluates (sum over pixels of the last composited position), out[5] tiles. */
+ * overlaps, out[1] visible Gaussians, out[2] (pixel, Gaussian) pairs with the
+ * pixel inside the Gaussian's support box before the pixel stops (what the
+ * forward must evaluate), out[3] pairs composited, out[4] support-box pairs
+ * before each pixel's last composited Gaussian (what the backward must
+ * evaluate), out[5] tiles. */
 int gsr_state_stats(gsr_ctx *ctx, gsr_state *state, int64_t out[6]);
 
 #ifdef __cplusplus

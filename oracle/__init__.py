@@ -58,6 +58,7 @@ def _load():
     lib.orc_loss_l1.argtypes = [i64, P, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
     lib.orc_loss_track.argtypes = [i64, P, P, P, P, P, ctypes.c_double, ctypes.c_float, P, P, P, P, P]
     lib.orc_adam.argtypes = [i64, P, P, P, P, i64] + [ctypes.c_double] * 4
+    lib.orc_pose_const_velocity.argtypes = [P, P, P]
     if hasattr(lib, "orc_conv2d_fwd"):
         _bind_cnn(lib)
     _lib = lib
@@ -232,3 +233,11 @@ def adam(param, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     gd = _d(g)
     lib.orc_adam(param.size, _p(param), _p(m), _p(v), _p(gd), step, lr, b1, b2, eps)
+
+
+def pose_const_velocity(pose_prev2, pose_prev1) -> np.ndarray:
+    """Eq. 13 on pose7 = (q, t)."""
+    lib = _load()
+    a = _d(pose_prev2); b = _d(pose_prev1); out = np.zeros(7)
+    lib.orc_pose_const_velocity(_p(a), _p(b), _p(out))
+    return out

@@ -944,4 +944,22 @@ int orc_adam(int64_t n, double* param, double* m, double* v, const double* g, in
   return 0;
 }
 
+// Constant-speed pose initialisation (Eq. 13) applied to pose7 = (q, t):
+// t = t1 + (t1 - t0); q = normalise(q1 + (q1 - q0')) where q0' is q0 or -q0,
+// whichever lies in q1's hemisphere (q and -q are the same rotation).
+int orc_pose_const_velocity(const double* p0, const double* p1, double* out) {
+  double d = 0;
+  for (int i = 0; i < 4; ++i) d += p0[i] * p1[i];
+  const double s = d < 0 ? -1.0 : 1.0;
+  double q[4], n = 0;
+  for (int i = 0; i < 4; ++i) {
+    q[i] = p1[i] + (p1[i] - s * p0[i]);
+    n += q[i] * q[i];
+  }
+  n = std::sqrt(n);
+  for (int i = 0; i < 4; ++i) out[i] = n > 0 ? q[i] / n : p1[i];
+  for (int i = 0; i < 3; ++i) out[4 + i] = p1[4 + i] + (p1[4 + i] - p0[4 + i]);
+  return 0;
+}
+
 }  // extern "C"

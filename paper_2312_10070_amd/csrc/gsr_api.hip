@@ -45,6 +45,21 @@ struct gsr_state {
   int sorted = 0;
 };
 
+struct gsr_track_graph {
+  gsr_ctx* ctx = nullptr;
+  gsr_state* s = nullptr;  // owned (not in the context's pool)
+  int32_t n_iters = 0;
+  int64_t K_cap = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* buf = nullptr;  // pose, Adam state, gradients, losses, images
+  float *pose = nullptr, *adam = nullptr, *dpose = nullptr, *loss = nullptr, *median = nullptr;
+  float *color = nullptr, *depth = nullptr, *alpha = nullptr, *gC = nullptr, *gD = nullptr;
+  float *obs_c = nullptr, *obs_d = nullptr;
+  uint32_t* sel_temp = nullptr;
+  int* h_flag = nullptr;
+};
+
 struct gsr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -246,6 +261,75 @@ struct Stage {
   }
 };
 
+// Projection + scan of tile counts (the overlap count K lands in s->d_K).
+void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st) {
+  gsr::ProjectArgs pa{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
+                      s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts};
+  {
+    Stage t(c, "project");
+    gsr::launch_project(s->R, pa, st);
+  }
+  {
+    Stage t(c, "scan");
+    gsr::launch_exclusive_scan(s->counts, s->offsets, s->n, s->d_K, s->scan_temp, st);
+  }
+}
+
+// Duplication, sort, ranges and compositing. grid_K sizes the K-dependent
+// grids: the exact K (eager) or the capacity (captured graphs, which read K
+// from the device and flag an overflow).
+void enqueue_back(gsr_ctx* c, gsr_state* s, hipStream_t st, int64_t grid_K, float* color, float* depth, float* alpha) {
+  const gsr::Raster& R = s->R;
+  gsr::BinArgs ba{s->n, s->rec_rgbz, s->rect, s->counts, s->offsets, s->d_K, grid_K, 0u,
+                  s->keys[0], s->vals[0], s->d_overflow};
+  {
+    Stage t(c, "duplicate");
+    gsr::launch_duplicate(R, ba, st);
+  }
+  {
+    Stage t(c, "radix_sort");
+    s->sorted = gsr::launch_radix_sort(s->keys, s->vals, s->d_K, grid_K, 32 + bits_for(R.n_tiles), s->sort_temp, st);
+  }
+  {
+    Stage t(c, "tile_ranges");
+    gsr::launch_tile_ranges(s->keys[s->sorted], s->d_K, grid_K, s->ranges, R.n_tiles, st);
+  }
+  gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz,
+                  color, depth, alpha, s->Tfin, s->last, nullptr};
+  {
+    Stage t(c, "render_fwd");
+    gsr::launch_render_fwd(R, fa, st);
+  }
+}
+
+// Backward of the compositing and the projection. grads may be NULL (pose only).
+void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, const float* gD, const float* gA,
+                 const gsr_grads* grads, float* dpose7, float* dtwist6) {
+  const gsr::Raster& R = s->R;
+  const bool want_pose = dpose7 || dtwist6;
+  {
+    Stage t(c, "fill");
+    gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n, st);
+    if (want_pose) gsr::launch_fill_f32(s->pose_acc, 0.f, 12, st);
+  }
+  gsr::BwdArgs ba{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
+                  gC, gD, gA, s->g2d};
+  {
+    Stage t(c, "render_bwd");
+    gsr::launch_render_bwd(R, ba, st);
+  }
+  gsr_grads none{};
+  const gsr_grads& G = grads ? *grads : none;
+  gsr::ProjectBwdArgs pb{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
+                         s->counts, s->g2d, G.means, G.scales, G.quats, G.opacities, G.colors,
+                         want_pose ? s->pose_acc : nullptr};
+  {
+    Stage t(c, "project_bwd");
+    gsr::launch_project_bwd(R, pb, st);
+    if (want_pose) gsr::launch_pose_finalize(s->pose7, s->pose_acc, dpose7, dtwist6, st);
+  }
+}
+
 gsr_state* acquire_state(gsr_ctx* c) {
   for (gsr_state* s : c->pool)
     if (!s->in_use) {
@@ -368,17 +452,7 @@ int gsr_render_fwd(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, co
   s->g = *g;
   s->pose7 = pose7;
   hipStream_t st = c->stream;
-
-  gsr::ProjectArgs pa{g->n, g->means, g->scales, g->quats, g->opacities, g->colors, pose7,
-                      s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts};
-  {
-    Stage t(c, "project");
-    gsr::launch_project(R, pa, st);
-  }
-  {
-    Stage t(c, "scan");
-    gsr::launch_exclusive_scan(s->counts, s->offsets, g->n, s->d_K, s->scan_temp, st);
-  }
+  enqueue_front(c, s, st);
   GSR_HIP(c, hipMemcpyAsync(c->h_K, s->d_K, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   GSR_HIP(c, hipStreamSynchronize(st));
   const int64_t K = (int64_t)*c->h_K;
@@ -388,26 +462,7 @@ int gsr_render_fwd(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, co
     s->in_use = false;
     return rc;
   }
-  gsr::BinArgs ba{g->n, s->rec_rgbz, s->rect, s->counts, s->offsets, s->d_K, K, 0u,
-                  s->keys[0], s->vals[0], s->d_overflow};
-  {
-    Stage t(c, "duplicate");
-    gsr::launch_duplicate(R, ba, st);
-  }
-  {
-    Stage t(c, "radix_sort");
-    s->sorted = gsr::launch_radix_sort(s->keys, s->vals, s->d_K, K, 32 + bits_for(R.n_tiles), s->sort_temp, st);
-  }
-  {
-    Stage t(c, "tile_ranges");
-    gsr::launch_tile_ranges(s->keys[s->sorted], s->d_K, K, s->ranges, R.n_tiles, st);
-  }
-  gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz,
-                  color, depth, alpha, s->Tfin, s->last, nullptr};
-  {
-    Stage t(c, "render_fwd");
-    gsr::launch_render_fwd(R, fa, st);
-  }
+  enqueue_back(c, s, st, K, color, depth, alpha);
   rc = check_launch(c, "gsr_render_fwd kernels");
   if (rc) {
     s->in_use = false;
@@ -422,32 +477,10 @@ int gsr_render_bwd(gsr_ctx* c, gsr_state* s, const float* dL_dcolor, const float
   if (!c || !s || !s->in_use || s->ctx != c) return fail(c, GSR_EINVAL, "invalid state");
   if (!dL_dcolor || !dL_ddepth) return fail(c, GSR_EINVAL, "dL/dcolor and dL/ddepth are required");
   GSR_HIP(c, hipSetDevice(c->device));
-  hipStream_t st = c->stream;
-  const gsr::Raster& R = s->R;
-  const bool want_pose = dL_dpose7 || dL_dtwist6;
-  {
-    Stage t(c, "fill");
-    gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n, st);
-    if (want_pose) gsr::launch_fill_f32(s->pose_acc, 0.f, 12, st);
-  }
-  gsr::BwdArgs ba{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
-                  dL_dcolor, dL_ddepth, dL_dalpha, s->g2d};
-  {
-    Stage t(c, "render_bwd");
-    gsr::launch_render_bwd(R, ba, st);
-  }
-  gsr_grads none{};
-  const gsr_grads& G = grads ? *grads : none;
-  if (G.quats && (reinterpret_cast<uintptr_t>(G.quats) & 15u) != 0)
+  const gsr_grads* G = grads;
+  if (G && G->quats && (reinterpret_cast<uintptr_t>(G->quats) & 15u) != 0)
     return fail(c, GSR_EINVAL, "the quaternion gradient must be 16-byte aligned");
-  gsr::ProjectBwdArgs pb{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
-                         s->counts, s->g2d, G.means, G.scales, G.quats, G.opacities, G.colors,
-                         want_pose ? s->pose_acc : nullptr};
-  {
-    Stage t(c, "project_bwd");
-    gsr::launch_project_bwd(R, pb, st);
-    if (want_pose) gsr::launch_pose_finalize(s->pose7, s->pose_acc, dL_dpose7, dL_dtwist6, st);
-  }
+  enqueue_bwd(c, s, c->stream, dL_dcolor, dL_ddepth, dL_dalpha, G, dL_dpose7, dL_dtwist6);
   return check_launch(c, "gsr_render_bwd kernels");
 }
 
@@ -552,7 +585,7 @@ int gsr_state_stats(gsr_ctx* c, gsr_state* s, int64_t out[6]) {
   hipStream_t st = c->stream;
   GSR_HIP(c, hipMemsetAsync(c->d_stats, 0, 64, st));
   gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz,
-                  nullptr, nullptr, nullptr, nullptr, nullptr, c->d_stats};
+                  nullptr, nullptr, nullptr, nullptr, s->last, c->d_stats};
   gsr::launch_render_fwd(s->R, fa, st);
   unsigned long long h[3] = {0, 0, 0};
   GSR_HIP(c, hipMemcpyAsync(h, c->d_stats, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -568,6 +601,184 @@ int gsr_state_stats(gsr_ctx* c, gsr_state* s, int64_t out[6]) {
   out[4] = (int64_t)h[2];
   out[5] = s->R.n_tiles;
   return check_launch(c, "gsr_state_stats");
+}
+
+int gsr_pose_adam(gsr_ctx* c, float* pose7, float* state, const float* grad7, float lr_q, float lr_t, float b1,
+                  float b2, float eps) {
+  if (!c || !pose7 || !state || !grad7) return fail(c, GSR_EINVAL, "pose, state and gradient are required");
+  GSR_HIP(c, hipSetDevice(c->device));
+  Stage t(c, "pose_adam");
+  gsr::launch_pose_adam(pose7, state, grad7, lr_q, lr_t, b1, b2, eps, c->stream);
+  return check_launch(c, "gsr_pose_adam");
+}
+
+int gsr_pose_const_velocity(gsr_ctx* c, const float* p0, const float* p1, float* out) {
+  if (!c || !p0 || !p1 || !out) return fail(c, GSR_EINVAL, "pose pointers are required");
+  GSR_HIP(c, hipSetDevice(c->device));
+  gsr::launch_pose_const_velocity(p0, p1, out, c->stream);
+  return check_launch(c, "gsr_pose_const_velocity");
+}
+
+int gsr_track_graph_destroy(gsr_ctx* c, gsr_track_graph* tg) {
+  if (!c || !tg || tg->ctx != c) return fail(c, GSR_EINVAL, "invalid tracking graph");
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (tg->exec) (void)hipGraphExecDestroy(tg->exec);
+  if (tg->graph) (void)hipGraphDestroy(tg->graph);
+  if (tg->buf) (void)hipFree(tg->buf);
+  if (tg->h_flag) (void)hipHostFree(tg->h_flag);
+  if (tg->s) {
+    if (tg->s->arenaA) (void)hipFree(tg->s->arenaA);
+    if (tg->s->arenaB) (void)hipFree(tg->s->arenaB);
+    delete tg->s;
+  }
+  delete tg;
+  return GSR_OK;
+}
+
+int gsr_track_graph_set_frame(gsr_ctx* c, gsr_track_graph* tg, const float* obs_color, const float* obs_depth) {
+  if (!c || !tg || tg->ctx != c || !obs_color || !obs_depth) return fail(c, GSR_EINVAL, "bad arguments");
+  GSR_HIP(c, hipSetDevice(c->device));
+  const int64_t P = tg->s->P;
+  GSR_HIP(c, hipMemcpyAsync(tg->obs_c, obs_color, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, c->stream));
+  GSR_HIP(c, hipMemcpyAsync(tg->obs_d, obs_depth, sizeof(float) * P, hipMemcpyDeviceToDevice, c->stream));
+  return GSR_OK;
+}
+
+int gsr_track_graph_create(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, const gsr_opts* opts,
+                           const gsr_track_opts* to, const float* obs_color, const float* obs_depth, int64_t K_cap,
+                           gsr_track_graph** out) {
+  if (!c || !g || !to || !out || !obs_color || !obs_depth) return fail(c, GSR_EINVAL, "bad arguments");
+  *out = nullptr;
+  if (g->n <= 0 || g->n >= (int64_t(1) << 31) || !g->means || !g->scales || !g->quats || !g->opacities || !g->colors)
+    return fail(c, GSR_EINVAL, "tracking needs a non-empty Gaussian set");
+  if ((reinterpret_cast<uintptr_t>(g->quats) & 15u) != 0) return fail(c, GSR_EINVAL, "quats must be 16-byte aligned");
+  if (to->n_iters <= 0 || to->n_iters > 100000) return fail(c, GSR_EINVAL, "n_iters must be in [1, 100000]");
+  if (K_cap <= 0 || K_cap >= (int64_t(1) << 31)) return fail(c, GSR_EINVAL, "K_cap must be in [1, 2^31)");
+  gsr::Raster R;
+  int rc = make_raster(c, cam, opts, &R);
+  if (rc) return rc;
+  GSR_HIP(c, hipSetDevice(c->device));
+  gsr_track_graph* tg = new (std::nothrow) gsr_track_graph();
+  if (!tg) return fail(c, GSR_ENOMEM, "host allocation failed");
+  tg->ctx = c;
+  tg->n_iters = to->n_iters;
+  tg->K_cap = K_cap;
+  tg->s = new (std::nothrow) gsr_state();
+  if (!tg->s) {
+    delete tg;
+    return fail(c, GSR_ENOMEM, "host allocation failed");
+  }
+  gsr_state* s = tg->s;
+  s->ctx = c;
+  s->in_use = true;
+  const int64_t P = (int64_t)R.W * R.H;
+  rc = ensure_A(c, s, g->n, P, R.n_tiles);
+  if (!rc) rc = ensure_B(c, s, K_cap);
+  // graph-owned device buffers
+  size_t bytes = 0;
+  auto carve = [&](char* base) {
+    Carver cv{base};
+    tg->pose = cv.take<float>(8);
+    tg->adam = cv.take<float>(20);
+    tg->dpose = cv.take<float>(8);
+    tg->loss = cv.take<float>(tg->n_iters);
+    tg->median = cv.take<float>(tg->n_iters);
+    tg->color = cv.take<float>(3 * P);
+    tg->depth = cv.take<float>(P);
+    tg->alpha = cv.take<float>(P);
+    tg->gC = cv.take<float>(3 * P);
+    tg->gD = cv.take<float>(P);
+    tg->obs_c = cv.take<float>(3 * P);
+    tg->obs_d = cv.take<float>(P);
+    tg->sel_temp = cv.take<uint32_t>(gsr::track_temp_words());
+    bytes = cv.off;
+  };
+  if (!rc) {
+    carve(nullptr);
+    if (hipMalloc(&tg->buf, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      rc = fail(c, GSR_ENOMEM, "device allocation of the tracking buffers failed");
+    } else {
+      carve((char*)tg->buf);
+    }
+  }
+  if (!rc && hipHostMalloc((void**)&tg->h_flag, 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = fail(c, GSR_ENOMEM, "pinned allocation failed");
+  }
+  if (rc) {
+    gsr_track_graph_destroy(c, tg);
+    return rc;
+  }
+  s->R = R;
+  s->n = g->n;
+  s->P = P;
+  s->g = *g;
+  s->pose7 = tg->pose;
+  s->K = K_cap;
+  hipStream_t st = c->stream;
+  // stale tile-list slots must hold in-range values: sentinel tiles, Gaussian 0
+  for (int b = 0; b < 2; ++b) {
+    gsr::launch_fill_u32(reinterpret_cast<uint32_t*>(s->keys[b]), 0xffffffffu, 2 * K_cap, st);
+    gsr::launch_fill_u32(s->vals[b], 0u, K_cap, st);
+  }
+  gsr::launch_fill_f32(tg->pose, 0.f, 8, st);
+  rc = gsr_track_graph_set_frame(c, tg, obs_color, obs_depth);
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = hip_fail(c, e, "hipStreamSynchronize");
+  }
+  // capture on a private stream (default priority)
+  hipStream_t cap = nullptr;
+  if (!rc && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = fail(c, GSR_EHIP, "capture stream creation failed");
+  }
+  if (!rc) {
+    const bool prof = c->prof;
+    c->prof = false;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      gsr::launch_fill_f32(tg->adam, 0.f, 20, cap);
+      gsr::launch_fill_u32(reinterpret_cast<uint32_t*>(s->d_overflow), 0u, 1, cap);
+      for (int it = 0; it < tg->n_iters; ++it) {
+        enqueue_front(c, s, cap);
+        enqueue_back(c, s, cap, K_cap, tg->color, tg->depth, tg->alpha);
+        gsr::launch_loss_track(tg->color, tg->depth, tg->alpha, tg->obs_c, tg->obs_d, P, to->lambda_c,
+                               to->inlier_mult, tg->loss + it, tg->gC, tg->gD, tg->median + it, tg->sel_temp, cap);
+        enqueue_bwd(c, s, cap, tg->gC, tg->gD, nullptr, nullptr, tg->dpose, nullptr);
+        gsr::launch_pose_adam(tg->pose, tg->adam, tg->dpose, to->lr_q, to->lr_t, to->beta1, to->beta2, to->eps, cap);
+      }
+      e = hipStreamEndCapture(cap, &tg->graph);
+    }
+    c->prof = prof;
+    if (e == hipSuccess) e = hipGraphInstantiate(&tg->exec, tg->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = hip_fail(c, e, "tracking graph capture");
+    (void)hipStreamDestroy(cap);
+  }
+  if (rc) {
+    gsr_track_graph_destroy(c, tg);
+    return rc;
+  }
+  *out = tg;
+  return GSR_OK;
+}
+
+int gsr_track_graph_run(gsr_ctx* c, gsr_track_graph* tg, float* pose7, float* losses) {
+  if (!c || !tg || tg->ctx != c || !pose7) return fail(c, GSR_EINVAL, "bad arguments");
+  GSR_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  Stage t(c, "track_graph");
+  GSR_HIP(c, hipMemcpyAsync(tg->pose, pose7, sizeof(float) * 7, hipMemcpyDeviceToDevice, st));
+  GSR_HIP(c, hipGraphLaunch(tg->exec, st));
+  GSR_HIP(c, hipMemcpyAsync(pose7, tg->pose, sizeof(float) * 7, hipMemcpyDeviceToDevice, st));
+  if (losses)
+    GSR_HIP(c, hipMemcpyAsync(losses, tg->loss, sizeof(float) * tg->n_iters, hipMemcpyDeviceToDevice, st));
+  GSR_HIP(c, hipMemcpyAsync(tg->h_flag, tg->s->d_overflow, sizeof(int), hipMemcpyDeviceToHost, st));
+  GSR_HIP(c, hipStreamSynchronize(st));
+  if (*tg->h_flag) return fail(c, GSR_EOVERFLOW, "tile-overlap capacity exceeded inside the tracking graph");
+  return GSR_OK;
 }
 
 }  // extern "C"

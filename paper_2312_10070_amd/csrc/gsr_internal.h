@@ -266,4 +266,8 @@ void launch_loss_track(const float* C, const float* D, const float* A, const flo
 void launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
                  float bc1, float bc2, hipStream_t s);
 
+void launch_pose_adam(float* pose, float* state, const float* g, float lr_q, float lr_t, float b1, float b2, float eps,
+                      hipStream_t s);
+void launch_pose_const_velocity(const float* p0, const float* p1, float* out, hipStream_t s);
+
 }  // namespace gsr

@@ -129,6 +129,45 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
   }
 }
 
+// Adam on the 7 pose parameters (q: lr_q, t: lr_t) with the step count kept
+// on the device, so a captured graph can run many iterations. state = [m(8),
+// v(8), step(1)].
+__global__ void k_pose_adam(float* __restrict__ pose, float* __restrict__ state, const float* __restrict__ g,
+                            float lr_q, float lr_t, float b1, float b2, float eps) {
+  const int i = threadIdx.x;
+  const float t = state[16] + 1.f;
+  __syncthreads();
+  if (i < 7) {
+    const float gi = g[i];
+    const float mi = b1 * state[i] + (1.f - b1) * gi;
+    const float vi = b2 * state[8 + i] + (1.f - b2) * gi * gi;
+    state[i] = mi;
+    state[8 + i] = vi;
+    const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
+    const float lr = i < 4 ? lr_q : lr_t;
+    pose[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+  __syncthreads();
+  if (i == 0) state[16] = t;
+}
+
+// Constant-speed initialisation (Eq. 13) on (q, t): t = 2 t1 - t0; q =
+// normalise(2 q1 - q0') with q0 flipped into q1's hemisphere.
+__global__ void k_pose_const_velocity(const float* __restrict__ p0, const float* __restrict__ p1,
+                                      float* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const float dot = p0[0] * p1[0] + p0[1] * p1[1] + p0[2] * p1[2] + p0[3] * p1[3];
+  const float sgn = dot < 0.f ? -1.f : 1.f;
+  float q[4], n2 = 0.f;
+  for (int i = 0; i < 4; ++i) {
+    q[i] = 2.f * p1[i] - sgn * p0[i];
+    n2 += q[i] * q[i];
+  }
+  const float inv = n2 > 0.f ? 1.f / sqrtf(n2) : 0.f;
+  for (int i = 0; i < 4; ++i) out[i] = n2 > 0.f ? q[i] * inv : p1[i];
+  for (int i = 4; i < 7; ++i) out[i] = 2.f * p1[i] - p0[i];
+}
+
 unsigned grid_for(int64_t n, int64_t cap) {
   int64_t b = (n + 255) / 256;
   if (b > cap) b = cap;
@@ -169,4 +208,14 @@ void launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float 
   hipLaunchKernelGGL(k_adam, dim3(grid_for(n, 4096)), dim3(256), 0, s, p, m, v, g, n, lr, b1, b2, eps, bc1, bc2);
 }
 
+}  // namespace gsr
+
+namespace gsr {
+void launch_pose_adam(float* pose, float* state, const float* g, float lr_q, float lr_t, float b1, float b2, float eps,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_pose_adam, dim3(1), dim3(64), 0, s, pose, state, g, lr_q, lr_t, b1, b2, eps);
+}
+void launch_pose_const_velocity(const float* p0, const float* p1, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pose_const_velocity, dim3(1), dim3(64), 0, s, p0, p1, out);
+}
 }  // namespace gsr

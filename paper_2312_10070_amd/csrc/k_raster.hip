@@ -44,8 +44,44 @@ __device__ __forceinline__ bool box_meets(float fbx, float fby, const Strip& s) 
   return x0 <= s.x1 && x1 >= s.x0 && y0 <= s.y1 && y1 >= s.y0;
 }
 
-// STATS = true: count evaluated and composited pairs instead of writing
-// outputs (work counters for the benchmark's roofline; same control flow).
+__device__ __forceinline__ bool box_holds(float fbx, float fby, int px, int py) {
+  const uint32_t bx = __float_as_uint(fbx), by = __float_as_uint(fby);
+  return px >= (int)(bx & 0xffffu) && px <= (int)(bx >> 16) && py >= (int)(by & 0xffffu) && py <= (int)(by >> 16);
+}
+
+// STATS = true: instead of writing outputs, count the algorithmic work (for the
+// benchmark's roofline): pairs whose pixel lies in the Gaussian's support box
+// before the pixel stops (forward), pairs composited, and pairs in the support
+// box before each pixel's last composited Gaussian (what the backward must
+// evaluate). Same control flow as the rendering launch.
+template <bool STATS>
+__global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs a);
+
+// Backward-pair counting needs the final `last`; done in a second sweep.
+__global__ __launch_bounds__(kTileThreads) void k_count_bwd_pairs(Raster Rr, FwdArgs a) {
+  __shared__ float4 s_cob[kTileThreads];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tyi = tile / Rr.ntx, txi = tile - tyi * Rr.ntx;
+  const int tid = threadIdx.x;
+  const int px = txi * Rr.tw + (tid & (Rr.tw - 1));
+  const int py = tyi * Rr.th + (tid >> Rr.tw_log2);
+  const bool inside = px < Rr.W && py < Rr.H;
+  const int last = inside ? a.last[(int64_t)py * Rr.W + px] : 0;
+  const int2 rg = a.ranges[tile];
+  unsigned long long n = 0;
+  for (int base = rg.x; base < rg.y; base += kTileThreads) {
+    __syncthreads();
+    if (base + tid < rg.y) s_cob[tid] = a.rec_cob[a.ids[base + tid]];
+    __syncthreads();
+    const int cnt = min(kTileThreads, rg.y - base);
+    for (int j = 0; j < cnt; ++j)
+      if (base - rg.x + j < last && box_holds(s_cob[j].z, s_cob[j].w, px, py)) ++n;
+  }
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+  if ((tid & 63) == 0) atomicAdd(&a.stats[2], n);
+}
+
+// STATS = true: count work instead of writing outputs (see above).
 template <bool STATS>
 __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs a) {
   __shared__ float4 s_uvab[kTileThreads];
@@ -96,7 +132,7 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
           const float4 g = s_uvab[j];
           const float4 cb = s_cob[j];
           const PairEval pe = eval_pair(fpx - g.x, fpy - g.y, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
-          if (STATS) ++n_eval;
+          if (STATS && box_holds(cb.z, cb.w, px, py)) ++n_eval;
           if (pe.use) {
             const float Tn = T * (1.f - pe.alpha);
             if (Tn < Rr.tmin) {
@@ -122,17 +158,15 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
     }
   }
   if (STATS) {
-    // counters: [0] evaluated pairs, [1] composited pairs, [2] backward pairs (sum of last)
-    unsigned long long e = n_eval, cm = n_comp, b = (unsigned long long)last;
+    // counters: [0] support-box pairs before stopping, [1] composited pairs
+    unsigned long long e = n_eval, cm = n_comp;
     for (int o = 32; o > 0; o >>= 1) {
       e += __shfl_xor(e, o, 64);
       cm += __shfl_xor(cm, o, 64);
-      b += __shfl_xor(b, o, 64);
     }
     if (lane == 0) {
       atomicAdd(&a.stats[0], e);
       atomicAdd(&a.stats[1], cm);
-      atomicAdd(&a.stats[2], b);
     }
     return;
   }
@@ -264,9 +298,10 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
 }  // namespace
 
 void launch_render_fwd(const Raster& R, const FwdArgs& a, hipStream_t s) {
-  if (a.stats)
+  if (a.stats) {
     hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
-  else
+    hipLaunchKernelGGL(k_count_bwd_pairs, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
+  } else
     hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
 }
 

@@ -206,12 +206,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
   }
 }
 
+// Tiles outside [0, n_ranges) (possible only for stale keys after a capacity
+// overflow, which the caller reports) are ignored.
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ d_K,
-                                                    int64_t cap, int2* __restrict__ ranges) {
+                                                    int64_t cap, int2* __restrict__ ranges, int64_t n_ranges) {
   const uint32_t K = clamp_K(d_K, cap);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)K) return;
   const uint32_t t = (uint32_t)(keys[i] >> 32);
+  if ((int64_t)t >= n_ranges) return;
   if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = (int)i;
   if (i == (int64_t)K - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (int)(i + 1);
 }
@@ -284,7 +287,8 @@ void launch_tile_ranges(const uint64_t* keys, const uint32_t* d_K, int64_t cap, 
   hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(2 * n_ranges)), dim3(256), 0, s, (uint32_t*)ranges, 0u,
                      2 * n_ranges);
   if (cap <= 0) return;
-  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, keys, d_K, cap, ranges);
+  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, keys, d_K, cap, ranges,
+                     n_ranges);
 }
 
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {

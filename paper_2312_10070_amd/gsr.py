@@ -48,6 +48,12 @@ class Grads(ctypes.Structure):
                 ("opacities", ctypes.c_void_p), ("colors", ctypes.c_void_p)]
 
 
+class TrackOpts(ctypes.Structure):
+    _fields_ = [("lambda_c", ctypes.c_float), ("inlier_mult", ctypes.c_float), ("lr_q", ctypes.c_float),
+                ("lr_t", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("n_iters", ctypes.c_int32)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -69,6 +75,14 @@ _SIGS = {
     "gsr_loss_track": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P, P]),
     "gsr_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float]),
+    "gsr_pose_const_velocity": (ctypes.c_int, [P, P, P, P]),
+    "gsr_pose_adam": (ctypes.c_int, [P, P, P, P] + [ctypes.c_float] * 5),
+    "gsr_track_graph_create": (ctypes.c_int, [P, ctypes.POINTER(Gaussians), ctypes.POINTER(Camera),
+                                              ctypes.POINTER(Opts), ctypes.POINTER(TrackOpts), P, P, ctypes.c_int64,
+                                              ctypes.POINTER(P)]),
+    "gsr_track_graph_set_frame": (ctypes.c_int, [P, P, P, P]),
+    "gsr_track_graph_run": (ctypes.c_int, [P, P, P, P]),
+    "gsr_track_graph_destroy": (ctypes.c_int, [P, P]),
     "gsr_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
     "gsr_profile_read": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_char_p, P, P, ctypes.POINTER(ctypes.c_int)]),
     "gsr_state_stats": (ctypes.c_int, [P, P, P]),
@@ -336,3 +350,68 @@ def state_stats(state: State) -> dict:
     ctx.check(ctx.lib.gsr_state_stats(ctx.h, state.h, out.ctypes.data_as(P)))
     return dict(K=int(out[0]), visible=int(out[1]), pairs_fwd=int(out[2]), pairs_composited=int(out[3]),
                 pairs_bwd=int(out[4]), tiles=int(out[5]))
+
+
+def pose_const_velocity(pose_prev2, pose_prev1, ctx: Context | None = None):
+    """Eq. 13 on the device: returns a new pose7 tensor."""
+    ctx = ctx or Context.get(pose_prev1.device.index or 0)
+    ctx.sync_stream()
+    _f32(pose_prev2, "pose_prev2", (7,)); _f32(pose_prev1, "pose_prev1", (7,))
+    out = torch.empty(7, device=pose_prev1.device, dtype=torch.float32)
+    ctx.check(ctx.lib.gsr_pose_const_velocity(ctx.h, _ptr(pose_prev2), _ptr(pose_prev1), _ptr(out)))
+    return out
+
+
+class TrackGraph:
+    """A captured tracking loop (n_iters iterations of render -> Eq. 15 loss ->
+    pose backward -> Adam) over a frozen set of Gaussians."""
+
+    def __init__(self, means, scales, quats, opacities, colors, camera: Camera, obs_color, obs_depth,
+                 n_iters=100, lambda_c=0.5, inlier_mult=50.0, lr_q=5e-4, lr_t=1e-3, betas=(0.9, 0.999), eps=1e-8,
+                 K_cap: int = 0, opts: RasterOpts | None = None, ctx: Context | None = None):
+        self.ctx = ctx or Context.get(means.device.index or 0)
+        self.ctx.sync_stream()
+        self.keep = (means, scales, quats, opacities, colors)
+        g = _gaussians(means, scales, quats, opacities, colors)
+        self.n_iters = int(n_iters)
+        to = TrackOpts(lambda_c, inlier_mult, lr_q, lr_t, betas[0], betas[1], eps, self.n_iters)
+        oc = (opts or RasterOpts()).c()
+        self.h = P()
+        _f32(obs_color, "obs_color"); _f32(obs_depth, "obs_depth")
+        self.ctx.check(self.ctx.lib.gsr_track_graph_create(self.ctx.h, ctypes.byref(g), ctypes.byref(camera),
+                                                           ctypes.byref(oc), ctypes.byref(to), _ptr(obs_color),
+                                                           _ptr(obs_depth), int(K_cap), ctypes.byref(self.h)))
+
+    def set_frame(self, obs_color, obs_depth):
+        self.ctx.sync_stream()
+        _f32(obs_color, "obs_color"); _f32(obs_depth, "obs_depth")
+        self.ctx.check(self.ctx.lib.gsr_track_graph_set_frame(self.ctx.h, self.h, _ptr(obs_color), _ptr(obs_depth)))
+
+    def run(self, pose7, losses=None):
+        """Optimise pose7 (device, in place); optionally fill losses [n_iters]."""
+        self.ctx.sync_stream()
+        _f32(pose7, "pose7", (7,))
+        if losses is not None:
+            _f32(losses, "losses", (self.n_iters,))
+        self.ctx.check(self.ctx.lib.gsr_track_graph_run(self.ctx.h, self.h, _ptr(pose7), _ptr(losses)))
+        return pose7
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            self.ctx.lib.gsr_track_graph_destroy(self.ctx.h, self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pose_adam_step(pose7, state, grad7, lr_q, lr_t, beta1=0.9, beta2=0.999, eps=1e-8, ctx: Context | None = None):
+    """In-place Adam step on a pose7; state: zero-initialised float32 [20] device tensor."""
+    ctx = ctx or Context.get(pose7.device.index or 0)
+    ctx.sync_stream()
+    _f32(pose7, "pose7", (7,)); _f32(state, "state", (20,)); _f32(grad7, "grad7", (7,))
+    ctx.check(ctx.lib.gsr_pose_adam(ctx.h, _ptr(pose7), _ptr(state), _ptr(grad7), float(lr_q), float(lr_t),
+                                    float(beta1), float(beta2), float(eps)))

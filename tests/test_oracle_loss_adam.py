@@ -73,3 +73,24 @@ def test_adam_matches_torch():
         tp.grad = torch.tensor(g, dtype=torch.float64)
         opt.step()
     np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_const_velocity_pins():
+    """Eq. 13: a pure translation extrapolates linearly; equal poses stay put;
+    q and -q are the same rotation; a rotation by a then b about one axis
+    extrapolates to (nearly) 2b - a for small steps."""
+    from scipy.spatial.transform import Rotation
+    p0 = np.array([1, 0, 0, 0, 0.1, 0.2, 0.3]); p1 = np.array([1, 0, 0, 0, 0.15, 0.1, 0.3])
+    np.testing.assert_allclose(oracle.pose_const_velocity(p0, p1), [1, 0, 0, 0, 0.2, 0.0, 0.3], atol=1e-15)
+    q = np.array([0.8, 0.2, -0.4, 0.4]); q /= np.linalg.norm(q)
+    p = np.concatenate([q, [1, 2, 3]])
+    np.testing.assert_allclose(oracle.pose_const_velocity(p, p), p, atol=1e-15)
+    pm = p.copy(); pm[:4] *= -1
+    np.testing.assert_allclose(oracle.pose_const_velocity(pm, p), p, atol=1e-15)
+    axis = np.array([0.3, -0.5, 0.8]) / np.linalg.norm([0.3, -0.5, 0.8])
+    def qa(ang):
+        x, y, z, w = Rotation.from_rotvec(axis * ang).as_quat()
+        return np.array([w, x, y, z, 0, 0, 0])
+    out = oracle.pose_const_velocity(qa(0.01), qa(0.02))
+    ang = Rotation.from_quat([out[1], out[2], out[3], out[0]]).magnitude()
+    assert abs(ang - 0.03) < 1e-6
