@@ -106,6 +106,18 @@ void gsr_default_opts(gsr_opts *out);
 int gsr_render_fwd(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cam, const gsr_opts *opts,
                    const float *pose7, float *color, float *depth, float *alpha, gsr_state **state);
 
+/* Batched forward over n_views keyframes of one sub-map (the active sub-map
+ * is optimised against all its keyframes, Sec. 3.2). poses7: device [V,7];
+ * outputs color [V,3,H,W], depth [V,H,W], alpha [V,H,W]. All views' (tile,
+ * depth) keys are sorted together and every (view, tile) item is composited
+ * by ONE launch: with blocks_per_cu > 0 a persistent grid of blocks_per_cu x
+ * (compute units) workgroups takes items from a work counter, longest tile
+ * list first; with 0, one workgroup per item. gsr_render_fwd is the V = 1,
+ * blocks_per_cu = 0 case. Synchronises once (overlap count). */
+int gsr_render_fwd_batch(gsr_ctx *ctx, const gsr_gaussians *g, int32_t n_views, const gsr_camera *cam,
+                         const gsr_opts *opts, int32_t blocks_per_cu, const float *poses7, float *color,
+                         float *depth, float *alpha, gsr_state **state);
+
 /* Backward of gsr_render_fwd for upstream gradients dL/dcolor [3,H,W],
  * dL/ddepth [H,W] and dL/dalpha [H,W] (NULL = zero). Writes the gradients
  * w.r.t. the activated parameters (Sec. 3.3; Eq. 8 for the depth-alpha term,
@@ -115,6 +127,21 @@ int gsr_render_fwd(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cam, 
  * T <- exp(xi^) T). Transmittance is recomputed back to front, not stored. */
 int gsr_render_bwd(gsr_ctx *ctx, gsr_state *state, const float *dL_dcolor, const float *dL_ddepth,
                    const float *dL_dalpha, const gsr_grads *grads, float *dL_dpose7, float *dL_dtwist6);
+/* For a batched state the same call takes [V,3,H,W] / [V,H,W] upstream
+ * gradients, sums the parameter gradients over the views, writes per-view pose
+ * gradients dL_dpose7 [V,7] / dL_dtwist6 [V,6], and runs the compositing
+ * backward with the forward's launch shape. */
+
+/* Tile-shape autotuner for the batched path: times forward + backward (reps
+ * runs after one warm-up, HIP events) for every tile shape in {16x16, 8x32,
+ * 32x8} and blocks_per_cu in {0, 1, 2, 4, 8} with the given upstream
+ * gradients, writes the fastest shape into opts->tile_w / tile_h (the other
+ * fields are inputs) and the fastest blocks_per_cu into *best_blocks_per_cu.
+ * ms_table (may be NULL) receives the 15 mean times, shape-major. Allocates
+ * scratch images; synchronises. */
+int gsr_autotune_batch(gsr_ctx *ctx, const gsr_gaussians *g, int32_t n_views, const gsr_camera *cam, gsr_opts *opts,
+                       const float *poses7, const float *dL_dcolor, const float *dL_ddepth, int32_t reps,
+                       int32_t *best_blocks_per_cu, float *ms_table);
 
 int gsr_state_release(gsr_ctx *ctx, gsr_state *state);
 

@@ -241,3 +241,70 @@ def pose_const_velocity(pose_prev2, pose_prev1) -> np.ndarray:
     a = _d(pose_prev2); b = _d(pose_prev1); out = np.zeros(7)
     lib.orc_pose_const_velocity(_p(a), _p(b), _p(out))
     return out
+
+
+# ---------------------------------------------------------------------------
+# CNN oracle (tracking-initialisation network), FP64, NCHW
+# ---------------------------------------------------------------------------
+
+def conv2d(x, w, b, stride=2, pad=1):
+    """3x3 (k x k) convolution by definition; x [B,C,H,W], w [O,C,k,k], b [O] or None."""
+    lib = _load()
+    x = _d(x); w = _d(w)
+    B, C, H, W = x.shape
+    O, _, k, _ = w.shape
+    oh = (H + 2 * pad - k) // stride + 1
+    ow = (W + 2 * pad - k) // stride + 1
+    out = np.zeros((B, O, oh, ow))
+    bb = None if b is None else _d(b)
+    lib.orc_conv2d_fwd(B, C, H, W, O, stride, pad, k, _p(x), _p(w), _p(bb), _p(out))
+    return out
+
+
+def conv2d_bwd(x, w, dout, stride=2, pad=1, want_dx=True):
+    """(dx or None, dw, db) of conv2d for upstream dout."""
+    lib = _load()
+    x = _d(x); w = _d(w); dout = _d(dout)
+    B, C, H, W = x.shape
+    O, _, k, _ = w.shape
+    dx = np.zeros_like(x) if want_dx else None
+    dw = np.zeros_like(w)
+    db = np.zeros(O)
+    lib.orc_conv2d_bwd(B, C, H, W, O, stride, pad, k, _p(x), _p(w), _p(dout), _p(dx), _p(dw), _p(db))
+    return dx, dw, db
+
+
+def initnet_forward(x, params):
+    """x [B,8,H,W]; params: w0..w3 [64,C,3,3], b0..b3 [64], wfc [6,64], bfc [6].
+    Four stride-2 3x3 convolutions with ReLU, global average pool, linear head.
+    Returns (out [B,6], cache)."""
+    acts = [np.asarray(x, np.float64)]
+    for l in range(4):
+        y = conv2d(acts[-1], params[f"w{l}"], params[f"b{l}"])
+        acts.append(np.maximum(y, 0.0))
+    pool = acts[-1].mean(axis=(2, 3))
+    out = pool @ np.asarray(params["wfc"], np.float64).T + np.asarray(params["bfc"], np.float64)
+    return out, (acts, pool)
+
+
+def initnet_backward(params, cache, dout):
+    """Gradients of the network parameters for upstream dL/dout [B,6]."""
+    acts, pool = cache
+    grads = {"wfc": dout.T @ pool, "bfc": dout.sum(0)}
+    dpool = dout @ np.asarray(params["wfc"], np.float64)
+    a = acts[-1]
+    dact = np.broadcast_to(dpool[:, :, None, None] / (a.shape[2] * a.shape[3]), a.shape).copy()
+    for l in range(3, -1, -1):
+        dy = dact * (acts[l + 1] > 0)
+        dx, dw, db = conv2d_bwd(acts[l], params[f"w{l}"], dy, want_dx=l > 0)
+        grads[f"w{l}"] = dw
+        grads[f"b{l}"] = db
+        dact = dx
+    return grads
+
+
+def initnet_loss(out, label, scale):
+    """L = 1/(2B) sum_b sum_j ((out - label) / scale_j)^2 and dL/dout."""
+    r = (np.asarray(out, np.float64) - np.asarray(label, np.float64)) / np.asarray(scale, np.float64)
+    B = r.shape[0]
+    return 0.5 * float((r * r).sum()) / B, r / np.asarray(scale, np.float64) / B

@@ -20,7 +20,7 @@ struct gsr_state {
   gsr_gaussians g{};
   const float* pose7 = nullptr;
   // capacities of the two arenas
-  int64_t n_cap = -1, P_cap = -1, tiles_cap = -1, K_cap = -1;
+  int64_t n_cap = -1, P_cap = -1, tiles_cap = -1, K_cap = -1, views_cap = -1;
   void* arenaA = nullptr;
   void* arenaB = nullptr;
   // arena A: per Gaussian / pixel / tile
@@ -37,7 +37,12 @@ struct gsr_state {
   int2* ranges = nullptr;
   uint32_t* d_K = nullptr;
   int* d_overflow = nullptr;
-  float* pose_acc = nullptr;
+  float* pose_acc = nullptr;  // [views, 12]
+  int* queue = nullptr;       // persistent-launch work counter
+  int* order = nullptr;       // [views * tiles] longest-list-first item order
+  int* order_temp = nullptr;  // 64 ints
+  int n_views = 1;
+  int blocks = 0;             // persistent workgroups (0 = one per item)
   // arena B: per overlap
   uint64_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
@@ -68,6 +73,7 @@ struct gsr_ctx {
   uint32_t* h_K = nullptr;  // pinned host word for the overlap count
   uint32_t* track_temp = nullptr;
   unsigned long long* d_stats = nullptr;
+  int n_cu = 256;  // compute units of the device
   // stage timing (gsr_profile_*): an event pair around each stage launch
   struct Rec {
     const char* name;
@@ -114,7 +120,8 @@ struct Carver {
   }
 };
 
-void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, size_t* bytes) {
+// n, P, tiles are totals over views.
+void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, int64_t views, size_t* bytes) {
   Carver c{base};
   s->rec_uvab = c.take<float4>(n);
   s->rec_cob = c.take<float4>(n);
@@ -129,7 +136,10 @@ void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, size
   s->ranges = c.take<int2>(tiles);
   s->d_K = c.take<uint32_t>(4);
   s->d_overflow = c.take<int>(4);
-  s->pose_acc = c.take<float>(16);
+  s->pose_acc = c.take<float>(12 * views + 4);
+  s->queue = c.take<int>(4);
+  s->order = c.take<int>(tiles);
+  s->order_temp = c.take<int>(64);
   *bytes = c.off;
 }
 
@@ -143,24 +153,25 @@ void carve_B(gsr_state* s, char* base, int64_t K, size_t* bytes) {
   *bytes = c.off;
 }
 
-int ensure_A(gsr_ctx* c, gsr_state* s, int64_t n, int64_t P, int64_t tiles) {
-  if (s->arenaA && n <= s->n_cap && P <= s->P_cap && tiles <= s->tiles_cap) return GSR_OK;
+int ensure_A(gsr_ctx* c, gsr_state* s, int64_t n, int64_t P, int64_t tiles, int64_t views) {
+  if (s->arenaA && n <= s->n_cap && P <= s->P_cap && tiles <= s->tiles_cap && views <= s->views_cap) return GSR_OK;
   if (s->arenaA) GSR_HIP(c, hipFree(s->arenaA));
   s->arenaA = nullptr;
   const int64_t nn = std::max<int64_t>(n + n / 4, 1024), PP = std::max<int64_t>(P, 256),
-                tt = std::max<int64_t>(tiles, 16);
+                tt = std::max<int64_t>(tiles, 16), vv = std::max<int64_t>(views, 1);
   size_t bytes = 0;
-  carve_A(s, nullptr, nn, PP, tt, &bytes);
+  carve_A(s, nullptr, nn, PP, tt, vv, &bytes);
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, GSR_ENOMEM, "device allocation of the per-Gaussian workspace failed");
   }
   s->arenaA = p;
-  carve_A(s, (char*)p, nn, PP, tt, &bytes);
+  carve_A(s, (char*)p, nn, PP, tt, vv, &bytes);
   s->n_cap = nn;
   s->P_cap = PP;
   s->tiles_cap = tt;
+  s->views_cap = vv;
   return GSR_OK;
 }
 
@@ -264,14 +275,14 @@ struct Stage {
 // Projection + scan of tile counts (the overlap count K lands in s->d_K).
 void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st) {
   gsr::ProjectArgs pa{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
-                      s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts};
+                      s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts, s->n_views};
   {
     Stage t(c, "project");
     gsr::launch_project(s->R, pa, st);
   }
   {
     Stage t(c, "scan");
-    gsr::launch_exclusive_scan(s->counts, s->offsets, s->n, s->d_K, s->scan_temp, st);
+    gsr::launch_exclusive_scan(s->counts, s->offsets, s->n * s->n_views, s->d_K, s->scan_temp, st);
   }
 }
 
@@ -280,7 +291,8 @@ void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st) {
 // from the device and flag an overflow).
 void enqueue_back(gsr_ctx* c, gsr_state* s, hipStream_t st, int64_t grid_K, float* color, float* depth, float* alpha) {
   const gsr::Raster& R = s->R;
-  gsr::BinArgs ba{s->n, s->rec_rgbz, s->rect, s->counts, s->offsets, s->d_K, grid_K, 0u,
+  const int n_items = R.n_tiles * s->n_views;
+  gsr::BinArgs ba{s->n, s->rec_rgbz, s->rect, s->counts, s->offsets, s->d_K, grid_K, s->n_views,
                   s->keys[0], s->vals[0], s->d_overflow};
   {
     Stage t(c, "duplicate");
@@ -288,14 +300,16 @@ void enqueue_back(gsr_ctx* c, gsr_state* s, hipStream_t st, int64_t grid_K, floa
   }
   {
     Stage t(c, "radix_sort");
-    s->sorted = gsr::launch_radix_sort(s->keys, s->vals, s->d_K, grid_K, 32 + bits_for(R.n_tiles), s->sort_temp, st);
+    s->sorted = gsr::launch_radix_sort(s->keys, s->vals, s->d_K, grid_K, 32 + bits_for(n_items), s->sort_temp, st);
   }
   {
     Stage t(c, "tile_ranges");
-    gsr::launch_tile_ranges(s->keys[s->sorted], s->d_K, grid_K, s->ranges, R.n_tiles, st);
+    gsr::launch_tile_ranges(s->keys[s->sorted], s->d_K, grid_K, s->ranges, n_items, st);
+    if (s->blocks > 0) gsr::launch_item_order(s->ranges, n_items, s->order, s->order_temp, st);
   }
   gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz,
-                  color, depth, alpha, s->Tfin, s->last, nullptr};
+                  color, depth, alpha, s->Tfin, s->last, nullptr,
+                  n_items, s->queue, s->blocks > 0 ? s->order : nullptr, s->blocks};
   {
     Stage t(c, "render_fwd");
     gsr::launch_render_fwd(R, fa, st);
@@ -307,13 +321,14 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
                  const gsr_grads* grads, float* dpose7, float* dtwist6) {
   const gsr::Raster& R = s->R;
   const bool want_pose = dpose7 || dtwist6;
+  const int n_items = R.n_tiles * s->n_views;
   {
     Stage t(c, "fill");
-    gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n, st);
-    if (want_pose) gsr::launch_fill_f32(s->pose_acc, 0.f, 12, st);
+    gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n * s->n_views, st);
+    if (want_pose) gsr::launch_fill_f32(s->pose_acc, 0.f, 12 * s->n_views, st);
   }
   gsr::BwdArgs ba{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
-                  gC, gD, gA, s->g2d};
+                  gC, gD, gA, s->g2d, n_items, s->queue, s->blocks > 0 ? s->order : nullptr, s->blocks};
   {
     Stage t(c, "render_bwd");
     gsr::launch_render_bwd(R, ba, st);
@@ -322,11 +337,11 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
   const gsr_grads& G = grads ? *grads : none;
   gsr::ProjectBwdArgs pb{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
                          s->counts, s->g2d, G.means, G.scales, G.quats, G.opacities, G.colors,
-                         want_pose ? s->pose_acc : nullptr};
+                         want_pose ? s->pose_acc : nullptr, s->n_views};
   {
     Stage t(c, "project_bwd");
     gsr::launch_project_bwd(R, pb, st);
-    if (want_pose) gsr::launch_pose_finalize(s->pose7, s->pose_acc, dpose7, dtwist6, st);
+    if (want_pose) gsr::launch_pose_finalize(s->pose7, s->pose_acc, dpose7, dtwist6, s->n_views, st);
   }
 }
 
@@ -385,6 +400,10 @@ int gsr_ctx_create(gsr_ctx** out, int device, void* hip_stream) {
   if (!c) return GSR_ENOMEM;
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+    c->n_cu = ncu;
+  (void)hipGetLastError();
   if (hipHostMalloc((void**)&c->h_K, 64, hipHostMallocDefault) != hipSuccess ||
       hipMalloc((void**)&c->track_temp, sizeof(uint32_t) * gsr::track_temp_words()) != hipSuccess ||
       hipMalloc((void**)&c->d_stats, 64) != hipSuccess) {
@@ -423,25 +442,29 @@ int gsr_set_stream(gsr_ctx* c, void* hip_stream) {
   return GSR_OK;
 }
 
-int gsr_render_fwd(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, const gsr_opts* opts,
-                   const float* pose7, float* color, float* depth, float* alpha, gsr_state** state) {
+int gsr_render_fwd_batch(gsr_ctx* c, const gsr_gaussians* g, int32_t n_views, const gsr_camera* cam,
+                         const gsr_opts* opts, int32_t blocks_per_cu, const float* poses7, float* color, float* depth,
+                         float* alpha, gsr_state** state) {
   if (!c || !g || !state) return fail(c, GSR_EINVAL, "ctx, gaussians and state are required");
   *state = nullptr;
   if (g->n < 0) return fail(c, GSR_EINVAL, "n must be >= 0");
-  if (g->n >= (int64_t(1) << 31)) return fail(c, GSR_EINVAL, "n must be < 2^31");
+  if (n_views < 1 || n_views > 1024) return fail(c, GSR_EINVAL, "n_views must be in [1, 1024]");
+  if (g->n * n_views >= (int64_t(1) << 31)) return fail(c, GSR_EINVAL, "n * n_views must be < 2^31");
+  if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(c, GSR_EINVAL, "blocks_per_cu must be in [0, 64]");
   if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->colors))
     return fail(c, GSR_EINVAL, "Gaussian parameter pointers are required");
   if (g->n > 0 && (reinterpret_cast<uintptr_t>(g->quats) & 15u) != 0)
     return fail(c, GSR_EINVAL, "quats must be 16-byte aligned");
-  if (!pose7 || !color || !depth || !alpha) return fail(c, GSR_EINVAL, "pose7 and the outputs are required");
+  if (!poses7 || !color || !depth || !alpha) return fail(c, GSR_EINVAL, "poses and the outputs are required");
   gsr::Raster R;
   int rc = make_raster(c, cam, opts, &R);
   if (rc) return rc;
+  if ((int64_t)R.n_tiles * n_views >= (int64_t(1) << 31)) return fail(c, GSR_EINVAL, "too many tiles");
   GSR_HIP(c, hipSetDevice(c->device));
   gsr_state* s = acquire_state(c);
   if (!s) return fail(c, GSR_ENOMEM, "host allocation failed");
   const int64_t P = (int64_t)R.W * R.H;
-  rc = ensure_A(c, s, g->n, P, R.n_tiles);
+  rc = ensure_A(c, s, g->n * n_views, P * n_views, (int64_t)R.n_tiles * n_views, n_views);
   if (rc) {
     s->in_use = false;
     return rc;
@@ -450,7 +473,9 @@ int gsr_render_fwd(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, co
   s->n = g->n;
   s->P = P;
   s->g = *g;
-  s->pose7 = pose7;
+  s->pose7 = poses7;
+  s->n_views = n_views;
+  s->blocks = blocks_per_cu * c->n_cu;
   hipStream_t st = c->stream;
   enqueue_front(c, s, st);
   GSR_HIP(c, hipMemcpyAsync(c->h_K, s->d_K, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -470,6 +495,11 @@ int gsr_render_fwd(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, co
   }
   *state = s;
   return GSR_OK;
+}
+
+int gsr_render_fwd(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera* cam, const gsr_opts* opts,
+                   const float* pose7, float* color, float* depth, float* alpha, gsr_state** state) {
+  return gsr_render_fwd_batch(c, g, 1, cam, opts, 0, pose7, color, depth, alpha, state);
 }
 
 int gsr_render_bwd(gsr_ctx* c, gsr_state* s, const float* dL_dcolor, const float* dL_ddepth, const float* dL_dalpha,
@@ -495,7 +525,8 @@ int gsr_tile_lists(gsr_ctx* c, const gsr_state* s, int64_t* K, int32_t* ranges, 
   GSR_HIP(c, hipSetDevice(c->device));
   *K = s->K;
   if (ranges)
-    GSR_HIP(c, hipMemcpyAsync(ranges, s->ranges, sizeof(int2) * s->R.n_tiles, hipMemcpyDeviceToDevice, c->stream));
+    GSR_HIP(c, hipMemcpyAsync(ranges, s->ranges, sizeof(int2) * s->R.n_tiles * s->n_views, hipMemcpyDeviceToDevice,
+                              c->stream));
   if (ids && s->K > 0)
     GSR_HIP(c, hipMemcpyAsync(ids, s->vals[s->sorted], sizeof(uint32_t) * s->K, hipMemcpyDeviceToDevice, c->stream));
   GSR_HIP(c, hipStreamSynchronize(c->stream));
@@ -537,6 +568,74 @@ int gsr_adam(gsr_ctx* c, float* param, float* m, float* v, const float* grad, in
   Stage t(c, "adam");
   gsr::launch_adam(param, m, v, grad, n, lr, b1, b2, eps, bc1, bc2, c->stream);
   return check_launch(c, "gsr_adam");
+}
+
+int gsr_autotune_batch(gsr_ctx* c, const gsr_gaussians* g, int32_t n_views, const gsr_camera* cam, gsr_opts* opts,
+                       const float* poses7, const float* dL_dcolor, const float* dL_ddepth, int32_t reps,
+                       int32_t* best_blocks_per_cu, float* ms_table) {
+  if (!c || !g || !cam || !opts || !poses7 || !dL_dcolor || !dL_ddepth || !best_blocks_per_cu)
+    return fail(c, GSR_EINVAL, "bad autotune arguments");
+  if (reps < 1 || reps > 1000) return fail(c, GSR_EINVAL, "reps must be in [1, 1000]");
+  if (n_views < 1 || n_views > 1024) return fail(c, GSR_EINVAL, "n_views must be in [1, 1024]");
+  GSR_HIP(c, hipSetDevice(c->device));
+  const int64_t P = (int64_t)cam->width * cam->height;
+  if (P <= 0) return fail(c, GSR_EINVAL, "image size must be positive");
+  float* buf = nullptr;
+  if (hipMalloc((void**)&buf, sizeof(float) * 5 * P * n_views) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, GSR_ENOMEM, "autotune scratch allocation failed");
+  }
+  float* color = buf;
+  float* depth = buf + 3 * P * n_views;
+  float* alpha = depth + P * n_views;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(buf);
+    return fail(c, GSR_EHIP, "event creation failed");
+  }
+  const int shapes[3][2] = {{16, 16}, {8, 32}, {32, 8}};
+  const int bpc[5] = {0, 1, 2, 4, 8};
+  float best = 1e30f;
+  int best_s = 0, best_b = 0, rc = GSR_OK;
+  const bool prof = c->prof;
+  c->prof = false;
+  for (int si = 0; si < 3 && rc == GSR_OK; ++si)
+    for (int bi = 0; bi < 5 && rc == GSR_OK; ++bi) {
+      gsr_opts o = *opts;
+      o.tile_w = shapes[si][0];
+      o.tile_h = shapes[si][1];
+      float total = 0.f;
+      for (int r = 0; r <= reps && rc == GSR_OK; ++r) {  // r == 0 warms up
+        gsr_state* st = nullptr;
+        (void)hipEventRecord(e0, c->stream);
+        rc = gsr_render_fwd_batch(c, g, n_views, cam, &o, bpc[bi], poses7, color, depth, alpha, &st);
+        if (rc == GSR_OK) rc = gsr_render_bwd(c, st, dL_dcolor, dL_ddepth, nullptr, nullptr, nullptr, nullptr);
+        (void)hipEventRecord(e1, c->stream);
+        if (st) gsr_state_release(c, st);
+        if (rc == GSR_OK && hipEventSynchronize(e1) == hipSuccess && r > 0) {
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          total += ms;
+        }
+      }
+      const float avg = total / reps;
+      if (ms_table) ms_table[si * 5 + bi] = avg;
+      if (rc == GSR_OK && avg < best) {
+        best = avg;
+        best_s = si;
+        best_b = bi;
+      }
+    }
+  c->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  if (rc != GSR_OK) return rc;
+  opts->tile_w = shapes[best_s][0];
+  opts->tile_h = shapes[best_s][1];
+  *best_blocks_per_cu = bpc[best_b];
+  return GSR_OK;
 }
 
 int gsr_profile_enable(gsr_ctx* c, int on) {
@@ -585,21 +684,23 @@ int gsr_state_stats(gsr_ctx* c, gsr_state* s, int64_t out[6]) {
   hipStream_t st = c->stream;
   GSR_HIP(c, hipMemsetAsync(c->d_stats, 0, 64, st));
   gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz,
-                  nullptr, nullptr, nullptr, nullptr, s->last, c->d_stats};
+                  nullptr, nullptr, nullptr, nullptr, s->last, c->d_stats,
+                  s->R.n_tiles * s->n_views, nullptr, nullptr, 0};
   gsr::launch_render_fwd(s->R, fa, st);
   unsigned long long h[3] = {0, 0, 0};
   GSR_HIP(c, hipMemcpyAsync(h, c->d_stats, sizeof(h), hipMemcpyDeviceToHost, st));
-  std::vector<uint32_t> counts((size_t)std::max<int64_t>(s->n, 1));
-  if (s->n > 0) GSR_HIP(c, hipMemcpyAsync(counts.data(), s->counts, 4 * s->n, hipMemcpyDeviceToHost, st));
+  const int64_t m = s->n * s->n_views;
+  std::vector<uint32_t> counts((size_t)std::max<int64_t>(m, 1));
+  if (m > 0) GSR_HIP(c, hipMemcpyAsync(counts.data(), s->counts, 4 * m, hipMemcpyDeviceToHost, st));
   GSR_HIP(c, hipStreamSynchronize(st));
   int64_t vis = 0;
-  for (int64_t i = 0; i < s->n; ++i) vis += counts[i] > 0;
+  for (int64_t i = 0; i < m; ++i) vis += counts[i] > 0;
   out[0] = s->K;
   out[1] = vis;
   out[2] = (int64_t)h[0];
   out[3] = (int64_t)h[1];
   out[4] = (int64_t)h[2];
-  out[5] = s->R.n_tiles;
+  out[5] = (int64_t)s->R.n_tiles * s->n_views;
   return check_launch(c, "gsr_state_stats");
 }
 
@@ -673,7 +774,7 @@ int gsr_track_graph_create(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera*
   s->ctx = c;
   s->in_use = true;
   const int64_t P = (int64_t)R.W * R.H;
-  rc = ensure_A(c, s, g->n, P, R.n_tiles);
+  rc = ensure_A(c, s, g->n, P, R.n_tiles, 1);
   if (!rc) rc = ensure_B(c, s, K_cap);
   // graph-owned device buffers
   size_t bytes = 0;

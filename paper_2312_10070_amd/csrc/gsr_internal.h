@@ -183,6 +183,7 @@ struct ProjectArgs {
   float4* rec_rgbz;
   int4* rect;          // tile rectangle (tx0, ty0, tx1, ty1)
   uint32_t* counts;    // tiles per Gaussian (0 = culled)
+  int n_views;         // outputs are [n_views * n]; view v uses pose7 + 7 v
 };
 void launch_project(const Raster& R, const ProjectArgs& a, hipStream_t s);
 
@@ -200,7 +201,7 @@ struct BinArgs {
   const uint32_t* offsets;
   const uint32_t* d_K;
   int64_t K_cap;
-  uint32_t tile_base;  // view * n_tiles for multi-view lists
+  int n_views;         // entries are [n_views * n]; tile ids of view v start at v * n_tiles
   uint64_t* keys;
   uint32_t* vals;
   int* overflow;
@@ -221,9 +222,13 @@ struct FwdArgs {
   const float4* rec_uvab;
   const float4* rec_cob;
   const float4* rec_rgbz;
-  float *color, *depth, *alpha, *Tfin;
+  float *color, *depth, *alpha, *Tfin;  // [V,3,H,W] / [V,H,W]
   int* last;
   unsigned long long* stats;  // non-NULL: count work only, write no outputs
+  int n_items;                // views * tiles; item = view * n_tiles + tile
+  int* queue;                 // persistent launch: work counter (zeroed first)
+  const int* order;           // persistent launch: item order (NULL = identity)
+  int blocks;                 // persistent launch: workgroups (0 = one per item)
 };
 void launch_render_fwd(const Raster& R, const FwdArgs& a, hipStream_t s);
 
@@ -236,7 +241,11 @@ struct BwdArgs {
   const float* Tfin;
   const int* last;
   const float *gC, *gD, *gA;
-  float* g2d;  // [n, 10]: u, v, pa, pb, pc, o, r, g, b, z
+  float* g2d;  // [V*n, 10]: u, v, pa, pb, pc, o, r, g, b, z
+  int n_items;
+  int* queue;
+  const int* order;
+  int blocks;
 };
 void launch_render_bwd(const Raster& R, const BwdArgs& a, hipStream_t s);
 
@@ -246,12 +255,16 @@ struct ProjectBwdArgs {
   const float* pose7;
   const uint32_t* counts;
   const float* g2d;
-  float *g_means, *g_scales, *g_quats, *g_opacities, *g_colors;  // may be NULL
-  float* pose_acc;  // [12]: dL/dR_p (9, row-major), dL/dt (3); NULL = skip
+  float *g_means, *g_scales, *g_quats, *g_opacities, *g_colors;  // may be NULL; summed over views
+  float* pose_acc;  // [n_views, 12]: dL/dR_p (9, row-major), dL/dt (3); NULL = skip
+  int n_views;
 };
 void launch_project_bwd(const Raster& R, const ProjectBwdArgs& a, hipStream_t s);
 void launch_pose_finalize(const float* pose7, const float* pose_acc, float* dL_dpose7, float* dL_dtwist6,
-                          hipStream_t s);
+                          int n_views, hipStream_t s);
+// Longest-list-first order of (view, tile) items for the persistent launches
+// (power-of-two length buckets). temp: 64 ints.
+void launch_item_order(const int2* ranges, int n_items, int* order, int* temp, hipStream_t s);
 
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);

@@ -130,20 +130,22 @@ __device__ __forceinline__ bool project_geo(const Raster& Rr, const PoseF& P, co
   return true;
 }
 
+// grid.y = view: view v reads pose7 + 7 v and writes entries v * n + k.
 __global__ __launch_bounds__(256) void k_project(Raster Rr, ProjectArgs a) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= a.n) return;
-  const PoseF P = load_pose(a.pose7);
+  const int64_t o = (int64_t)blockIdx.y * a.n + k;
+  const PoseF P = load_pose(a.pose7 + 7 * blockIdx.y);
   Geo g;
   uint32_t count = 0;
   int4 rect = make_int4(0, 0, -1, -1);
   if (project_geo(Rr, P, a.means, a.scales, a.quats, k, g)) {
-    const float o = a.opacities[k];
-    if (o >= Rr.amin && isfinite(o)) {
+    const float op = a.opacities[k];
+    if (op >= Rr.amin && isfinite(op)) {
       const float idet = 1.f / g.det;
       const float ca = g.Syy * idet, cb = -g.Sxy * idet, cc = g.Sxx * idet;
       // support: o exp(-sigma) >= alpha_min needs sigma <= ln(o / alpha_min)
-      const float smax = logf(o / Rr.amin);
+      const float smax = logf(op / Rr.amin);
       const float rx = sqrtf(2.f * smax * g.Sxx), ry = sqrtf(2.f * smax * g.Syy);
       const float ex0 = g.u - rx, ex1 = g.u + rx, ey0 = g.v - ry, ey1 = g.v + ry;
       if (isfinite(ex0) && isfinite(ex1) && isfinite(ey0) && isfinite(ey1)) {
@@ -154,142 +156,171 @@ __global__ __launch_bounds__(256) void k_project(Raster Rr, ProjectArgs a) {
           rect = make_int4(px0 >> Rr.tw_log2, py0 / Rr.th, px1 >> Rr.tw_log2, py1 / Rr.th);
           count = (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1));
           const float s = -0.5f * kLog2e;
-          a.rec_uvab[k] = make_float4(g.u, g.v, s * ca, -kLog2e * cb);
-          a.rec_cob[k] = make_float4(s * cc, o, __uint_as_float((uint32_t)px0 | ((uint32_t)px1 << 16)),
+          a.rec_uvab[o] = make_float4(g.u, g.v, s * ca, -kLog2e * cb);
+          a.rec_cob[o] = make_float4(s * cc, op, __uint_as_float((uint32_t)px0 | ((uint32_t)px1 << 16)),
                                      __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16)));
-          a.rec_rgbz[k] = make_float4(a.colors[3 * k], a.colors[3 * k + 1], a.colors[3 * k + 2], g.x[2]);
+          a.rec_rgbz[o] = make_float4(a.colors[3 * k], a.colors[3 * k + 1], a.colors[3 * k + 2], g.x[2]);
         }
       }
     }
   }
-  a.rect[k] = rect;
-  a.counts[k] = count;
+  a.rect[o] = rect;
+  a.counts[o] = count;
 }
 
-// Backward of the projection for one Gaussian. g2d holds dL/d(u, v, pa, pb,
-// pc, o, r, g, b, z) accumulated by the compositing backward.
+// Backward of the projection for one (Gaussian, view). g2d holds dL/d(u, v,
+// pa, pb, pc, o, r, g, b, z) accumulated by the compositing backward. Adds to
+// the parameter gradients and returns the pose partials (dL/dR_p, dL/dt).
+__device__ __forceinline__ void chain_one(const Raster& Rr, const PoseF& P, const ProjectBwdArgs& a, int64_t k,
+                                          const float* __restrict__ G2, float gm[3], float gs[3], float gq[4],
+                                          float& go, float gc[3], float pacc[12]) {
+  Geo g;
+  if (!project_geo(Rr, P, a.means, a.scales, a.quats, k, g)) return;
+  const float g_u = G2[0], g_v = G2[1];
+  // stored (pa, pb, pc) = -log2(e) (a/2, b, c/2) for the conic (a, b, c)
+  const float g_a = -0.5f * kLog2e * G2[2];
+  const float g_b = -kLog2e * G2[3];
+  const float g_c = -0.5f * kLog2e * G2[4];
+  go += G2[5];
+  gc[0] += G2[6];
+  gc[1] += G2[7];
+  gc[2] += G2[8];
+  const float g_zd = G2[9];
+  const float idet = 1.f / g.det;
+  const float A00 = g.Syy * idet, A01 = -g.Sxy * idet, A11 = g.Sxx * idet;
+  // dL/dSigma' = -A Mg A with Mg = [[g_a, g_b/2], [g_b/2, g_c]]
+  const float m01 = 0.5f * g_b;
+  const float t00 = A00 * g_a + A01 * m01, t01 = A00 * m01 + A01 * g_c;
+  const float t10 = A01 * g_a + A11 * m01, t11 = A01 * m01 + A11 * g_c;
+  const float G00 = -(t00 * A00 + t01 * A01);
+  const float G01 = -(t00 * A01 + t01 * A11);
+  const float G11 = -(t10 * A01 + t11 * A11);
+  // Sigma' = J Sc J^T:  dL/dSc = J^T G J,  dL/dJ = 2 G J Sc
+  const float J00 = g.J00, J02 = g.J02, J11 = g.J11, J12 = g.J12;
+  const float r0[3] = {J00 * g.Sc[0] + J02 * g.Sc[2], J00 * g.Sc[1] + J02 * g.Sc[4], J00 * g.Sc[2] + J02 * g.Sc[5]};
+  const float r1[3] = {J11 * g.Sc[1] + J12 * g.Sc[2], J11 * g.Sc[3] + J12 * g.Sc[4], J11 * g.Sc[4] + J12 * g.Sc[5]};
+  const float dJ00 = 2.f * (G00 * r0[0] + G01 * r1[0]);
+  const float dJ02 = 2.f * (G00 * r0[2] + G01 * r1[2]);
+  const float dJ11 = 2.f * (G01 * r0[1] + G11 * r1[1]);
+  const float dJ12 = 2.f * (G01 * r0[2] + G11 * r1[2]);
+  // J^T G J for J columns c0 = (J00, 0), c1 = (0, J11), c2 = (J02, J12)
+  float GSc[9];
+  {
+    const float c[3][2] = {{J00, 0.f}, {0.f, J11}, {J02, J12}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        GSc[3 * i + j] = c[i][0] * (G00 * c[j][0] + G01 * c[j][1]) + c[i][1] * (G01 * c[j][0] + G11 * c[j][1]);
+  }
+  const float z = g.x[2], iz = 1.f / z, iz2 = iz * iz;
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  gz += dJ00 * (-Rr.fx * iz2) + dJ11 * (-Rr.fy * iz2);
+  if (!g.clx) {
+    gx += dJ02 * (-Rr.fx * iz2);
+    gz += dJ02 * (2.f * Rr.fx * g.x[0] * iz2 * iz);
+  } else {
+    gz += dJ02 * (Rr.fx * g.Xc * iz2);
+  }
+  if (!g.cly) {
+    gy += dJ12 * (-Rr.fy * iz2);
+    gz += dJ12 * (2.f * Rr.fy * g.x[1] * iz2 * iz);
+  } else {
+    gz += dJ12 * (Rr.fy * g.Yc * iz2);
+  }
+  gx += g_u * Rr.fx * iz;
+  gz += -g_u * Rr.fx * g.x[0] * iz2;
+  gy += g_v * Rr.fy * iz;
+  gz += -g_v * Rr.fy * g.x[1] * iz2;
+  gz += g_zd;
+  // mean: x = R_p mu + t
+#pragma unroll
+  for (int i = 0; i < 3; ++i) gm[i] += P.R[i] * gx + P.R[3 + i] * gy + P.R[6 + i] * gz;
+  // dL/dSigma = R_p^T GSc R_p
+  float U[9], GS[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) U[3 * i + j] = P.R[i] * GSc[j] + P.R[3 + i] * GSc[3 + j] + P.R[6 + i] * GSc[6 + j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) GS[3 * i + j] = U[3 * i] * P.R[j] + U[3 * i + 1] * P.R[3 + j] + U[3 * i + 2] * P.R[6 + j];
+  // Sigma = M M^T, M = R diag(s): dL/dM = 2 GS M
+  float M[9], GM[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[3 * i + j] = g.R[3 * i + j] * g.s[j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      GM[3 * i + j] = 2.f * (GS[3 * i] * M[j] + GS[3 * i + 1] * M[3 + j] + GS[3 * i + 2] * M[6 + j]);
+  float GR[9];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    gs[j] += GM[j] * g.R[j] + GM[3 + j] * g.R[3 + j] + GM[6 + j] * g.R[6 + j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) GR[3 * i + j] = GM[3 * i + j] * g.s[j];
+  }
+  float dq[4];
+  quat_rot_vjp(g.qh, g.inv_qn, GR, dq);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) gq[i] += dq[i];
+  if (a.pose_acc) {
+    // dL/dR_p = gx mu^T + 2 GSc R_p Sigma ;  dL/dt = gx
+    const float mu[3] = {a.means[3 * k], a.means[3 * k + 1], a.means[3 * k + 2]};
+    const float S[9] = {g.Sig[0], g.Sig[1], g.Sig[2], g.Sig[1], g.Sig[3], g.Sig[4], g.Sig[2], g.Sig[4], g.Sig[5]};
+    float RS[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) RS[3 * i + j] = P.R[3 * i] * S[j] + P.R[3 * i + 1] * S[3 + j] + P.R[3 * i + 2] * S[6 + j];
+    const float gxv[3] = {gx, gy, gz};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        pacc[3 * i + j] = gxv[i] * mu[j] + 2.f * (GSc[3 * i] * RS[j] + GSc[3 * i + 1] * RS[3 + j] + GSc[3 * i + 2] * RS[6 + j]);
+    pacc[9] = gx;
+    pacc[10] = gy;
+    pacc[11] = gz;
+  }
+}
+
+// One thread per Gaussian, looping over the views: parameter gradients are the
+// sum over views; pose partials are reduced per view (workgroup sum + one
+// atomic per value).
 __global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a) {
+  __shared__ float red[4][12];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const PoseF P = load_pose(a.pose7);
-  float pacc[12];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
+  for (int v = 0; v < a.n_views; ++v) {
+    const PoseF P = load_pose(a.pose7 + 7 * v);
+    float pacc[12];
 #pragma unroll
-  for (int i = 0; i < 12; ++i) pacc[i] = 0.f;
-  if (k < a.n) {
-    float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.f, gc[3] = {0, 0, 0};
-    Geo g;
-    if (a.counts[k] > 0 && project_geo(Rr, P, a.means, a.scales, a.quats, k, g)) {
-      const float* G2 = a.g2d + 10 * k;
-      const float g_u = G2[0], g_v = G2[1];
-      // stored (pa, pb, pc) = -log2(e) (a/2, b, c/2) for the conic (a, b, c)
-      const float g_a = -0.5f * kLog2e * G2[2];
-      const float g_b = -kLog2e * G2[3];
-      const float g_c = -0.5f * kLog2e * G2[4];
-      go = G2[5];
-      gc[0] = G2[6];
-      gc[1] = G2[7];
-      gc[2] = G2[8];
-      const float g_zd = G2[9];
-      const float idet = 1.f / g.det;
-      const float A00 = g.Syy * idet, A01 = -g.Sxy * idet, A11 = g.Sxx * idet;
-      // dL/dSigma' = -A Mg A with Mg = [[g_a, g_b/2], [g_b/2, g_c]]
-      const float m01 = 0.5f * g_b;
-      const float t00 = A00 * g_a + A01 * m01, t01 = A00 * m01 + A01 * g_c;
-      const float t10 = A01 * g_a + A11 * m01, t11 = A01 * m01 + A11 * g_c;
-      const float G00 = -(t00 * A00 + t01 * A01);
-      const float G01 = -(t00 * A01 + t01 * A11);
-      const float G11 = -(t10 * A01 + t11 * A11);
-      // Sigma' = J Sc J^T:  dL/dSc = J^T G J,  dL/dJ = 2 G J Sc
-      const float J00 = g.J00, J02 = g.J02, J11 = g.J11, J12 = g.J12;
-      // rows of J Sc
-      const float r0[3] = {J00 * g.Sc[0] + J02 * g.Sc[2], J00 * g.Sc[1] + J02 * g.Sc[4], J00 * g.Sc[2] + J02 * g.Sc[5]};
-      const float r1[3] = {J11 * g.Sc[1] + J12 * g.Sc[2], J11 * g.Sc[3] + J12 * g.Sc[4], J11 * g.Sc[4] + J12 * g.Sc[5]};
-      const float dJ00 = 2.f * (G00 * r0[0] + G01 * r1[0]);
-      const float dJ02 = 2.f * (G00 * r0[2] + G01 * r1[2]);
-      const float dJ11 = 2.f * (G01 * r0[1] + G11 * r1[1]);
-      const float dJ12 = 2.f * (G01 * r0[2] + G11 * r1[2]);
-      // J^T G J for J columns c0 = (J00, 0), c1 = (0, J11), c2 = (J02, J12)
-      float GSc[9];
-      {
-        const float c[3][2] = {{J00, 0.f}, {0.f, J11}, {J02, J12}};
+    for (int i = 0; i < 12; ++i) pacc[i] = 0.f;
+    const int64_t o = (int64_t)v * a.n + k;
+    if (k < a.n && a.counts[o] > 0) chain_one(Rr, P, a, k, a.g2d + 10 * o, gm, gs, gq, go, gc, pacc);
+    if (a.pose_acc) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j)
-            GSc[3 * i + j] = c[i][0] * (G00 * c[j][0] + G01 * c[j][1]) + c[i][1] * (G01 * c[j][0] + G11 * c[j][1]);
+      for (int i = 0; i < 12; ++i) {
+        const float s = wave_sum_all(pacc[i]);
+        if (lane == 0) red[w][i] = s;
       }
-      const float z = g.x[2], iz = 1.f / z, iz2 = iz * iz;
-      float gx = 0.f, gy = 0.f, gz = 0.f;
-      gz += dJ00 * (-Rr.fx * iz2) + dJ11 * (-Rr.fy * iz2);
-      if (!g.clx) {
-        gx += dJ02 * (-Rr.fx * iz2);
-        gz += dJ02 * (2.f * Rr.fx * g.x[0] * iz2 * iz);
-      } else {
-        gz += dJ02 * (Rr.fx * g.Xc * iz2);
+      __syncthreads();
+      if (threadIdx.x < 12) {
+        const int nw = (blockDim.x + 63) >> 6;
+        float s = 0.f;
+        for (int i = 0; i < nw; ++i) s += red[i][threadIdx.x];
+        atomicAdd(&a.pose_acc[12 * v + threadIdx.x], s);
       }
-      if (!g.cly) {
-        gy += dJ12 * (-Rr.fy * iz2);
-        gz += dJ12 * (2.f * Rr.fy * g.x[1] * iz2 * iz);
-      } else {
-        gz += dJ12 * (Rr.fy * g.Yc * iz2);
-      }
-      gx += g_u * Rr.fx * iz;
-      gz += -g_u * Rr.fx * g.x[0] * iz2;
-      gy += g_v * Rr.fy * iz;
-      gz += -g_v * Rr.fy * g.x[1] * iz2;
-      gz += g_zd;
-      // mean: x = R_p mu + t
-#pragma unroll
-      for (int i = 0; i < 3; ++i) gm[i] = P.R[i] * gx + P.R[3 + i] * gy + P.R[6 + i] * gz;
-      // dL/dSigma = R_p^T GSc R_p
-      float U[9], GS[9];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) U[3 * i + j] = P.R[i] * GSc[j] + P.R[3 + i] * GSc[3 + j] + P.R[6 + i] * GSc[6 + j];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) GS[3 * i + j] = U[3 * i] * P.R[j] + U[3 * i + 1] * P.R[3 + j] + U[3 * i + 2] * P.R[6 + j];
-      // Sigma = M M^T, M = R diag(s): dL/dM = 2 GS M
-      float M[9], GM[9];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) M[3 * i + j] = g.R[3 * i + j] * g.s[j];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-          GM[3 * i + j] = 2.f * (GS[3 * i] * M[j] + GS[3 * i + 1] * M[3 + j] + GS[3 * i + 2] * M[6 + j]);
-      float GR[9];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        gs[j] = GM[j] * g.R[j] + GM[3 + j] * g.R[3 + j] + GM[6 + j] * g.R[6 + j];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) GR[3 * i + j] = GM[3 * i + j] * g.s[j];
-      }
-      quat_rot_vjp(g.qh, g.inv_qn, GR, gq);
-      if (a.pose_acc) {
-        // dL/dR_p = gx mu^T + 2 GSc R_p Sigma ;  dL/dt = gx
-        const float mu[3] = {a.means[3 * k], a.means[3 * k + 1], a.means[3 * k + 2]};
-        const float S[9] = {g.Sig[0], g.Sig[1], g.Sig[2], g.Sig[1], g.Sig[3], g.Sig[4], g.Sig[2], g.Sig[4], g.Sig[5]};
-        float RS[9];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j) RS[3 * i + j] = P.R[3 * i] * S[j] + P.R[3 * i + 1] * S[3 + j] + P.R[3 * i + 2] * S[6 + j];
-        const float gxv[3] = {gx, gy, gz};
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j)
-            pacc[3 * i + j] = gxv[i] * mu[j] +
-                              2.f * (GSc[3 * i] * RS[j] + GSc[3 * i + 1] * RS[3 + j] + GSc[3 * i + 2] * RS[6 + j]);
-        pacc[9] = gx;
-        pacc[10] = gy;
-        pacc[11] = gz;
-      }
+      __syncthreads();
     }
+  }
+  if (k < a.n) {
     if (a.g_means) {
       a.g_means[3 * k] = gm[0];
       a.g_means[3 * k + 1] = gm[1];
@@ -308,31 +339,19 @@ __global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a
       a.g_colors[3 * k + 2] = gc[2];
     }
   }
-  if (a.pose_acc) {
-    // workgroup reduction of the 12 pose partials, one atomic per value
-    __shared__ float red[4][12];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      const float s = wave_sum_all(pacc[i]);
-      if (lane == 0) red[w][i] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < 12) {
-      const int nw = (blockDim.x + 63) >> 6;
-      float s = 0.f;
-      for (int i = 0; i < nw; ++i) s += red[i][threadIdx.x];
-      atomicAdd(&a.pose_acc[threadIdx.x], s);
-    }
-  }
 }
 
 // From dL/dR_p and dL/dt to the quaternion/translation gradient and the twist
 // of the left perturbation (R <- Exp(phi) R, t <- Exp(phi) t + rho):
 //   dL/drho = dL/dt,   dL/dphi = sum_j R[:, j] x G[:, j] + t x dL/dt.
-__global__ void k_pose_finalize(const float* __restrict__ pose7, const float* __restrict__ acc,
-                                float* __restrict__ dpose7, float* __restrict__ dtwist6) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void k_pose_finalize(const float* __restrict__ poses7, const float* __restrict__ accs,
+                                float* __restrict__ dposes7, float* __restrict__ dtwists6, int n_views) {
+  const int v = threadIdx.x;
+  if (v >= n_views || blockIdx.x != 0) return;
+  const float* pose7 = poses7 + 7 * v;
+  const float* acc = accs + 12 * v;
+  float* dpose7 = dposes7 ? dposes7 + 7 * v : nullptr;
+  float* dtwist6 = dtwists6 ? dtwists6 + 6 * v : nullptr;
   const PoseF P = load_pose(pose7);
   float G[9];
   for (int i = 0; i < 9; ++i) G[i] = acc[i];
@@ -364,7 +383,7 @@ __global__ void k_pose_finalize(const float* __restrict__ pose7, const float* __
 void launch_project(const Raster& R, const ProjectArgs& a, hipStream_t s) {
   if (a.n <= 0) return;
   const int64_t blocks = (a.n + 255) / 256;
-  hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, R, a);
+  hipLaunchKernelGGL(k_project, dim3((unsigned)blocks, (unsigned)a.n_views), dim3(256), 0, s, R, a);
 }
 
 void launch_project_bwd(const Raster& R, const ProjectBwdArgs& a, hipStream_t s) {
@@ -373,8 +392,10 @@ void launch_project_bwd(const Raster& R, const ProjectBwdArgs& a, hipStream_t s)
   hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, R, a);
 }
 
-void launch_pose_finalize(const float* pose7, const float* acc, float* dpose7, float* dtwist6, hipStream_t s) {
-  hipLaunchKernelGGL(k_pose_finalize, dim3(1), dim3(64), 0, s, pose7, acc, dpose7, dtwist6);
+void launch_pose_finalize(const float* pose7, const float* acc, float* dpose7, float* dtwist6, int n_views,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_pose_finalize, dim3(1), dim3(64 * ((n_views + 63) / 64)), 0, s, pose7, acc, dpose7, dtwist6,
+                     n_views);
 }
 
 }  // namespace gsr

@@ -1,10 +1,11 @@
-// Per-tile compositing. One 256-thread workgroup per tile, one pixel per lane.
-// Gaussian records of the tile's depth-sorted list are staged through LDS in
-// batches of 256 (one coalesced fetch per record per workgroup). Each wave
-// then ballots, 64 records at a time, which records' support boxes overlap its
-// own pixel strip, and visits only those, in list order, with the record
-// broadcast from LDS. Skipping a record whose box misses the strip cannot
-// change the result: outside its box a Gaussian has alpha < alpha_min.
+// Per-tile compositing. One 256-thread workgroup per (view, tile) item, one
+// pixel per lane. Gaussian records of the item's depth-sorted list are staged
+// through LDS in batches of 256 (one coalesced fetch per record per
+// workgroup). Each wave then ballots, 64 records at a time, which records'
+// support boxes overlap its own pixel strip, and visits only those, in list
+// order, with the record broadcast from LDS. Skipping a record whose box
+// misses the strip cannot change the result: outside its box a Gaussian has
+// alpha < alpha_min.
 //
 // Forward: front to back (Eq. 3 colour, Eq. 4 alpha, Eq. 6 depth). A lane
 // stops before the Gaussian that would take its transmittance below T_min; a
@@ -16,7 +17,11 @@
 // (1 - alpha_j) instead of being stored; suffix sums of c alpha T and z alpha T
 // give the second terms of dC/dalpha and Eq. 8. The ten per-Gaussian partials
 // of a wave are summed with a field-splitting butterfly and added to the
-// [n, 10] gradient buffer with one 10-lane atomic per (Gaussian, wave).
+// [V n, 10] gradient buffer with one 10-lane atomic per (Gaussian, wave).
+//
+// Launch shapes: one workgroup per item (items dealt to XCDs in contiguous
+// runs), or a persistent grid whose workgroups pull items from a counter in
+// longest-list-first order until the queue is empty (multi-keyframe mapping).
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -27,14 +32,35 @@ struct Strip {
   int x0, x1, y0, y1;  // inclusive pixel rectangle of a wave
 };
 
-__device__ __forceinline__ Strip wave_strip(const Raster& Rr, int txi, int tyi, int wave) {
+struct Pixel {
+  int tile, view;
+  int px, py;
+  bool inside;
+  float fpx, fpy;
+  int64_t p;    // pixel index inside the view
+  int64_t off;  // view * W * H
+  Strip strip;
+};
+
+__device__ __forceinline__ Pixel item_pixel(const Raster& Rr, int item) {
+  Pixel q;
+  q.view = item / Rr.n_tiles;
+  q.tile = item - q.view * Rr.n_tiles;
+  const int tyi = q.tile / Rr.ntx, txi = q.tile - tyi * Rr.ntx;
+  const int tid = threadIdx.x;
+  q.px = txi * Rr.tw + (tid & (Rr.tw - 1));
+  q.py = tyi * Rr.th + (tid >> Rr.tw_log2);
+  q.inside = q.px < Rr.W && q.py < Rr.H;
+  q.fpx = (float)q.px;
+  q.fpy = (float)q.py;
+  q.p = (int64_t)q.py * Rr.W + q.px;
+  q.off = (int64_t)q.view * Rr.W * Rr.H;
   const int rows = kWave >> Rr.tw_log2;  // pixel rows per wave
-  Strip s;
-  s.x0 = txi * Rr.tw;
-  s.x1 = s.x0 + Rr.tw - 1;
-  s.y0 = tyi * Rr.th + wave * rows;
-  s.y1 = s.y0 + rows - 1;
-  return s;
+  q.strip.x0 = txi * Rr.tw;
+  q.strip.x1 = q.strip.x0 + Rr.tw - 1;
+  q.strip.y0 = tyi * Rr.th + (tid >> 6) * rows;
+  q.strip.y1 = q.strip.y0 + rows - 1;
+  return q;
 }
 
 // Does the packed support box (bx = x0 | x1 << 16, by = y0 | y1 << 16) meet the strip?
@@ -49,57 +75,30 @@ __device__ __forceinline__ bool box_holds(float fbx, float fby, int px, int py) 
   return px >= (int)(bx & 0xffffu) && px <= (int)(bx >> 16) && py >= (int)(by & 0xffffu) && py <= (int)(by >> 16);
 }
 
+struct FwdSmem {
+  float4 uvab[kTileThreads];
+  float4 cob[kTileThreads];
+  float4 rgbz[kTileThreads];
+};
+
+struct BwdSmem {
+  float4 uvab[kTileThreads];
+  float4 cob[kTileThreads];
+  float4 rgbz[kTileThreads];
+  uint32_t gid[kTileThreads];
+  int max_last;
+};
+
 // STATS = true: instead of writing outputs, count the algorithmic work (for the
 // benchmark's roofline): pairs whose pixel lies in the Gaussian's support box
-// before the pixel stops (forward), pairs composited, and pairs in the support
-// box before each pixel's last composited Gaussian (what the backward must
-// evaluate). Same control flow as the rendering launch.
+// before the pixel stops, and pairs composited.
 template <bool STATS>
-__global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs a);
-
-// Backward-pair counting needs the final `last`; done in a second sweep.
-__global__ __launch_bounds__(kTileThreads) void k_count_bwd_pairs(Raster Rr, FwdArgs a) {
-  __shared__ float4 s_cob[kTileThreads];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tyi = tile / Rr.ntx, txi = tile - tyi * Rr.ntx;
-  const int tid = threadIdx.x;
-  const int px = txi * Rr.tw + (tid & (Rr.tw - 1));
-  const int py = tyi * Rr.th + (tid >> Rr.tw_log2);
-  const bool inside = px < Rr.W && py < Rr.H;
-  const int last = inside ? a.last[(int64_t)py * Rr.W + px] : 0;
-  const int2 rg = a.ranges[tile];
-  unsigned long long n = 0;
-  for (int base = rg.x; base < rg.y; base += kTileThreads) {
-    __syncthreads();
-    if (base + tid < rg.y) s_cob[tid] = a.rec_cob[a.ids[base + tid]];
-    __syncthreads();
-    const int cnt = min(kTileThreads, rg.y - base);
-    for (int j = 0; j < cnt; ++j)
-      if (base - rg.x + j < last && box_holds(s_cob[j].z, s_cob[j].w, px, py)) ++n;
-  }
-  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
-  if ((tid & 63) == 0) atomicAdd(&a.stats[2], n);
-}
-
-// STATS = true: count work instead of writing outputs (see above).
-template <bool STATS>
-__global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs a) {
-  __shared__ float4 s_uvab[kTileThreads];
-  __shared__ float4 s_cob[kTileThreads];
-  __shared__ float4 s_rgbz[kTileThreads];
-
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tyi = tile / Rr.ntx, txi = tile - tyi * Rr.ntx;
+__device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int item, FwdSmem& sm) {
   const int tid = threadIdx.x, lane = tid & 63;
-  const int px = txi * Rr.tw + (tid & (Rr.tw - 1));
-  const int py = tyi * Rr.th + (tid >> Rr.tw_log2);
-  const bool inside = px < Rr.W && py < Rr.H;
-  const float fpx = (float)px, fpy = (float)py;
-  const Strip strip = wave_strip(Rr, txi, tyi, tid >> 6);
-
-  const int2 rg = a.ranges[tile];
+  const Pixel q = item_pixel(Rr, item);
+  const int2 rg = a.ranges[item];
   const int start = rg.x, end = rg.y;
-  bool done = !inside;
+  bool done = !q.inside;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   int last = 0;
   uint32_t n_eval = 0, n_comp = 0;
@@ -109,9 +108,9 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
     const int i = base + tid;
     if (i < end) {
       const uint32_t gid = a.ids[i];
-      s_uvab[tid] = a.rec_uvab[gid];
-      s_cob[tid] = a.rec_cob[gid];
-      s_rgbz[tid] = a.rec_rgbz[gid];
+      sm.uvab[tid] = a.rec_uvab[gid];
+      sm.cob[tid] = a.rec_cob[gid];
+      sm.rgbz[tid] = a.rec_rgbz[gid];
     }
     __syncthreads();
     if (!__any(!done)) continue;
@@ -121,24 +120,24 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
       const int r = c * kWave + lane;
       bool meets = false;
       if (r < cnt) {
-        const float4 cb = s_cob[r];
-        meets = box_meets(cb.z, cb.w, strip);
+        const float4 cb = sm.cob[r];
+        meets = box_meets(cb.z, cb.w, q.strip);
       }
       uint64_t m = __ballot(meets);
       while (m) {
         const int j = c * kWave + __builtin_ctzll(m);
         m &= m - 1;
         if (!done) {
-          const float4 g = s_uvab[j];
-          const float4 cb = s_cob[j];
-          const PairEval pe = eval_pair(fpx - g.x, fpy - g.y, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
-          if (STATS && box_holds(cb.z, cb.w, px, py)) ++n_eval;
+          const float4 g = sm.uvab[j];
+          const float4 cb = sm.cob[j];
+          const PairEval pe = eval_pair(q.fpx - g.x, q.fpy - g.y, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
+          if (STATS && box_holds(cb.z, cb.w, q.px, q.py)) ++n_eval;
           if (pe.use) {
             const float Tn = T * (1.f - pe.alpha);
             if (Tn < Rr.tmin) {
               done = true;
             } else {
-              const float4 cz = s_rgbz[j];
+              const float4 cz = sm.rgbz[j];
               const float w = pe.alpha * T;
               C0 = fmaf(cz.x, w, C0);
               C1 = fmaf(cz.y, w, C1);
@@ -158,7 +157,6 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
     }
   }
   if (STATS) {
-    // counters: [0] support-box pairs before stopping, [1] composited pairs
     unsigned long long e = n_eval, cm = n_comp;
     for (int o = 32; o > 0; o >>= 1) {
       e += __shfl_xor(e, o, 64);
@@ -170,12 +168,13 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
     }
     return;
   }
-  if (inside) {
+  if (q.inside) {
     const int64_t P = (int64_t)Rr.W * Rr.H;
-    const int64_t p = (int64_t)py * Rr.W + px;
-    a.color[p] = fmaf(T, Rr.bg0, C0);
-    a.color[P + p] = fmaf(T, Rr.bg1, C1);
-    a.color[2 * P + p] = fmaf(T, Rr.bg2, C2);
+    const int64_t p = q.off + q.p;
+    float* col = a.color + 3 * q.off;
+    col[q.p] = fmaf(T, Rr.bg0, C0);
+    col[P + q.p] = fmaf(T, Rr.bg1, C1);
+    col[2 * P + q.p] = fmaf(T, Rr.bg2, C2);
     a.depth[p] = D;
     a.alpha[p] = 1.f - T;
     a.Tfin[p] = T;
@@ -183,32 +182,20 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
   }
 }
 
-__global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs a) {
-  __shared__ float4 s_uvab[kTileThreads];
-  __shared__ float4 s_cob[kTileThreads];
-  __shared__ float4 s_rgbz[kTileThreads];
-  __shared__ uint32_t s_gid[kTileThreads];
-  __shared__ int s_max;
-
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tyi = tile / Rr.ntx, txi = tile - tyi * Rr.ntx;
+__device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int item, BwdSmem& sm) {
   const int tid = threadIdx.x, lane = tid & 63;
-  const int px = txi * Rr.tw + (tid & (Rr.tw - 1));
-  const int py = tyi * Rr.th + (tid >> Rr.tw_log2);
-  const bool inside = px < Rr.W && py < Rr.H;
-  const float fpx = (float)px, fpy = (float)py;
+  const Pixel q = item_pixel(Rr, item);
   const int64_t P = (int64_t)Rr.W * Rr.H;
-  const int64_t p = (int64_t)py * Rr.W + px;
-  const Strip strip = wave_strip(Rr, txi, tyi, tid >> 6);
-
   float T = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gd = 0.f, ga = 0.f;
   int last = 0;
-  if (inside) {
+  if (q.inside) {
+    const int64_t p = q.off + q.p;
+    const float* gC = a.gC + 3 * q.off;
     T = a.Tfin[p];
     last = a.last[p];
-    g0 = a.gC[p];
-    g1 = a.gC[P + p];
-    g2 = a.gC[2 * P + p];
+    g0 = gC[q.p];
+    g1 = gC[P + q.p];
+    g2 = gC[2 * P + q.p];
     gd = a.gD[p];
     ga = a.gA ? a.gA[p] : 0.f;
   }
@@ -216,13 +203,14 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
   // suffix sums: the background enters dC/dalpha through T_final * bg
   float S0 = T * Rr.bg0, S1 = T * Rr.bg1, S2 = T * Rr.bg2, SD = 0.f;
 
-  if (tid == 0) s_max = 0;
+  __syncthreads();  // the previous item (persistent launch) is done with max_last
+  if (tid == 0) sm.max_last = 0;
   __syncthreads();
-  if (last > 0) atomicMax(&s_max, last);
+  if (last > 0) atomicMax(&sm.max_last, last);
   const int wmax = wave_max_int(last);
   __syncthreads();
-  const int bmax = s_max;
-  const int start = a.ranges[tile].x;
+  const int bmax = sm.max_last;
+  const int start = a.ranges[item].x;
 
   for (int bend = start + bmax; bend > start; bend -= kTileThreads) {
     const int bstart = max(start, bend - kTileThreads);
@@ -230,10 +218,10 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
     const int i = bstart + tid;
     if (i < bend) {
       const uint32_t gid = a.ids[i];
-      s_gid[tid] = gid;
-      s_uvab[tid] = a.rec_uvab[gid];
-      s_cob[tid] = a.rec_cob[gid];
-      s_rgbz[tid] = a.rec_rgbz[gid];
+      sm.gid[tid] = gid;
+      sm.uvab[tid] = a.rec_uvab[gid];
+      sm.cob[tid] = a.rec_cob[gid];
+      sm.rgbz[tid] = a.rec_rgbz[gid];
     }
     __syncthreads();
     const int cnt = min(bend, start + wmax) - bstart;  // records this wave may need
@@ -241,8 +229,8 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
       const int r = c * kWave + lane;
       bool meets = false;
       if (r < cnt) {
-        const float4 cb = s_cob[r];
-        meets = box_meets(cb.z, cb.w, strip);
+        const float4 cb = sm.cob[r];
+        meets = box_meets(cb.z, cb.w, q.strip);
       }
       uint64_t m = __ballot(meets);
       while (m) {
@@ -255,13 +243,13 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
         for (int f = 0; f < 10; ++f) v[f] = 0.f;
         bool hit = false;
         if (pos < last) {
-          const float4 g = s_uvab[li];
-          const float4 cb = s_cob[li];
-          const float dx = fpx - g.x, dy = fpy - g.y;
+          const float4 g = sm.uvab[li];
+          const float4 cb = sm.cob[li];
+          const float dx = q.fpx - g.x, dy = q.fpy - g.y;
           const PairEval pe = eval_pair(dx, dy, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
           if (pe.use) {
             hit = true;
-            const float4 cz = s_rgbz[li];
+            const float4 cz = sm.rgbz[li];
             const float inv = 1.f / (1.f - pe.alpha);
             const float Tj = T * inv;
             const float w = pe.alpha * Tj;
@@ -289,24 +277,134 @@ __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs 
             }
           }
         }
-        if (__any(hit)) wave_add10(v, a.g2d + 10 * (int64_t)s_gid[li], lane);
+        if (__any(hit)) wave_add10(v, a.g2d + 10 * (int64_t)sm.gid[li], lane);
       }
     }
   }
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs a) {
+  __shared__ FwdSmem sm;
+  fwd_item<STATS>(Rr, a, xcd_tile(blockIdx.x, gridDim.x), sm);
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs a) {
+  __shared__ BwdSmem sm;
+  bwd_item(Rr, a, xcd_tile(blockIdx.x, gridDim.x), sm);
+}
+
+// Persistent workgroups: take the next item from the queue until it is empty.
+// Every workgroup reaches the exit once the counter passes n_items.
+__device__ __forceinline__ int next_item(int* queue, const int* order, int n_items, int* s_item) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_item = atomicAdd(queue, 1);
+  __syncthreads();
+  const int qi = *s_item;
+  if (qi >= n_items) return -1;
+  return order ? order[qi] : qi;
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_render_fwd_persistent(Raster Rr, FwdArgs a) {
+  __shared__ FwdSmem sm;
+  __shared__ int s_item;
+  for (;;) {
+    const int item = next_item(a.queue, a.order, a.n_items, &s_item);
+    if (item < 0) break;
+    fwd_item<false>(Rr, a, item, sm);
+  }
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_render_bwd_persistent(Raster Rr, BwdArgs a) {
+  __shared__ BwdSmem sm;
+  __shared__ int s_item;
+  for (;;) {
+    const int item = next_item(a.queue, a.order, a.n_items, &s_item);
+    if (item < 0) break;
+    bwd_item(Rr, a, item, sm);
+  }
+}
+
+// Support-box pairs before each pixel's last composited Gaussian: the pairs
+// the backward must evaluate (work counter; reads the forward's `last`).
+__global__ __launch_bounds__(kTileThreads) void k_count_bwd_pairs(Raster Rr, FwdArgs a) {
+  __shared__ float4 s_cob[kTileThreads];
+  const int item = blockIdx.x;
+  const Pixel q = item_pixel(Rr, item);
+  const int last = q.inside ? a.last[q.off + q.p] : 0;
+  const int2 rg = a.ranges[item];
+  unsigned long long n = 0;
+  for (int base = rg.x; base < rg.y; base += kTileThreads) {
+    __syncthreads();
+    if (base + (int)threadIdx.x < rg.y) s_cob[threadIdx.x] = a.rec_cob[a.ids[base + threadIdx.x]];
+    __syncthreads();
+    const int cnt = min(kTileThreads, rg.y - base);
+    for (int j = 0; j < cnt; ++j)
+      if (base - rg.x + j < last && box_holds(s_cob[j].z, s_cob[j].w, q.px, q.py)) ++n;
+  }
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&a.stats[2], n);
+}
+
+// Longest-list-first item order: bucket items by floor(log2(len + 1)) and
+// emit the buckets from the longest down (order inside a bucket is arbitrary).
+__global__ void k_order_hist(const int2* __restrict__ ranges, int n_items, int* __restrict__ temp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const int2 r = ranges[i];
+  const int b = 31 - __clz(r.y - r.x + 1);
+  atomicAdd(&temp[b], 1);
+}
+
+__global__ void k_order_scan(int* temp) {
+  if (threadIdx.x != 0) return;
+  int s = 0;
+  for (int b = 31; b >= 0; --b) {
+    const int c = temp[b];
+    temp[32 + b] = s;
+    s += c;
+  }
+}
+
+__global__ void k_order_scatter(const int2* __restrict__ ranges, int n_items, int* __restrict__ temp,
+                                int* __restrict__ order) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const int2 r = ranges[i];
+  const int b = 31 - __clz(r.y - r.x + 1);
+  const int pos = atomicAdd(&temp[32 + b], 1);
+  order[pos] = i;
 }
 
 }  // namespace
 
 void launch_render_fwd(const Raster& R, const FwdArgs& a, hipStream_t s) {
   if (a.stats) {
-    hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
-    hipLaunchKernelGGL(k_count_bwd_pairs, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
-  } else
-    hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
+    hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)a.n_items), dim3(kTileThreads), 0, s, R, a);
+    hipLaunchKernelGGL(k_count_bwd_pairs, dim3((unsigned)a.n_items), dim3(kTileThreads), 0, s, R, a);
+  } else if (a.blocks > 0) {
+    launch_fill_u32(reinterpret_cast<uint32_t*>(a.queue), 0u, 1, s);
+    hipLaunchKernelGGL(k_render_fwd_persistent, dim3((unsigned)a.blocks), dim3(kTileThreads), 0, s, R, a);
+  } else {
+    hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)a.n_items), dim3(kTileThreads), 0, s, R, a);
+  }
 }
 
 void launch_render_bwd(const Raster& R, const BwdArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)R.n_tiles), dim3(kTileThreads), 0, s, R, a);
+  if (a.blocks > 0) {
+    launch_fill_u32(reinterpret_cast<uint32_t*>(a.queue), 0u, 1, s);
+    hipLaunchKernelGGL(k_render_bwd_persistent, dim3((unsigned)a.blocks), dim3(kTileThreads), 0, s, R, a);
+  } else {
+    hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)a.n_items), dim3(kTileThreads), 0, s, R, a);
+  }
+}
+
+void launch_item_order(const int2* ranges, int n_items, int* order, int* temp, hipStream_t s) {
+  launch_fill_u32(reinterpret_cast<uint32_t*>(temp), 0u, 64, s);
+  const unsigned g = (unsigned)((n_items + 255) / 256);
+  hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, s, ranges, n_items, temp);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, temp);
+  hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, s, ranges, n_items, temp, order);
 }
 
 }  // namespace gsr

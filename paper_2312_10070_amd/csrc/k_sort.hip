@@ -105,8 +105,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
 // so the bits order like the values); value = Gaussian index. Writing in
 // index order makes the stable sort break depth ties by index.
 __global__ __launch_bounds__(256) void k_duplicate(Raster Rr, BinArgs a) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.n) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // view * n + Gaussian
+  if (k >= a.n * a.n_views) return;
   const uint32_t cnt = a.counts[k];
   if (cnt == 0) return;
   const uint64_t off = a.offsets[k];
@@ -116,12 +116,13 @@ __global__ __launch_bounds__(256) void k_duplicate(Raster Rr, BinArgs a) {
   }
   const int4 r = a.rect[k];
   const uint32_t zb = __float_as_uint(a.rec_rgbz[k].w);
+  const uint32_t tile_base = (uint32_t)(k / a.n) * (uint32_t)Rr.n_tiles;
   uint64_t* kp = a.keys + off;
   uint32_t* vp = a.vals + off;
   int i = 0;
   for (int ty = r.y; ty <= r.w; ++ty)
     for (int tx = r.x; tx <= r.z; ++tx) {
-      const uint32_t tile = a.tile_base + (uint32_t)(ty * Rr.ntx + tx);
+      const uint32_t tile = tile_base + (uint32_t)(ty * Rr.ntx + tx);
       kp[i] = ((uint64_t)tile << 32) | zb;
       vp[i] = (uint32_t)k;
       ++i;
@@ -251,8 +252,9 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_
 }
 
 void launch_duplicate(const Raster& R, const BinArgs& a, hipStream_t s) {
-  if (a.n <= 0) return;
-  hipLaunchKernelGGL(k_duplicate, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, R, a);
+  const int64_t m = a.n * a.n_views;
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_duplicate, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, R, a);
 }
 
 int64_t radix_temp_words(int64_t cap) {

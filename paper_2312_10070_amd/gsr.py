@@ -69,6 +69,11 @@ _SIGS = {
     "gsr_render_fwd": (ctypes.c_int, [P, ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), ctypes.POINTER(Opts), P,
                                       P, P, P, ctypes.POINTER(P)]),
     "gsr_render_bwd": (ctypes.c_int, [P, P, P, P, P, ctypes.POINTER(Grads), P, P]),
+    "gsr_render_fwd_batch": (ctypes.c_int, [P, ctypes.POINTER(Gaussians), ctypes.c_int32, ctypes.POINTER(Camera),
+                                            ctypes.POINTER(Opts), ctypes.c_int32, P, P, P, P, ctypes.POINTER(P)]),
+    "gsr_autotune_batch": (ctypes.c_int, [P, ctypes.POINTER(Gaussians), ctypes.c_int32, ctypes.POINTER(Camera),
+                                          ctypes.POINTER(Opts), P, P, P, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32), P]),
     "gsr_state_release": (ctypes.c_int, [P, P]),
     "gsr_tile_lists": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_int64), P, P]),
     "gsr_loss_l1": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P]),
@@ -236,6 +241,54 @@ def render_fwd(means, scales, quats, opacities, colors, pose7, camera: Camera, o
     return color, depth, alpha, state
 
 
+def render_fwd_batch(means, scales, quats, opacities, colors, poses7, camera: Camera, opts: RasterOpts | None = None,
+                     blocks_per_cu: int = 0, ctx: Context | None = None):
+    """Batched forward over V views (poses7 [V,7]); returns color [V,3,H,W], depth, alpha [V,H,W], State."""
+    ctx = ctx or Context.get(means.device.index or 0)
+    ctx.sync_stream()
+    opts = opts or RasterOpts()
+    g = _gaussians(means, scales, quats, opacities, colors)
+    V = poses7.shape[0]
+    _f32(poses7, "poses7", (V, 7))
+    H, W = camera.height, camera.width
+    dev = means.device
+    color = torch.empty((V, 3, H, W), device=dev, dtype=torch.float32)
+    depth = torch.empty((V, H, W), device=dev, dtype=torch.float32)
+    alpha = torch.empty((V, H, W), device=dev, dtype=torch.float32)
+    st = P()
+    oc = opts.c()
+    ctx.check(ctx.lib.gsr_render_fwd_batch(ctx.h, ctypes.byref(g), V, ctypes.byref(camera), ctypes.byref(oc),
+                                           int(blocks_per_cu), _ptr(poses7), _ptr(color), _ptr(depth), _ptr(alpha),
+                                           ctypes.byref(st)))
+    state = State(ctx, st, (means, scales, quats, opacities, colors, poses7))
+    state.shape = (H, W)
+    state.views = V
+    return color, depth, alpha, state
+
+
+def autotune_batch(means, scales, quats, opacities, colors, poses7, camera: Camera, dL_dcolor, dL_ddepth,
+                   opts: RasterOpts | None = None, reps: int = 3, ctx: Context | None = None):
+    """Returns (RasterOpts with the fastest tile shape, blocks_per_cu, {(tw, th, bpc): ms})."""
+    import numpy as np
+    ctx = ctx or Context.get(means.device.index or 0)
+    ctx.sync_stream()
+    opts = opts or RasterOpts()
+    g = _gaussians(means, scales, quats, opacities, colors)
+    V = poses7.shape[0]
+    oc = opts.c()
+    bpc = ctypes.c_int32()
+    table = np.zeros(15, np.float32)
+    ctx.check(ctx.lib.gsr_autotune_batch(ctx.h, ctypes.byref(g), V, ctypes.byref(camera), ctypes.byref(oc),
+                                         _ptr(poses7), _ptr(_f32(dL_dcolor, "dL_dcolor")),
+                                         _ptr(_f32(dL_ddepth, "dL_ddepth")), int(reps), ctypes.byref(bpc),
+                                         table.ctypes.data_as(P)))
+    best = RasterOpts(opts.lowpass, opts.alpha_min, opts.alpha_max, opts.T_min, opts.guard, oc.tile_w, oc.tile_h)
+    shapes = [(16, 16), (8, 32), (32, 8)]
+    bpcs = [0, 1, 2, 4, 8]
+    timings = {(shapes[i // 5][0], shapes[i // 5][1], bpcs[i % 5]): float(table[i]) for i in range(15)}
+    return best, int(bpc.value), timings
+
+
 def render_bwd(state: State, dL_dcolor, dL_ddepth, dL_dalpha=None, want_params=True, want_pose=True):
     """Backward; returns dict of gradients (means, scales, quats, opacities, colors, pose7, twist6)."""
     ctx = state.ctx
@@ -255,8 +308,9 @@ def render_bwd(state: State, dL_dcolor, dL_ddepth, dL_dalpha=None, want_params=T
     else:
         gr = Grads()
     if want_pose:
-        out["pose7"] = torch.empty(7, device=dev, dtype=torch.float32)
-        out["twist6"] = torch.empty(6, device=dev, dtype=torch.float32)
+        V = getattr(state, "views", None)
+        out["pose7"] = torch.empty((7,) if V is None else (V, 7), device=dev, dtype=torch.float32)
+        out["twist6"] = torch.empty((6,) if V is None else (V, 6), device=dev, dtype=torch.float32)
     ctx.check(ctx.lib.gsr_render_bwd(ctx.h, state.h, _ptr(gC), _ptr(gD), _ptr(gA), ctypes.byref(gr),
                                      _ptr(out.get("pose7")), _ptr(out.get("twist6"))))
     return out
