@@ -220,6 +220,45 @@ int gsr_track_graph_set_frame(gsr_ctx *ctx, gsr_track_graph *tg, const float *ob
 int gsr_track_graph_run(gsr_ctx *ctx, gsr_track_graph *tg, float *pose7, float *losses);
 int gsr_track_graph_destroy(gsr_ctx *ctx, gsr_track_graph *tg);
 
+/* Learned tracking initialisation ------------------------------------------
+ * A small CNN that proposes a pose correction from the render at the current
+ * pose and the observed frame. Input: 8 channels at 160 x 120 (rendered RGB,
+ * rendered depth x depth_scale, observed RGB, observed depth x depth_scale,
+ * f x f average-pooled from the full frames). Four 3x3 stride-2 convolutions
+ * with 64 channels and ReLU (implicit GEMMs on the BF16 matrix cores, FP32
+ * accumulation, BF16 activations), global average pooling, linear head to 6
+ * outputs (the twist (rho, phi) of a left perturbation). The paper suggests
+ * learned components in its limitations (Sec. 5) and uses a loss-judged
+ * alternative initialiser in its supplement; this network is such an
+ * initialiser, judged against constant-speed init by the tracking loss. */
+typedef struct gsr_initnet gsr_initnet;
+
+int gsr_initnet_create(gsr_ctx *ctx, int32_t max_batch, gsr_initnet **out);
+int gsr_initnet_destroy(gsr_ctx *ctx, gsr_initnet *net);
+/* Flat FP32 parameters and gradients (device, count floats), in order:
+ * per layer l = 0..3: W_l [64][KP_l] (K ordered (3 ky + kx, channel),
+ * KP_0 = 96 with 24 zero pad columns, KP_1..3 = 576), b_l [64]; then the head
+ * W_fc [6][64], b_fc [6]. The caller initialises them (zero after create). */
+int gsr_initnet_params(gsr_ctx *ctx, gsr_initnet *net, float **params, float **grads, int64_t *count);
+/* Device pointers of layer l's activation (l = 0: the packed input, BF16
+ * NHWC [B,120,160,8]; l = 1..4: post-ReLU outputs [B,H_l,W_l,64]) and of the
+ * gradient w.r.t. layer l's pre-activation (l >= 1) after a backward. */
+int gsr_initnet_activation(gsr_ctx *ctx, gsr_initnet *net, int32_t layer, uint16_t **act, uint16_t **dact);
+/* Pack one sample (input slot `slot`) from full-resolution frames (W = 160 f,
+ * H = 120 f). */
+int gsr_initnet_input(gsr_ctx *ctx, gsr_initnet *net, int32_t slot, const float *rend_color, const float *rend_depth,
+                      const float *obs_color, const float *obs_depth, int32_t H, int32_t W, float depth_scale);
+/* Forward of slots 0..batch-1 with the current parameters; out: device [B,6] or NULL. */
+int gsr_initnet_forward(gsr_ctx *ctx, gsr_initnet *net, int32_t batch, float *out);
+/* Backward of the last forward: with dL_dout == NULL the loss is
+ * L = 1/(2B) sum_b sum_j ((out - label) / scale_j)^2 (labels [B,6], scale [6],
+ * device; L written to *loss if non-NULL), else dL_dout [B,6] is used.
+ * Overwrites the gradient buffer. */
+int gsr_initnet_backward(gsr_ctx *ctx, gsr_initnet *net, int32_t batch, const float *labels, const float *scale,
+                         const float *dL_dout, float *loss);
+/* Adam step on all parameters (bias-corrected, internal step count). */
+int gsr_initnet_adam(gsr_ctx *ctx, gsr_initnet *net, float lr, float beta1, float beta2, float eps);
+
 /* Measurement ------------------------------------------------------------ */
 
 /* Stage timing for benchmarks: while enabled, every stage a call enqueues

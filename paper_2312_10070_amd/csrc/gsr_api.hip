@@ -65,6 +65,30 @@ struct gsr_track_graph {
   int* h_flag = nullptr;
 };
 
+// Tracking-initialisation network: FP32 master parameters (flat), BF16
+// working copies, activations and gradients for up to max_batch samples.
+struct gsr_initnet {
+  static constexpr int kLayers = 4;
+  static constexpr int kInH = 120, kInW = 160, kInC = 8, kCh = 64;
+  gsr_ctx* ctx = nullptr;
+  int max_batch = 0;
+  void* buf = nullptr;
+  int64_t n_params = 0;
+  float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+  float* w[kLayers] = {};   // into params
+  float* b[kLayers] = {};
+  float* dw[kLayers] = {};  // into grads
+  float* db[kLayers] = {};
+  float *wfc = nullptr, *bfc = nullptr, *dwfc = nullptr, *dbfc = nullptr;
+  uint16_t* wk[kLayers] = {};
+  uint16_t* wt[kLayers] = {};
+  uint16_t* act[kLayers + 1] = {};  // act[0] = packed input
+  uint16_t* dact[kLayers + 1] = {}; // gradient w.r.t. each layer's pre-activation (masked)
+  int H[kLayers + 1] = {}, W[kLayers + 1] = {}, C[kLayers + 1] = {};
+  float *pool = nullptr, *out = nullptr, *scratch = nullptr;
+  int64_t step = 0;
+};
+
 struct gsr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -636,6 +660,173 @@ int gsr_autotune_batch(gsr_ctx* c, const gsr_gaussians* g, int32_t n_views, cons
   opts->tile_h = shapes[best_s][1];
   *best_blocks_per_cu = bpc[best_b];
   return GSR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tracking-initialisation network
+// ---------------------------------------------------------------------------
+
+int gsr_initnet_destroy(gsr_ctx* c, gsr_initnet* net) {
+  if (!c || !net || net->ctx != c) return fail(c, GSR_EINVAL, "invalid network");
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (net->buf) (void)hipFree(net->buf);
+  delete net;
+  return GSR_OK;
+}
+
+int gsr_initnet_create(gsr_ctx* c, int32_t max_batch, gsr_initnet** out) {
+  if (!c || !out || max_batch < 1 || max_batch > 4096) return fail(c, GSR_EINVAL, "max_batch must be in [1, 4096]");
+  *out = nullptr;
+  GSR_HIP(c, hipSetDevice(c->device));
+  gsr_initnet* net = new (std::nothrow) gsr_initnet();
+  if (!net) return fail(c, GSR_ENOMEM, "host allocation failed");
+  net->ctx = c;
+  net->max_batch = max_batch;
+  using N = gsr_initnet;
+  net->H[0] = N::kInH;
+  net->W[0] = N::kInW;
+  net->C[0] = N::kInC;
+  for (int l = 1; l <= N::kLayers; ++l) {
+    net->H[l] = (net->H[l - 1] + 1) / 2;
+    net->W[l] = (net->W[l - 1] + 1) / 2;
+    net->C[l] = N::kCh;
+  }
+  int64_t np = 0;
+  for (int l = 0; l < N::kLayers; ++l) np += (int64_t)N::kCh * gsr::conv_kp(net->C[l]) + N::kCh;
+  np += 6 * N::kCh + 6;
+  net->n_params = np;
+  const int64_t B = max_batch;
+  size_t bytes = 0;
+  auto carve = [&](char* base) {
+    Carver cv{base};
+    net->params = cv.take<float>(np);
+    net->grads = cv.take<float>(np);
+    net->m = cv.take<float>(np);
+    net->v = cv.take<float>(np);
+    for (int l = 0; l < N::kLayers; ++l) {
+      net->wk[l] = cv.take<uint16_t>((int64_t)N::kCh * gsr::conv_kp(net->C[l]));
+      net->wt[l] = cv.take<uint16_t>((int64_t)net->C[l] * 9 * N::kCh);
+    }
+    for (int l = 0; l <= N::kLayers; ++l) {
+      const int64_t sz = B * net->H[l] * net->W[l] * net->C[l];
+      net->act[l] = cv.take<uint16_t>(sz);
+      net->dact[l] = cv.take<uint16_t>(sz);
+    }
+    net->pool = cv.take<float>(B * N::kCh);
+    net->out = cv.take<float>(B * 6);
+    net->scratch = cv.take<float>(B * 6 + 64);
+    bytes = cv.off;
+  };
+  carve(nullptr);
+  if (hipMalloc(&net->buf, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete net;
+    return fail(c, GSR_ENOMEM, "device allocation of the network failed");
+  }
+  carve((char*)net->buf);
+  float* p = net->params;
+  float* g = net->grads;
+  for (int l = 0; l < N::kLayers; ++l) {
+    const int64_t nw = (int64_t)N::kCh * gsr::conv_kp(net->C[l]);
+    net->w[l] = p;
+    net->dw[l] = g;
+    p += nw;
+    g += nw;
+    net->b[l] = p;
+    net->db[l] = g;
+    p += N::kCh;
+    g += N::kCh;
+  }
+  net->wfc = p;
+  net->dwfc = g;
+  net->bfc = p + 6 * N::kCh;
+  net->dbfc = g + 6 * N::kCh;
+  for (float* q : {net->params, net->grads, net->m, net->v}) gsr::launch_fill_f32(q, 0.f, np, c->stream);
+  *out = net;
+  return check_launch(c, "gsr_initnet_create");
+}
+
+int gsr_initnet_params(gsr_ctx* c, gsr_initnet* net, float** params, float** grads, int64_t* count) {
+  if (!c || !net || net->ctx != c || !count) return fail(c, GSR_EINVAL, "invalid network");
+  if (params) *params = net->params;
+  if (grads) *grads = net->grads;
+  *count = net->n_params;
+  return GSR_OK;
+}
+
+int gsr_initnet_activation(gsr_ctx* c, gsr_initnet* net, int32_t layer, uint16_t** act, uint16_t** dact) {
+  if (!c || !net || net->ctx != c || layer < 0 || layer > gsr_initnet::kLayers)
+    return fail(c, GSR_EINVAL, "invalid layer");
+  if (act) *act = net->act[layer];
+  if (dact) *dact = net->dact[layer];
+  return GSR_OK;
+}
+
+int gsr_initnet_input(gsr_ctx* c, gsr_initnet* net, int32_t slot, const float* rend_color, const float* rend_depth,
+                      const float* obs_color, const float* obs_depth, int32_t H, int32_t W, float depth_scale) {
+  if (!c || !net || net->ctx != c || !rend_color || !rend_depth || !obs_color || !obs_depth)
+    return fail(c, GSR_EINVAL, "bad input arguments");
+  if (slot < 0 || slot >= net->max_batch) return fail(c, GSR_EINVAL, "slot out of range");
+  const int f = W / gsr_initnet::kInW;
+  if (f < 1 || W != f * gsr_initnet::kInW || H != f * gsr_initnet::kInH)
+    return fail(c, GSR_EINVAL, "frames must be an integer multiple of 160 x 120");
+  GSR_HIP(c, hipSetDevice(c->device));
+  uint16_t* dst = net->act[0] + (int64_t)slot * gsr_initnet::kInH * gsr_initnet::kInW * gsr_initnet::kInC;
+  gsr::launch_pack_input(rend_color, rend_depth, obs_color, obs_depth, H, W, f, depth_scale, dst, c->stream);
+  return check_launch(c, "gsr_initnet_input");
+}
+
+int gsr_initnet_forward(gsr_ctx* c, gsr_initnet* net, int32_t batch, float* out) {
+  if (!c || !net || net->ctx != c || batch < 1 || batch > net->max_batch)
+    return fail(c, GSR_EINVAL, "bad forward arguments");
+  GSR_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  Stage t(c, "initnet_fwd");
+  for (int l = 0; l < gsr_initnet::kLayers; ++l) {
+    gsr::launch_cast_weights(net->w[l], net->C[l], net->wk[l], net->wt[l], st);
+    gsr::launch_conv_fwd(batch, net->H[l], net->W[l], net->C[l], net->act[l], net->wk[l], net->b[l], net->act[l + 1],
+                         st);
+  }
+  const int L = gsr_initnet::kLayers;
+  gsr::launch_head_fwd(batch, net->H[L] * net->W[L], net->act[L], net->wfc, net->bfc, net->pool, net->out, st);
+  if (out) GSR_HIP(c, hipMemcpyAsync(out, net->out, sizeof(float) * 6 * batch, hipMemcpyDeviceToDevice, st));
+  return check_launch(c, "gsr_initnet_forward");
+}
+
+int gsr_initnet_backward(gsr_ctx* c, gsr_initnet* net, int32_t batch, const float* labels, const float* scale,
+                         const float* dL_dout, float* loss) {
+  if (!c || !net || net->ctx != c || batch < 1 || batch > net->max_batch)
+    return fail(c, GSR_EINVAL, "bad backward arguments");
+  if (!dL_dout && (!labels || !scale)) return fail(c, GSR_EINVAL, "labels and scale (or dL/dout) are required");
+  GSR_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  Stage t(c, "initnet_bwd");
+  const int L = gsr_initnet::kLayers;
+  gsr::launch_fill_f32(net->grads, 0.f, net->n_params, st);
+  float* lp = loss ? loss : net->scratch;
+  gsr::launch_fill_f32(lp, 0.f, 1, st);
+  gsr::launch_head_bwd(batch, net->H[L] * net->W[L], net->out, labels, scale, net->pool, net->wfc, net->act[L], dL_dout,
+                       net->dwfc, net->dbfc, net->dact[L], lp, st);
+  for (int l = L - 1; l >= 0; --l) {
+    // dact[l + 1] holds dL/d(pre-activation of layer l)
+    gsr::launch_conv_bwd_weight(batch, net->H[l], net->W[l], net->C[l], net->dact[l + 1], net->act[l], net->dw[l],
+                                net->db[l], st);
+    if (l > 0)
+      gsr::launch_conv_bwd_data(batch, net->H[l], net->W[l], net->C[l], net->dact[l + 1], net->wt[l], net->act[l],
+                                net->dact[l], st);
+  }
+  return check_launch(c, "gsr_initnet_backward");
+}
+
+int gsr_initnet_adam(gsr_ctx* c, gsr_initnet* net, float lr, float b1, float b2, float eps) {
+  if (!c || !net || net->ctx != c) return fail(c, GSR_EINVAL, "invalid network");
+  GSR_HIP(c, hipSetDevice(c->device));
+  net->step += 1;
+  const float bc1 = (float)(1.0 - std::pow((double)b1, (double)net->step));
+  const float bc2 = (float)(1.0 - std::pow((double)b2, (double)net->step));
+  gsr::launch_adam(net->params, net->m, net->v, net->grads, net->n_params, lr, b1, b2, eps, bc1, bc2, c->stream);
+  return check_launch(c, "gsr_initnet_adam");
 }
 
 int gsr_profile_enable(gsr_ctx* c, int on) {

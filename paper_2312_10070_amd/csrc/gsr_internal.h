@@ -281,6 +281,23 @@ void launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float 
 
 void launch_pose_adam(float* pose, float* state, const float* g, float lr_q, float lr_t, float b1, float b2, float eps,
                       hipStream_t s);
+
+// Tracking-initialisation CNN (k_initnet.hip). BF16 values travel as uint16_t bits.
+int conv_kp(int C);
+void launch_conv_fwd(int B, int H, int W, int C, const uint16_t* in, const uint16_t* wk, const float* bias,
+                     uint16_t* out, hipStream_t st);
+void launch_conv_bwd_data(int B, int H, int W, int C, const uint16_t* dout, const uint16_t* wt, const uint16_t* in,
+                          uint16_t* din, hipStream_t st);
+void launch_conv_bwd_weight(int B, int H, int W, int C, const uint16_t* dy, const uint16_t* in, float* dw, float* db,
+                            hipStream_t st);
+void launch_head_fwd(int B, int npix, const uint16_t* act, const float* wfc, const float* bfc, float* pool, float* out,
+                     hipStream_t st);
+void launch_head_bwd(int B, int npix, const float* out, const float* label, const float* scale, const float* pool,
+                     const float* wfc, const uint16_t* act, const float* dout, float* dwfc, float* dbfc,
+                     uint16_t* dact, float* loss, hipStream_t st);
+void launch_cast_weights(const float* w, int C, uint16_t* wk, uint16_t* wt, hipStream_t st);
+void launch_pack_input(const float* rc, const float* rd, const float* oc, const float* od, int H, int W, int f,
+                       float depth_scale, uint16_t* out, hipStream_t st);
 void launch_pose_const_velocity(const float* p0, const float* p1, float* out, hipStream_t s);
 
 }  // namespace gsr
