@@ -190,6 +190,11 @@ int gsr_pose_const_velocity(gsr_ctx *ctx, const float *pose_prev2, const float *
 int gsr_pose_adam(gsr_ctx *ctx, float *pose7, float *state, const float *grad7, float lr_q, float lr_t, float beta1,
                   float beta2, float eps);
 
+/* Left perturbation of a pose by a twist (rho, phi): R' = Exp(phi) R,
+ * t' = Exp(phi) t + rho (device pose7 in, twist6, pose7 out; the output
+ * quaternion is unit). This is how a proposed correction is applied. */
+int gsr_pose_apply_twist(gsr_ctx *ctx, const float *pose7, const float *twist6, float *pose_out);
+
 typedef struct gsr_track_graph gsr_track_graph; /* opaque: a captured tracking loop */
 
 typedef struct {
@@ -235,20 +240,27 @@ typedef struct gsr_initnet gsr_initnet;
 
 int gsr_initnet_create(gsr_ctx *ctx, int32_t max_batch, gsr_initnet **out);
 int gsr_initnet_destroy(gsr_ctx *ctx, gsr_initnet *net);
-/* Flat FP32 parameters and gradients (device, count floats), in order:
- * per layer l = 0..3: W_l [64][KP_l] (K ordered (3 ky + kx, channel),
- * KP_0 = 96 with 24 zero pad columns, KP_1..3 = 576), b_l [64]; then the head
- * W_fc [6][64], b_fc [6]. The caller initialises them (zero after create). */
-int gsr_initnet_params(gsr_ctx *ctx, gsr_initnet *net, float **params, float **grads, int64_t *count);
-/* Device pointers of layer l's activation (l = 0: the packed input, BF16
- * NHWC [B,120,160,8]; l = 1..4: post-ReLU outputs [B,H_l,W_l,64]) and of the
- * gradient w.r.t. layer l's pre-activation (l >= 1) after a backward. */
-int gsr_initnet_activation(gsr_ctx *ctx, gsr_initnet *net, int32_t layer, uint16_t **act, uint16_t **dact);
-/* Pack one sample (input slot `slot`) from full-resolution frames (W = 160 f,
- * H = 120 f). */
-int gsr_initnet_input(gsr_ctx *ctx, gsr_initnet *net, int32_t slot, const float *rend_color, const float *rend_depth,
-                      const float *obs_color, const float *obs_depth, int32_t H, int32_t W, float depth_scale);
-/* Forward of slots 0..batch-1 with the current parameters; out: device [B,6] or NULL. */
+/* Parameters: a flat FP32 vector of n_params floats, in order: per layer
+ * l = 0..3: W_l [64][KP_l] (K ordered (3 ky + kx, channel); KP_0 = 96 with
+ * 24 zero pad columns, KP_1..3 = 576), b_l [64]; then the head W_fc [6][64],
+ * b_fc [6]. Zero after create. set_params copies a device vector in (and
+ * resets Adam); get_params copies parameters and/or the last gradients out
+ * (either pointer may be NULL). */
+int gsr_initnet_count(gsr_ctx *ctx, gsr_initnet *net, int64_t *n_params);
+int gsr_initnet_set_params(gsr_ctx *ctx, gsr_initnet *net, const float *src);
+int gsr_initnet_get_params(gsr_ctx *ctx, gsr_initnet *net, float *params, float *grads);
+/* Inputs are BF16 NHWC [B,120,160,8] (device, BF16 bit patterns). */
+int gsr_initnet_set_input(gsr_ctx *ctx, gsr_initnet *net, int32_t batch, const uint16_t *src);
+/* Copy out layer l's activation (l = 0: input; 1..4: post-ReLU [B,H_l,W_l,64])
+ * and/or the gradient w.r.t. its pre-activation (after a backward). */
+int gsr_initnet_get_activation(gsr_ctx *ctx, gsr_initnet *net, int32_t layer, int32_t batch, uint16_t *act,
+                               uint16_t *dact);
+/* Pack one input sample from full-resolution frames (W = 160 f, H = 120 f):
+ * f x f average pooling of rendered and observed colour and depth (x
+ * depth_scale) into dst (BF16 [120,160,8]). */
+int gsr_pack_rgbd_pair(gsr_ctx *ctx, const float *rend_color, const float *rend_depth, const float *obs_color,
+                       const float *obs_depth, int32_t H, int32_t W, float depth_scale, uint16_t *dst);
+/* Forward of the first `batch` input samples; out: device [B,6] or NULL. */
 int gsr_initnet_forward(gsr_ctx *ctx, gsr_initnet *net, int32_t batch, float *out);
 /* Backward of the last forward: with dL_dout == NULL the loss is
  * L = 1/(2B) sum_b sum_j ((out - label) / scale_j)^2 (labels [B,6], scale [6],

@@ -59,6 +59,7 @@ def _load():
     lib.orc_loss_track.argtypes = [i64, P, P, P, P, P, ctypes.c_double, ctypes.c_float, P, P, P, P, P]
     lib.orc_adam.argtypes = [i64, P, P, P, P, i64] + [ctypes.c_double] * 4
     lib.orc_pose_const_velocity.argtypes = [P, P, P]
+    lib.orc_pose_apply_twist.argtypes = [P, P, P]
     if hasattr(lib, "orc_conv2d_fwd"):
         _bind_cnn(lib)
     _lib = lib
@@ -308,3 +309,11 @@ def initnet_loss(out, label, scale):
     r = (np.asarray(out, np.float64) - np.asarray(label, np.float64)) / np.asarray(scale, np.float64)
     B = r.shape[0]
     return 0.5 * float((r * r).sum()) / B, r / np.asarray(scale, np.float64) / B
+
+
+def pose_apply_twist(pose7, twist6) -> np.ndarray:
+    """exp(xi^) T (Rodrigues), unit quaternion with w >= 0."""
+    lib = _load()
+    a = _d(pose7); x = _d(twist6); out = np.zeros(7)
+    lib.orc_pose_apply_twist(_p(a), _p(x), _p(out))
+    return out

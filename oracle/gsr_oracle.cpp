@@ -944,6 +944,44 @@ int orc_adam(int64_t n, double* param, double* m, double* v, const double* g, in
   return 0;
 }
 
+// Left perturbation exp(xi^) T of pose7 by the twist xi = (rho, phi):
+// R' = Exp(phi) R (Rodrigues' formula), t' = Exp(phi) t + rho. The output
+// quaternion is R' as a unit quaternion with w >= 0 (Shepperd's method).
+int orc_pose_apply_twist(const double* p7, const double* xi, double* out) {
+  const Pose P = read_pose(p7);
+  const double th = std::sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]);
+  double K[9] = {0, -xi[5], xi[4], xi[5], 0, -xi[3], -xi[4], xi[3], 0};
+  double E[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  if (th > 0) {
+    double K2[9];
+    mm3(K, K, K2);
+    const double a = std::sin(th) / th, b = (1 - std::cos(th)) / (th * th);
+    for (int i = 0; i < 9; ++i) E[i] += a * K[i] + b * K2[i];
+  }
+  double R[9];
+  mm3(E, P.R, R);
+  for (int i = 0; i < 3; ++i) out[4 + i] = E[3 * i] * P.t[0] + E[3 * i + 1] * P.t[1] + E[3 * i + 2] * P.t[2] + xi[i];
+  const double tr = R[0] + R[4] + R[8];
+  double q[4];
+  if (tr > 0) {
+    const double s = std::sqrt(tr + 1.0) * 2;
+    q[0] = 0.25 * s; q[1] = (R[7] - R[5]) / s; q[2] = (R[2] - R[6]) / s; q[3] = (R[3] - R[1]) / s;
+  } else if (R[0] > R[4] && R[0] > R[8]) {
+    const double s = std::sqrt(1.0 + R[0] - R[4] - R[8]) * 2;
+    q[0] = (R[7] - R[5]) / s; q[1] = 0.25 * s; q[2] = (R[1] + R[3]) / s; q[3] = (R[2] + R[6]) / s;
+  } else if (R[4] > R[8]) {
+    const double s = std::sqrt(1.0 + R[4] - R[0] - R[8]) * 2;
+    q[0] = (R[2] - R[6]) / s; q[1] = (R[1] + R[3]) / s; q[2] = 0.25 * s; q[3] = (R[5] + R[7]) / s;
+  } else {
+    const double s = std::sqrt(1.0 + R[8] - R[0] - R[4]) * 2;
+    q[0] = (R[3] - R[1]) / s; q[1] = (R[2] + R[6]) / s; q[2] = (R[5] + R[7]) / s; q[3] = 0.25 * s;
+  }
+  const double sg = q[0] < 0 ? -1.0 : 1.0;
+  const double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int i = 0; i < 4; ++i) out[i] = sg * q[i] / n;
+  return 0;
+}
+
 // Constant-speed pose initialisation (Eq. 13) applied to pose7 = (q, t):
 // t = t1 + (t1 - t0); q = normalise(q1 + (q1 - q0')) where q0' is q0 or -q0,
 // whichever lies in q1's hemisphere (q and -q are the same rotation).

@@ -747,34 +747,61 @@ int gsr_initnet_create(gsr_ctx* c, int32_t max_batch, gsr_initnet** out) {
   return check_launch(c, "gsr_initnet_create");
 }
 
-int gsr_initnet_params(gsr_ctx* c, gsr_initnet* net, float** params, float** grads, int64_t* count) {
-  if (!c || !net || net->ctx != c || !count) return fail(c, GSR_EINVAL, "invalid network");
-  if (params) *params = net->params;
-  if (grads) *grads = net->grads;
-  *count = net->n_params;
+int gsr_initnet_count(gsr_ctx* c, gsr_initnet* net, int64_t* n_params) {
+  if (!c || !net || net->ctx != c || !n_params) return fail(c, GSR_EINVAL, "invalid network");
+  *n_params = net->n_params;
   return GSR_OK;
 }
 
-int gsr_initnet_activation(gsr_ctx* c, gsr_initnet* net, int32_t layer, uint16_t** act, uint16_t** dact) {
-  if (!c || !net || net->ctx != c || layer < 0 || layer > gsr_initnet::kLayers)
-    return fail(c, GSR_EINVAL, "invalid layer");
-  if (act) *act = net->act[layer];
-  if (dact) *dact = net->dact[layer];
+int gsr_initnet_set_params(gsr_ctx* c, gsr_initnet* net, const float* src) {
+  if (!c || !net || net->ctx != c || !src) return fail(c, GSR_EINVAL, "invalid network or source");
+  GSR_HIP(c, hipSetDevice(c->device));
+  GSR_HIP(c, hipMemcpyAsync(net->params, src, sizeof(float) * net->n_params, hipMemcpyDeviceToDevice, c->stream));
+  gsr::launch_fill_f32(net->m, 0.f, net->n_params, c->stream);
+  gsr::launch_fill_f32(net->v, 0.f, net->n_params, c->stream);
+  net->step = 0;
+  return check_launch(c, "gsr_initnet_set_params");
+}
+
+int gsr_initnet_get_params(gsr_ctx* c, gsr_initnet* net, float* params, float* grads) {
+  if (!c || !net || net->ctx != c) return fail(c, GSR_EINVAL, "invalid network");
+  GSR_HIP(c, hipSetDevice(c->device));
+  if (params)
+    GSR_HIP(c, hipMemcpyAsync(params, net->params, sizeof(float) * net->n_params, hipMemcpyDeviceToDevice, c->stream));
+  if (grads)
+    GSR_HIP(c, hipMemcpyAsync(grads, net->grads, sizeof(float) * net->n_params, hipMemcpyDeviceToDevice, c->stream));
   return GSR_OK;
 }
 
-int gsr_initnet_input(gsr_ctx* c, gsr_initnet* net, int32_t slot, const float* rend_color, const float* rend_depth,
-                      const float* obs_color, const float* obs_depth, int32_t H, int32_t W, float depth_scale) {
-  if (!c || !net || net->ctx != c || !rend_color || !rend_depth || !obs_color || !obs_depth)
+int gsr_initnet_set_input(gsr_ctx* c, gsr_initnet* net, int32_t batch, const uint16_t* src) {
+  if (!c || !net || net->ctx != c || !src || batch < 1 || batch > net->max_batch)
     return fail(c, GSR_EINVAL, "bad input arguments");
-  if (slot < 0 || slot >= net->max_batch) return fail(c, GSR_EINVAL, "slot out of range");
+  GSR_HIP(c, hipSetDevice(c->device));
+  const int64_t n = (int64_t)batch * gsr_initnet::kInH * gsr_initnet::kInW * gsr_initnet::kInC;
+  GSR_HIP(c, hipMemcpyAsync(net->act[0], src, sizeof(uint16_t) * n, hipMemcpyDeviceToDevice, c->stream));
+  return GSR_OK;
+}
+
+int gsr_initnet_get_activation(gsr_ctx* c, gsr_initnet* net, int32_t layer, int32_t batch, uint16_t* act,
+                               uint16_t* dact) {
+  if (!c || !net || net->ctx != c || layer < 0 || layer > gsr_initnet::kLayers || batch < 1 || batch > net->max_batch)
+    return fail(c, GSR_EINVAL, "bad activation arguments");
+  GSR_HIP(c, hipSetDevice(c->device));
+  const int64_t n = (int64_t)batch * net->H[layer] * net->W[layer] * net->C[layer];
+  if (act) GSR_HIP(c, hipMemcpyAsync(act, net->act[layer], 2 * n, hipMemcpyDeviceToDevice, c->stream));
+  if (dact) GSR_HIP(c, hipMemcpyAsync(dact, net->dact[layer], 2 * n, hipMemcpyDeviceToDevice, c->stream));
+  return GSR_OK;
+}
+
+int gsr_pack_rgbd_pair(gsr_ctx* c, const float* rend_color, const float* rend_depth, const float* obs_color,
+                       const float* obs_depth, int32_t H, int32_t W, float depth_scale, uint16_t* dst) {
+  if (!c || !rend_color || !rend_depth || !obs_color || !obs_depth || !dst) return fail(c, GSR_EINVAL, "bad arguments");
   const int f = W / gsr_initnet::kInW;
   if (f < 1 || W != f * gsr_initnet::kInW || H != f * gsr_initnet::kInH)
     return fail(c, GSR_EINVAL, "frames must be an integer multiple of 160 x 120");
   GSR_HIP(c, hipSetDevice(c->device));
-  uint16_t* dst = net->act[0] + (int64_t)slot * gsr_initnet::kInH * gsr_initnet::kInW * gsr_initnet::kInC;
   gsr::launch_pack_input(rend_color, rend_depth, obs_color, obs_depth, H, W, f, depth_scale, dst, c->stream);
-  return check_launch(c, "gsr_initnet_input");
+  return check_launch(c, "gsr_pack_rgbd_pair");
 }
 
 int gsr_initnet_forward(gsr_ctx* c, gsr_initnet* net, int32_t batch, float* out) {
@@ -902,6 +929,13 @@ int gsr_pose_adam(gsr_ctx* c, float* pose7, float* state, const float* grad7, fl
   Stage t(c, "pose_adam");
   gsr::launch_pose_adam(pose7, state, grad7, lr_q, lr_t, b1, b2, eps, c->stream);
   return check_launch(c, "gsr_pose_adam");
+}
+
+int gsr_pose_apply_twist(gsr_ctx* c, const float* pose7, const float* twist6, float* out) {
+  if (!c || !pose7 || !twist6 || !out) return fail(c, GSR_EINVAL, "pose, twist and output are required");
+  GSR_HIP(c, hipSetDevice(c->device));
+  gsr::launch_pose_apply_twist(pose7, twist6, out, c->stream);
+  return check_launch(c, "gsr_pose_apply_twist");
 }
 
 int gsr_pose_const_velocity(gsr_ctx* c, const float* p0, const float* p1, float* out) {

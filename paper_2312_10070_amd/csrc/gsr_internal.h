@@ -299,5 +299,6 @@ void launch_cast_weights(const float* w, int C, uint16_t* wk, uint16_t* wt, hipS
 void launch_pack_input(const float* rc, const float* rd, const float* oc, const float* od, int H, int W, int f,
                        float depth_scale, uint16_t* out, hipStream_t st);
 void launch_pose_const_velocity(const float* p0, const float* p1, float* out, hipStream_t s);
+void launch_pose_apply_twist(const float* pose, const float* xi, float* out, hipStream_t s);
 
 }  // namespace gsr

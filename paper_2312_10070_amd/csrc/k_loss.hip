@@ -168,6 +168,30 @@ __global__ void k_pose_const_velocity(const float* __restrict__ p0, const float*
   for (int i = 4; i < 7; ++i) out[i] = 2.f * p1[i] - p0[i];
 }
 
+// Left perturbation of a pose by a twist xi = (rho, phi): R' = Exp(phi) R,
+// t' = Exp(phi) t + rho; the quaternion is dq * q / |q| with dq the unit
+// quaternion of the rotation vector phi.
+__global__ void k_pose_apply_twist(const float* __restrict__ pose, const float* __restrict__ xi,
+                                   float* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const float px = xi[3], py = xi[4], pz = xi[5];
+  const float th = sqrtf(px * px + py * py + pz * pz);
+  const float h = 0.5f * th;
+  const float sc = th > 1e-12f ? sinf(h) / th : 0.5f;
+  const float dw = cosf(h), dx = sc * px, dy = sc * py, dz = sc * pz;
+  float qw = pose[0], qx = pose[1], qy = pose[2], qz = pose[3];
+  const float n = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  const float in = n > 0.f ? 1.f / n : 0.f;
+  qw *= in; qx *= in; qy *= in; qz *= in;
+  out[0] = dw * qw - dx * qx - dy * qy - dz * qz;
+  out[1] = dw * qx + dx * qw + dy * qz - dz * qy;
+  out[2] = dw * qy - dx * qz + dy * qw + dz * qx;
+  out[3] = dw * qz + dx * qy - dy * qx + dz * qw;
+  float R[9];
+  quat_rot(dw, dx, dy, dz, R);
+  for (int i = 0; i < 3; ++i) out[4 + i] = R[3 * i] * pose[4] + R[3 * i + 1] * pose[5] + R[3 * i + 2] * pose[6] + xi[i];
+}
+
 unsigned grid_for(int64_t n, int64_t cap) {
   int64_t b = (n + 255) / 256;
   if (b > cap) b = cap;
@@ -217,5 +241,8 @@ void launch_pose_adam(float* pose, float* state, const float* g, float lr_q, flo
 }
 void launch_pose_const_velocity(const float* p0, const float* p1, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_pose_const_velocity, dim3(1), dim3(64), 0, s, p0, p1, out);
+}
+void launch_pose_apply_twist(const float* pose, const float* xi, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pose_apply_twist, dim3(1), dim3(64), 0, s, pose, xi, out);
 }
 }  // namespace gsr

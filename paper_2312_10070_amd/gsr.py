@@ -82,12 +82,24 @@ _SIGS = {
                                 ctypes.c_float, ctypes.c_float]),
     "gsr_pose_const_velocity": (ctypes.c_int, [P, P, P, P]),
     "gsr_pose_adam": (ctypes.c_int, [P, P, P, P] + [ctypes.c_float] * 5),
+    "gsr_pose_apply_twist": (ctypes.c_int, [P, P, P, P]),
     "gsr_track_graph_create": (ctypes.c_int, [P, ctypes.POINTER(Gaussians), ctypes.POINTER(Camera),
                                               ctypes.POINTER(Opts), ctypes.POINTER(TrackOpts), P, P, ctypes.c_int64,
                                               ctypes.POINTER(P)]),
     "gsr_track_graph_set_frame": (ctypes.c_int, [P, P, P, P]),
     "gsr_track_graph_run": (ctypes.c_int, [P, P, P, P]),
     "gsr_track_graph_destroy": (ctypes.c_int, [P, P]),
+    "gsr_initnet_create": (ctypes.c_int, [P, ctypes.c_int32, ctypes.POINTER(P)]),
+    "gsr_initnet_destroy": (ctypes.c_int, [P, P]),
+    "gsr_initnet_count": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_int64)]),
+    "gsr_initnet_set_params": (ctypes.c_int, [P, P, P]),
+    "gsr_initnet_get_params": (ctypes.c_int, [P, P, P, P]),
+    "gsr_initnet_set_input": (ctypes.c_int, [P, P, ctypes.c_int32, P]),
+    "gsr_initnet_get_activation": (ctypes.c_int, [P, P, ctypes.c_int32, ctypes.c_int32, P, P]),
+    "gsr_pack_rgbd_pair": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P]),
+    "gsr_initnet_forward": (ctypes.c_int, [P, P, ctypes.c_int32, P]),
+    "gsr_initnet_backward": (ctypes.c_int, [P, P, ctypes.c_int32, P, P, P, P]),
+    "gsr_initnet_adam": (ctypes.c_int, [P, P] + [ctypes.c_float] * 4),
     "gsr_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
     "gsr_profile_read": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_char_p, P, P, ctypes.POINTER(ctypes.c_int)]),
     "gsr_state_stats": (ctypes.c_int, [P, P, P]),
@@ -469,3 +481,95 @@ def pose_adam_step(pose7, state, grad7, lr_q, lr_t, beta1=0.9, beta2=0.999, eps=
     _f32(pose7, "pose7", (7,)); _f32(state, "state", (20,)); _f32(grad7, "grad7", (7,))
     ctx.check(ctx.lib.gsr_pose_adam(ctx.h, _ptr(pose7), _ptr(state), _ptr(grad7), float(lr_q), float(lr_t),
                                     float(beta1), float(beta2), float(eps)))
+
+
+class InitNet:
+    """Handle of the tracking-initialisation CNN (BF16 MFMA kernels in libgsr)."""
+
+    IN_H, IN_W, IN_C = 120, 160, 8
+
+    def __init__(self, max_batch: int, ctx: Context | None = None):
+        self.ctx = ctx or Context.get(torch.cuda.current_device())
+        self.ctx.sync_stream()
+        self.max_batch = int(max_batch)
+        self.h = P()
+        self.ctx.check(self.ctx.lib.gsr_initnet_create(self.ctx.h, self.max_batch, ctypes.byref(self.h)))
+        n = ctypes.c_int64()
+        self.ctx.check(self.ctx.lib.gsr_initnet_count(self.ctx.h, self.h, ctypes.byref(n)))
+        self.n_params = int(n.value)
+
+    def set_params(self, flat):
+        self.ctx.sync_stream()
+        _f32(flat, "params", (self.n_params,))
+        self.ctx.check(self.ctx.lib.gsr_initnet_set_params(self.ctx.h, self.h, _ptr(flat)))
+
+    def get_params(self, with_grads=False):
+        self.ctx.sync_stream()
+        p = torch.empty(self.n_params, device="cuda", dtype=torch.float32)
+        g = torch.empty(self.n_params, device="cuda", dtype=torch.float32) if with_grads else None
+        self.ctx.check(self.ctx.lib.gsr_initnet_get_params(self.ctx.h, self.h, _ptr(p), _ptr(g)))
+        return (p, g) if with_grads else p
+
+    def set_input(self, x):
+        """x: BF16 [B,120,160,8] device tensor."""
+        self.ctx.sync_stream()
+        if x.dtype != torch.bfloat16 or not x.is_contiguous() or tuple(x.shape[1:]) != (self.IN_H, self.IN_W, self.IN_C):
+            raise ValueError("input must be a contiguous bfloat16 [B,120,160,8] tensor")
+        self.ctx.check(self.ctx.lib.gsr_initnet_set_input(self.ctx.h, self.h, x.shape[0], _ptr(x)))
+
+    def activation(self, layer: int, batch: int, shape):
+        self.ctx.sync_stream()
+        a = torch.empty((batch,) + tuple(shape), device="cuda", dtype=torch.bfloat16)
+        d = torch.empty_like(a)
+        self.ctx.check(self.ctx.lib.gsr_initnet_get_activation(self.ctx.h, self.h, layer, batch, _ptr(a), _ptr(d)))
+        return a, d
+
+    def forward(self, batch: int):
+        self.ctx.sync_stream()
+        out = torch.empty((batch, 6), device="cuda", dtype=torch.float32)
+        self.ctx.check(self.ctx.lib.gsr_initnet_forward(self.ctx.h, self.h, batch, _ptr(out)))
+        return out
+
+    def backward(self, batch: int, labels=None, scale=None, dL_dout=None):
+        self.ctx.sync_stream()
+        loss = torch.zeros(1, device="cuda", dtype=torch.float32)
+        self.ctx.check(self.ctx.lib.gsr_initnet_backward(self.ctx.h, self.h, batch, _ptr(labels), _ptr(scale),
+                                                         _ptr(dL_dout), _ptr(loss)))
+        return loss
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.ctx.sync_stream()
+        self.ctx.check(self.ctx.lib.gsr_initnet_adam(self.ctx.h, self.h, float(lr), float(beta1), float(beta2),
+                                                     float(eps)))
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            self.ctx.lib.gsr_initnet_destroy(self.ctx.h, self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pack_rgbd_pair(rend_color, rend_depth, obs_color, obs_depth, dst, depth_scale=0.25, ctx: Context | None = None):
+    """Pack one sample into dst (BF16 [120,160,8] device tensor view)."""
+    ctx = ctx or Context.get(rend_color.device.index or 0)
+    ctx.sync_stream()
+    H, W = rend_depth.shape
+    if dst.dtype != torch.bfloat16 or not dst.is_contiguous():
+        raise ValueError("dst must be a contiguous bfloat16 tensor")
+    ctx.check(ctx.lib.gsr_pack_rgbd_pair(ctx.h, _ptr(rend_color), _ptr(rend_depth), _ptr(obs_color), _ptr(obs_depth),
+                                         H, W, float(depth_scale), _ptr(dst)))
+
+
+def pose_apply_twist(pose7, twist6, ctx: Context | None = None):
+    """exp(twist^) T on the device; returns a new pose7 tensor."""
+    ctx = ctx or Context.get(pose7.device.index or 0)
+    ctx.sync_stream()
+    _f32(pose7, "pose7", (7,)); _f32(twist6, "twist6", (6,))
+    out = torch.empty(7, device=pose7.device, dtype=torch.float32)
+    ctx.check(ctx.lib.gsr_pose_apply_twist(ctx.h, _ptr(pose7), _ptr(twist6), _ptr(out)))
+    return out

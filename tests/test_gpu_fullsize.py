@@ -11,7 +11,7 @@ from paper_2312_10070_amd import gsr, synth
 from tests import gpu_cases as G
 from tests import helpers as H
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(300)]
 
 # FP32 projection of a mean 600 px off-centre carries ~1e-4 px of rounding, so
 # the ambiguity band of the threshold decisions is widened accordingly.

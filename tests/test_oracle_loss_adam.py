@@ -94,3 +94,22 @@ def test_const_velocity_pins():
     out = oracle.pose_const_velocity(qa(0.01), qa(0.02))
     ang = Rotation.from_quat([out[1], out[2], out[3], out[0]]).magnitude()
     assert abs(ang - 0.03) < 1e-6
+
+
+def test_apply_twist_matches_scipy_and_inverts():
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(4)
+    for _ in range(10):
+        q = rng.normal(size=4); q /= np.linalg.norm(q)
+        p = np.concatenate([q, rng.normal(size=3)])
+        xi = np.concatenate([rng.normal(0, 0.05, 3), rng.normal(0, 0.3, 3)])
+        out = oracle.pose_apply_twist(p, xi)
+        Rphi = Rotation.from_rotvec(xi[3:]).as_matrix()
+        Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        Ro = Rotation.from_quat([out[1], out[2], out[3], out[0]]).as_matrix()
+        np.testing.assert_allclose(Ro, Rphi @ Rq, atol=1e-12)
+        np.testing.assert_allclose(out[4:], Rphi @ p[4:] + xi[:3], atol=1e-12)
+        # exp(-xi) undoes exp(xi) when rho is transported: T = exp(xi') exp(xi) T with xi' = (-Exp(-phi) rho, -phi)
+        back = oracle.pose_apply_twist(out, np.concatenate([-(Rphi.T @ xi[:3]), -xi[3:]]))
+        qb = back[:4] * np.sign(back[0]) ; qq = q * np.sign(q[0])
+        np.testing.assert_allclose(qb, qq, atol=1e-12)
