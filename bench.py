@@ -54,7 +54,7 @@ def stage_work(stage: str, st: dict, n: int, P: int, radix_passes: int) -> tuple
     if stage == "duplicate":
         return "hbm", n * 24.0 + K * 12.0
     if stage == "adam":
-        return "hbm", 28.0 * 14 * n / 5.0  # per launch (5 launches per step)
+        return "hbm", 28.0 * 14 * n  # all 14 n parameters in one launch
     if stage == "loss_l1":
         return "hbm", P * 8 * 4.0 * 2
     return "hbm", 0.0
@@ -198,8 +198,9 @@ def main() -> int:
         loss, gC, gD = gsr.loss_l1(color, depth, tgt_c, tgt_d)
         grads = gsr.render_bwd(st, gC, gD, None, want_params=True, want_pose=False)
         step_no[0] += 1
-        for k in params:
-            gsr.adam_step(params[k], adam_m[k], adam_v[k], grads[k], step_no[0], lrs[k])
+        keys = list(params)
+        gsr.adam_groups([params[k] for k in keys], [adam_m[k] for k in keys], [adam_v[k] for k in keys],
+                        [grads[k] for k in keys], [lrs[k] for k in keys], step_no[0])
         st.release()
         return loss
 

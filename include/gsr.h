@@ -177,6 +177,14 @@ int gsr_loss_track(gsr_ctx *ctx, const float *color, const float *depth, const f
 int gsr_adam(gsr_ctx *ctx, float *param, float *exp_avg, float *exp_avg_sq, const float *grad, int64_t n,
              int64_t step, float lr, float beta1, float beta2, float eps);
 
+/* The same step on up to 8 parameter tensors in one launch (e.g. the five
+ * Gaussian parameter groups of a mapping iteration), each with its own step
+ * size: params[i], exp_avg[i], exp_avg_sq[i], grads[i] hold counts[i] device
+ * floats; the pointer arrays, counts and lrs are host arrays. */
+int gsr_adam_groups(gsr_ctx *ctx, int32_t n_groups, float *const *params, float *const *exp_avg,
+                    float *const *exp_avg_sq, const float *const *grads, const int64_t *counts, const float *lrs,
+                    int64_t step, float beta1, float beta2, float eps);
+
 /* Tracking (Sec. 3.4) ------------------------------------------------------ */
 
 /* Constant-speed pose initialisation (Eq. 13) on the quaternion and the

@@ -922,6 +922,34 @@ int gsr_state_stats(gsr_ctx* c, gsr_state* s, int64_t out[6]) {
   return check_launch(c, "gsr_state_stats");
 }
 
+int gsr_adam_groups(gsr_ctx* c, int32_t n_groups, float* const* params, float* const* exp_avg,
+                    float* const* exp_avg_sq, const float* const* grads, const int64_t* counts, const float* lrs,
+                    int64_t step, float b1, float b2, float eps) {
+  if (!c) return GSR_EINVAL;
+  if (n_groups < 1 || n_groups > gsr::kAdamGroups || !params || !exp_avg || !exp_avg_sq || !grads || !counts || !lrs ||
+      step < 1)
+    return fail(c, GSR_EINVAL, "bad Adam group arguments");
+  gsr::AdamGroups a{};
+  a.n = n_groups;
+  a.off[0] = 0;
+  for (int i = 0; i < n_groups; ++i) {
+    if (counts[i] < 0 || (counts[i] > 0 && (!params[i] || !exp_avg[i] || !exp_avg_sq[i] || !grads[i])))
+      return fail(c, GSR_EINVAL, "bad Adam group");
+    a.p[i] = params[i];
+    a.m[i] = exp_avg[i];
+    a.v[i] = exp_avg_sq[i];
+    a.g[i] = grads[i];
+    a.lr[i] = lrs[i];
+    a.off[i + 1] = a.off[i] + counts[i];
+  }
+  GSR_HIP(c, hipSetDevice(c->device));
+  const float bc1 = (float)(1.0 - std::pow((double)b1, (double)step));
+  const float bc2 = (float)(1.0 - std::pow((double)b2, (double)step));
+  Stage t(c, "adam");
+  gsr::launch_adam_multi(a, b1, b2, eps, bc1, bc2, c->stream);
+  return check_launch(c, "gsr_adam_groups");
+}
+
 int gsr_pose_adam(gsr_ctx* c, float* pose7, float* state, const float* grad7, float lr_q, float lr_t, float b1,
                   float b2, float eps) {
   if (!c || !pose7 || !state || !grad7) return fail(c, GSR_EINVAL, "pose, state and gradient are required");

@@ -281,6 +281,17 @@ void launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float 
 
 void launch_pose_adam(float* pose, float* state, const float* g, float lr_q, float lr_t, float b1, float b2, float eps,
                       hipStream_t s);
+constexpr int kAdamGroups = 8;
+struct AdamGroups {
+  float* p[kAdamGroups];
+  float* m[kAdamGroups];
+  float* v[kAdamGroups];
+  const float* g[kAdamGroups];
+  float lr[kAdamGroups];
+  int64_t off[kAdamGroups + 1];
+  int n;
+};
+void launch_adam_multi(const AdamGroups& a, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
 
 // Tracking-initialisation CNN (k_initnet.hip). BF16 values travel as uint16_t bits.
 int conv_kp(int C);

@@ -129,6 +129,23 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
   }
 }
 
+// Adam over up to kAdamGroups parameter tensors in one launch (each with its
+// own step size); the flat index space is the concatenation of the groups.
+__global__ __launch_bounds__(256) void k_adam_multi(AdamGroups a, float b1, float b2, float eps, float bc1, float bc2) {
+  const int64_t total = a.off[a.n];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    int gi = 0;
+    while (gi + 1 < a.n && i >= a.off[gi + 1]) ++gi;
+    const int64_t j = i - a.off[gi];
+    const float g = a.g[gi][j];
+    const float mi = b1 * a.m[gi][j] + (1.f - b1) * g;
+    const float vi = b2 * a.v[gi][j] + (1.f - b2) * g * g;
+    a.m[gi][j] = mi;
+    a.v[gi][j] = vi;
+    a.p[gi][j] -= a.lr[gi] * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+}
+
 // Adam on the 7 pose parameters (q: lr_q, t: lr_t) with the step count kept
 // on the device, so a captured graph can run many iterations. state = [m(8),
 // v(8), step(1)].
@@ -205,7 +222,8 @@ void launch_loss_l1(const float* C, const float* D, const float* Ct, const float
                     float* loss, float* gC, float* gD, hipStream_t s) {
   launch_fill_f32(loss, 0.f, 1, s);
   if (P <= 0) return;
-  hipLaunchKernelGGL(k_loss_l1, dim3(grid_for(P, 2048)), dim3(256), 0, s, C, D, Ct, Dt, P, wc / (3.f * (float)P),
+  // a few hundred workgroups: each ends with one atomic on the same address
+  hipLaunchKernelGGL(k_loss_l1, dim3(grid_for(P, 512)), dim3(256), 0, s, C, D, Ct, Dt, P, wc / (3.f * (float)P),
                      wd / (float)P, loss, gC, gD);
 }
 
@@ -216,13 +234,13 @@ void launch_loss_track(const float* C, const float* D, const float* A, const flo
                        uint32_t* temp, hipStream_t s) {
   launch_fill_f32(loss, 0.f, 1, s);
   hipLaunchKernelGGL(k_select_init, dim3(1), dim3(256), 0, s, temp);
-  const unsigned g = grid_for(P, 1024);
+  const unsigned g = grid_for(P, 512);
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 24 - 8 * pass;
     hipLaunchKernelGGL(k_select_hist, dim3(g), dim3(256), 0, s, D, Dt, P, shift, temp);
     hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(64), 0, s, temp, shift, pass == 0 ? 1 : 0);
   }
-  hipLaunchKernelGGL(k_loss_track, dim3(grid_for(P, 2048)), dim3(256), 0, s, C, D, A, Ct, Dt, P, lambda_c,
+  hipLaunchKernelGGL(k_loss_track, dim3(grid_for(P, 512)), dim3(256), 0, s, C, D, A, Ct, Dt, P, lambda_c,
                      inlier_mult, (const uint32_t*)temp, loss, gC, gD, median);
 }
 
@@ -238,6 +256,10 @@ namespace gsr {
 void launch_pose_adam(float* pose, float* state, const float* g, float lr_q, float lr_t, float b1, float b2, float eps,
                       hipStream_t s) {
   hipLaunchKernelGGL(k_pose_adam, dim3(1), dim3(64), 0, s, pose, state, g, lr_q, lr_t, b1, b2, eps);
+}
+void launch_adam_multi(const AdamGroups& a, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s) {
+  if (a.n <= 0 || a.off[a.n] <= 0) return;
+  hipLaunchKernelGGL(k_adam_multi, dim3(grid_for(a.off[a.n], 4096)), dim3(256), 0, s, a, b1, b2, eps, bc1, bc2);
 }
 void launch_pose_const_velocity(const float* p0, const float* p1, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_pose_const_velocity, dim3(1), dim3(64), 0, s, p0, p1, out);

@@ -80,6 +80,8 @@ _SIGS = {
     "gsr_loss_track": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P, P]),
     "gsr_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float]),
+    "gsr_adam_groups": (ctypes.c_int, [P, ctypes.c_int32, P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_float]),
     "gsr_pose_const_velocity": (ctypes.c_int, [P, P, P, P]),
     "gsr_pose_adam": (ctypes.c_int, [P, P, P, P] + [ctypes.c_float] * 5),
     "gsr_pose_apply_twist": (ctypes.c_int, [P, P, P, P]),
@@ -573,3 +575,20 @@ def pose_apply_twist(pose7, twist6, ctx: Context | None = None):
     out = torch.empty(7, device=pose7.device, dtype=torch.float32)
     ctx.check(ctx.lib.gsr_pose_apply_twist(ctx.h, _ptr(pose7), _ptr(twist6), _ptr(out)))
     return out
+
+
+def adam_groups(params, exp_avgs, exp_avg_sqs, grads, lrs, step, beta1=0.9, beta2=0.999, eps=1e-8,
+                ctx: Context | None = None):
+    """One fused Adam launch over several float32 device tensors (<= 8)."""
+    ctx = ctx or Context.get(params[0].device.index or 0)
+    ctx.sync_stream()
+    n = len(params)
+    arr = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])
+    for group in (params, exp_avgs, exp_avg_sqs, grads):
+        for t in group:
+            _f32(t, "adam tensor")
+    counts = (ctypes.c_int64 * n)(*[t.numel() for t in params])
+    lr = (ctypes.c_float * n)(*[float(x) for x in lrs])
+    ctx.check(ctx.lib.gsr_adam_groups(ctx.h, n, arr(params), arr(exp_avgs), arr(exp_avg_sqs), arr(grads),
+                                      ctypes.cast(counts, P), ctypes.cast(lr, P), int(step), float(beta1),
+                                      float(beta2), float(eps)))

@@ -243,3 +243,22 @@ def test_invalid_arguments_are_rejected():
     nan_cam = gsr.make_camera(32, 32, float("nan"), 30, 16, 16)
     with pytest.raises(gsr.GsrError):
         gsr.render_fwd(d["means"], d["scales"], d["quats"], d["opacities"], d["colors"], pose, nan_cam)
+
+
+def test_fused_adam_groups_match_oracle():
+    torch = torch_()
+    rng = np.random.default_rng(5)
+    sizes = [7, 300, 1, 64]
+    lrs = [1e-2, 3e-3, 5e-2, 1e-4]
+    ps = [rng.normal(size=n) for n in sizes]
+    ms = [np.zeros(n) for n in sizes]; vs = [np.zeros(n) for n in sizes]
+    pd = [torch.tensor(p, dtype=torch.float32, device="cuda") for p in ps]
+    md = [torch.zeros(n, device="cuda") for n in sizes]; vd = [torch.zeros(n, device="cuda") for n in sizes]
+    for step in range(1, 11):
+        gs = [rng.normal(size=n).astype(np.float32) for n in sizes]
+        for p, m, v, g, lr in zip(ps, ms, vs, gs, lrs):
+            oracle.adam(p, m, v, g.astype(np.float64), step, lr)
+        gsr.adam_groups(pd, md, vd, [torch.from_numpy(g).cuda() for g in gs], lrs, step)
+    torch.cuda.synchronize()
+    for p, d in zip(ps, pd):
+        np.testing.assert_allclose(d.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
