@@ -26,11 +26,12 @@
 //
 // "Several results are correct" handling: a discrete decision whose FP64
 // margin is within a relative band `amb_rel` (alpha vs alpha_min, T' vs T_min,
-// raw alpha vs alpha_max) is an ambiguity event. A pixel with exactly one
-// event also gets the result with that decision flipped ("alt"), and its
-// gradient contributions under both branches feed a per-element slack. Two or
-// more events (or a near tie in depth between two considered Gaussians) mark
-// the pixel unverifiable.
+// raw alpha vs alpha_max), or the order of two consecutive candidates whose
+// depths agree within `amb_z`, is an ambiguity event. A pixel with exactly one
+// event also gets the result with that decision flipped (the pair swapped,
+// for an order event) as "alt", and its gradient contributions under both
+// branches feed a per-element slack. Two or more events mark the pixel
+// unverifiable.
 
 #include <algorithm>
 #include <cmath>
@@ -335,22 +336,50 @@ struct PixResult {
 };
 
 // Front-to-back compositing of one pixel (Eq. 3, Eq. 4, Eq. 6). `flip` names
-// the ambiguity event (counted from 0) whose decision is inverted; -1 = none.
+// the ambiguity event (counted from 0, in processing order) whose decision is
+// inverted; -1 = none. Events: alpha within amb_rel of alpha_max (clamp) or of
+// alpha_min (skip), T' within amb_rel of T_min (stop), and two consecutive
+// candidates that both may be composited and whose depths agree within amb_z
+// (their order; the flipped branch composites them swapped).
 void composite_pixel(const Scene& S, int px, int py, bool pruned, int flip, bool keep_pairs,
                      PixResult& r) {
   const Opt& opt = S.opt;
+  // candidates in depth order
+  std::vector<int64_t> cand;
+  std::vector<double> raw_alpha;
+  for (int64_t k : S.order) {
+    const Proj& g = S.proj[k];
+    if (pruned && (px < g.px0 || px > g.px1 || py < g.py0 || py > g.py1)) continue;
+    const double dx = px - g.u, dy = py - g.v;
+    const double sigma = 0.5 * (g.a * dx * dx + g.c * dy * dy) + g.b * dx * dy;
+    const double a = std::min(opt.amax, g.o * std::exp(-sigma));
+    if (a < opt.amin * (1.0 - opt.amb_rel)) continue;  // certainly skipped
+    cand.push_back(k);
+    raw_alpha.push_back(a);
+  }
   double T = 1.0, C[3] = {0, 0, 0}, D = 0;
   int ev = 0, nc = 0;
-  bool tie = false;
-  double last_z = -1;
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](uint64_t v) {
     h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
   };
   r.pairs.clear();
-  for (int64_t k : S.order) {
+  bool tie = false;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    // an order event with the next candidate
+    if (i + 1 < cand.size()) {
+      const double za = S.proj[cand[i]].x[2], zb = S.proj[cand[i + 1]].x[2];
+      if (std::fabs(zb - za) <= opt.amb_z * zb) {
+        if (ev == flip) {
+          std::swap(cand[i], cand[i + 1]);
+          std::swap(raw_alpha[i], raw_alpha[i + 1]);
+        }
+        ++ev;
+        tie = true;
+      }
+    }
+    const int64_t k = cand[i];
     const Proj& g = S.proj[k];
-    if (pruned && (px < g.px0 || px > g.px1 || py < g.py0 || py > g.py1)) continue;
     const double dx = px - g.u, dy = py - g.v;
     const double sigma = 0.5 * (g.a * dx * dx + g.c * dy * dy) + g.b * dx * dy;
     const double e = std::exp(-sigma);
@@ -367,9 +396,6 @@ void composite_pixel(const Scene& S, int px, int py, bool pruned, int flip, bool
       ++ev;
     }
     if (skip) continue;
-    // considered Gaussian: its depth order relative to the previous one matters
-    if (last_z >= 0 && std::fabs(g.x[2] - last_z) <= opt.amb_z * g.x[2]) tie = true;
-    last_z = g.x[2];
     const double Tn = T * (1.0 - alpha);
     bool stop = Tn < opt.tmin;
     if (std::fabs(Tn - opt.tmin) <= opt.amb_rel * opt.tmin) {
@@ -384,13 +410,14 @@ void composite_pixel(const Scene& S, int px, int py, bool pruned, int flip, bool
     T = Tn;
     ++nc;
   }
+  (void)tie;
   for (int ch = 0; ch < 3; ++ch) r.C[ch] = C[ch] + T * S.cam.bg[ch];
   r.D = D;
   r.A = 1.0 - T;
   r.T = T;
   r.ncomp = nc;
   r.events = ev;
-  r.tie = tie;
+  r.tie = false;  // ties are events with a swapped alternate branch
   r.hash = h;
 }
 

@@ -14,8 +14,10 @@ from tests import helpers as H
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(300)]
 
 # FP32 projection of a mean 600 px off-centre carries ~1e-4 px of rounding, so
-# the ambiguity band of the threshold decisions is widened accordingly.
-OPTS = oracle.Opts(amb_rel=2e-4, amb_z=1e-6)
+# the ambiguity band of the threshold decisions is widened accordingly; the
+# FP32 camera depth carries up to ~3e-7 relative error, so depths closer than
+# 5e-7 relative may be ordered either way.
+OPTS = oracle.Opts(amb_rel=2e-4, amb_z=5e-7)
 
 
 def torch_():

@@ -331,6 +331,14 @@ def test_ambiguity_flags():
     out = oracle.render(g, ID, C1CAM, opts, mode=0)
     assert out["amb"][24, 35] == 1 and out["amb"][24, 32] == 0
     assert out["alpha"][24, 35] > 0 and out["alt_alpha"][24, 35] == 0
+    # equal depths: one order event whose alternate branch is the swapped order,
+    # i.e. the primary result of the permuted input
     g2 = cat(one([0, 0, 2], 0.05, [1, 0, 0, 0], 0.6, [1, 0, 0]), one([0, 0, 2], 0.05, [1, 0, 0, 0], 0.6, [0, 1, 0]))
     out2 = oracle.render(g2, ID, C1CAM, opts, mode=0)
-    assert out2["amb"][24, 32] == 2
+    assert out2["amb"][24, 32] == 1
+    swapped = oracle.render({k: v[::-1].copy() for k, v in g2.items()}, ID, C1CAM, opts, mode=0)
+    np.testing.assert_allclose(out2["alt_color"][:, 24, 32], swapped["color"][:, 24, 32], atol=1e-15)
+    assert out2["color"][0, 24, 32] > out2["color"][1, 24, 32]  # red in front on the primary branch
+    # three Gaussians tied in depth: two events, unverifiable
+    g3 = cat(g2, one([0, 0, 2], 0.05, [1, 0, 0, 0], 0.6, [0, 0, 1]))
+    assert oracle.render(g3, ID, C1CAM, opts, mode=0)["amb"][24, 32] == 2
