@@ -27,11 +27,14 @@
 // "Several results are correct" handling: a discrete decision whose FP64
 // margin is within a relative band `amb_rel` (alpha vs alpha_min, T' vs T_min,
 // raw alpha vs alpha_max), or the order of two consecutive candidates whose
-// depths agree within `amb_z`, is an ambiguity event. A pixel with exactly one
-// event also gets the result with that decision flipped (the pair swapped,
-// for an order event) as "alt", and its gradient contributions under both
-// branches feed a per-element slack. Two or more events mark the pixel
-// unverifiable.
+// depths agree within `amb_z`, is an ambiguity event. In the forward, a pixel
+// with exactly one event also gets the result with that decision flipped (the
+// pair swapped, for an order event) as "alt"; two or more events mark its
+// image values unverifiable. In the backward, every decision path of a pixel
+// with events is enumerated (each branch flips a subset of the events met on
+// its own path) and the per-element maximum of |branch - primary| over the
+// branches feeds a slack; only a pixel with more than kMaxEventBits events is
+// unverifiable there.
 
 #include <algorithm>
 #include <cmath>
@@ -330,19 +333,24 @@ struct PixResult {
   double C[3], D, A, T;
   int ncomp;
   int events;       // ambiguity events met on this branch
-  bool tie;         // near depth tie between two considered Gaussians
   uint64_t hash;    // fingerprint of every discrete decision
   std::vector<Pair> pairs;
+  std::vector<int64_t> cand;  // Gaussians that may be composited on some branch (keep_pairs only)
+  bool tie3;        // three or more consecutive candidates chained by depth ties
 };
 
-// Front-to-back compositing of one pixel (Eq. 3, Eq. 4, Eq. 6). `flip` names
-// the ambiguity event (counted from 0, in processing order) whose decision is
-// inverted; -1 = none. Events: alpha within amb_rel of alpha_max (clamp) or of
+// Branches are enumerated over at most this many events per pixel.
+constexpr int kMaxEventBits = 10;
+
+// Front-to-back compositing of one pixel (Eq. 3, Eq. 4, Eq. 6). Bit e of
+// `flips` inverts the decision of ambiguity event e (counted from 0, in
+// processing order along this branch); 0 = the primary branch. Events: alpha within amb_rel of alpha_max (clamp) or of
 // alpha_min (skip), T' within amb_rel of T_min (stop), and two consecutive
 // candidates that both may be composited and whose depths agree within amb_z
 // (their order; the flipped branch composites them swapped).
-void composite_pixel(const Scene& S, int px, int py, bool pruned, int flip, bool keep_pairs,
+void composite_pixel(const Scene& S, int px, int py, bool pruned, uint64_t flips, bool keep_pairs,
                      PixResult& r) {
+  auto flipped = [flips](int ev) { return ev < 64 && ((flips >> ev) & 1ull); };
   const Opt& opt = S.opt;
   // candidates in depth order
   std::vector<int64_t> cand;
@@ -364,18 +372,24 @@ void composite_pixel(const Scene& S, int px, int py, bool pruned, int flip, bool
     h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
   };
   r.pairs.clear();
-  bool tie = false;
+  if (keep_pairs) r.cand = cand;
+  // Adjacent swaps reach both orders of a tied pair but not every order of a
+  // longer tie chain; such a pixel is flagged (its backward is unverifiable).
+  r.tie3 = false;
+  for (size_t i = 0; i + 2 < cand.size(); ++i) {
+    const double z0 = S.proj[cand[i]].x[2], z1 = S.proj[cand[i + 1]].x[2], z2 = S.proj[cand[i + 2]].x[2];
+    if (std::fabs(z1 - z0) <= opt.amb_z * z1 && std::fabs(z2 - z1) <= opt.amb_z * z2) r.tie3 = true;
+  }
   for (size_t i = 0; i < cand.size(); ++i) {
     // an order event with the next candidate
     if (i + 1 < cand.size()) {
       const double za = S.proj[cand[i]].x[2], zb = S.proj[cand[i + 1]].x[2];
       if (std::fabs(zb - za) <= opt.amb_z * zb) {
-        if (ev == flip) {
+        if (flipped(ev)) {
           std::swap(cand[i], cand[i + 1]);
           std::swap(raw_alpha[i], raw_alpha[i + 1]);
         }
         ++ev;
-        tie = true;
       }
     }
     const int64_t k = cand[i];
@@ -386,20 +400,20 @@ void composite_pixel(const Scene& S, int px, int py, bool pruned, int flip, bool
     const double raw = g.o * e;
     bool clamped = raw > opt.amax;
     if (std::fabs(raw - opt.amax) <= opt.amb_rel * opt.amax) {
-      if (ev == flip) clamped = !clamped;
+      if (flipped(ev)) clamped = !clamped;
       ++ev;
     }
     const double alpha = std::min(opt.amax, raw);
     bool skip = alpha < opt.amin;
     if (std::fabs(alpha - opt.amin) <= opt.amb_rel * opt.amin) {
-      if (ev == flip) skip = !skip;
+      if (flipped(ev)) skip = !skip;
       ++ev;
     }
     if (skip) continue;
     const double Tn = T * (1.0 - alpha);
     bool stop = Tn < opt.tmin;
     if (std::fabs(Tn - opt.tmin) <= opt.amb_rel * opt.tmin) {
-      if (ev == flip) stop = !stop;
+      if (flipped(ev)) stop = !stop;
       ++ev;
     }
     mix((uint64_t)k * 4 + (stop ? 1 : 0) + (clamped ? 2 : 0));
@@ -410,14 +424,12 @@ void composite_pixel(const Scene& S, int px, int py, bool pruned, int flip, bool
     T = Tn;
     ++nc;
   }
-  (void)tie;
   for (int ch = 0; ch < 3; ++ch) r.C[ch] = C[ch] + T * S.cam.bg[ch];
   r.D = D;
   r.A = 1.0 - T;
   r.T = T;
   r.ncomp = nc;
   r.events = ev;
-  r.tie = false;  // ties are events with a swapped alternate branch
   r.hash = h;
 }
 
@@ -670,7 +682,7 @@ int orc_project(int64_t n, const double* means, const double* scales, const doub
 // pix = NULL renders every pixel, else only the npix listed linear indices.
 // Outputs are full-size planar arrays; unlisted pixels are left untouched.
 // amb: 0 = no ambiguity, 1 = one event (alt_* hold the flipped branch),
-//      2 = unverifiable (two or more events, or a near depth tie).
+//      2 = unverifiable image values (two or more events).
 int orc_render(int64_t n, const double* means, const double* scales, const double* quats,
                const double* opac, const double* colors, const double* pose7, const double* cam,
                const double* opt, int mode, int64_t npix, const int64_t* pix, int nthreads,
@@ -687,20 +699,18 @@ int orc_render(int64_t n, const double* means, const double* scales, const doubl
     for (int64_t i = b; i < e; ++i) {
       const int64_t p = pix ? pix[i] : i;
       const int px = (int)(p % W), py = (int)(p / W);
-      composite_pixel(S, px, py, mode == 1, -1, false, r);
+      composite_pixel(S, px, py, mode == 1, 0, false, r);
       for (int ch = 0; ch < 3; ++ch) color[ch * P + p] = r.C[ch];
       depth[p] = r.D;
       alpha[p] = r.A;
       if (Tfin) Tfin[p] = r.T;
       if (ncomp) ncomp[p] = r.ncomp;
       if (dec_hash) dec_hash[p] = r.hash;
-      int a = 0;
-      if (r.events == 1 && !r.tie) a = 1;
-      if (r.events >= 2 || r.tie) a = 2;
+      int a = r.events == 0 ? 0 : r.events == 1 ? 1 : 2;
       if (amb) amb[p] = a;
       if (a == 1) {
-        composite_pixel(S, px, py, mode == 1, 0, false, ra);
-        if (ra.events != 1 || ra.tie) a = 2;
+        composite_pixel(S, px, py, mode == 1, 1, false, ra);
+        if (ra.events != 1) a = 2;
         if (amb) amb[p] = a;
       }
       if (alt_color) {
@@ -720,9 +730,12 @@ int orc_render(int64_t n, const double* means, const double* scales, const doubl
 //   means 3n | scales 3n | quats 4n | opacities n | colors 3n | pose7 | twist6
 // (g2d: [n,10]). aref = sum over pixels of absolute per-pixel terms, chained
 // with absolute Jacobians (an upper bound used as a tolerance floor). slack =
-// per-element |branch difference| over one-event ambiguous pixels.
-// Returns the number of unverifiable pixels among those with nonzero upstream
-// gradient (their contributions are still included, on the primary branch).
+// sum over pixels of the per-element maximum |branch - primary| over every
+// decision path of the pixel (absolute Jacobians again).
+// Returns the number of unverifiable pixels (more than kMaxEventBits events, or
+// a chain of three or more depth ties)
+// among those with nonzero upstream gradient: their contributions are included
+// on the primary branch and every candidate Gaussian of theirs gets slack 1e30.
 int64_t orc_backward(int64_t n, const double* means, const double* scales, const double* quats,
                      const double* opac, const double* colors, const double* pose7, const double* cam,
                      const double* opt, int mode, int64_t npix, const int64_t* pix, int nthreads,
@@ -744,50 +757,73 @@ int64_t orc_backward(int64_t n, const double* means, const double* scales, const
   }
   parallel_for(cnt, nthreads, [&](int t, int64_t b, int64_t e) {
     PixResult r, ra;
-    std::vector<G2> c1, c2;
+    std::vector<G2> c1, c2, maxd;
     for (int64_t i = b; i < e; ++i) {
       const int64_t p = pix ? pix[i] : i;
       const int px = (int)(p % W), py = (int)(p / W);
       const double g3[3] = {gC[p], gC[P + p], gC[2 * P + p]};
       const double gd = gD[p], ga = gA ? gA[p] : 0.0;
       if (g3[0] == 0 && g3[1] == 0 && g3[2] == 0 && gd == 0 && ga == 0) continue;
-      composite_pixel(S, px, py, mode == 1, -1, true, r);
+      composite_pixel(S, px, py, mode == 1, 0, true, r);
       pixel_backward(S, r, g3, gd, ga, c1);
       for (const G2& c : c1)
         for (int f = 0; f < 10; ++f) {
           acc[t][10 * c.id + f] += c.g[f];
           aabs[t][10 * c.id + f] += std::fabs(c.g[f]);
         }
-      int a = 0;
-      if (r.events == 1 && !r.tie) a = 1;
-      if (r.events >= 2 || r.tie) a = 2;
-      if (a == 1) {
-        composite_pixel(S, px, py, mode == 1, 0, true, ra);
-        if (ra.events != 1 || ra.tie) {
-          a = 2;
-        } else {
+      if (r.events == 0) continue;
+      // every other decision path of this pixel: per-element max |branch - primary|
+      maxd.clear();
+      auto merge = [&](int64_t id, const double* d) {
+        for (G2& m : maxd)
+          if (m.id == id) {
+            for (int f = 0; f < 10; ++f) m.g[f] = std::max(m.g[f], std::fabs(d[f]));
+            return;
+          }
+        G2 m{id, {}};
+        for (int f = 0; f < 10; ++f) m.g[f] = std::fabs(d[f]);
+        maxd.push_back(m);
+      };
+      int width = r.events;
+      uint64_t next = 1;
+      bool complete = width <= kMaxEventBits && !r.tie3;
+      while (complete) {
+        const uint64_t lim = 1ull << width;
+        int widest = width;
+        for (uint64_t m = next; m < lim; ++m) {
+          composite_pixel(S, px, py, mode == 1, m, true, ra);
+          widest = std::max(widest, ra.events);
           pixel_backward(S, ra, g3, gd, ga, c2);
-          // per-Gaussian difference of the two branches' contributions
-          std::vector<G2> diff = c1;
           for (const G2& c : c2) {
-            bool found = false;
-            for (G2& d : diff)
-              if (d.id == c.id) {
-                for (int f = 0; f < 10; ++f) d.g[f] -= c.g[f];
-                found = true;
+            double d[10];
+            for (int f = 0; f < 10; ++f) d[f] = c.g[f];
+            for (const G2& b : c1)
+              if (b.id == c.id) {
+                for (int f = 0; f < 10; ++f) d[f] -= b.g[f];
                 break;
               }
-            if (!found) {
-              G2 m = c;
-              for (int f = 0; f < 10; ++f) m.g[f] = -m.g[f];
-              diff.push_back(m);
-            }
+            merge(c.id, d);
           }
-          for (const G2& d : diff)
-            for (int f = 0; f < 10; ++f) aslk[t][10 * d.id + f] += std::fabs(d.g[f]);
+          for (const G2& b : c1) {
+            bool in2 = false;
+            for (const G2& c : c2) in2 = in2 || c.id == b.id;
+            if (!in2) merge(b.id, b.g);
+          }
         }
+        next = lim;
+        if (widest <= width) break;
+        if (widest > kMaxEventBits) complete = false;
+        width = widest;
       }
-      if (a == 2) unver[t]++;
+      if (complete) {
+        for (const G2& m : maxd)
+          for (int f = 0; f < 10; ++f) aslk[t][10 * m.id + f] += m.g[f];
+      } else {
+        // too many events to enumerate: exclude every candidate of this pixel
+        unver[t]++;
+        for (int64_t id : r.cand)
+          for (int f = 0; f < 10; ++f) aslk[t][10 * id + f] = 1e30;
+      }
     }
   });
   std::vector<double> g2(10 * n, 0.0), ab2(10 * n, 0.0), sl2(10 * n, 0.0);

@@ -149,3 +149,48 @@ def test_zero_upstream_gives_zero_gradient_and_ground_truth_pose_is_stationary()
     assert L == 0 and not gC.any() and not gD.any()
     b = oracle.backward(g, pose, cam, opts, gC, gD, nthreads=4)
     assert all(not v.any() for v in b["grads"].values())
+
+
+def _slack_scene():
+    """Four Gaussians over one pixel: two depth ties (z = 2 and z = 3), so the
+    pixel has two order events and four decision paths."""
+    mk = lambda z, col, o: dict(means=[0.01 * z, -0.02 * z, z], scales=[0.06, 0.05, 0.05], quats=[1, 0, 0, 0],
+                                opacities=o, colors=col)
+    parts = [mk(2.0, [1, 0, 0], 0.5), mk(2.0, [0, 1, 0], 0.4), mk(3.0, [0, 0, 1], 0.6), mk(3.0, [1, 1, 0], 0.3)]
+    g = {k: np.array([p[k] for p in parts], np.float64) for k in parts[0]}
+    return g
+
+
+def test_backward_slack_covers_every_decision_path():
+    """The slack of a pixel with two order events covers the gradient of each
+    of its four decision paths, each computed independently as the primary
+    branch of a permuted input; a pixel of a three-way tie chain is reported
+    unverifiable."""
+    g = _slack_scene()
+    cam = oracle.Camera(64, 48, 60.0, 60.0, 32.0, 24.0, 0.2, (0.1, 0.2, 0.3))
+    pose = np.array([1.0, 0, 0, 0, 0, 0, 0])
+    opts = oracle.Opts(amb_z=1e-9)
+    gC = np.zeros((3, 48, 64)); gD = np.zeros((48, 64))
+    gC[:, 24, 32] = [0.3, -0.7, 0.5]; gD[24, 32] = 0.9
+    ref = oracle.backward(g, pose, cam, opts, gC, gD, pixels=np.array([24 * 64 + 32]))
+    assert ref["n_unverifiable"] == 0
+    plain = oracle.Opts(amb_z=0.0)
+    seen = 0
+    for perm in ([0, 1, 2, 3], [1, 0, 2, 3], [0, 1, 3, 2], [1, 0, 3, 2]):
+        gp = {k: v[perm].copy() for k, v in g.items()}
+        out = oracle.backward(gp, pose, cam, plain, gC, gD, pixels=np.array([24 * 64 + 32]))
+        inv = np.argsort(perm)
+        for k in ("means", "scales", "opacities", "colors"):
+            branch = out["grads"][k][inv]
+            diff = np.abs(branch - ref["grads"][k])
+            assert np.all(diff <= ref["slack"][k] * (1 + 1e-9) + 1e-15), (perm, k)
+            seen += int(diff.max() > 1e-6)
+    assert seen >= 3  # the branches really differ
+    # the slack is no larger than the largest branch difference summed over elements' own maxima
+    assert ref["slack"]["colors"].max() < 1.0
+    # three Gaussians tied at z = 2: unverifiable for the backward
+    g3 = {k: np.concatenate([v[:2], v[:1]]) for k, v in g.items()}
+    g3["colors"][2] = [0, 0, 1]
+    ref3 = oracle.backward(g3, pose, cam, opts, gC, gD, pixels=np.array([24 * 64 + 32]))
+    assert ref3["n_unverifiable"] == 1
+    assert ref3["slack"]["colors"].min() > 1e20
