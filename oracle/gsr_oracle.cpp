@@ -446,28 +446,72 @@ struct G2 {
   double g[10];
 };
 
+// Rounding error bound of an FP32 evaluation of the screen position (Eq. 1):
+// each coordinate of the camera-space mean x = R mu + t carries a few ulps of
+// |R||mu| + |t|, and u = fx x / z + cx a few ulps of |u| more (eight and four
+// ulps are taken).
+void screen_delta(const Scene& S, const Proj& g, double& du, double& dv) {
+  const double ulp = std::ldexp(1.0, -24);
+  // |R mu| = |mu| <= |x| + |t| (R is a rotation), so |R||mu| + |t| <= |x| + 2 |t|
+  const double tn = std::sqrt(S.P.t[0] * S.P.t[0] + S.P.t[1] * S.P.t[1] + S.P.t[2] * S.P.t[2]);
+  const double xn = std::sqrt(g.x[0] * g.x[0] + g.x[1] * g.x[1] + g.x[2] * g.x[2]);
+  const double dcam = 8 * ulp * (xn + 2 * tn);
+  const double z = g.x[2];
+  du = 4 * ulp * std::fabs(g.u) + S.cam.fx / z * (dcam + std::fabs(g.x[0] / z) * dcam);
+  dv = 4 * ulp * std::fabs(g.v) + S.cam.fy / z * (dcam + std::fabs(g.x[1] / z) * dcam);
+}
+
+// With `mag` non-NULL it also receives, per pair, the same ten terms with every
+// factor replaced by its magnitude and every sum (in particular the two terms
+// of dC/dalpha and Eq. 8, which nearly cancel where a Gaussian matches what
+// lies behind it) by the sum of magnitudes, times the pixel's transmittance
+// condition number kappa = 1 + sum_k alpha_k / (1 - alpha_k) (a relative
+// error e in every alpha_k moves every T_j by at most kappa e): the scale
+// FP32 rounding acts on.
+//
+// With `pos` non-NULL it receives, per pair, a first-order bound of how much
+// the ten terms move when the Gaussian's screen position (u, v) carries the
+// rounding error of its FP32 evaluation, delta_u and delta_v (screen_delta):
+// next to a Gaussian's centre, dx = px - u is small and that rounding is a
+// large part of it.
 void pixel_backward(const Scene& S, const PixResult& r, const double gC[3], double gD, double gA,
-                    std::vector<G2>& out) {
+                    std::vector<G2>& out, std::vector<G2>* mag = nullptr, std::vector<G2>* pos = nullptr) {
   out.clear();
-  double SC[3], SD = 0;
-  for (int ch = 0; ch < 3; ++ch) SC[ch] = r.T * S.cam.bg[ch];
+  if (mag) mag->clear();
+  if (pos) pos->clear();
+  double SC[3], SD = 0, MC[3], MD = 0;
+  for (int ch = 0; ch < 3; ++ch) {
+    SC[ch] = r.T * S.cam.bg[ch];
+    MC[ch] = std::fabs(SC[ch]);
+  }
   const double Tfin = r.T;
+  double kappa = 1.0;
+  for (const Pair& p : r.pairs) kappa += p.alpha / (1.0 - p.alpha);
   for (int j = (int)r.pairs.size() - 1; j >= 0; --j) {
     const Pair& p = r.pairs[j];
     const Proj& g = S.proj[p.id];
-    G2 c;
-    c.id = p.id;
-    for (int f = 0; f < 10; ++f) c.g[f] = 0;
+    G2 c, m;
+    c.id = m.id = p.id;
+    for (int f = 0; f < 10; ++f) c.g[f] = m.g[f] = 0;
     const double w = p.alpha * p.T;
     for (int ch = 0; ch < 3; ++ch) c.g[6 + ch] = w * gC[ch];
     c.g[9] = w * gD;
     const double inv = 1.0 / (1.0 - p.alpha);
-    double dA = 0;
-    for (int ch = 0; ch < 3; ++ch) dA += gC[ch] * (g.col[ch] * p.T - SC[ch] * inv);
+    double dA = 0, mA = 0;
+    for (int ch = 0; ch < 3; ++ch) {
+      dA += gC[ch] * (g.col[ch] * p.T - SC[ch] * inv);
+      mA += std::fabs(gC[ch]) * (std::fabs(g.col[ch]) * p.T + MC[ch] * inv);
+    }
     dA += gD * (g.x[2] * p.T - SD * inv);
+    mA += std::fabs(gD) * (std::fabs(g.x[2]) * p.T + MD * inv);
     dA += gA * Tfin * inv;
-    for (int ch = 0; ch < 3; ++ch) SC[ch] += g.col[ch] * w;
+    mA += std::fabs(gA) * Tfin * inv;
+    for (int ch = 0; ch < 3; ++ch) {
+      SC[ch] += g.col[ch] * w;
+      MC[ch] += std::fabs(g.col[ch]) * w;
+    }
     SD += g.x[2] * w;
+    MD += std::fabs(g.x[2]) * w;
     if (!p.clamped) {
       c.g[5] = dA * p.e;  // d alpha / d o = exp(-sigma)
       const double gs = -dA * p.alpha;  // d alpha / d sigma = -alpha
@@ -476,8 +520,40 @@ void pixel_backward(const Scene& S, const PixResult& r, const double gC[3], doub
       c.g[4] = gs * 0.5 * p.dy * p.dy;
       c.g[0] = gs * -(g.a * p.dx + g.b * p.dy);
       c.g[1] = gs * -(g.b * p.dx + g.c * p.dy);
+      if (mag) {
+        const double ms = mA * p.alpha;
+        m.g[5] = mA * p.e;
+        m.g[2] = ms * 0.5 * p.dx * p.dx;
+        m.g[3] = ms * std::fabs(p.dx * p.dy);
+        m.g[4] = ms * 0.5 * p.dy * p.dy;
+        m.g[0] = ms * (std::fabs(g.a * p.dx) + std::fabs(g.b * p.dy));
+        m.g[1] = ms * (std::fabs(g.b * p.dx) + std::fabs(g.c * p.dy));
+      }
     }
     out.push_back(c);
+    if (mag) {
+      for (int f = 6; f < 10; ++f) m.g[f] = std::fabs(c.g[f]);
+      for (int f = 0; f < 10; ++f) m.g[f] *= kappa;
+      mag->push_back(m);
+    }
+    if (pos) {
+      double du, dv;
+      screen_delta(S, g, du, dv);
+      G2 d;
+      d.id = p.id;
+      // alpha moves by alpha |d sigma / d(u, v)| (delta_u, delta_v); every term is linear in alpha
+      const double ea = std::fabs(g.a * p.dx + g.b * p.dy) * du + std::fabs(g.b * p.dx + g.c * p.dy) * dv;
+      for (int f = 0; f < 10; ++f) d.g[f] = std::fabs(c.g[f]) * ea;
+      if (!p.clamped) {
+        const double as = std::fabs(dA * p.alpha);
+        d.g[0] += as * (std::fabs(g.a) * du + std::fabs(g.b) * dv);
+        d.g[1] += as * (std::fabs(g.b) * du + std::fabs(g.c) * dv);
+        d.g[2] += as * std::fabs(p.dx) * du;
+        d.g[3] += as * (std::fabs(p.dy) * du + std::fabs(p.dx) * dv);
+        d.g[4] += as * std::fabs(p.dy) * dv;
+      }
+      pos->push_back(d);
+    }
   }
 }
 
@@ -728,10 +804,12 @@ int orc_render(int64_t n, const double* means, const double* scales, const doubl
 // gD [H,W], gA [H,W] (NULL = 0) over the listed pixels (NULL = all).
 // gflat / aref / slack / g2d use the flat layout
 //   means 3n | scales 3n | quats 4n | opacities n | colors 3n | pose7 | twist6
-// (g2d: [n,10]). aref = sum over pixels of absolute per-pixel terms, chained
-// with absolute Jacobians (an upper bound used as a tolerance floor). slack =
+// (g2d: [n,10]). aref = sum over pixels of the per-pixel term magnitudes of
+// pixel_backward (sums of magnitudes before any cancellation), chained with
+// absolute Jacobians: the scale of FP32 rounding, used as a tolerance floor. slack =
 // sum over pixels of the per-element maximum |branch - primary| over every
-// decision path of the pixel (absolute Jacobians again).
+// decision path of the pixel, plus the FP32 screen-position bound of
+// pixel_backward (absolute Jacobians again).
 // Returns the number of unverifiable pixels (more than kMaxEventBits events, or
 // a chain of three or more depth ties)
 // among those with nonzero upstream gradient: their contributions are included
@@ -757,7 +835,7 @@ int64_t orc_backward(int64_t n, const double* means, const double* scales, const
   }
   parallel_for(cnt, nthreads, [&](int t, int64_t b, int64_t e) {
     PixResult r, ra;
-    std::vector<G2> c1, c2, maxd;
+    std::vector<G2> c1, c2, cm, cpos, maxd;
     for (int64_t i = b; i < e; ++i) {
       const int64_t p = pix ? pix[i] : i;
       const int px = (int)(p % W), py = (int)(p / W);
@@ -765,11 +843,12 @@ int64_t orc_backward(int64_t n, const double* means, const double* scales, const
       const double gd = gD[p], ga = gA ? gA[p] : 0.0;
       if (g3[0] == 0 && g3[1] == 0 && g3[2] == 0 && gd == 0 && ga == 0) continue;
       composite_pixel(S, px, py, mode == 1, 0, true, r);
-      pixel_backward(S, r, g3, gd, ga, c1);
-      for (const G2& c : c1)
+      pixel_backward(S, r, g3, gd, ga, c1, &cm, &cpos);
+      for (size_t q = 0; q < c1.size(); ++q)
         for (int f = 0; f < 10; ++f) {
-          acc[t][10 * c.id + f] += c.g[f];
-          aabs[t][10 * c.id + f] += std::fabs(c.g[f]);
+          acc[t][10 * c1[q].id + f] += c1[q].g[f];
+          aabs[t][10 * c1[q].id + f] += cm[q].g[f];
+          aslk[t][10 * c1[q].id + f] += cpos[q].g[f];
         }
       if (r.events == 0) continue;
       // every other decision path of this pixel: per-element max |branch - primary|
