@@ -154,6 +154,161 @@ def bench_tracking(seed: int, n: int, frames: int) -> dict:
             "final_error_cm_deg": [round(100 * e1[0], 4), round(e1[1], 4)]}
 
 
+def bench_batched(seed: int, n: int, reps: int) -> dict:
+    """Multi-keyframe mapping: a 1,000,000-Gaussian sub-map seeded from 16
+    views of a procedural room, 8 keyframes at 1200x680 chosen so that their
+    visible fractions spread over about 10-70 %. One fwd + L1 + bwd over all 8
+    views with one sort and one compositing launch each way (tile shape and
+    blocks per CU from the autotuner) against 8 sequential single-view passes."""
+    import torch
+    from paper_2312_10070_amd import gsr, synth
+    inp = synth.batched_inputs(seed, n)
+    cam_i = inp["camera"]
+    cam = gsr.camera_from(cam_i)
+    g = {k: torch.from_numpy(v).cuda() for k, v in inp["gaussians"].items()}
+    args = (g["means"], g["scales"], g["quats"], g["opacities"], g["colors"])
+    cands = inp["candidate_views"]
+    vis = []
+    for pose in cands:
+        _, _, _, st = gsr.render_fwd(*args, torch.from_numpy(pose).cuda(), cam)
+        vis.append(gsr.state_stats(st)["visible"] / n)
+        st.release()
+    vis = np.array(vis)
+    chosen = []
+    for target in np.linspace(0.10, 0.70, inp["n_views"]):
+        order = np.argsort(np.abs(vis - target))
+        chosen.append(next(int(i) for i in order if int(i) not in chosen))
+    poses_np = np.stack([cands[i] for i in chosen])
+    frames = [synth.render_frame(inp["room"], cam_i, p) for p in poses_np]
+    tgt_c = torch.from_numpy(np.stack([f[0] for f in frames]).astype(np.float32)).cuda()
+    tgt_d = torch.from_numpy(np.stack([f[1] for f in frames]).astype(np.float32)).cuda()
+    poses = torch.from_numpy(poses_np).cuda()
+    V = poses.shape[0]
+
+    # upstream gradients for the autotuner: the L1 gradients at the current parameters
+    cb, db, ab, st = gsr.render_fwd_batch(*args, poses, cam)
+    _, gC, gD = gsr.loss_l1(cb, db, tgt_c, tgt_d)
+    st.release()
+    opts, bpc, table = gsr.autotune_batch(*args, poses, cam, gC, gD)
+
+    def batched():
+        c, d, a, s = gsr.render_fwd_batch(*args, poses, cam, opts, blocks_per_cu=bpc)
+        _, gc, gd = gsr.loss_l1(c, d, tgt_c, tgt_d)
+        out = gsr.render_bwd(s, gc, gd, None, want_params=True, want_pose=False)
+        s.release()
+        return out
+
+    def sequential():
+        outs = []
+        for v in range(V):
+            c, d, a, s = gsr.render_fwd(*args, poses[v].contiguous(), cam)
+            _, gc, gd = gsr.loss_l1(c, d, tgt_c[v], tgt_d[v])
+            outs.append(gsr.render_bwd(s, gc, gd, None, want_params=True, want_pose=False))
+            s.release()
+        return outs
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_b = timed(batched)
+    ms_s = timed(sequential)
+    return {"workload": "8 keyframes 1200x680, %d Gaussians, fwd + L1 loss + bwd of all views" % n,
+            "visible_fraction": [round(float(vis[i]), 3) for i in chosen],
+            "tile": "%dx%d" % (opts.tile_w, opts.tile_h), "blocks_per_cu": int(bpc),
+            "ms_batched": round(ms_b, 3), "ms_sequential": round(ms_s, 3),
+            "speedup": round(ms_s / ms_b, 3), "reps": reps}
+
+
+def bench_initnet(seed: int, n: int, frames: int, train_pairs: int, train_steps: int) -> dict:
+    """Learned tracking initialisation on tracking frames (640x480, n
+    Gaussians, 2 cm / 1 degree perturbation): the CNN is trained on pairs
+    rendered at 320x240 (the same field of view) from random procedural
+    rooms. Per frame, the target error is plain tracking's final error after
+    100 iterations (+5 %, floor 0.5 mm); reported are the iterations and
+    ms/frame plain tracking (from the initial pose) and learned tracking (from
+    the proposal, kept when the tracking loss prefers it) need to reach it."""
+    import torch
+    from paper_2312_10070_amd import gsr, initnet, synth, tracking
+    half = synth.Intrinsics(320, 240, 262.5, 262.5, 160.0, 120.0)
+    t0 = time.perf_counter()
+    x, y = initnet.generate_pairs(train_pairs, seed=1000 + seed, cam=half)
+    net = gsr.InitNet(max_batch=64)
+    net.set_params(torch.from_numpy(initnet.init_params(seed)).cuda())
+    initnet.train(net, x, y, steps=train_steps, batch=64, lr=2e-3)
+    del x, y
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    budgets = (10, 15, 20, 30, 40, 50, 60, 80, 100)
+    rows = []
+    for f in range(frames):
+        inp = synth.tracking_inputs(200 + 17 * seed + f, n)
+        cam = gsr.camera_from(inp["camera"])
+        g = {k: torch.from_numpy(v).cuda() for k, v in inp["gaussians"].items()}
+        args = (g["means"], g["scales"], g["quats"], g["opacities"], g["colors"])
+        oc, od, _, st = gsr.render_fwd(*args, torch.from_numpy(inp["gt_pose7"]).cuda(), cam)
+        st.release()
+        init = torch.from_numpy(inp["init_pose7"]).cuda()
+        kcap = tracking.overlap_capacity(*args, init, cam)
+        graphs = {b: gsr.TrackGraph(*args, cam, oc, od, n_iters=b, K_cap=kcap) for b in budgets}
+        for tg in graphs.values():  # warm-up (graph upload)
+            tg.run(init.clone())
+        torch.cuda.synchronize()
+
+        def run(b, start):
+            q = start.clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            graphs[b].run(q)
+            ms = (time.perf_counter() - t) * 1e3
+            return ms, synth.pose_error(q.cpu().numpy(), inp["gt_pose7"])[0]
+
+        _, e100 = run(100, init)
+        thr = max(1.05 * e100, 5e-4)
+
+        def first_reaching(start):
+            for b in budgets:
+                ms, e = run(b, start)
+                if e <= thr:
+                    return b, ms
+            return None, None
+
+        n_plain, ms_plain = first_reaching(init)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        start, used, _, _ = initnet.propose(net, args, cam, oc, od, init)
+        torch.cuda.synchronize()
+        ms_prop = (time.perf_counter() - t) * 1e3
+        e_start = synth.pose_error(start.cpu().numpy(), inp["gt_pose7"])[0]
+        n_learn, ms_learn = first_reaching(start)
+        for tg in graphs.values():
+            tg.close()
+        rows.append(dict(thr=thr, n_plain=n_plain, ms_plain=ms_plain, used=used, e_start=e_start,
+                         n_learn=n_learn, ms_learn=(ms_prop + ms_learn) if n_learn else None, ms_prop=ms_prop))
+    mean = lambda k: (round(float(np.mean([r[k] for r in rows if r[k] is not None])), 3)
+                      if any(r[k] is not None for r in rows) else None)
+    return {"workload": "tracking frames 640x480, %d Gaussians; CNN trained on %d pairs x %d steps (%.0f s)"
+                        % (n, train_pairs, train_steps, t_train),
+            "frames": frames,
+            "target_error_cm": [round(100 * r["thr"], 4) for r in rows],
+            "iterations_plain": [r["n_plain"] for r in rows],
+            "iterations_learned": [r["n_learn"] for r in rows],
+            "ms_per_frame_plain": mean("ms_plain"),
+            "ms_per_frame_learned": mean("ms_learn"),
+            "ms_proposal": mean("ms_prop"),
+            "proposal_error_cm": [round(100 * r["e_start"], 3) for r in rows],
+            "proposal_used": int(sum(r["used"] for r in rows)),
+            "fallback_rate": round(1.0 - sum(r["used"] for r in rows) / len(rows), 3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +320,13 @@ def main() -> int:
     ap.add_argument("--cpu-rows-every", type=int, default=68)
     ap.add_argument("--no-tracking", action="store_true")
     ap.add_argument("--tracking-frames", type=int, default=5)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-gaussians", type=int, default=1_000_000)
+    ap.add_argument("--batched-reps", type=int, default=5)
+    ap.add_argument("--no-initnet", action="store_true")
+    ap.add_argument("--initnet-frames", type=int, default=3)
+    ap.add_argument("--initnet-pairs", type=int, default=12288)
+    ap.add_argument("--initnet-steps", type=int, default=2500)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -259,6 +421,15 @@ def main() -> int:
     if not args.no_tracking:
         track = bench_tracking(args.seed, args.gaussians, args.tracking_frames)
 
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(args.seed, args.batched_gaussians, args.batched_reps)
+
+    learned = None
+    if not args.no_initnet:
+        learned = bench_initnet(args.seed, args.gaussians, args.initnet_frames, args.initnet_pairs,
+                                args.initnet_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, 16)
@@ -285,6 +456,8 @@ def main() -> int:
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(stages.items())},
         "work": stats,
         "tracking": track,
+        "batched_mapping": batched,
+        "learned_init": learned,
         "loss": float(loss.item()),
     }
     print(json.dumps(line), flush=True)

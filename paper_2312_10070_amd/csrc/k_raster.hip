@@ -1,10 +1,10 @@
 // Per-tile compositing. One 256-thread workgroup per (view, tile) item, one
-// pixel per lane. Gaussian records of the item's depth-sorted list are staged
+// pixel per lane, one 8x8 pixel block per wave. Gaussian records of the item's depth-sorted list are staged
 // through LDS in batches of 256 (one coalesced fetch per record per
 // workgroup). Each wave then ballots, 64 records at a time, which records'
-// support boxes overlap its own pixel strip, and visits only those, in list
+// support boxes overlap its own pixel block, and visits only those, in list
 // order, with the record broadcast from LDS. Skipping a record whose box
-// misses the strip cannot change the result: outside its box a Gaussian has
+// misses the block cannot change the result: outside its box a Gaussian has
 // alpha < alpha_min.
 //
 // Forward: front to back (Eq. 3 colour, Eq. 4 alpha, Eq. 6 depth). A lane
@@ -28,8 +28,8 @@ namespace gsr {
 
 namespace {
 
-struct Strip {
-  int x0, x1, y0, y1;  // inclusive pixel rectangle of a wave
+struct Block {
+  int x0, x1, y0, y1;  // inclusive pixel rectangle of a wave (8x8)
 };
 
 struct Pixel {
@@ -39,40 +39,44 @@ struct Pixel {
   float fpx, fpy;
   int64_t p;    // pixel index inside the view
   int64_t off;  // view * W * H
-  Strip strip;
+  Block blk;
 };
 
+// Each wave covers one 8x8 pixel block of the tile (a square block meets fewer
+// support boxes than a 16x4 or 32x2 strip); the four blocks are row-major in
+// the tile, lanes row-major in the block.
 __device__ __forceinline__ Pixel item_pixel(const Raster& Rr, int item) {
   Pixel q;
   q.view = item / Rr.n_tiles;
   q.tile = item - q.view * Rr.n_tiles;
   const int tyi = q.tile / Rr.ntx, txi = q.tile - tyi * Rr.ntx;
-  const int tid = threadIdx.x;
-  q.px = txi * Rr.tw + (tid & (Rr.tw - 1));
-  q.py = tyi * Rr.th + (tid >> Rr.tw_log2);
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int bpr_log2 = Rr.tw_log2 - 3;  // 8x8 blocks per tile row: 1, 2 or 4
+  const int bx = w & ((1 << bpr_log2) - 1), by = w >> bpr_log2;
+  q.blk.x0 = txi * Rr.tw + 8 * bx;
+  q.blk.x1 = q.blk.x0 + 7;
+  q.blk.y0 = tyi * Rr.th + 8 * by;
+  q.blk.y1 = q.blk.y0 + 7;
+  q.px = q.blk.x0 + (l & 7);
+  q.py = q.blk.y0 + (l >> 3);
   q.inside = q.px < Rr.W && q.py < Rr.H;
   q.fpx = (float)q.px;
   q.fpy = (float)q.py;
   q.p = (int64_t)q.py * Rr.W + q.px;
   q.off = (int64_t)q.view * Rr.W * Rr.H;
-  const int rows = kWave >> Rr.tw_log2;  // pixel rows per wave
-  q.strip.x0 = txi * Rr.tw;
-  q.strip.x1 = q.strip.x0 + Rr.tw - 1;
-  q.strip.y0 = tyi * Rr.th + (tid >> 6) * rows;
-  q.strip.y1 = q.strip.y0 + rows - 1;
   return q;
 }
 
-// Does the packed support box (bx = x0 | x1 << 16, by = y0 | y1 << 16) meet the strip?
-__device__ __forceinline__ bool box_meets(float fbx, float fby, const Strip& s) {
+// Does the packed support box (bx = x0 | x1 << 16, by = y0 | y1 << 16) meet the block?
+__device__ __forceinline__ bool box_meets(float fbx, float fby, const Block& s) {
   const uint32_t bx = __float_as_uint(fbx), by = __float_as_uint(fby);
   const int x0 = (int)(bx & 0xffffu), x1 = (int)(bx >> 16), y0 = (int)(by & 0xffffu), y1 = (int)(by >> 16);
-  return x0 <= s.x1 && x1 >= s.x0 && y0 <= s.y1 && y1 >= s.y0;
+  return (x0 <= s.x1) & (x1 >= s.x0) & (y0 <= s.y1) & (y1 >= s.y0);  // no short-circuit branches
 }
 
 __device__ __forceinline__ bool box_holds(float fbx, float fby, int px, int py) {
   const uint32_t bx = __float_as_uint(fbx), by = __float_as_uint(fby);
-  return px >= (int)(bx & 0xffffu) && px <= (int)(bx >> 16) && py >= (int)(by & 0xffffu) && py <= (int)(by >> 16);
+  return (px >= (int)(bx & 0xffffu)) & (px <= (int)(bx >> 16)) & (py >= (int)(by & 0xffffu)) & (py <= (int)(by >> 16));
 }
 
 struct FwdSmem {
@@ -121,34 +125,31 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
       bool meets = false;
       if (r < cnt) {
         const float4 cb = sm.cob[r];
-        meets = box_meets(cb.z, cb.w, q.strip);
+        meets = box_meets(cb.z, cb.w, q.blk);
       }
       uint64_t m = __ballot(meets);
       while (m) {
         const int j = c * kWave + __builtin_ctzll(m);
         m &= m - 1;
-        if (!done) {
-          const float4 g = sm.uvab[j];
-          const float4 cb = sm.cob[j];
-          const PairEval pe = eval_pair(q.fpx - g.x, q.fpy - g.y, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
-          if (STATS && box_holds(cb.z, cb.w, q.px, q.py)) ++n_eval;
-          if (pe.use) {
-            const float Tn = T * (1.f - pe.alpha);
-            if (Tn < Rr.tmin) {
-              done = true;
-            } else {
-              const float4 cz = sm.rgbz[j];
-              const float w = pe.alpha * T;
-              C0 = fmaf(cz.x, w, C0);
-              C1 = fmaf(cz.y, w, C1);
-              C2 = fmaf(cz.z, w, C2);
-              D = fmaf(cz.w, w, D);
-              T = Tn;
-              last = base - start + j + 1;
-              if (STATS) ++n_comp;
-            }
-          }
-        }
+        // Every lane runs the same instructions; a lane that does not composite
+        // this record adds w = 0 and keeps its transmittance.
+        const float4 g = sm.uvab[j];
+        const float4 cb = sm.cob[j];
+        const float4 cz = sm.rgbz[j];
+        const PairEval pe = eval_pair(q.fpx - g.x, q.fpy - g.y, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
+        if (STATS && !done && box_holds(cb.z, cb.w, q.px, q.py)) ++n_eval;
+        const float Tn = T * (1.f - pe.alpha);
+        const bool live = !done && pe.use;
+        const bool comp = live && Tn >= Rr.tmin;
+        done = done || (live && Tn < Rr.tmin);
+        const float w = comp ? pe.alpha * T : 0.f;
+        C0 = fmaf(cz.x, w, C0);
+        C1 = fmaf(cz.y, w, C1);
+        C2 = fmaf(cz.z, w, C2);
+        D = fmaf(cz.w, w, D);
+        T = comp ? Tn : T;
+        last = comp ? base - start + j + 1 : last;
+        if (STATS && comp) ++n_comp;
         if (!__any(!done)) {
           wave_done = true;
           break;
@@ -230,7 +231,7 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
       bool meets = false;
       if (r < cnt) {
         const float4 cb = sm.cob[r];
-        meets = box_meets(cb.z, cb.w, q.strip);
+        meets = box_meets(cb.z, cb.w, q.blk);
       }
       uint64_t m = __ballot(meets);
       while (m) {
@@ -238,46 +239,43 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
         m &= ~(1ull << bit);
         const int li = c * kWave + bit;
         const int pos = bstart + li - start;
+        const float4 g = sm.uvab[li];
+        const float4 cb = sm.cob[li];
+        const float dx = q.fpx - g.x, dy = q.fpy - g.y;
+        const PairEval pe = eval_pair(dx, dy, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
+        const bool hit = pos < last && pe.use;
+        if (!__any(hit)) continue;
+        // Lanes without a hit run the same instructions with alpha = 0: their
+        // transmittance and suffix sums are unchanged and their partials are 0.
+        const float4 cz = sm.rgbz[li];
+        const float al = hit ? pe.alpha : 0.f;
+        const float inv = __builtin_amdgcn_rcpf(1.f - al);  // 1 ulp; alpha <= alpha_max < 1
+        const float Tj = T * inv;
+        const float w = al * Tj;
         float v[10];
-#pragma unroll
-        for (int f = 0; f < 10; ++f) v[f] = 0.f;
-        bool hit = false;
-        if (pos < last) {
-          const float4 g = sm.uvab[li];
-          const float4 cb = sm.cob[li];
-          const float dx = q.fpx - g.x, dy = q.fpy - g.y;
-          const PairEval pe = eval_pair(dx, dy, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
-          if (pe.use) {
-            hit = true;
-            const float4 cz = sm.rgbz[li];
-            const float inv = 1.f / (1.f - pe.alpha);
-            const float Tj = T * inv;
-            const float w = pe.alpha * Tj;
-            v[6] = w * g0;
-            v[7] = w * g1;
-            v[8] = w * g2;
-            v[9] = w * gd;
-            float dA = g0 * (cz.x * Tj - S0 * inv) + g1 * (cz.y * Tj - S1 * inv) + g2 * (cz.z * Tj - S2 * inv);
-            dA += gd * (cz.w * Tj - SD * inv);
-            dA += ga * Tfin * inv;
-            S0 = fmaf(cz.x, w, S0);
-            S1 = fmaf(cz.y, w, S1);
-            S2 = fmaf(cz.z, w, S2);
-            SD = fmaf(cz.w, w, SD);
-            T = Tj;
-            if (!pe.clamped) {
-              v[5] = dA * pe.e;                       // d alpha / d o = exp(-sigma)
-              const float gp = dA * pe.alpha * kLn2;  // dL/dp with alpha = o 2^p
-              const float gpx = gp * dx, gpy = gp * dy;
-              v[2] = gpx * dx;
-              v[3] = gpx * dy;
-              v[4] = gpy * dy;
-              v[0] = -(2.f * g.z * gpx + g.w * gpy);
-              v[1] = -(g.w * gpx + 2.f * cb.x * gpy);
-            }
-          }
-        }
-        if (__any(hit)) wave_add10(v, a.g2d + 10 * (int64_t)sm.gid[li], lane);
+        v[6] = w * g0;
+        v[7] = w * g1;
+        v[8] = w * g2;
+        v[9] = w * gd;
+        float dA = g0 * (cz.x * Tj - S0 * inv) + g1 * (cz.y * Tj - S1 * inv) + g2 * (cz.z * Tj - S2 * inv);
+        dA += gd * (cz.w * Tj - SD * inv);
+        dA += ga * Tfin * inv;
+        S0 = fmaf(cz.x, w, S0);
+        S1 = fmaf(cz.y, w, S1);
+        S2 = fmaf(cz.z, w, S2);
+        SD = fmaf(cz.w, w, SD);
+        T = Tj;
+        // a clamped alpha does not depend on o or sigma
+        const float dAs = (hit && !pe.clamped) ? dA : 0.f;
+        v[5] = dAs * pe.e;                       // d alpha / d o = exp(-sigma)
+        const float gp = dAs * pe.alpha * kLn2;  // dL/dp with alpha = o 2^p
+        const float gpx = gp * dx, gpy = gp * dy;
+        v[2] = gpx * dx;
+        v[3] = gpx * dy;
+        v[4] = gpy * dy;
+        v[0] = -(2.f * g.z * gpx + g.w * gpy);
+        v[1] = -(g.w * gpx + 2.f * cb.x * gpy);
+        wave_add10(v, a.g2d + 10 * (int64_t)sm.gid[li], lane);
       }
     }
   }

@@ -160,11 +160,12 @@ def test_proposals_reduce_held_out_pose_error(trained):
 
 def test_learned_init_gain(trained):
     """Tracking from the network's proposal (kept only when Eq. 15 prefers it)
-    reaches the final pose error of plain tracking with fewer iterations."""
+    reaches the accuracy of 100 plain iterations (their final error + 5 %, at
+    least 0.5 mm) in fewer iterations, on average, than plain tracking does."""
     torch = torch_()
     net, _, _, _ = trained
-    errs_plain, iters_needed, used = [], [], 0
-    budgets = (20, 30, 45, 60, 80, 100)
+    budgets = (10, 15, 20, 30, 40, 50, 60, 80, 100)
+    n_plain, n_learned, used = [], [], 0
     for frame in range(4):
         inp = synth.tracking_inputs(100 + frame, 60_000, CAM, n_views=3, trans_m=0.03, rot_deg=2.0)
         g = {k: torch.from_numpy(v).cuda() for k, v in inp["gaussians"].items()}
@@ -175,24 +176,21 @@ def test_learned_init_gain(trained):
         st.release()
         init = torch.from_numpy(inp["init_pose7"]).cuda()
         kcap = tracking.overlap_capacity(*args, init, cam)
-        plain = gsr.TrackGraph(*args, cam, oc, od, n_iters=100, K_cap=kcap)
-        p = init.clone()
-        plain.run(p)
-        e_plain = synth.pose_error(p.cpu().numpy(), inp["gt_pose7"])[0]
-        errs_plain.append(e_plain)
+        graphs = {n: gsr.TrackGraph(*args, cam, oc, od, n_iters=n, K_cap=kcap) for n in budgets}
+
+        def err_after(n, start):
+            q = start.clone()
+            graphs[n].run(q)
+            return synth.pose_error(q.cpu().numpy(), inp["gt_pose7"])[0]
+
+        thr = max(1.05 * err_after(100, init), 5e-4)
+        first = lambda start: next((n for n in budgets if err_after(n, start) <= thr), 101)
+        n_plain.append(first(init))
         start, use, l0, l1 = initnet.propose(net, args, cam, oc, od, init)
         used += use
-        need = 101
-        for n in budgets:
-            tg = gsr.TrackGraph(*args, cam, oc, od, n_iters=n, K_cap=kcap)
-            q = start.clone()
-            tg.run(q)
+        n_learned.append(first(start))
+        for tg in graphs.values():
             tg.close()
-            if synth.pose_error(q.cpu().numpy(), inp["gt_pose7"])[0] <= e_plain * 1.05:
-                need = n
-                break
-        iters_needed.append(need)
-        plain.close()
-    print("iterations to reach the plain final error:", iters_needed, "proposals used:", used)
+    print("iterations to the target error: plain", n_plain, "learned", n_learned, "proposals used:", used)
     assert used >= 2, "the proposal should usually beat the initial pose"
-    assert np.mean(iters_needed) < 100, iters_needed
+    assert np.mean(n_learned) < np.mean(n_plain), (n_plain, n_learned)
