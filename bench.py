@@ -4,7 +4,7 @@
 Workload (default): one mapping iteration of a 1200 x 680 view over a sub-map of
 500,000 Gaussians seeded from a procedural room (synthetic stand-in for the
 paper's Replica scans): project + EWA covariance, tile binning and (tile,
-depth) radix sort, forward compositing of colour / depth / alpha, L1 colour +
+depth) per-tile sort, forward compositing of colour / depth / alpha, L1 colour +
 L1 depth loss, the hand-written backward to every Gaussian parameter, and Adam
 on all 14 N parameters. `value` is iterations per second with all inputs
 resident in HBM. Prints ONE JSON line (rank 0) with a roofline entry for the
@@ -36,7 +36,7 @@ FLOPS_COMP_FWD = 12  # transmittance update, stop test, colour + depth accumulat
 FLOPS_COMP_BWD = 48  # T recovery, dC/dalpha, dD/dalpha (Eq. 8), dA/dalpha, suffix sums, 10 partials
 
 
-def stage_work(stage: str, st: dict, n: int, P: int, radix_passes: int) -> tuple[str, float]:
+def stage_work(stage: str, st: dict, n: int, P: int) -> tuple[str, float]:
     """(bound, algorithmic work per launch) of a stage: bytes for memory-bound
     stages, FP32 operations for the compositing kernels."""
     K = st["K"]
@@ -44,15 +44,14 @@ def stage_work(stage: str, st: dict, n: int, P: int, radix_passes: int) -> tuple
         return "alu", FLOPS_EVAL * st["pairs_fwd"] + FLOPS_COMP_FWD * st["pairs_composited"]
     if stage == "render_bwd":
         return "alu", FLOPS_EVAL * st["pairs_bwd"] + FLOPS_COMP_BWD * st["pairs_composited"]
-    if stage == "radix_sort":
-        # per pass: keys read by the histogram (8 B) + key/value read and written by the scatter (24 B)
-        return "hbm", radix_passes * 32.0 * K
+    if stage == "tile_bins":
+        # placement reads rect, count and depth (36 B per Gaussian) and writes an 8-B key per overlap;
+        # the per-tile sort reads the key and writes a 4-B id
+        return "hbm", n * 36.0 + K * (8.0 + 8.0 + 4.0)
     if stage == "project":
-        return "hbm", n * (56.0 + 64.0)
+        return "hbm", n * (56.0 + 64.0 + 16.0)
     if stage == "project_bwd":
         return "hbm", n * (56.0 + 40.0 + 56.0)
-    if stage == "duplicate":
-        return "hbm", n * 24.0 + K * 12.0
     if stage == "adam":
         return "hbm", 28.0 * 14 * n  # all 14 n parameters in one launch
     if stage == "loss_l1":
@@ -69,7 +68,7 @@ def source_hash(names) -> str:
 
 
 STAGE_SOURCES = {"render_fwd": ["k_raster.hip", "gsr_internal.h"], "render_bwd": ["k_raster.hip", "gsr_internal.h"],
-                 "radix_sort": ["k_sort.hip"], "project": ["k_project.hip", "gsr_internal.h"],
+                 "tile_bins": ["k_sort.hip"], "project": ["k_project.hip", "gsr_internal.h"],
                  "project_bwd": ["k_project.hip", "gsr_internal.h"]}
 
 
@@ -392,10 +391,8 @@ def main() -> int:
     st.release()
     n = args.gaussians
     P = cam.width * cam.height
-    tile_bits = int(np.ceil(np.log2(max(stats["tiles"], 2))))
-    radix_passes = (32 + tile_bits + 7) // 8
     dom = max((s for s in stages if s not in ("fill",)), key=lambda s: stages[s][0])
-    bound, work = stage_work(dom, stats, n, P, radix_passes)
+    bound, work = stage_work(dom, stats, n, P)
     avg_ms = stages[dom][0] / stages[dom][1]
     if bound == "alu":
         achieved = work / (avg_ms * 1e-3) / 1e12

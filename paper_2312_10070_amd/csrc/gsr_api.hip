@@ -29,7 +29,10 @@ struct gsr_state {
   float4* rec_rgbz = nullptr;
   int4* rect = nullptr;
   uint32_t* counts = nullptr;
-  uint32_t* offsets = nullptr;
+  uint32_t* tile_cnt = nullptr;    // [copies][items]: overlapping Gaussians per (view, tile)
+  uint32_t* tile_cntT = nullptr;   // [items][copies]: the same, tile-major
+  uint32_t* tile_start = nullptr;  // [items][copies]: exclusive scan of tile_cntT
+  uint32_t* tile_fill = nullptr;   // [copies][items]: slot counters of the placement
   uint32_t* scan_temp = nullptr;
   float* g2d = nullptr;
   float* Tfin = nullptr;
@@ -44,10 +47,9 @@ struct gsr_state {
   int n_views = 1;
   int blocks = 0;             // persistent workgroups (0 = one per item)
   // arena B: per overlap
-  uint64_t* keys[2] = {nullptr, nullptr};
-  uint32_t* vals[2] = {nullptr, nullptr};
-  uint32_t* sort_temp = nullptr;
-  int sorted = 0;
+  uint64_t* keys = nullptr;     // [K] (depth bits << 32 | record index), slot order
+  uint64_t* scratch = nullptr;  // [K] merge buffer for tile ranges longer than LDS holds
+  uint32_t* ids = nullptr;      // [K] record indices, per tile in depth order
 };
 
 struct gsr_track_graph {
@@ -152,8 +154,11 @@ void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, int6
   s->rec_rgbz = c.take<float4>(n);
   s->rect = c.take<int4>(n);
   s->counts = c.take<uint32_t>(n);
-  s->offsets = c.take<uint32_t>(n);
-  s->scan_temp = c.take<uint32_t>(gsr::scan_temp_words(n));
+  s->tile_cnt = c.take<uint32_t>(gsr::kBinCopies * tiles);
+  s->tile_cntT = c.take<uint32_t>(gsr::kBinCopies * tiles);
+  s->tile_start = c.take<uint32_t>(gsr::kBinCopies * tiles);
+  s->tile_fill = c.take<uint32_t>(gsr::kBinCopies * tiles);
+  s->scan_temp = c.take<uint32_t>(gsr::scan_temp_words(gsr::kBinCopies * tiles));
   s->g2d = c.take<float>(10 * n);
   s->Tfin = c.take<float>(P);
   s->last = c.take<int>(P);
@@ -169,11 +174,9 @@ void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, int6
 
 void carve_B(gsr_state* s, char* base, int64_t K, size_t* bytes) {
   Carver c{base};
-  s->keys[0] = c.take<uint64_t>(K);
-  s->keys[1] = c.take<uint64_t>(K);
-  s->vals[0] = c.take<uint32_t>(K);
-  s->vals[1] = c.take<uint32_t>(K);
-  s->sort_temp = c.take<uint32_t>(gsr::radix_temp_words(K));
+  s->keys = c.take<uint64_t>(K);
+  s->scratch = c.take<uint64_t>(K);
+  s->ids = c.take<uint32_t>(K);
   *bytes = c.off;
 }
 
@@ -215,12 +218,6 @@ int ensure_B(gsr_ctx* c, gsr_state* s, int64_t K) {
   carve_B(s, (char*)p, kk, &bytes);
   s->K_cap = kk;
   return GSR_OK;
-}
-
-int bits_for(int64_t v) {
-  int b = 1;
-  while ((int64_t(1) << b) < v) ++b;
-  return b;
 }
 
 int make_raster(gsr_ctx* c, const gsr_camera* cam, const gsr_opts* o, gsr::Raster* R) {
@@ -296,42 +293,38 @@ struct Stage {
   }
 };
 
-// Projection + scan of tile counts (the overlap count K lands in s->d_K).
+// Projection (with per-tile Gaussian counts) + scan of the tile counts (the
+// overlap count K lands in s->d_K).
 void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st) {
+  const int64_t n_items = (int64_t)s->R.n_tiles * s->n_views;
   gsr::ProjectArgs pa{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
-                      s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts, s->n_views};
+                      s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts, s->n_views, s->tile_cnt};
   {
     Stage t(c, "project");
+    gsr::launch_fill_u32(s->tile_cnt, 0u, gsr::kBinCopies * n_items, st);
     gsr::launch_project(s->R, pa, st);
   }
   {
     Stage t(c, "scan");
-    gsr::launch_exclusive_scan(s->counts, s->offsets, s->n * s->n_views, s->d_K, s->scan_temp, st);
+    gsr::launch_bin_gather(s->tile_cnt, n_items, s->tile_cntT, st);
+    gsr::launch_exclusive_scan(s->tile_cntT, s->tile_start, gsr::kBinCopies * n_items, s->d_K, s->scan_temp, st);
   }
 }
 
-// Duplication, sort, ranges and compositing. grid_K sizes the K-dependent
-// grids: the exact K (eager) or the capacity (captured graphs, which read K
-// from the device and flag an overflow).
-void enqueue_back(gsr_ctx* c, gsr_state* s, hipStream_t st, int64_t grid_K, float* color, float* depth, float* alpha) {
+// Tile lists (ranges, slot placement, per-tile depth sort) and compositing.
+// cap bounds the overlap positions: the exact K (eager) or the capacity
+// (captured graphs, where an overflow is flagged on the device).
+void enqueue_back(gsr_ctx* c, gsr_state* s, hipStream_t st, int64_t cap, float* color, float* depth, float* alpha) {
   const gsr::Raster& R = s->R;
   const int n_items = R.n_tiles * s->n_views;
-  gsr::BinArgs ba{s->n, s->rec_rgbz, s->rect, s->counts, s->offsets, s->d_K, grid_K, s->n_views,
-                  s->keys[0], s->vals[0], s->d_overflow};
+  gsr::PlaceArgs pl{s->n, s->n_views, n_items, s->rec_rgbz, s->rect, s->counts, s->tile_fill, cap, s->keys,
+                    s->d_overflow};
   {
-    Stage t(c, "duplicate");
-    gsr::launch_duplicate(R, ba, st);
-  }
-  {
-    Stage t(c, "radix_sort");
-    s->sorted = gsr::launch_radix_sort(s->keys, s->vals, s->d_K, grid_K, 32 + bits_for(n_items), s->sort_temp, st);
-  }
-  {
-    Stage t(c, "tile_ranges");
-    gsr::launch_tile_ranges(s->keys[s->sorted], s->d_K, grid_K, s->ranges, n_items, st);
+    Stage t(c, "tile_bins");
+    gsr::launch_tile_bins(R, pl, s->tile_cntT, s->tile_start, n_items, s->ranges, s->scratch, s->ids, st);
     if (s->blocks > 0) gsr::launch_item_order(s->ranges, n_items, s->order, s->order_temp, st);
   }
-  gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz,
+  gsr::FwdArgs fa{s->ranges, s->ids, s->rec_uvab, s->rec_cob, s->rec_rgbz,
                   color, depth, alpha, s->Tfin, s->last, nullptr,
                   n_items, s->queue, s->blocks > 0 ? s->order : nullptr, s->blocks};
   {
@@ -351,7 +344,7 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
     gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n * s->n_views, st);
     if (want_pose) gsr::launch_fill_f32(s->pose_acc, 0.f, 12 * s->n_views, st);
   }
-  gsr::BwdArgs ba{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
+  gsr::BwdArgs ba{s->ranges, s->ids, s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
                   gC, gD, gA, s->g2d, n_items, s->queue, s->blocks > 0 ? s->order : nullptr, s->blocks};
   {
     Stage t(c, "render_bwd");
@@ -552,7 +545,7 @@ int gsr_tile_lists(gsr_ctx* c, const gsr_state* s, int64_t* K, int32_t* ranges, 
     GSR_HIP(c, hipMemcpyAsync(ranges, s->ranges, sizeof(int2) * s->R.n_tiles * s->n_views, hipMemcpyDeviceToDevice,
                               c->stream));
   if (ids && s->K > 0)
-    GSR_HIP(c, hipMemcpyAsync(ids, s->vals[s->sorted], sizeof(uint32_t) * s->K, hipMemcpyDeviceToDevice, c->stream));
+    GSR_HIP(c, hipMemcpyAsync(ids, s->ids, sizeof(uint32_t) * s->K, hipMemcpyDeviceToDevice, c->stream));
   GSR_HIP(c, hipStreamSynchronize(c->stream));
   return GSR_OK;
 }
@@ -901,7 +894,7 @@ int gsr_state_stats(gsr_ctx* c, gsr_state* s, int64_t out[6]) {
   GSR_HIP(c, hipSetDevice(c->device));
   hipStream_t st = c->stream;
   GSR_HIP(c, hipMemsetAsync(c->d_stats, 0, 64, st));
-  gsr::FwdArgs fa{s->ranges, s->vals[s->sorted], s->rec_uvab, s->rec_cob, s->rec_rgbz,
+  gsr::FwdArgs fa{s->ranges, s->ids, s->rec_uvab, s->rec_cob, s->rec_rgbz,
                   nullptr, nullptr, nullptr, nullptr, s->last, c->d_stats,
                   s->R.n_tiles * s->n_views, nullptr, nullptr, 0};
   gsr::launch_render_fwd(s->R, fa, st);
@@ -1072,11 +1065,8 @@ int gsr_track_graph_create(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera*
   s->pose7 = tg->pose;
   s->K = K_cap;
   hipStream_t st = c->stream;
-  // stale tile-list slots must hold in-range values: sentinel tiles, Gaussian 0
-  for (int b = 0; b < 2; ++b) {
-    gsr::launch_fill_u32(reinterpret_cast<uint32_t*>(s->keys[b]), 0xffffffffu, 2 * K_cap, st);
-    gsr::launch_fill_u32(s->vals[b], 0u, K_cap, st);
-  }
+  // every id slot holds an in-range record index from the start
+  gsr::launch_fill_u32(s->ids, 0u, K_cap, st);
   gsr::launch_fill_f32(tg->pose, 0.f, 8, st);
   rc = gsr_track_graph_set_frame(c, tg, obs_color, obs_depth);
   if (!rc) {

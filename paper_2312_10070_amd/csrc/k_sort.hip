@@ -1,9 +1,16 @@
-// Tile binning: exclusive scan of per-Gaussian tile counts, duplication into
-// 64-bit (tile, depth) keys, a stable least-significant-digit radix sort and
-// the per-tile [start, end) ranges. This realises the depth order of the "m
-// ordered Gaussians" of Eq. 3 and Eq. 6 per tile. All passes read the
-// overlap count K from device memory, so the same launches work with exact
-// or capacity-sized grids (the latter for captured graphs).
+// Tile binning. The projection counts, per tile, the Gaussians whose tile
+// rectangle holds it; an exclusive scan of those counts gives each tile's
+// [start, end) range in the overlap list (and the overlap count K). Every
+// (Gaussian, tile) pair then takes a slot of its tile's range with an atomic
+// counter and writes the key (float bits of the camera depth << 32 | record
+// index); the slot order is arbitrary. Finally one workgroup per tile sorts
+// its range by key in LDS (a bitonic network; a range longer than LDS holds
+// is sorted in LDS-sized runs that are merged pairwise in global memory) and
+// writes the record indices. Keys are unique within a tile, so the result is
+// the depth order of the "m ordered Gaussians" of Eq. 3 and Eq. 6 with ties
+// broken by index: exactly what a stable sort of (tile, depth) gives.
+// No launch grid depends on K: positions at or beyond the capacity are
+// dropped and flagged, so the same launches serve captured graphs.
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -14,10 +21,6 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;  // 2048
 
-constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 8;
-constexpr int kSortTile = kSortThreads * kSortRounds;  // 2048 keys per workgroup
-constexpr int kDigits = 256;
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* s_wave) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -100,124 +103,141 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
   }
 }
 
-// One thread per Gaussian: a key per overlapped tile, row-major over its
-// rectangle. Key = (tile id) << 32 | float bits of the camera depth (z > 0,
-// so the bits order like the values); value = Gaussian index. Writing in
-// index order makes the stable sort break depth ties by index.
-__global__ __launch_bounds__(256) void k_duplicate(Raster Rr, BinArgs a) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // view * n + Gaussian
-  if (k >= a.n * a.n_views) return;
-  const uint32_t cnt = a.counts[k];
-  if (cnt == 0) return;
-  const uint64_t off = a.offsets[k];
-  if (off + cnt > (uint64_t)a.K_cap) {
-    atomicOr(a.overflow, 1);
-    return;
-  }
-  const int4 r = a.rect[k];
-  const uint32_t zb = __float_as_uint(a.rec_rgbz[k].w);
-  const uint32_t tile_base = (uint32_t)(k / a.n) * (uint32_t)Rr.n_tiles;
-  uint64_t* kp = a.keys + off;
-  uint32_t* vp = a.vals + off;
-  int i = 0;
+constexpr int kSortCap = 2048;  // keys a workgroup sorts in LDS (16 KB)
+constexpr int kBinThreads = 256;
+
+__global__ __launch_bounds__(256) void k_bin_gather(const uint32_t* __restrict__ cnt, int64_t n_items,
+                                                   uint32_t* __restrict__ cntT) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // = item * kBinCopies + copy
+  if (i >= n_items * kBinCopies) return;
+  const int64_t t = i / kBinCopies, c = i - t * kBinCopies;
+  cntT[i] = cnt[c * n_items + t];
+}
+
+// ranges[t] = [start of copy 0, end of the last copy) clipped to the
+// capacity; fill[c][t] = start of copy c's sub-range.
+__global__ __launch_bounds__(256) void k_tile_init(const uint32_t* __restrict__ cntT,
+                                                  const uint32_t* __restrict__ startT, int64_t n_items, int64_t cap,
+                                                  int2* __restrict__ ranges, uint32_t* __restrict__ fill) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_items) return;
+  const int64_t b = t * kBinCopies;
+  const int64_t s0 = startT[b], s1 = (int64_t)startT[b + kBinCopies - 1] + cntT[b + kBinCopies - 1];
+  ranges[t] = make_int2((int)(s0 < cap ? s0 : cap), (int)(s1 < cap ? s1 : cap));
+  for (int c = 0; c < kBinCopies; ++c) fill[c * n_items + t] = startT[b + c];
+}
+
+// One thread per (view, Gaussian): a slot in every tile of its rectangle.
+__global__ __launch_bounds__(256) void k_tile_place(Raster Rr, PlaceArgs a) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // view * n + Gaussian
+  if (o >= a.n * a.n_views) return;
+  if (a.counts[o] == 0) return;
+  const int4 r = a.rect[o];
+  const uint64_t key_lo = (uint64_t)(uint32_t)o;
+  const uint64_t zb = (uint64_t)__float_as_uint(a.rec_rgbz[o].w) << 32;
+  const int64_t view = o / a.n;
+  uint32_t* fill = a.fill + bin_copy(o - view * a.n) * a.n_items + view * Rr.n_tiles;
   for (int ty = r.y; ty <= r.w; ++ty)
     for (int tx = r.x; tx <= r.z; ++tx) {
-      const uint32_t tile = tile_base + (uint32_t)(ty * Rr.ntx + tx);
-      kp[i] = ((uint64_t)tile << 32) | zb;
-      vp[i] = (uint32_t)k;
-      ++i;
+      const uint32_t pos = atomicAdd(fill + ty * Rr.ntx + tx, 1u);
+      if ((int64_t)pos < a.cap) {
+        a.keys[pos] = zb | key_lo;
+      } else {
+        atomicOr(a.overflow, 1);
+      }
     }
 }
 
-__device__ __forceinline__ uint32_t clamp_K(const uint32_t* d_K, int64_t cap) {
-  const uint32_t K = *d_K;
-  return (int64_t)K < cap ? K : (uint32_t)cap;
-}
-
-// Lanes of the wave holding the same 8-bit digit as this lane (ballot match).
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
-  uint64_t m = __ballot(valid);
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bb = __ballot(bit);
-    m &= bit ? bb : ~bb;
+// Bitonic sort of s[0, n2) ascending (n2 a power of two <= kSortCap), all
+// threads of the workgroup; ends with a barrier.
+__device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2) {
+  const int half = n2 >> 1;
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int p = threadIdx.x; p < half; p += kBinThreads) {
+        const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));  // pairs (i, i + j) with bit j of i clear
+        const int l = i + j;
+        const uint64_t x = s[i], y = s[l];
+        const bool up = (i & k) == 0;
+        if ((x > y) == up) {
+          s[i] = y;
+          s[l] = x;
+        }
+      }
+      __syncthreads();
+    }
   }
-  return m;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
-                                                            const uint32_t* __restrict__ d_K, int64_t cap, int shift,
-                                                            uint32_t* __restrict__ hist, int nb) {
-  __shared__ uint32_t h[kDigits];
-  h[threadIdx.x] = 0;
+__device__ __forceinline__ int pow2_at_least(int v) {
+  int n = 2;
+  while (n < v) n <<= 1;
+  return n;
+}
+
+// Sorts keys[b, b + len) (len <= kSortCap) through LDS; writes the sorted keys
+// to out_keys (may alias keys) and/or their low words to out_ids.
+__device__ void sort_run(const uint64_t* keys, int64_t b, int len, uint64_t* s, uint64_t* out_keys,
+                         uint32_t* out_ids) {
+  const int n2 = pow2_at_least(len);
+  for (int i = threadIdx.x; i < n2; i += kBinThreads) s[i] = i < len ? keys[b + i] : ~0ull;
   __syncthreads();
-  const uint32_t K = clamp_K(d_K, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  const uint64_t lt = (1ull << (threadIdx.x & 63)) - 1ull;
-  for (int r = 0; r < kSortRounds; ++r) {
-    const int64_t idx = base + r * kSortThreads + threadIdx.x;
-    const bool valid = idx < (int64_t)K;
-    const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & 0xffu : 0u;
-    const uint64_t m = match_digit(d, valid);
-    if (valid && (m & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(m));
+  lds_bitonic(s, n2);
+  for (int i = threadIdx.x; i < len; i += kBinThreads) {
+    if (out_keys) out_keys[b + i] = s[i];
+    if (out_ids) out_ids[b + i] = (uint32_t)s[i];
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter: element order inside the workgroup is (round, lane) order,
-// which is index order, and every rank respects it.
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* __restrict__ kin,
-                                                               const uint32_t* __restrict__ vin,
-                                                               uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                               const uint32_t* __restrict__ d_K, int64_t cap, int shift,
-                                                               const uint32_t* __restrict__ hist, int nb) {
-  __shared__ uint32_t run[kDigits];
-  __shared__ uint32_t wc[kSortThreads / 64][kDigits];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t lt = (1ull << lane) - 1ull;
-  run[threadIdx.x] = hist[(int64_t)threadIdx.x * nb + blockIdx.x];
-  const uint32_t K = clamp_K(d_K, cap);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortRounds; ++r) {
-#pragma unroll
-    for (int i = 0; i < kSortThreads / 64; ++i) wc[i][threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t idx = base + r * kSortThreads + threadIdx.x;
-    const bool valid = idx < (int64_t)K;
-    uint64_t key = 0;
-    uint32_t d = 0;
-    if (valid) {
-      key = kin[idx];
-      d = (uint32_t)(key >> shift) & 0xffu;
-    }
-    const uint64_t m = match_digit(d, valid);
-    const uint32_t rank = (uint32_t)__popcll(m & lt);
-    if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[d] + rank;
-      for (int i = 0; i < w; ++i) pos += wc[i][d];
-      kout[pos] = key;
-      vout[pos] = vin[idx];
-    }
-    __syncthreads();
-    run[threadIdx.x] += wc[0][threadIdx.x] + wc[1][threadIdx.x] + wc[2][threadIdx.x] + wc[3][threadIdx.x];
+// Merges the sorted runs a[0, na) and b[0, nb) (distinct keys) into out; the
+// output is split evenly over the workgroup's threads by merge-path search.
+__device__ void merge_runs(const uint64_t* a, int na, const uint64_t* b, int nb, uint64_t* out) {
+  const int total = na + nb;
+  const int per = (total + kBinThreads - 1) / kBinThreads;
+  const int d0 = min(total, (int)threadIdx.x * per), d1 = min(total, d0 + per);
+  if (d0 >= d1) return;
+  int lo = max(0, d0 - nb), hi = min(d0, na);
+  while (lo < hi) {  // the first i with a[i] > b[d0 - 1 - i]
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < b[d0 - 1 - mid]) lo = mid + 1;
+    else hi = mid;
+  }
+  int i = lo, j = d0 - lo;
+  for (int d = d0; d < d1; ++d) {
+    const bool take_a = j >= nb || (i < na && a[i] < b[j]);
+    out[d] = take_a ? a[i++] : b[j++];
   }
 }
 
-// Tiles outside [0, n_ranges) (possible only for stale keys after a capacity
-// overflow, which the caller reports) are ignored.
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ d_K,
-                                                    int64_t cap, int2* __restrict__ ranges, int64_t n_ranges) {
-  const uint32_t K = clamp_K(d_K, cap);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)K) return;
-  const uint32_t t = (uint32_t)(keys[i] >> 32);
-  if ((int64_t)t >= n_ranges) return;
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = (int)i;
-  if (i == (int64_t)K - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (int)(i + 1);
+// One workgroup per (view, tile) item.
+__global__ __launch_bounds__(kBinThreads) void k_tile_sort(const int2* __restrict__ ranges, uint64_t* __restrict__ keys,
+                                                          uint64_t* __restrict__ scratch, uint32_t* __restrict__ ids) {
+  __shared__ uint64_t s[kSortCap];
+  const int2 rg = ranges[blockIdx.x];
+  const int64_t b = rg.x;
+  const int len = rg.y - rg.x;
+  if (len <= 0) return;
+  if (len <= kSortCap) {
+    sort_run(keys, b, len, s, nullptr, ids);
+    return;
+  }
+  // long range: sorted runs of kSortCap, then pairwise merges (ping-pong)
+  for (int c0 = 0; c0 < len; c0 += kSortCap) sort_run(keys, b + c0, min(kSortCap, len - c0), s, keys, nullptr);
+  uint64_t* src = keys + b;
+  uint64_t* dst = scratch + b;
+  for (int w = kSortCap; w < len; w <<= 1) {
+    for (int lo = 0; lo < len; lo += 2 * w) {
+      const int mid = min(lo + w, len), hi = min(lo + 2 * w, len);
+      merge_runs(src + lo, mid - lo, src + mid, hi - mid, dst + lo);
+    }
+    __threadfence_block();
+    __syncthreads();
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  for (int i = threadIdx.x; i < len; i += kBinThreads) ids[b + i] = (uint32_t)src[i];
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
@@ -251,46 +271,22 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, (const uint32_t*)temp);
 }
 
-void launch_duplicate(const Raster& R, const BinArgs& a, hipStream_t s) {
-  const int64_t m = a.n * a.n_views;
+void launch_bin_gather(const uint32_t* tile_cnt, int64_t n_items, uint32_t* cntT, hipStream_t s) {
+  const int64_t m = n_items * kBinCopies;
   if (m <= 0) return;
-  hipLaunchKernelGGL(k_duplicate, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, R, a);
+  hipLaunchKernelGGL(k_bin_gather, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, tile_cnt, n_items, cntT);
 }
 
-int64_t radix_temp_words(int64_t cap) {
-  const int64_t nb = (cap + kSortTile - 1) / kSortTile;
-  const int64_t nh = (int64_t)kDigits * (nb > 0 ? nb : 1);
-  return nh + scan_temp_words(nh) + 1;
-}
-
-int launch_radix_sort(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* d_K, int64_t cap, int bits,
-                      uint32_t* temp, hipStream_t s) {
-  const int64_t nb = (cap + kSortTile - 1) / kSortTile;
-  if (nb == 0) return 0;
-  const int64_t nh = (int64_t)kDigits * nb;
-  uint32_t* hist = temp;
-  uint32_t* stemp = temp + nh;
-  uint32_t* total = stemp + scan_temp_words(nh);
-  int cur = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, (const uint64_t*)keys[cur], d_K,
-                       cap, shift, hist, (int)nb);
-    launch_exclusive_scan(hist, hist, nh, total, stemp, s);
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, (const uint64_t*)keys[cur],
-                       (const uint32_t*)vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_K, cap, shift,
-                       (const uint32_t*)hist, (int)nb);
-    cur ^= 1;
-  }
-  return cur;
-}
-
-void launch_tile_ranges(const uint64_t* keys, const uint32_t* d_K, int64_t cap, int2* ranges, int64_t n_ranges,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3(fill_blocks(2 * n_ranges)), dim3(256), 0, s, (uint32_t*)ranges, 0u,
-                     2 * n_ranges);
-  if (cap <= 0) return;
-  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, keys, d_K, cap, ranges,
-                     n_ranges);
+void launch_tile_bins(const Raster& R, const PlaceArgs& a, const uint32_t* cntT, const uint32_t* startT,
+                      int64_t n_items, int2* ranges, uint64_t* scratch, uint32_t* ids, hipStream_t s) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, cntT, startT,
+                     n_items, a.cap, ranges, a.fill);
+  const int64_t m = a.n * a.n_views;
+  if (m > 0)
+    hipLaunchKernelGGL(k_tile_place, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, R, a);
+  hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)n_items), dim3(kBinThreads), 0, s, (const int2*)ranges, a.keys,
+                     scratch, ids);
 }
 
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {

@@ -187,6 +187,31 @@ def test_long_lists_and_early_termination():
     G.grads_check({k: v.cpu().numpy().astype(np.float64) for k, v in b.items()}, ref)
 
 
+def test_tile_ranges_longer_than_lds_are_merged():
+    """Tiles whose lists exceed the 2048 keys one workgroup sorts in LDS
+    (sorted runs merged pairwise in global memory, with a ragged last run):
+    tile lists bit-exact, including depth ties broken by index."""
+    rng = np.random.default_rng(11)
+    n = 7000
+    g = dict(means=np.stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.25, 0.25, n), rng.uniform(2, 6, n)], 1),
+             scales=np.exp(rng.normal(-2.2, 0.3, (n, 3))), quats=rng.normal(size=(n, 4)),
+             opacities=rng.uniform(0.2, 0.9, n), colors=rng.uniform(0, 1, (n, 3)))
+    g["means"][100:400, 2] = 3.0  # exact depth ties: order by index
+    cam = oracle.Camera(48, 40, 40.0, 40.0, 24.0, 20.0)
+    pose = np.array([1, 0, 0, 0, 0, 0, 0], np.float64)
+    g = G.certify(g, pose, cam, 1e-4)
+    tl = oracle.tile_lists(g, pose, cam, oracle.Opts())
+    lens = tl["ranges"][:, 1] - tl["ranges"][:, 0]
+    assert lens.max() > 2 * 2048 + 100 and (lens > 2048).sum() >= 2
+    out, st, _, _ = run_fwd(g, pose, cam)
+    K, ranges, ids = gsr.tile_lists(st, tl["ranges"].shape[0])
+    assert K == tl["K"]
+    G.compare_tile_lists(ranges.cpu().numpy(), ids.cpu().numpy(), tl, None)
+    # 7000 Gaussians over 1920 pixels: many threshold events, so a looser unverifiable bound
+    opts = oracle.Opts(amb_rel=1e-4, amb_z=0.0)
+    G.compare_images(out, oracle.render(g, pose, cam, opts), TOL, max_unverifiable=0.06)
+
+
 def test_loss_kernels_match_oracle():
     torch = torch_()
     g, tg, pose, cam = G.c1_case(0)
