@@ -44,6 +44,9 @@ def stage_work(stage: str, st: dict, n: int, P: int) -> tuple[str, float]:
         return "alu", FLOPS_EVAL * st["pairs_fwd"] + FLOPS_COMP_FWD * st["pairs_composited"]
     if stage == "render_bwd":
         return "alu", FLOPS_EVAL * st["pairs_bwd"] + FLOPS_COMP_BWD * st["pairs_composited"]
+    if stage == "bin_count":
+        # rectangles and counts read (20 B per Gaussian); the [tile][workgroup] matrix is written, scanned, read
+        return "hbm", n * 20.0 + st["tiles"] * 256 * 4.0 * 4
     if stage == "tile_bins":
         # placement reads rect, count and depth (36 B per Gaussian) and writes an 8-B key per overlap;
         # the per-tile sort reads the key and writes a 4-B id
@@ -68,7 +71,7 @@ def source_hash(names) -> str:
 
 
 STAGE_SOURCES = {"render_fwd": ["k_raster.hip", "gsr_internal.h"], "render_bwd": ["k_raster.hip", "gsr_internal.h"],
-                 "tile_bins": ["k_sort.hip"], "project": ["k_project.hip", "gsr_internal.h"],
+                 "tile_bins": ["k_sort.hip"], "bin_count": ["k_sort.hip"], "project": ["k_project.hip", "gsr_internal.h"],
                  "project_bwd": ["k_project.hip", "gsr_internal.h"]}
 
 
@@ -229,7 +232,7 @@ def bench_batched(seed: int, n: int, reps: int) -> dict:
 
 def bench_initnet(seed: int, n: int, frames: int, train_pairs: int, train_steps: int) -> dict:
     """Learned tracking initialisation on tracking frames (640x480, n
-    Gaussians, 2 cm / 1 degree perturbation): the CNN is trained on pairs
+    Gaussians, perturbed by 5 cm / 3 degrees, the training range): the CNN is trained on pairs
     rendered at 320x240 (the same field of view) from random procedural
     rooms. Per frame, the target error is plain tracking's final error after
     100 iterations (+5 %, floor 0.5 mm); reported are the iterations and
@@ -249,7 +252,7 @@ def bench_initnet(seed: int, n: int, frames: int, train_pairs: int, train_steps:
     budgets = (10, 15, 20, 30, 40, 50, 60, 80, 100)
     rows = []
     for f in range(frames):
-        inp = synth.tracking_inputs(200 + 17 * seed + f, n)
+        inp = synth.tracking_inputs(200 + 17 * seed + f, n, trans_m=0.05, rot_deg=3.0)
         cam = gsr.camera_from(inp["camera"])
         g = {k: torch.from_numpy(v).cuda() for k, v in inp["gaussians"].items()}
         args = (g["means"], g["scales"], g["quats"], g["opacities"], g["colors"])
@@ -294,8 +297,8 @@ def bench_initnet(seed: int, n: int, frames: int, train_pairs: int, train_steps:
                          n_learn=n_learn, ms_learn=(ms_prop + ms_learn) if n_learn else None, ms_prop=ms_prop))
     mean = lambda k: (round(float(np.mean([r[k] for r in rows if r[k] is not None])), 3)
                       if any(r[k] is not None for r in rows) else None)
-    return {"workload": "tracking frames 640x480, %d Gaussians; CNN trained on %d pairs x %d steps (%.0f s)"
-                        % (n, train_pairs, train_steps, t_train),
+    return {"workload": "tracking frames 640x480, %d Gaussians, 5 cm / 3 deg perturbation; CNN trained on %d pairs "
+                        "x %d steps (%.0f s)" % (n, train_pairs, train_steps, t_train),
             "frames": frames,
             "target_error_cm": [round(100 * r["thr"], 4) for r in rows],
             "iterations_plain": [r["n_plain"] for r in rows],
@@ -323,9 +326,9 @@ def main() -> int:
     ap.add_argument("--batched-gaussians", type=int, default=1_000_000)
     ap.add_argument("--batched-reps", type=int, default=5)
     ap.add_argument("--no-initnet", action="store_true")
-    ap.add_argument("--initnet-frames", type=int, default=3)
-    ap.add_argument("--initnet-pairs", type=int, default=12288)
-    ap.add_argument("--initnet-steps", type=int, default=2500)
+    ap.add_argument("--initnet-frames", type=int, default=4)
+    ap.add_argument("--initnet-pairs", type=int, default=32768)
+    ap.add_argument("--initnet-steps", type=int, default=8000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

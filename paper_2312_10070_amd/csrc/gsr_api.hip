@@ -20,7 +20,7 @@ struct gsr_state {
   gsr_gaussians g{};
   const float* pose7 = nullptr;
   // capacities of the two arenas
-  int64_t n_cap = -1, P_cap = -1, tiles_cap = -1, K_cap = -1, views_cap = -1;
+  int64_t n_cap = -1, P_cap = -1, tiles_cap = -1, K_cap = -1, views_cap = -1, bin_cap = -1;
   void* arenaA = nullptr;
   void* arenaB = nullptr;
   // arena A: per Gaussian / pixel / tile
@@ -29,10 +29,9 @@ struct gsr_state {
   float4* rec_rgbz = nullptr;
   int4* rect = nullptr;
   uint32_t* counts = nullptr;
-  uint32_t* tile_cnt = nullptr;    // [copies][items]: overlapping Gaussians per (view, tile)
-  uint32_t* tile_cntT = nullptr;   // [items][copies]: the same, tile-major
-  uint32_t* tile_start = nullptr;  // [items][copies]: exclusive scan of tile_cntT
-  uint32_t* tile_fill = nullptr;   // [copies][items]: slot counters of the placement
+  int n_wg = 1;                    // binning workgroups per view
+  uint32_t* bin_M = nullptr;       // [items][n_wg]: pairs per (view, tile) and workgroup
+  uint32_t* bin_S = nullptr;       // [items][n_wg]: exclusive scan of bin_M
   uint32_t* scan_temp = nullptr;
   float* g2d = nullptr;
   float* Tfin = nullptr;
@@ -146,19 +145,18 @@ struct Carver {
   }
 };
 
-// n, P, tiles are totals over views.
-void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, int64_t views, size_t* bytes) {
+// n, P, tiles are totals over views; nm = entries of the binning matrices.
+void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, int64_t views, int64_t nm,
+             size_t* bytes) {
   Carver c{base};
   s->rec_uvab = c.take<float4>(n);
   s->rec_cob = c.take<float4>(n);
   s->rec_rgbz = c.take<float4>(n);
   s->rect = c.take<int4>(n);
   s->counts = c.take<uint32_t>(n);
-  s->tile_cnt = c.take<uint32_t>(gsr::kBinCopies * tiles);
-  s->tile_cntT = c.take<uint32_t>(gsr::kBinCopies * tiles);
-  s->tile_start = c.take<uint32_t>(gsr::kBinCopies * tiles);
-  s->tile_fill = c.take<uint32_t>(gsr::kBinCopies * tiles);
-  s->scan_temp = c.take<uint32_t>(gsr::scan_temp_words(gsr::kBinCopies * tiles));
+  s->bin_M = c.take<uint32_t>(nm);
+  s->bin_S = c.take<uint32_t>(nm);
+  s->scan_temp = c.take<uint32_t>(gsr::scan_temp_words(nm));
   s->g2d = c.take<float>(10 * n);
   s->Tfin = c.take<float>(P);
   s->last = c.take<int>(P);
@@ -181,20 +179,25 @@ void carve_B(gsr_state* s, char* base, int64_t K, size_t* bytes) {
 }
 
 int ensure_A(gsr_ctx* c, gsr_state* s, int64_t n, int64_t P, int64_t tiles, int64_t views) {
-  if (s->arenaA && n <= s->n_cap && P <= s->P_cap && tiles <= s->tiles_cap && views <= s->views_cap) return GSR_OK;
+  const int64_t nm_req = tiles * gsr::bin_workgroups(n / std::max<int64_t>(views, 1));
+  if (s->arenaA && n <= s->n_cap && P <= s->P_cap && tiles <= s->tiles_cap && views <= s->views_cap &&
+      nm_req <= s->bin_cap)
+    return GSR_OK;
   if (s->arenaA) GSR_HIP(c, hipFree(s->arenaA));
   s->arenaA = nullptr;
   const int64_t nn = std::max<int64_t>(n + n / 4, 1024), PP = std::max<int64_t>(P, 256),
                 tt = std::max<int64_t>(tiles, 16), vv = std::max<int64_t>(views, 1);
+  const int64_t nm = std::max<int64_t>(tt * gsr::bin_workgroups(nn / vv), nm_req);
   size_t bytes = 0;
-  carve_A(s, nullptr, nn, PP, tt, vv, &bytes);
+  carve_A(s, nullptr, nn, PP, tt, vv, nm, &bytes);
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, GSR_ENOMEM, "device allocation of the per-Gaussian workspace failed");
   }
   s->arenaA = p;
-  carve_A(s, (char*)p, nn, PP, tt, vv, &bytes);
+  carve_A(s, (char*)p, nn, PP, tt, vv, nm, &bytes);
+  s->bin_cap = nm;
   s->n_cap = nn;
   s->P_cap = PP;
   s->tiles_cap = tt;
@@ -293,21 +296,26 @@ struct Stage {
   }
 };
 
-// Projection (with per-tile Gaussian counts) + scan of the tile counts (the
-// overlap count K lands in s->d_K).
+gsr::BinArgs bin_args(gsr_state* s, int64_t cap) {
+  return gsr::BinArgs{s->n, s->n_views, s->n_wg, s->rect, s->counts, s->rec_rgbz, s->bin_M, s->bin_S,
+                      cap, s->keys, s->d_overflow};
+}
+
+// Projection, per-(tile, workgroup) pair counts and their scan (the overlap
+// count K lands in s->d_K).
 void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st) {
   const int64_t n_items = (int64_t)s->R.n_tiles * s->n_views;
   gsr::ProjectArgs pa{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
-                      s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts, s->n_views, s->tile_cnt};
+                      s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts, s->n_views};
   {
     Stage t(c, "project");
-    gsr::launch_fill_u32(s->tile_cnt, 0u, gsr::kBinCopies * n_items, st);
     gsr::launch_project(s->R, pa, st);
   }
   {
-    Stage t(c, "scan");
-    gsr::launch_bin_gather(s->tile_cnt, n_items, s->tile_cntT, st);
-    gsr::launch_exclusive_scan(s->tile_cntT, s->tile_start, gsr::kBinCopies * n_items, s->d_K, s->scan_temp, st);
+    Stage t(c, "bin_count");
+    s->n_wg = gsr::bin_workgroups(s->n);
+    gsr::launch_bin_count(s->R, bin_args(s, 0), st);
+    gsr::launch_exclusive_scan(s->bin_M, s->bin_S, n_items * s->n_wg, s->d_K, s->scan_temp, st);
   }
 }
 
@@ -317,11 +325,9 @@ void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st) {
 void enqueue_back(gsr_ctx* c, gsr_state* s, hipStream_t st, int64_t cap, float* color, float* depth, float* alpha) {
   const gsr::Raster& R = s->R;
   const int n_items = R.n_tiles * s->n_views;
-  gsr::PlaceArgs pl{s->n, s->n_views, n_items, s->rec_rgbz, s->rect, s->counts, s->tile_fill, cap, s->keys,
-                    s->d_overflow};
   {
     Stage t(c, "tile_bins");
-    gsr::launch_tile_bins(R, pl, s->tile_cntT, s->tile_start, n_items, s->ranges, s->scratch, s->ids, st);
+    gsr::launch_tile_bins(R, bin_args(s, cap), n_items, s->ranges, s->scratch, s->ids, st);
     if (s->blocks > 0) gsr::launch_item_order(s->ranges, n_items, s->order, s->order_temp, st);
   }
   gsr::FwdArgs fa{s->ranges, s->ids, s->rec_uvab, s->rec_cob, s->rec_rgbz,

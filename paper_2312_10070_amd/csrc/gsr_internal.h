@@ -15,13 +15,6 @@ constexpr float kLn2 = 0.6931471805599453f;
 constexpr int kTileThreads = 256;  // one pixel per lane, 4 waves per tile
 constexpr int kWave = 64;
 
-// Per-tile counters are kept in kBinCopies copies (copy-major, so the copies
-// of one tile sit in different cache lines): the L2 atomic unit serialises
-// updates of one line, and a few hundred Gaussians per tile would otherwise
-// queue on each line. Gaussian k uses copy bin_copy(k) when counting and when
-// taking its slots.
-constexpr int kBinCopies = 32;
-__device__ __forceinline__ int bin_copy(int64_t k) { return (int)((k >> 8) & (kBinCopies - 1)); }
 
 // Launch constants of one render (by value into every kernel).
 struct Raster {
@@ -192,7 +185,6 @@ struct ProjectArgs {
   int4* rect;          // tile rectangle (tx0, ty0, tx1, ty1)
   uint32_t* counts;    // tiles per Gaussian (0 = culled)
   int n_views;         // outputs are [n_views * n]; view v uses pose7 + 7 v
-  uint32_t* tile_cnt;  // [kBinCopies][n_views * n_tiles], zeroed by the caller: Gaussians per tile (atomic)
 };
 void launch_project(const Raster& R, const ProjectArgs& a, hipStream_t s);
 
@@ -202,27 +194,30 @@ int64_t scan_temp_words(int64_t n);
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* temp,
                            hipStream_t s);
 
-// Slot placement of every (Gaussian, tile) pair (see k_sort.hip).
-struct PlaceArgs {
+// Tile binning (see k_sort.hip). Workgroup w of view v handles the Gaussians
+// [w c, (w + 1) c) with c = ceil(n / n_wg); M[item][w] counts its pairs per
+// (view, tile) item and S = exclusive scan of M in (item, workgroup) order.
+struct BinArgs {
   int64_t n;
-  int n_views;             // entries are [n_views * n]; tile ids of view v start at v * n_tiles
-  int64_t n_items;         // n_views * n_tiles
-  const float4* rec_rgbz;  // camera depth in .w
+  int n_views;
+  int n_wg;                // workgroups per view
   const int4* rect;
   const uint32_t* counts;
-  uint32_t* fill;          // [kBinCopies][n_items]: next free position of each copy's sub-range
+  const float4* rec_rgbz;  // camera depth in .w
+  uint32_t* M;             // [n_items][n_wg]
+  uint32_t* S;             // [n_items][n_wg]
   int64_t cap;             // positions >= cap are dropped and flagged
   uint64_t* keys;          // [cap] (depth bits << 32 | record index)
   int* overflow;
 };
-// Copy-major per-tile counts -> tile-major cntT [n_items][kBinCopies] (the
-// order of the scan that lays the copies' sub-ranges out inside each tile).
-void launch_bin_gather(const uint32_t* tile_cnt, int64_t n_items, uint32_t* cntT, hipStream_t s);
-// ranges/fill from cntT and its exclusive scan startT, slot placement, then
-// one LDS sort per tile writing ids[cap] (record indices in depth order).
+int bin_workgroups(int64_t n);
+// M from the tile rectangles (LDS histograms, no global atomics).
+void launch_bin_count(const Raster& R, const BinArgs& a, hipStream_t s);
+// ranges from M and S, slot placement (LDS counters seeded from S), then one
+// LDS sort per tile writing ids[cap] (record indices in depth order).
 // scratch: [cap] keys, used by ranges longer than LDS holds.
-void launch_tile_bins(const Raster& R, const PlaceArgs& a, const uint32_t* cntT, const uint32_t* startT,
-                      int64_t n_items, int2* ranges, uint64_t* scratch, uint32_t* ids, hipStream_t s);
+void launch_tile_bins(const Raster& R, const BinArgs& a, int64_t n_items, int2* ranges, uint64_t* scratch,
+                      uint32_t* ids, hipStream_t s);
 
 struct FwdArgs {
   const int2* ranges;

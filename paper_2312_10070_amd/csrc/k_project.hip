@@ -155,12 +155,6 @@ __global__ __launch_bounds__(256) void k_project(Raster Rr, ProjectArgs a) {
           const int px0 = (int)fx0, px1 = (int)fx1, py0 = (int)fy0, py1 = (int)fy1;
           rect = make_int4(px0 >> Rr.tw_log2, py0 / Rr.th, px1 >> Rr.tw_log2, py1 / Rr.th);
           count = (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1));
-          if (a.tile_cnt) {
-            const int64_t n_items = (int64_t)Rr.n_tiles * a.n_views;
-            uint32_t* tc = a.tile_cnt + bin_copy(k) * n_items + (int64_t)blockIdx.y * Rr.n_tiles;
-            for (int ty = rect.y; ty <= rect.w; ++ty)
-              for (int tx = rect.x; tx <= rect.z; ++tx) atomicAdd(tc + ty * Rr.ntx + tx, 1u);
-          }
           const float s = -0.5f * kLog2e;
           a.rec_uvab[o] = make_float4(g.u, g.v, s * ca, -kLog2e * cb);
           a.rec_cob[o] = make_float4(s * cc, op, __uint_as_float((uint32_t)px0 | ((uint32_t)px1 << 16)),

@@ -1,16 +1,19 @@
-// Tile binning. The projection counts, per tile, the Gaussians whose tile
-// rectangle holds it; an exclusive scan of those counts gives each tile's
-// [start, end) range in the overlap list (and the overlap count K). Every
-// (Gaussian, tile) pair then takes a slot of its tile's range with an atomic
-// counter and writes the key (float bits of the camera depth << 32 | record
-// index); the slot order is arbitrary. Finally one workgroup per tile sorts
-// its range by key in LDS (a bitonic network; a range longer than LDS holds
-// is sorted in LDS-sized runs that are merged pairwise in global memory) and
-// writes the record indices. Keys are unique within a tile, so the result is
-// the depth order of the "m ordered Gaussians" of Eq. 3 and Eq. 6 with ties
-// broken by index: exactly what a stable sort of (tile, depth) gives.
-// No launch grid depends on K: positions at or beyond the capacity are
-// dropped and flagged, so the same launches serve captured graphs.
+// Tile binning without global atomics. Each binning workgroup owns a
+// contiguous run of Gaussians and counts their (Gaussian, tile) pairs per tile
+// in an LDS histogram, written out as column w of a [tile][workgroup] matrix
+// M. An exclusive scan of M in (tile, workgroup) order gives every workgroup
+// its sub-range inside every tile's [start, end) range (and the overlap count
+// K). The workgroup then walks its Gaussians again, takes positions from LDS
+// counters seeded with its sub-range starts, and writes the keys (float bits
+// of the camera depth << 32 | record index) in arbitrary order. Finally one
+// workgroup per tile sorts its range by key in LDS (a bitonic network; a
+// range longer than LDS holds is sorted in LDS-sized runs merged pairwise in
+// global memory) and writes the record indices. Keys are unique within a
+// tile, so the result is the depth order of the "m ordered Gaussians" of
+// Eq. 3 and Eq. 6 with ties broken by index: exactly what a stable sort of
+// (tile, depth) gives. No launch grid depends on K: positions at or beyond
+// the capacity are dropped and flagged, so the same launches serve captured
+// graphs.
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -106,46 +109,83 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
 constexpr int kSortCap = 2048;  // keys a workgroup sorts in LDS (16 KB)
 constexpr int kBinThreads = 256;
 
-__global__ __launch_bounds__(256) void k_bin_gather(const uint32_t* __restrict__ cnt, int64_t n_items,
-                                                   uint32_t* __restrict__ cntT) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // = item * kBinCopies + copy
-  if (i >= n_items * kBinCopies) return;
-  const int64_t t = i / kBinCopies, c = i - t * kBinCopies;
-  cntT[i] = cnt[c * n_items + t];
+// Tiles one workgroup's LDS histogram covers (64 KB); more tiles per view are
+// handled in chunks (grid.z).
+constexpr int kBinTileChunk = 16384;
+
+struct Chunk {
+  int64_t g0, g1;  // Gaussians of this workgroup
+  int t0, nt;      // tiles of this chunk
+};
+
+__device__ __forceinline__ Chunk bin_chunk(const Raster& Rr, const BinArgs& a) {
+  Chunk c;
+  const int64_t per = (a.n + a.n_wg - 1) / a.n_wg;
+  c.g0 = (int64_t)blockIdx.x * per;
+  c.g1 = c.g0 + per < a.n ? c.g0 + per : a.n;
+  c.t0 = (int)blockIdx.z * kBinTileChunk;
+  c.nt = min(Rr.n_tiles - c.t0, kBinTileChunk);
+  return c;
 }
 
-// ranges[t] = [start of copy 0, end of the last copy) clipped to the
-// capacity; fill[c][t] = start of copy c's sub-range.
-__global__ __launch_bounds__(256) void k_tile_init(const uint32_t* __restrict__ cntT,
-                                                  const uint32_t* __restrict__ startT, int64_t n_items, int64_t cap,
-                                                  int2* __restrict__ ranges, uint32_t* __restrict__ fill) {
+// M[(v n_tiles + t) n_wg + w] = pairs of workgroup w's Gaussians on tile t of view v.
+__global__ __launch_bounds__(256) void k_bin_count(Raster Rr, BinArgs a) {
+  extern __shared__ uint32_t hist[];
+  const Chunk c = bin_chunk(Rr, a);
+  const int64_t view = blockIdx.y;
+  for (int i = threadIdx.x; i < c.nt; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  for (int64_t g = c.g0 + threadIdx.x; g < c.g1; g += blockDim.x) {
+    const int64_t o = view * a.n + g;
+    if (a.counts[o] == 0) continue;
+    const int4 r = a.rect[o];
+    for (int ty = r.y; ty <= r.w; ++ty)
+      for (int tx = r.x; tx <= r.z; ++tx) {
+        const int t = ty * Rr.ntx + tx - c.t0;
+        if ((unsigned)t < (unsigned)c.nt) atomicAdd(&hist[t], 1u);
+      }
+  }
+  __syncthreads();
+  const int64_t row = view * Rr.n_tiles + c.t0;
+  for (int i = threadIdx.x; i < c.nt; i += blockDim.x) a.M[(row + i) * a.n_wg + blockIdx.x] = hist[i];
+}
+
+// ranges[t] = [S[t][0], S[t][n_wg - 1] + M[t][n_wg - 1]) clipped to the capacity.
+__global__ __launch_bounds__(256) void k_tile_init(const uint32_t* __restrict__ M, const uint32_t* __restrict__ S,
+                                                  int64_t n_items, int n_wg, int64_t cap, int2* __restrict__ ranges) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_items) return;
-  const int64_t b = t * kBinCopies;
-  const int64_t s0 = startT[b], s1 = (int64_t)startT[b + kBinCopies - 1] + cntT[b + kBinCopies - 1];
+  const int64_t b = t * n_wg;
+  const int64_t s0 = S[b], s1 = (int64_t)S[b + n_wg - 1] + M[b + n_wg - 1];
   ranges[t] = make_int2((int)(s0 < cap ? s0 : cap), (int)(s1 < cap ? s1 : cap));
-  for (int c = 0; c < kBinCopies; ++c) fill[c * n_items + t] = startT[b + c];
 }
 
-// One thread per (view, Gaussian): a slot in every tile of its rectangle.
-__global__ __launch_bounds__(256) void k_tile_place(Raster Rr, PlaceArgs a) {
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // view * n + Gaussian
-  if (o >= a.n * a.n_views) return;
-  if (a.counts[o] == 0) return;
-  const int4 r = a.rect[o];
-  const uint64_t key_lo = (uint64_t)(uint32_t)o;
-  const uint64_t zb = (uint64_t)__float_as_uint(a.rec_rgbz[o].w) << 32;
-  const int64_t view = o / a.n;
-  uint32_t* fill = a.fill + bin_copy(o - view * a.n) * a.n_items + view * Rr.n_tiles;
-  for (int ty = r.y; ty <= r.w; ++ty)
-    for (int tx = r.x; tx <= r.z; ++tx) {
-      const uint32_t pos = atomicAdd(fill + ty * Rr.ntx + tx, 1u);
-      if ((int64_t)pos < a.cap) {
-        a.keys[pos] = zb | key_lo;
-      } else {
-        atomicOr(a.overflow, 1);
+// Every (Gaussian, tile) pair of the workgroup takes the next position of its
+// tile's sub-range (LDS counters seeded from S) and writes its key there.
+__global__ __launch_bounds__(256) void k_bin_place(Raster Rr, BinArgs a) {
+  extern __shared__ uint32_t next[];
+  const Chunk c = bin_chunk(Rr, a);
+  const int64_t view = blockIdx.y;
+  const int64_t row = view * Rr.n_tiles + c.t0;
+  for (int i = threadIdx.x; i < c.nt; i += blockDim.x) next[i] = a.S[(row + i) * a.n_wg + blockIdx.x];
+  __syncthreads();
+  for (int64_t g = c.g0 + threadIdx.x; g < c.g1; g += blockDim.x) {
+    const int64_t o = view * a.n + g;
+    if (a.counts[o] == 0) continue;
+    const int4 r = a.rect[o];
+    const uint64_t key = ((uint64_t)__float_as_uint(a.rec_rgbz[o].w) << 32) | (uint64_t)(uint32_t)o;
+    for (int ty = r.y; ty <= r.w; ++ty)
+      for (int tx = r.x; tx <= r.z; ++tx) {
+        const int t = ty * Rr.ntx + tx - c.t0;
+        if ((unsigned)t >= (unsigned)c.nt) continue;
+        const uint32_t pos = atomicAdd(&next[t], 1u);
+        if ((int64_t)pos < a.cap) {
+          a.keys[pos] = key;
+        } else {
+          atomicOr(a.overflow, 1);
+        }
       }
-    }
+  }
 }
 
 // Bitonic sort of s[0, n2) ascending (n2 a power of two <= kSortCap), all
@@ -271,20 +311,29 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, (const uint32_t*)temp);
 }
 
-void launch_bin_gather(const uint32_t* tile_cnt, int64_t n_items, uint32_t* cntT, hipStream_t s) {
-  const int64_t m = n_items * kBinCopies;
-  if (m <= 0) return;
-  hipLaunchKernelGGL(k_bin_gather, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, tile_cnt, n_items, cntT);
+int bin_workgroups(int64_t n) {
+  const int64_t w = (n + 1023) / 1024;
+  return (int)(w < 1 ? 1 : (w > 256 ? 256 : w));
 }
 
-void launch_tile_bins(const Raster& R, const PlaceArgs& a, const uint32_t* cntT, const uint32_t* startT,
-                      int64_t n_items, int2* ranges, uint64_t* scratch, uint32_t* ids, hipStream_t s) {
+namespace {
+dim3 bin_grid(const Raster& R, const BinArgs& a) {
+  return dim3((unsigned)a.n_wg, (unsigned)a.n_views, (unsigned)((R.n_tiles + kBinTileChunk - 1) / kBinTileChunk));
+}
+size_t bin_lds(const Raster& R) { return sizeof(uint32_t) * (size_t)min(R.n_tiles, kBinTileChunk); }
+}  // namespace
+
+void launch_bin_count(const Raster& R, const BinArgs& a, hipStream_t s) {
+  if (R.n_tiles <= 0 || a.n_views <= 0) return;
+  hipLaunchKernelGGL(k_bin_count, bin_grid(R, a), dim3(256), bin_lds(R), s, R, a);
+}
+
+void launch_tile_bins(const Raster& R, const BinArgs& a, int64_t n_items, int2* ranges, uint64_t* scratch,
+                      uint32_t* ids, hipStream_t s) {
   if (n_items <= 0) return;
-  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, cntT, startT,
-                     n_items, a.cap, ranges, a.fill);
-  const int64_t m = a.n * a.n_views;
-  if (m > 0)
-    hipLaunchKernelGGL(k_tile_place, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, R, a);
+  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, (const uint32_t*)a.M,
+                     (const uint32_t*)a.S, n_items, a.n_wg, a.cap, ranges);
+  hipLaunchKernelGGL(k_bin_place, bin_grid(R, a), dim3(256), bin_lds(R), s, R, a);
   hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)n_items), dim3(kBinThreads), 0, s, (const int2*)ranges, a.keys,
                      scratch, ids);
 }

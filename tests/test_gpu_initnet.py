@@ -129,11 +129,12 @@ CAM = synth.Intrinsics(320, 240, 262.5, 262.5, 160.0, 120.0)
 @pytest.fixture(scope="module")
 def trained():
     torch = torch_()
-    x, y = initnet.generate_pairs(12288, seed=11, cam=CAM)
+    x, y = initnet.generate_pairs(32768, seed=11, cam=CAM)
     xv, yv = initnet.generate_pairs(512, seed=12, cam=CAM)
     net = gsr.InitNet(max_batch=64)
     net.set_params(torch.from_numpy(initnet.init_params(0)).cuda())
-    losses = initnet.train(net, x, y, steps=2500, batch=64, lr=2e-3)
+    losses = initnet.train(net, x, y, steps=8000, batch=64, lr=2e-3)
+    del x, y
     return net, losses, xv, yv
 
 
@@ -144,7 +145,7 @@ def test_training_reduces_loss(trained):
 
 def test_proposals_reduce_held_out_pose_error(trained):
     """On held-out rooms the predicted twist removes a clear part of the
-    perturbation: its mean squared (scaled) error is below 0.75 of the zero
+    perturbation: its mean squared (scaled) error is below 0.6 of the zero
     predictor's. A global-average-pooled network cannot undo every
     rotation/translation ambiguity, so the bar is a clear gain, not a fit."""
     torch = torch_()
@@ -155,19 +156,20 @@ def test_proposals_reduce_held_out_pose_error(trained):
     mse_pred = np.mean(((preds - y) / s) ** 2)
     mse_zero = np.mean((y / s) ** 2)
     print("held-out scaled MSE: network", mse_pred, "zero predictor", mse_zero)
-    assert mse_pred < 0.75 * mse_zero, (mse_pred, mse_zero)
+    assert mse_pred < 0.6 * mse_zero, (mse_pred, mse_zero)
 
 
 def test_learned_init_gain(trained):
-    """Tracking from the network's proposal (kept only when Eq. 15 prefers it)
+    """On frames perturbed by 5 cm / 3 degrees (the training range), tracking
+    from the network's proposal (kept only when Eq. 15 prefers it)
     reaches the accuracy of 100 plain iterations (their final error + 5 %, at
     least 0.5 mm) in fewer iterations, on average, than plain tracking does."""
     torch = torch_()
     net, _, _, _ = trained
     budgets = (10, 15, 20, 30, 40, 50, 60, 80, 100)
     n_plain, n_learned, used = [], [], 0
-    for frame in range(4):
-        inp = synth.tracking_inputs(100 + frame, 60_000, CAM, n_views=3, trans_m=0.03, rot_deg=2.0)
+    for frame in range(8):
+        inp = synth.tracking_inputs(100 + frame, 60_000, CAM, n_views=3, trans_m=0.05, rot_deg=3.0)
         g = {k: torch.from_numpy(v).cuda() for k, v in inp["gaussians"].items()}
         args = (g["means"], g["scales"], g["quats"], g["opacities"], g["colors"])
         cam = gsr.camera_from(CAM)
@@ -192,5 +194,5 @@ def test_learned_init_gain(trained):
         for tg in graphs.values():
             tg.close()
     print("iterations to the target error: plain", n_plain, "learned", n_learned, "proposals used:", used)
-    assert used >= 2, "the proposal should usually beat the initial pose"
+    assert used >= 4, "the proposal should usually beat the initial pose"
     assert np.mean(n_learned) < np.mean(n_plain), (n_plain, n_learned)
