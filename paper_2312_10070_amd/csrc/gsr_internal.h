@@ -11,7 +11,6 @@
 namespace gsr {
 
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kLn2 = 0.6931471805599453f;
 constexpr int kTileThreads = 256;  // one pixel per lane, 4 waves per tile
 constexpr int kWave = 64;
 
@@ -244,7 +243,7 @@ struct BwdArgs {
   const float* Tfin;
   const int* last;
   const float *gC, *gD, *gA;
-  float* g2d;  // [V*n, 10]: u, v, pa, pb, pc, o, r, g, b, z
+  float* g2d;  // [V*n, 10]: sums of q (dx, dy, dx^2, dx dy, dy^2), q = dL/dp / ln 2; o, r, g, b, z
   int n_items;
   int* queue;
   const int* order;

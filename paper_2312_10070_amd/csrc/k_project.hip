@@ -168,26 +168,33 @@ __global__ __launch_bounds__(256) void k_project(Raster Rr, ProjectArgs a) {
   a.counts[o] = count;
 }
 
-// Backward of the projection for one (Gaussian, view). g2d holds dL/d(u, v,
-// pa, pb, pc, o, r, g, b, z) accumulated by the compositing backward. Adds to
+// Backward of the projection for one (Gaussian, view). g2d holds the ten
+// per-Gaussian sums of the compositing backward (see below for the first five;
+// then dL/d(o, r, g, b) and the direct dL/dz). Adds to
 // the parameter gradients and returns the pose partials (dL/dR_p, dL/dt).
 __device__ __forceinline__ void chain_one(const Raster& Rr, const PoseF& P, const ProjectBwdArgs& a, int64_t k,
                                           const float* __restrict__ G2, float gm[3], float gs[3], float gq[4],
                                           float& go, float gc[3], float pacc[12]) {
   Geo g;
   if (!project_geo(Rr, P, a.means, a.scales, a.quats, k, g)) return;
-  const float g_u = G2[0], g_v = G2[1];
-  // stored (pa, pb, pc) = -log2(e) (a/2, b, c/2) for the conic (a, b, c)
-  const float g_a = -0.5f * kLog2e * G2[2];
-  const float g_b = -kLog2e * G2[3];
-  const float g_c = -0.5f * kLog2e * G2[4];
+  const float idet = 1.f / g.det;
+  const float A00 = g.Syy * idet, A01 = -g.Sxy * idet, A11 = g.Sxx * idet;
+  // The compositing backward accumulates q = (dL/dalpha) alpha = (dL/dp) / ln 2
+  // per pair, with alpha = o 2^p, p = pa dx^2 + pb dx dy + pc dy^2, dx = px - u
+  // and the stored (pa, pb, pc) = -log2(e) (a/2, b, c/2) of the conic (a, b, c):
+  // G2[0..4] = sum q (dx, dy, dx^2, dx dy, dy^2). As pa, pb, pc are constant per
+  // Gaussian, dL/du = -ln2 (2 pa G2[0] + pb G2[1]) = a G2[0] + b G2[1] (likewise
+  // for v) and dL/da = -ln2 log2(e) G2[2] / 2 = -G2[2] / 2, dL/db = -G2[3].
+  const float g_u = A00 * G2[0] + A01 * G2[1];
+  const float g_v = A01 * G2[0] + A11 * G2[1];
+  const float g_a = -0.5f * G2[2];
+  const float g_b = -G2[3];
+  const float g_c = -0.5f * G2[4];
   go += G2[5];
   gc[0] += G2[6];
   gc[1] += G2[7];
   gc[2] += G2[8];
   const float g_zd = G2[9];
-  const float idet = 1.f / g.det;
-  const float A00 = g.Syy * idet, A01 = -g.Sxy * idet, A11 = g.Sxx * idet;
   // dL/dSigma' = -A Mg A with Mg = [[g_a, g_b/2], [g_b/2, g_c]]
   const float m01 = 0.5f * g_b;
   const float t00 = A00 * g_a + A01 * m01, t01 = A00 * m01 + A01 * g_c;

@@ -16,8 +16,10 @@
 // transmittance in front of Gaussian j is recomputed as T_j = T_{j+1} /
 // (1 - alpha_j) instead of being stored; suffix sums of c alpha T and z alpha T
 // give the second terms of dC/dalpha and Eq. 8. The ten per-Gaussian partials
-// of a wave are summed with a field-splitting butterfly and added to the
-// [V n, 10] gradient buffer with one 10-lane atomic per (Gaussian, wave).
+// (sums of q (dx, dy, dx^2, dx dy, dy^2) with q = dL/dp / ln 2 for alpha =
+// o 2^p, then opacity, colour, direct depth) of a wave are summed with a field-splitting
+// butterfly and added to the [V n, 10] gradient buffer with one 10-lane
+// atomic per (Gaussian, wave).
 //
 // Launch shapes: one workgroup per item (items dealt to XCDs in contiguous
 // runs), or a persistent grid whose workgroups pull items from a counter in
@@ -200,9 +202,12 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
     gd = a.gD[p];
     ga = a.gA ? a.gA[p] : 0.f;
   }
-  const float Tfin = T;
-  // suffix sums: the background enters dC/dalpha through T_final * bg
-  float S0 = T * Rr.bg0, S1 = T * Rr.bg1, S2 = T * Rr.bg2, SD = 0.f;
+  // dL/dalpha_j = T_j (g . c_j) - (g . S_j + ga T_fin) / (1 - alpha_j) with the
+  // suffix sums S_j = sum_{u > j} c_u alpha_u T_u + T_fin bg (colour) and
+  // sum_{u > j} z_u alpha_u T_u (depth), g = (gC, gD). Only the dot product
+  // gS = g . S_j is needed; the background enters it through T_fin bg.
+  float gS = T * (g0 * Rr.bg0 + g1 * Rr.bg1 + g2 * Rr.bg2);
+  const float gA = ga * T;
 
   __syncthreads();  // the previous item (persistent launch) is done with max_last
   if (tid == 0) sm.max_last = 0;
@@ -257,24 +262,22 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
         v[7] = w * g1;
         v[8] = w * g2;
         v[9] = w * gd;
-        float dA = g0 * (cz.x * Tj - S0 * inv) + g1 * (cz.y * Tj - S1 * inv) + g2 * (cz.z * Tj - S2 * inv);
-        dA += gd * (cz.w * Tj - SD * inv);
-        dA += ga * Tfin * inv;
-        S0 = fmaf(cz.x, w, S0);
-        S1 = fmaf(cz.y, w, S1);
-        S2 = fmaf(cz.z, w, S2);
-        SD = fmaf(cz.w, w, SD);
+        const float gc = fmaf(g0, cz.x, fmaf(g1, cz.y, fmaf(g2, cz.z, gd * cz.w)));
+        const float dA = fmaf(Tj, gc, -inv * (gS - gA));
+        gS = fmaf(gc, w, gS);
         T = Tj;
         // a clamped alpha does not depend on o or sigma
         const float dAs = (hit && !pe.clamped) ? dA : 0.f;
         v[5] = dAs * pe.e;                       // d alpha / d o = exp(-sigma)
-        const float gp = dAs * pe.alpha * kLn2;  // dL/dp with alpha = o 2^p
+        // q = dL/dp / ln 2 with alpha = o 2^p; the projection backward turns the
+        // sums of q (dx, dy, dx^2, dx dy, dy^2) into dL/d(u, v) and the conic terms
+        const float gp = dAs * pe.alpha;
         const float gpx = gp * dx, gpy = gp * dy;
+        v[0] = gpx;
+        v[1] = gpy;
         v[2] = gpx * dx;
         v[3] = gpx * dy;
         v[4] = gpy * dy;
-        v[0] = -(2.f * g.z * gpx + g.w * gpy);
-        v[1] = -(g.w * gpx + 2.f * cb.x * gpy);
         wave_add10(v, a.g2d + 10 * (int64_t)sm.gid[li], lane);
       }
     }
