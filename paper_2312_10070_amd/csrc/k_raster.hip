@@ -104,13 +104,14 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
   const Pixel q = item_pixel(Rr, item);
   const int2 rg = a.ranges[item];
   const int start = rg.x, end = rg.y;
-  bool done = !q.inside;
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
+  // T > 0: the lane is compositing; T < 0: it has stopped and -T is its final
+  // transmittance (T >= T_min > 0 while compositing, so the sign is free).
+  float T = q.inside ? 1.f : -1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
   int last = 0;
   uint32_t n_eval = 0, n_comp = 0;
 
   for (int base = start; base < end; base += kTileThreads) {
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(T > 0.f) == 0) break;
     const int i = base + tid;
     if (i < end) {
       const uint32_t gid = a.ids[i];
@@ -119,7 +120,7 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
       sm.rgbz[tid] = a.rec_rgbz[gid];
     }
     __syncthreads();
-    if (!__any(!done)) continue;
+    if (!__any(T > 0.f)) continue;
     const int cnt = min(kTileThreads, end - base);
     bool wave_done = false;
     for (int c = 0; c * kWave < cnt && !wave_done; ++c) {
@@ -133,26 +134,26 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
       while (m) {
         const int j = c * kWave + __builtin_ctzll(m);
         m &= m - 1;
-        // Every lane runs the same instructions; a lane that does not composite
-        // this record adds w = 0 and keeps its transmittance.
+        // Every lane runs the same instructions. A skipped pair (alpha <
+        // alpha_min) acts as alpha = 0; a stopped lane has T < 0, so its Tn < T_min
+        // and it adds w = 0 and keeps T.
         const float4 g = sm.uvab[j];
         const float4 cb = sm.cob[j];
         const float4 cz = sm.rgbz[j];
         const PairEval pe = eval_pair(q.fpx - g.x, q.fpy - g.y, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
-        if (STATS && !done && box_holds(cb.z, cb.w, q.px, q.py)) ++n_eval;
-        const float Tn = T * (1.f - pe.alpha);
-        const bool live = !done && pe.use;
-        const bool comp = live && Tn >= Rr.tmin;
-        done = done || (live && Tn < Rr.tmin);
-        const float w = comp ? pe.alpha * T : 0.f;
+        if (STATS && T > 0.f && box_holds(cb.z, cb.w, q.px, q.py)) ++n_eval;
+        const float al = pe.use ? pe.alpha : 0.f;
+        const float Tn = T * (1.f - al);
+        const bool comp = Tn >= Rr.tmin;  // false for a stopped lane and at the stop
+        const float w = comp ? al * T : 0.f;
         C0 = fmaf(cz.x, w, C0);
         C1 = fmaf(cz.y, w, C1);
         C2 = fmaf(cz.z, w, C2);
         D = fmaf(cz.w, w, D);
-        T = comp ? Tn : T;
-        last = comp ? base - start + j + 1 : last;
-        if (STATS && comp) ++n_comp;
-        if (!__any(!done)) {
+        last = (comp && pe.use) ? base - start + j + 1 : last;
+        if (STATS && comp && pe.use) ++n_comp;
+        T = comp ? Tn : -fabsf(T);
+        if (!__any(T > 0.f)) {
           wave_done = true;
           break;
         }
@@ -172,6 +173,7 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
     return;
   }
   if (q.inside) {
+    T = fabsf(T);
     const int64_t P = (int64_t)Rr.W * Rr.H;
     const int64_t p = q.off + q.p;
     float* col = a.color + 3 * q.off;
