@@ -96,6 +96,7 @@ struct gsr_ctx {
   std::string err;
   std::vector<gsr_state*> pool;
   uint32_t* h_K = nullptr;  // pinned host word for the overlap count
+  uint32_t* red = nullptr;  // grid-reduction scratch of the L1 loss
   uint32_t* track_temp = nullptr;
   unsigned long long* d_stats = nullptr;
   int n_cu = 256;  // compute units of the device
@@ -429,10 +430,22 @@ int gsr_ctx_create(gsr_ctx** out, int device, void* hip_stream) {
   (void)hipGetLastError();
   if (hipHostMalloc((void**)&c->h_K, 64, hipHostMallocDefault) != hipSuccess ||
       hipMalloc((void**)&c->track_temp, sizeof(uint32_t) * gsr::track_temp_words()) != hipSuccess ||
+      hipMalloc((void**)&c->red, sizeof(uint32_t) * gsr::reduce_temp_words()) != hipSuccess ||
       hipMalloc((void**)&c->d_stats, 64) != hipSuccess) {
     (void)hipGetLastError();
+    if (c->h_K) (void)hipHostFree(c->h_K);
+    if (c->track_temp) (void)hipFree(c->track_temp);
+    if (c->red) (void)hipFree(c->red);
+    if (c->d_stats) (void)hipFree(c->d_stats);
     delete c;
     return GSR_ENOMEM;
+  }
+  gsr::launch_fill_u32(c->track_temp, 0u, gsr::track_temp_words(), c->stream);
+  gsr::launch_fill_u32(c->red, 0u, gsr::reduce_temp_words(), c->stream);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    gsr_ctx_destroy(c);
+    return GSR_EHIP;
   }
   *out = c;
   return GSR_OK;
@@ -449,6 +462,7 @@ int gsr_ctx_destroy(gsr_ctx* c) {
   }
   if (c->h_K) (void)hipHostFree(c->h_K);
   if (c->track_temp) (void)hipFree(c->track_temp);
+  if (c->red) (void)hipFree(c->red);
   if (c->d_stats) (void)hipFree(c->d_stats);
   for (auto& r : c->recs) {
     (void)hipEventDestroy(r.a);
@@ -563,7 +577,8 @@ int gsr_loss_l1(gsr_ctx* c, const float* color, const float* depth, const float*
     return fail(c, GSR_EINVAL, "bad loss arguments");
   GSR_HIP(c, hipSetDevice(c->device));
   Stage t(c, "loss_l1");
-  gsr::launch_loss_l1(color, depth, tgt_color, tgt_depth, P, w_color, w_depth, loss, dL_dcolor, dL_ddepth, c->stream);
+  gsr::launch_loss_l1(color, depth, tgt_color, tgt_depth, P, w_color, w_depth, loss, dL_dcolor, dL_ddepth, c->red,
+                      c->stream);
   return check_launch(c, "gsr_loss_l1");
 }
 
@@ -1074,6 +1089,7 @@ int gsr_track_graph_create(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera*
   // every id slot holds an in-range record index from the start
   gsr::launch_fill_u32(s->ids, 0u, K_cap, st);
   gsr::launch_fill_f32(tg->pose, 0.f, 8, st);
+  gsr::launch_fill_u32(tg->sel_temp, 0u, gsr::track_temp_words(), st);
   rc = gsr_track_graph_set_frame(c, tg, obs_color, obs_depth);
   if (!rc) {
     hipError_t e = hipStreamSynchronize(st);

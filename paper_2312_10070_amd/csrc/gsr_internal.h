@@ -271,9 +271,12 @@ void launch_item_order(const int2* ranges, int n_items, int* order, int* temp, h
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 
+// red: reduce_temp_words() uint32, zero before its first use (the loss kernels
+// leave it zero again).
+int64_t reduce_temp_words();
 void launch_loss_l1(const float* C, const float* D, const float* Ct, const float* Dt, int64_t P, float wc, float wd,
-                    float* loss, float* gC, float* gD, hipStream_t s);
-// temp: track_temp_words() uint32
+                    float* loss, float* gC, float* gD, uint32_t* red, hipStream_t s);
+// temp: track_temp_words() uint32, zero before its first use
 int64_t track_temp_words();
 void launch_loss_track(const float* C, const float* D, const float* A, const float* Ct, const float* Dt, int64_t P,
                        float lambda_c, float inlier_mult, float* loss, float* gC, float* gD, float* median,

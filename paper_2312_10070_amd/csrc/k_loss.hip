@@ -9,20 +9,97 @@ namespace {
 
 __device__ __forceinline__ float sgnf(float r) { return (float)((r > 0.f) - (r < 0.f)); }
 
-__device__ __forceinline__ void block_add(float v, float* dst) {
-  __shared__ float red[4];
+constexpr int kRedSlots = 1024;  // most workgroups a grid_sum launch may have
+constexpr int kRedGroup = 32;    // workgroups per first-level ticket
+constexpr int kRedGroups = kRedSlots / kRedGroup;
+constexpr int kLine = 16;        // words per 64-byte line: one ticket per line
+// red layout (uint32 words): partials | group sums | group tickets | final ticket
+constexpr int kRedSums = kRedSlots, kRedTickets = kRedSums + kRedGroups;
+constexpr int kRedFinal = kRedTickets + kRedGroups * kLine;
+constexpr int kRedWords = kRedFinal + kLine;
+
+__device__ __forceinline__ float block_sum(float v) {
+  __shared__ float part[4];
   const float s = wave_sum_all(v);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();  // part[] may still be read from a previous call
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(dst, red[0] + red[1] + red[2] + red[3]);
+  return part[0] + part[1] + part[2] + part[3];
 }
 
+// Stores `value` to the device-coherent level, waits for it, then takes a
+// ticket; returns true for the last of `n` takers (who resets the ticket).
+// No release fence: that would also write back the workgroup's unrelated stores.
+__device__ __forceinline__ bool publish_and_count(float* slot, float value, uint32_t* ticket, uint32_t n) {
+  __hip_atomic_store(slot, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (t != n - 1) return false;
+  __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+// Sum of v over the whole grid into *out (overwritten), in a fixed order and
+// with at most kRedGroup same-address atomics in a row (those serialise in
+// L2): every workgroup publishes its partial; the last of each group of
+// kRedGroup workgroups sums the group's partials and publishes that; the last
+// group sums the group sums. Tickets return to zero. red: kRedWords words,
+// zero before the first launch.
+__device__ __forceinline__ void grid_sum(float v, float* out, uint32_t* red) {
+  __shared__ bool go;
+  float* f = reinterpret_cast<float*>(red);
+  const uint32_t b = blockIdx.x, n = gridDim.x;
+  const uint32_t g = b / kRedGroup, n_groups = (n + kRedGroup - 1) / kRedGroup;
+  const uint32_t in_group = min((uint32_t)kRedGroup, n - g * kRedGroup);
+  const float s = block_sum(v);
+  if (threadIdx.x == 0) go = publish_and_count(f + b, s, red + kRedTickets + kLine * g, in_group);
+  __syncthreads();
+  if (!go) return;
+  float acc = threadIdx.x < in_group
+                  ? __hip_atomic_load(f + g * kRedGroup + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                  : 0.f;
+  const float gs = block_sum(acc);
+  if (threadIdx.x == 0) go = publish_and_count(f + kRedSums + g, gs, red + kRedFinal, n_groups);
+  __syncthreads();
+  if (!go) return;
+  acc = threadIdx.x < n_groups
+            ? __hip_atomic_load(f + kRedSums + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+            : 0.f;
+  const float total = block_sum(acc);
+  if (threadIdx.x == 0) *out = total;
+}
+
+__device__ __forceinline__ float4 ld4(const float* p, int64_t i) { return reinterpret_cast<const float4*>(p)[i]; }
+__device__ __forceinline__ void st4(float* p, int64_t i, float4 v) { reinterpret_cast<float4*>(p)[i] = v; }
+__device__ __forceinline__ float l1_term(float r, float w, float* g) {
+  *g = sgnf(r) * w;
+  return fabsf(r) * w;
+}
+
+// P4 = P / 4 when every plane is 16-byte aligned (float4 path for pixels
+// [0, 4 P4)), else 0; the rest is handled one pixel at a time.
 __global__ __launch_bounds__(256) void k_loss_l1(const float* __restrict__ C, const float* __restrict__ D,
                                                 const float* __restrict__ Ct, const float* __restrict__ Dt, int64_t P,
-                                                float wc3, float wd1, float* __restrict__ loss, float* __restrict__ gC,
-                                                float* __restrict__ gD) {
+                                                int64_t P4, float wc3, float wd1, float* __restrict__ loss,
+                                                float* __restrict__ gC, float* __restrict__ gD,
+                                                uint32_t* __restrict__ red) {
   float acc = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P4; i += stride) {
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      const float* X = ch < 3 ? C + ch * P : D;
+      const float* Y = ch < 3 ? Ct + ch * P : Dt;
+      float* G = ch < 3 ? gC + ch * P : gD;
+      const float w = ch < 3 ? wc3 : wd1;
+      const float4 x = ld4(X, i), y = ld4(Y, i);
+      float4 g;
+      acc += l1_term(x.x - y.x, w, &g.x) + l1_term(x.y - y.y, w, &g.y) + l1_term(x.z - y.z, w, &g.z) +
+             l1_term(x.w - y.w, w, &g.w);
+      st4(G, i, g);
+    }
+  }
+  for (int64_t i = 4 * P4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += stride) {
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       const float r = C[ch * P + i] - Ct[ch * P + i];
@@ -33,7 +110,7 @@ __global__ __launch_bounds__(256) void k_loss_l1(const float* __restrict__ C, co
     acc += fabsf(rd) * wd1;
     gD[i] = sgnf(rd) * wd1;
   }
-  block_add(acc, loss);
+  grid_sum(acc, loss, red);
 }
 
 // ---- exact lower median of e = |D - D*| over pixels with D* > 0 ----------
@@ -90,7 +167,8 @@ __global__ __launch_bounds__(256) void k_loss_track(const float* __restrict__ C,
                                                    const float* __restrict__ Dt, int64_t P, float lambda_c,
                                                    float inlier_mult, const uint32_t* __restrict__ st,
                                                    float* __restrict__ loss, float* __restrict__ gC,
-                                                   float* __restrict__ gD, float* __restrict__ median) {
+                                                   float* __restrict__ gD, float* __restrict__ median,
+                                                   uint32_t* __restrict__ red) {
   const bool any = st[kSelCount] > 0;
   const float med = any ? __uint_as_float(st[kSelPrefix]) : 0.f;
   if (median && blockIdx.x == 0 && threadIdx.x == 0) *median = med;
@@ -113,7 +191,7 @@ __global__ __launch_bounds__(256) void k_loss_track(const float* __restrict__ C,
     gD[i] = w * ld * sgnf(rd);
     acc += w * (lc * l + ld * fabsf(rd));
   }
-  block_add(acc, loss);
+  grid_sum(acc, loss, red);
 }
 
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
@@ -129,20 +207,47 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
   }
 }
 
+__device__ __forceinline__ float adam_one(float& p, float& m, float& v, float g, float lr, float b1, float b2,
+                                          float eps, float bc1, float bc2) {
+  m = b1 * m + (1.f - b1) * g;
+  v = b2 * v + (1.f - b2) * g * g;
+  p -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+  return p;
+}
+
 // Adam over up to kAdamGroups parameter tensors in one launch (each with its
-// own step size); the flat index space is the concatenation of the groups.
+// own step size): grid row y = group, float4 loads where the group's four
+// arrays are 16-byte aligned, then a scalar tail.
 __global__ __launch_bounds__(256) void k_adam_multi(AdamGroups a, float b1, float b2, float eps, float bc1, float bc2) {
-  const int64_t total = a.off[a.n];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    int gi = 0;
-    while (gi + 1 < a.n && i >= a.off[gi + 1]) ++gi;
-    const int64_t j = i - a.off[gi];
-    const float g = a.g[gi][j];
-    const float mi = b1 * a.m[gi][j] + (1.f - b1) * g;
-    const float vi = b2 * a.v[gi][j] + (1.f - b2) * g * g;
-    a.m[gi][j] = mi;
-    a.v[gi][j] = vi;
-    a.p[gi][j] -= a.lr[gi] * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  const int gi = blockIdx.y;
+  const int64_t n = a.off[gi + 1] - a.off[gi];
+  float* __restrict__ P = a.p[gi];
+  float* __restrict__ M = a.m[gi];
+  float* __restrict__ V = a.v[gi];
+  const float* __restrict__ G = a.g[gi];
+  const float lr = a.lr[gi];
+  const bool vec = ((reinterpret_cast<uintptr_t>(P) | reinterpret_cast<uintptr_t>(M) | reinterpret_cast<uintptr_t>(V) |
+                     reinterpret_cast<uintptr_t>(G)) & 15u) == 0;
+  const int64_t n4 = vec ? n / 4 : 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+    float4 p = reinterpret_cast<float4*>(P)[i], m = reinterpret_cast<float4*>(M)[i];
+    float4 v = reinterpret_cast<float4*>(V)[i];
+    const float4 g = reinterpret_cast<const float4*>(G)[i];
+    adam_one(p.x, m.x, v.x, g.x, lr, b1, b2, eps, bc1, bc2);
+    adam_one(p.y, m.y, v.y, g.y, lr, b1, b2, eps, bc1, bc2);
+    adam_one(p.z, m.z, v.z, g.z, lr, b1, b2, eps, bc1, bc2);
+    adam_one(p.w, m.w, v.w, g.w, lr, b1, b2, eps, bc1, bc2);
+    reinterpret_cast<float4*>(P)[i] = p;
+    reinterpret_cast<float4*>(M)[i] = m;
+    reinterpret_cast<float4*>(V)[i] = v;
+  }
+  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    float p = P[i], m = M[i], v = V[i];
+    adam_one(p, m, v, G[i], lr, b1, b2, eps, bc1, bc2);
+    P[i] = p;
+    M[i] = m;
+    V[i] = v;
   }
 }
 
@@ -209,6 +314,8 @@ __global__ void k_pose_apply_twist(const float* __restrict__ pose, const float* 
   for (int i = 0; i < 3; ++i) out[4 + i] = R[3 * i] * pose[4] + R[3 * i + 1] * pose[5] + R[3 * i + 2] * pose[6] + xi[i];
 }
 
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 unsigned grid_for(int64_t n, int64_t cap) {
   int64_t b = (n + 255) / 256;
   if (b > cap) b = cap;
@@ -218,21 +325,30 @@ unsigned grid_for(int64_t n, int64_t cap) {
 
 }  // namespace
 
+int64_t reduce_temp_words() { return kRedWords; }
+
 void launch_loss_l1(const float* C, const float* D, const float* Ct, const float* Dt, int64_t P, float wc, float wd,
-                    float* loss, float* gC, float* gD, hipStream_t s) {
-  launch_fill_f32(loss, 0.f, 1, s);
-  if (P <= 0) return;
-  // a few hundred workgroups: each ends with one atomic on the same address
-  hipLaunchKernelGGL(k_loss_l1, dim3(grid_for(P, 512)), dim3(256), 0, s, C, D, Ct, Dt, P, wc / (3.f * (float)P),
-                     wd / (float)P, loss, gC, gD);
+                    float* loss, float* gC, float* gD, uint32_t* red, hipStream_t s) {
+  if (P <= 0) {
+    launch_fill_f32(loss, 0.f, 1, s);
+    return;
+  }
+  const bool vec = P % 4 == 0 && aligned16(C) && aligned16(D) && aligned16(Ct) && aligned16(Dt) && aligned16(gC) &&
+                   aligned16(gD);
+  const int64_t P4 = vec ? P / 4 : 0;
+  hipLaunchKernelGGL(k_loss_l1, dim3(grid_for(vec ? P4 : P, kRedSlots)), dim3(256), 0, s, C, D, Ct, Dt, P, P4,
+                     wc / (3.f * (float)P), wd / (float)P, loss, gC, gD, red);
 }
 
-int64_t track_temp_words() { return kSelWords; }
+int64_t track_temp_words() { return kSelWords + kRedWords; }
 
 void launch_loss_track(const float* C, const float* D, const float* A, const float* Ct, const float* Dt, int64_t P,
                        float lambda_c, float inlier_mult, float* loss, float* gC, float* gD, float* median,
                        uint32_t* temp, hipStream_t s) {
-  launch_fill_f32(loss, 0.f, 1, s);
+  if (P <= 0) {
+    launch_fill_f32(loss, 0.f, 1, s);
+    return;
+  }
   hipLaunchKernelGGL(k_select_init, dim3(1), dim3(256), 0, s, temp);
   const unsigned g = grid_for(P, 512);
   for (int pass = 0; pass < 4; ++pass) {
@@ -241,7 +357,7 @@ void launch_loss_track(const float* C, const float* D, const float* A, const flo
     hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(64), 0, s, temp, shift, pass == 0 ? 1 : 0);
   }
   hipLaunchKernelGGL(k_loss_track, dim3(grid_for(P, 512)), dim3(256), 0, s, C, D, A, Ct, Dt, P, lambda_c,
-                     inlier_mult, (const uint32_t*)temp, loss, gC, gD, median);
+                     inlier_mult, (const uint32_t*)temp, loss, gC, gD, median, temp + kSelWords);
 }
 
 void launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
@@ -259,7 +375,10 @@ void launch_pose_adam(float* pose, float* state, const float* g, float lr_q, flo
 }
 void launch_adam_multi(const AdamGroups& a, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s) {
   if (a.n <= 0 || a.off[a.n] <= 0) return;
-  hipLaunchKernelGGL(k_adam_multi, dim3(grid_for(a.off[a.n], 4096)), dim3(256), 0, s, a, b1, b2, eps, bc1, bc2);
+  int64_t most = 0;
+  for (int i = 0; i < a.n; ++i) most = std::max<int64_t>(most, a.off[i + 1] - a.off[i]);
+  hipLaunchKernelGGL(k_adam_multi, dim3(grid_for((most + 3) / 4, 2048), (unsigned)a.n), dim3(256), 0, s, a, b1, b2,
+                     eps, bc1, bc2);
 }
 void launch_pose_const_velocity(const float* p0, const float* p1, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_pose_const_velocity, dim3(1), dim3(64), 0, s, p0, p1, out);
