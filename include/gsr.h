@@ -98,9 +98,11 @@ void gsr_default_opts(gsr_opts *out);
 /* Forward render (Eq. 1-4, 6) ------------------------------------------ */
 
 /* Render colour (+ background), depth (sum z alpha T, background depth 0) and
- * accumulated alpha 1 - T_final. Projection, tile binning, (tile, depth)
- * radix sort and compositing all run on the device. The call synchronises
- * once, after the tile-overlap count is known, to size its buffers.
+ * accumulated alpha 1 - T_final. Projection, tile binning, the per-tile depth
+ * sort and compositing all run on the device. The call waits once for the
+ * tile-overlap count K (to size its buffers); when the state's tile-list
+ * workspace from an earlier call is large enough, the rest of the forward is
+ * already queued by then, so the device does not wait for the host.
  * *state receives a handle the backward needs; release it with
  * gsr_state_release (it owns the sorted tile lists and per-pixel state). */
 int gsr_render_fwd(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cam, const gsr_opts *opts,

@@ -96,6 +96,7 @@ struct gsr_ctx {
   std::string err;
   std::vector<gsr_state*> pool;
   uint32_t* h_K = nullptr;  // pinned host word for the overlap count
+  hipEvent_t k_ev = nullptr;  // recorded after the copy of the overlap count
   uint32_t* red = nullptr;  // grid-reduction scratch of the L1 loss
   uint32_t* track_temp = nullptr;
   unsigned long long* d_stats = nullptr;
@@ -440,6 +441,11 @@ int gsr_ctx_create(gsr_ctx** out, int device, void* hip_stream) {
     delete c;
     return GSR_ENOMEM;
   }
+  if (hipEventCreateWithFlags(&c->k_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    gsr_ctx_destroy(c);
+    return GSR_EHIP;
+  }
   gsr::launch_fill_u32(c->track_temp, 0u, gsr::track_temp_words(), c->stream);
   gsr::launch_fill_u32(c->red, 0u, gsr::reduce_temp_words(), c->stream);
   if (hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -464,6 +470,7 @@ int gsr_ctx_destroy(gsr_ctx* c) {
   if (c->track_temp) (void)hipFree(c->track_temp);
   if (c->red) (void)hipFree(c->red);
   if (c->d_stats) (void)hipFree(c->d_stats);
+  if (c->k_ev) (void)hipEventDestroy(c->k_ev);
   for (auto& r : c->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -516,15 +523,25 @@ int gsr_render_fwd_batch(gsr_ctx* c, const gsr_gaussians* g, int32_t n_views, co
   hipStream_t st = c->stream;
   enqueue_front(c, s, st);
   GSR_HIP(c, hipMemcpyAsync(c->h_K, s->d_K, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  GSR_HIP(c, hipStreamSynchronize(st));
+  GSR_HIP(c, hipEventRecord(c->k_ev, st));
+  // With a tile-list workspace from an earlier forward, the second half is
+  // queued before the overlap count is known (positions beyond the capacity
+  // would be dropped), so the device does not wait for the host; it is redone
+  // in the rare case that the count exceeds the capacity.
+  const bool speculative = s->arenaB != nullptr && s->K_cap > 0;
+  if (speculative) enqueue_back(c, s, st, s->K_cap, color, depth, alpha);
+  GSR_HIP(c, hipEventSynchronize(c->k_ev));
   const int64_t K = (int64_t)*c->h_K;
   s->K = K;
-  rc = ensure_B(c, s, K);
-  if (rc) {
-    s->in_use = false;
-    return rc;
+  if (!speculative || K > s->K_cap) {
+    if (speculative) GSR_HIP(c, hipStreamSynchronize(st));  // before the workspace is replaced
+    rc = ensure_B(c, s, K);
+    if (rc) {
+      s->in_use = false;
+      return rc;
+    }
+    enqueue_back(c, s, st, K, color, depth, alpha);
   }
-  enqueue_back(c, s, st, K, color, depth, alpha);
   rc = check_launch(c, "gsr_render_fwd kernels");
   if (rc) {
     s->in_use = false;

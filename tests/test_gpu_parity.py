@@ -212,6 +212,27 @@ def test_tile_ranges_longer_than_lds_are_merged():
     G.compare_images(out, oracle.render(g, pose, cam, opts), TOL, max_unverifiable=0.06)
 
 
+def test_workspace_growth_between_calls():
+    """A forward whose overlap count exceeds the tile-list workspace left by the
+    previous forward on the same (reused) state: the speculatively queued
+    second half is redone with a larger workspace, and the lists and image
+    still match the oracle."""
+    g, _, pose, cam = G.c1_case(0, n=200)
+    out, st, _, _ = run_fwd(g, pose, cam)
+    k_small = gsr.tile_lists(st, 12)[0]
+    st.release()
+    g2, _, _, _ = G.c1_case(1, n=3000)
+    g2["scales"] = (g2["scales"] * 3.0).astype(np.float32)
+    g2 = G.certify(g2, pose, cam, 1e-4)
+    out2, st2, _, _ = run_fwd(g2, pose, cam)
+    tl = oracle.tile_lists(g2, pose, cam, oracle.Opts())
+    assert tl["K"] > 2 * k_small
+    K, ranges, ids = gsr.tile_lists(st2, tl["ranges"].shape[0])
+    assert K == tl["K"]
+    G.compare_tile_lists(ranges.cpu().numpy(), ids.cpu().numpy(), tl, None)
+    G.compare_images(out2, oracle.render(g2, pose, cam, C1_OPTS), TOL, max_unverifiable=0.02)
+
+
 def test_loss_kernels_match_oracle():
     torch = torch_()
     g, tg, pose, cam = G.c1_case(0)
