@@ -352,8 +352,9 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
     gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n * s->n_views, st);
     if (want_pose) gsr::launch_fill_f32(s->pose_acc, 0.f, 12 * s->n_views, st);
   }
+  const bool geom_only = !grads || (!grads->opacities && !grads->colors);
   gsr::BwdArgs ba{s->ranges, s->ids, s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
-                  gC, gD, gA, s->g2d, n_items, s->queue, s->blocks > 0 ? s->order : nullptr, s->blocks};
+                  gC, gD, gA, s->g2d, geom_only, n_items, s->queue, s->blocks > 0 ? s->order : nullptr, s->blocks};
   {
     Stage t(c, "render_bwd");
     gsr::launch_render_bwd(R, ba, st);

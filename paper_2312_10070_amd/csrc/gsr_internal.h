@@ -131,6 +131,29 @@ __device__ __forceinline__ void wave_add10(const float v[10], float* __restrict_
   if ((lane & 3) == 0 && f < 10) atomicAdd(dst + f, r4);
 }
 
+// The same for the six fields the mean, scale, rotation and camera-pose
+// gradients need (v[0..4] and v[9]; opacity and colour are not reduced): three exchange steps, then the
+// 8-lane sum. Lane L with (L & 7) == 0 ends with field 2 b4 + b5 (b3 = 0) or,
+// for b3 = 1 and b4 = 0, field 4 + b5 (v[4] or v[9]).
+__device__ __forceinline__ void wave_add6(const float v[10], float* __restrict__ dst, int lane) {
+  const float r10 = perm_add32(v[0], v[1]);
+  const float r11 = perm_add32(v[2], v[3]);
+  const float r12 = perm_add32(v[4], v[9]);
+  const float r20 = perm_add16(r10, r11);
+  const float r21 = perm_add16(r12, 0.f);
+  const bool b3 = (lane >> 3) & 1;
+  const float a0 = b3 ? r21 : r20, c0 = b3 ? r20 : r21;
+  float r = a0 + dpp_f<0x140>(c0);  // row_mirror
+  r += dpp_f<0x141>(r);             // row_half_mirror
+  r += dpp_f<0xb1>(r);              // quad_perm [1,0,3,2]
+  r += dpp_f<0x4e>(r);              // quad_perm [2,3,0,1]
+  const int b4 = (lane >> 4) & 1, b5 = (lane >> 5) & 1;
+  if ((lane & 7) == 0) {
+    if (!b3) atomicAdd(dst + 2 * b4 + b5, r);
+    else if (!b4) atomicAdd(dst + (b5 ? 9 : 4), r);
+  }
+}
+
 __device__ __forceinline__ int wave_max_int(int v) {
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
@@ -244,6 +267,7 @@ struct BwdArgs {
   const int* last;
   const float *gC, *gD, *gA;
   float* g2d;  // [V*n, 10]: sums of q (dx, dy, dx^2, dx dy, dy^2), q = dL/dp / ln 2; o, r, g, b, z
+  bool geom_only;  // only fields 0-4 and 9 are needed (no opacity or colour gradient wanted)
   int n_items;
   int* queue;
   const int* order;

@@ -114,52 +114,90 @@ __global__ __launch_bounds__(256) void k_loss_l1(const float* __restrict__ C, co
 }
 
 // ---- exact lower median of e = |D - D*| over pixels with D* > 0 ----------
-// State (uint32 words): [0..255] histogram, [256] prefix, [257] prefix mask,
-// [258] remaining rank, [259] number of valid pixels.
-constexpr int kSelHist = 0, kSelPrefix = 256, kSelMask = 257, kSelRank = 258, kSelCount = 259;
-constexpr int kSelWords = 260;
+// Radix select on the float bits of e (non-negative, so the bits order like
+// the values), 8 bits per pass from the top. Pass p builds the 256-bin
+// histogram hist[p] of the digit at bits [24 - 8p, 32 - 8p) among the pixels
+// whose higher digits equal the prefix chosen so far; every workgroup of pass
+// p (and of the loss kernel) re-derives that prefix from hist[0..p-1] with a
+// wave scan, so no separate single-workgroup "pick" launches are needed.
+constexpr int kSelPasses = 4;
+constexpr int kSelWords = kSelPasses * 256;
+
+struct SelState {
+  uint32_t prefix, mask, rank, count;
+};
+
+// Digit of the pass whose histogram is h holding rank k (lower median rule):
+// lane L covers bins 4L..4L+3. Returns the digit and the rank inside it.
+__device__ __forceinline__ void pick_digit(const uint32_t* __restrict__ h, uint32_t k, uint32_t& digit,
+                                           uint32_t& k_in, uint32_t& total) {
+  const int lane = threadIdx.x & 63;
+  const uint4 c = reinterpret_cast<const uint4*>(h)[lane];
+  const uint32_t s = c.x + c.y + c.z + c.w;
+  uint32_t incl = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  total = __shfl(incl, 63, 64);
+  const uint32_t excl = incl - s;
+  const uint64_t m = __ballot(k >= excl && k < incl);
+  if (m == 0) {  // no valid pixel: the median is unused
+    digit = 255;
+    k_in = 0;
+    return;
+  }
+  const int L = __builtin_ctzll(m);
+  uint32_t kk = k - __shfl(excl, L, 64);
+  const uint32_t c0 = __shfl(c.x, L, 64), c1 = __shfl(c.y, L, 64), c2 = __shfl(c.z, L, 64);
+  uint32_t d = 4 * L;
+  if (kk >= c0) { kk -= c0; ++d;
+    if (kk >= c1) { kk -= c1; ++d;
+      if (kk >= c2) { kk -= c2; ++d; } } }
+  digit = d;
+  k_in = kk;
+}
+
+// State after the picks of passes 0..passes-1 (wave-uniform; every wave computes it).
+__device__ __forceinline__ SelState select_state(const uint32_t* __restrict__ st, int passes) {
+  SelState r{0u, 0u, 0u, 0u};
+  for (int p = 0; p < passes; ++p) {
+    uint32_t d, kin, total;
+    pick_digit(st + 256 * p, r.rank, d, kin, total);
+    if (p == 0) {
+      r.count = total;
+      // rank of the lower median among `total` values
+      const uint32_t k0 = total > 0 ? (total - 1) / 2 : 0;
+      pick_digit(st, k0, d, kin, total);
+    }
+    const int shift = 24 - 8 * p;
+    r.prefix |= d << shift;
+    r.mask |= 0xffu << shift;
+    r.rank = kin;
+  }
+  return r;
+}
 
 __global__ void k_select_init(uint32_t* st) {
   for (int i = threadIdx.x; i < kSelWords; i += blockDim.x) st[i] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_select_hist(const float* __restrict__ D, const float* __restrict__ Dt, int64_t P,
-                                                    int shift, uint32_t* __restrict__ st) {
+                                                    int pass, uint32_t* __restrict__ st) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
+  const SelState sel = select_state(st, pass);
+  const int shift = 24 - 8 * pass;
   __syncthreads();
-  const uint32_t prefix = st[kSelPrefix], mask = st[kSelMask];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
     if (Dt[i] > 0.f) {
       const uint32_t b = __float_as_uint(fabsf(D[i] - Dt[i]));
-      if ((b & mask) == prefix) atomicAdd(&h[(b >> shift) & 0xffu], 1u);
+      if ((b & sel.mask) == sel.prefix) atomicAdd(&h[(b >> shift) & 0xffu], 1u);
     }
   }
   __syncthreads();
-  if (h[threadIdx.x]) atomicAdd(&st[kSelHist + threadIdx.x], h[threadIdx.x]);
-}
-
-// One thread: pick the digit holding the target rank, narrow the prefix.
-__global__ void k_select_pick(uint32_t* st, int shift, int first) {
-  if (threadIdx.x != 0) return;
-  if (first) {
-    uint32_t n = 0;
-    for (int d = 0; d < 256; ++d) n += st[kSelHist + d];
-    st[kSelCount] = n;
-    st[kSelRank] = n > 0 ? (n - 1) / 2 : 0;
-  }
-  uint32_t k = st[kSelRank], c = 0;
-  int d = 0;
-  for (; d < 256; ++d) {
-    const uint32_t h = st[kSelHist + d];
-    if (k < c + h) break;
-    c += h;
-  }
-  if (d == 256) d = 255;  // no valid pixel: the median is unused
-  st[kSelRank] = k - c;
-  st[kSelPrefix] |= (uint32_t)d << shift;
-  st[kSelMask] |= 0xffu << shift;
-  for (int i = 0; i < 256; ++i) st[kSelHist + i] = 0;
+  if (h[threadIdx.x]) atomicAdd(&st[256 * pass + threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void k_loss_track(const float* __restrict__ C, const float* __restrict__ D,
@@ -169,8 +207,9 @@ __global__ __launch_bounds__(256) void k_loss_track(const float* __restrict__ C,
                                                    float* __restrict__ loss, float* __restrict__ gC,
                                                    float* __restrict__ gD, float* __restrict__ median,
                                                    uint32_t* __restrict__ red) {
-  const bool any = st[kSelCount] > 0;
-  const float med = any ? __uint_as_float(st[kSelPrefix]) : 0.f;
+  const SelState sel = select_state(st, kSelPasses);
+  const bool any = sel.count > 0;
+  const float med = any ? __uint_as_float(sel.prefix) : 0.f;
   if (median && blockIdx.x == 0 && threadIdx.x == 0) *median = med;
   const float thr = inlier_mult * med;
   const float lc = lambda_c, ld = 1.f - lambda_c;
@@ -350,12 +389,9 @@ void launch_loss_track(const float* C, const float* D, const float* A, const flo
     return;
   }
   hipLaunchKernelGGL(k_select_init, dim3(1), dim3(256), 0, s, temp);
-  const unsigned g = grid_for(P, 512);
-  for (int pass = 0; pass < 4; ++pass) {
-    const int shift = 24 - 8 * pass;
-    hipLaunchKernelGGL(k_select_hist, dim3(g), dim3(256), 0, s, D, Dt, P, shift, temp);
-    hipLaunchKernelGGL(k_select_pick, dim3(1), dim3(64), 0, s, temp, shift, pass == 0 ? 1 : 0);
-  }
+  const unsigned g = grid_for(P, 256);
+  for (int pass = 0; pass < kSelPasses; ++pass)
+    hipLaunchKernelGGL(k_select_hist, dim3(g), dim3(256), 0, s, D, Dt, P, pass, temp);
   hipLaunchKernelGGL(k_loss_track, dim3(grid_for(P, 512)), dim3(256), 0, s, C, D, A, Ct, Dt, P, lambda_c,
                      inlier_mult, (const uint32_t*)temp, loss, gC, gD, median, temp + kSelWords);
 }

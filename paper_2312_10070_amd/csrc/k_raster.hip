@@ -187,6 +187,7 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
   }
 }
 
+template <bool GEOM_ONLY>
 __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int item, BwdSmem& sm) {
   const int tid = threadIdx.x, lane = tid & 63;
   const Pixel q = item_pixel(Rr, item);
@@ -280,7 +281,11 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
         v[2] = gpx * dx;
         v[3] = gpx * dy;
         v[4] = gpy * dy;
-        wave_add10(v, a.g2d + 10 * (int64_t)sm.gid[li], lane);
+        if (GEOM_ONLY) {
+          wave_add6(v, a.g2d + 10 * (int64_t)sm.gid[li], lane);
+        } else {
+          wave_add10(v, a.g2d + 10 * (int64_t)sm.gid[li], lane);
+        }
       }
     }
   }
@@ -292,9 +297,10 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs 
   fwd_item<STATS>(Rr, a, xcd_tile(blockIdx.x, gridDim.x), sm);
 }
 
+template <bool GEOM_ONLY>
 __global__ __launch_bounds__(kTileThreads) void k_render_bwd(Raster Rr, BwdArgs a) {
   __shared__ BwdSmem sm;
-  bwd_item(Rr, a, xcd_tile(blockIdx.x, gridDim.x), sm);
+  bwd_item<GEOM_ONLY>(Rr, a, xcd_tile(blockIdx.x, gridDim.x), sm);
 }
 
 // Persistent workgroups: take the next item from the queue until it is empty.
@@ -318,13 +324,14 @@ __global__ __launch_bounds__(kTileThreads) void k_render_fwd_persistent(Raster R
   }
 }
 
+template <bool GEOM_ONLY>
 __global__ __launch_bounds__(kTileThreads) void k_render_bwd_persistent(Raster Rr, BwdArgs a) {
   __shared__ BwdSmem sm;
   __shared__ int s_item;
   for (;;) {
     const int item = next_item(a.queue, a.order, a.n_items, &s_item);
     if (item < 0) break;
-    bwd_item(Rr, a, item, sm);
+    bwd_item<GEOM_ONLY>(Rr, a, item, sm);
   }
 }
 
@@ -396,9 +403,14 @@ void launch_render_fwd(const Raster& R, const FwdArgs& a, hipStream_t s) {
 void launch_render_bwd(const Raster& R, const BwdArgs& a, hipStream_t s) {
   if (a.blocks > 0) {
     launch_fill_u32(reinterpret_cast<uint32_t*>(a.queue), 0u, 1, s);
-    hipLaunchKernelGGL(k_render_bwd_persistent, dim3((unsigned)a.blocks), dim3(kTileThreads), 0, s, R, a);
+    if (a.geom_only)
+      hipLaunchKernelGGL(k_render_bwd_persistent<true>, dim3((unsigned)a.blocks), dim3(kTileThreads), 0, s, R, a);
+    else
+      hipLaunchKernelGGL(k_render_bwd_persistent<false>, dim3((unsigned)a.blocks), dim3(kTileThreads), 0, s, R, a);
+  } else if (a.geom_only) {
+    hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)a.n_items), dim3(kTileThreads), 0, s, R, a);
   } else {
-    hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)a.n_items), dim3(kTileThreads), 0, s, R, a);
+    hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)a.n_items), dim3(kTileThreads), 0, s, R, a);
   }
 }
 

@@ -130,6 +130,12 @@ def test_posed_ragged_forward_backward_and_tiles():
     G.grads_check(got, ref)
     H.check_grad("pose7", got["pose7"], ref["grads"]["pose7"], ref["aref"]["pose7"], ref["slack"]["pose7"])
     H.check_grad("twist6", got["twist6"], ref["grads"]["twist6"], ref["aref"]["twist6"], ref["slack"]["twist6"])
+    # pose only: the six-field reduction (no opacity / colour fields)
+    out_p = gsr.render_bwd(st, torch.from_numpy(gC).cuda(), torch.from_numpy(gD).cuda(), want_params=False)
+    torch.cuda.synchronize()
+    for k in ("pose7", "twist6"):
+        gp = out_p[k].cpu().numpy().astype(np.float64)
+        H.check_grad(k, gp, ref["grads"][k], ref["aref"][k], ref["slack"][k])
 
 
 def test_empty_and_fully_culled_inputs_render_background():
