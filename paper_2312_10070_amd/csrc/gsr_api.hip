@@ -39,7 +39,7 @@ struct gsr_state {
   int2* ranges = nullptr;
   uint32_t* d_K = nullptr;
   int* d_overflow = nullptr;
-  float* pose_acc = nullptr;  // [views, 12]
+  float* pose_acc = nullptr;  // [views][projection-backward workgroups][12]
   int* queue = nullptr;       // persistent-launch work counter
   int* order = nullptr;       // [views * tiles] longest-list-first item order
   int* order_temp = nullptr;  // 64 ints
@@ -165,7 +165,8 @@ void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, int6
   s->ranges = c.take<int2>(tiles);
   s->d_K = c.take<uint32_t>(4);
   s->d_overflow = c.take<int>(4);
-  s->pose_acc = c.take<float>(12 * views + 4);
+  // sum over views of ceil(n_view / 256) <= ceil(n / 256) + views workgroups
+  s->pose_acc = c.take<float>(12 * (gsr::project_bwd_blocks(n) + views + 1));
   s->queue = c.take<int>(4);
   s->order = c.take<int>(tiles);
   s->order_temp = c.take<int>(64);
@@ -350,7 +351,6 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
   {
     Stage t(c, "fill");
     gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n * s->n_views, st);
-    if (want_pose) gsr::launch_fill_f32(s->pose_acc, 0.f, 12 * s->n_views, st);
   }
   const bool geom_only = !grads || (!grads->opacities && !grads->colors);
   gsr::BwdArgs ba{s->ranges, s->ids, s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
@@ -367,7 +367,9 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
   {
     Stage t(c, "project_bwd");
     gsr::launch_project_bwd(R, pb, st);
-    if (want_pose) gsr::launch_pose_finalize(s->pose7, s->pose_acc, dpose7, dtwist6, s->n_views, st);
+    if (want_pose)
+      gsr::launch_pose_finalize(s->pose7, s->pose_acc, gsr::project_bwd_blocks(s->n), dpose7, dtwist6, s->n_views,
+                                st);
   }
 }
 

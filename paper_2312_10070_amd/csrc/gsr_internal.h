@@ -282,12 +282,15 @@ struct ProjectBwdArgs {
   const uint32_t* counts;
   const float* g2d;
   float *g_means, *g_scales, *g_quats, *g_opacities, *g_colors;  // may be NULL; summed over views
-  float* pose_acc;  // [n_views, 12]: dL/dR_p (9, row-major), dL/dt (3); NULL = skip
+  float* pose_acc;  // [n_views][blocks][12] per-workgroup dL/dR_p (9, row-major), dL/dt (3); NULL = skip
   int n_views;
 };
+// workgroups of the projection backward (one per 256 Gaussians)
+int64_t project_bwd_blocks(int64_t n);
 void launch_project_bwd(const Raster& R, const ProjectBwdArgs& a, hipStream_t s);
-void launch_pose_finalize(const float* pose7, const float* pose_acc, float* dL_dpose7, float* dL_dtwist6,
-                          int n_views, hipStream_t s);
+// Sums the per-workgroup pose partials in a fixed order and converts them.
+void launch_pose_finalize(const float* pose7, const float* pose_acc, int64_t blocks, float* dL_dpose7,
+                          float* dL_dtwist6, int n_views, hipStream_t s);
 // Longest-list-first order of (view, tile) items for the persistent launches
 // (power-of-two length buckets). temp: 64 ints.
 void launch_item_order(const int2* ranges, int n_items, int* order, int* temp, hipStream_t s);

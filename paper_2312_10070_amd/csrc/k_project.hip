@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a
         const int nw = (blockDim.x + 63) >> 6;
         float s = 0.f;
         for (int i = 0; i < nw; ++i) s += red[i][threadIdx.x];
-        atomicAdd(&a.pose_acc[12 * v + threadIdx.x], s);
+        a.pose_acc[((int64_t)v * gridDim.x + blockIdx.x) * 12 + threadIdx.x] = s;
       }
       __syncthreads();
     }
@@ -351,12 +351,32 @@ __global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a
 // From dL/dR_p and dL/dt to the quaternion/translation gradient and the twist
 // of the left perturbation (R <- Exp(phi) R, t <- Exp(phi) t + rho):
 //   dL/drho = dL/dt,   dL/dphi = sum_j R[:, j] x G[:, j] + t x dL/dt.
-__global__ void k_pose_finalize(const float* __restrict__ poses7, const float* __restrict__ accs,
-                                float* __restrict__ dposes7, float* __restrict__ dtwists6, int n_views) {
-  const int v = threadIdx.x;
-  if (v >= n_views || blockIdx.x != 0) return;
+// One workgroup per view: the 12 pose partials summed over the projection
+// backward's workgroups (fixed order), then dL/d(q, t) and the twist.
+__global__ __launch_bounds__(256) void k_pose_finalize(const float* __restrict__ poses7,
+                                                      const float* __restrict__ parts, int64_t blocks,
+                                                      float* __restrict__ dposes7, float* __restrict__ dtwists6) {
+  const int v = blockIdx.x;
+  __shared__ float red[4][12];
+  __shared__ float acc[12];
+  float s[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) s[i] = 0.f;
+  const float* part = parts + (int64_t)v * blocks * 12;
+  for (int64_t b = threadIdx.x; b < blocks; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) s[i] += part[b * 12 + i];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const float t = wave_sum_all(s[i]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][i] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 12) acc[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                                           red[3][threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   const float* pose7 = poses7 + 7 * v;
-  const float* acc = accs + 12 * v;
   float* dpose7 = dposes7 ? dposes7 + 7 * v : nullptr;
   float* dtwist6 = dtwists6 ? dtwists6 + 6 * v : nullptr;
   const PoseF P = load_pose(pose7);
@@ -393,16 +413,18 @@ void launch_project(const Raster& R, const ProjectArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_project, dim3((unsigned)blocks, (unsigned)a.n_views), dim3(256), 0, s, R, a);
 }
 
+int64_t project_bwd_blocks(int64_t n) { return (n + 255) / 256; }
+
 void launch_project_bwd(const Raster& R, const ProjectBwdArgs& a, hipStream_t s) {
   if (a.n <= 0) return;
-  const int64_t blocks = (a.n + 255) / 256;
-  hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, s, R, a);
+  hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)project_bwd_blocks(a.n)), dim3(256), 0, s, R, a);
 }
 
-void launch_pose_finalize(const float* pose7, const float* acc, float* dpose7, float* dtwist6, int n_views,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_pose_finalize, dim3(1), dim3(64 * ((n_views + 63) / 64)), 0, s, pose7, acc, dpose7, dtwist6,
-                     n_views);
+void launch_pose_finalize(const float* pose7, const float* parts, int64_t blocks, float* dpose7, float* dtwist6,
+                          int n_views, hipStream_t s) {
+  if (n_views <= 0) return;
+  hipLaunchKernelGGL(k_pose_finalize, dim3((unsigned)n_views), dim3(256), 0, s, pose7, parts, blocks, dpose7,
+                     dtwist6);
 }
 
 }  // namespace gsr
