@@ -71,6 +71,7 @@ def source_hash(names) -> str:
 
 
 STAGE_SOURCES = {"render_fwd": ["k_raster.hip", "gsr_internal.h"], "render_bwd": ["k_raster.hip", "gsr_internal.h"],
+                 "adam": ["k_loss.hip"], "loss_l1": ["k_loss.hip"],
                  "tile_bins": ["k_sort.hip"], "bin_count": ["k_sort.hip"], "project": ["k_project.hip", "gsr_internal.h"],
                  "project_bwd": ["k_project.hip", "gsr_internal.h"]}
 
@@ -92,6 +93,91 @@ def read_traffic(stage: str, workload: str):
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+# kernels of each stage, as rocprofv3 names them (prefix after the namespace)
+STAGE_KERNELS = {"render_bwd": ["k_render_bwd<false>("], "render_fwd": ["k_render_fwd<false>("],
+                 "tile_bins": ["k_tile_init(", "k_bin_place(", "k_tile_sort("],
+                 "bin_count": ["k_bin_count(", "k_scan_reduce(", "k_scan_partials(", "k_scan_down("],
+                 "project": ["k_project("], "project_bwd": ["k_project_bwd("]}
+PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {counter} -d <dir> -o run --output-format csv -- python3 bench.py "
+               "--steps 5 --warmup 2 --no-cpu-baseline --no-tracking --no-batched --no-initnet --calib-copy-mib {mib}")
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, calib_mib: int, workload: str = "H") -> None:
+    """Writes profiles/<stage>_<workload>_traffic.txt from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch). Each counter is scaled by
+    what it reads for the calibration copy of calib_mib MiB (a device-to-device
+    copy of known size, read once and written once)."""
+    import csv
+    import collections
+
+    def load(path, counter):
+        per = collections.defaultdict(list)
+        copies = []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].replace("gsr::(anonymous namespace)::", "").replace("void ", "")
+            v = float(r["Counter_Value"]) * 1024.0
+            per[name].append(v)
+            if "copyBuffer" in name:
+                copies.append(v)
+        return per, max(copies) if copies else None
+
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    fetch, f_copy = load(fetch_csv, "FETCH_SIZE")
+    write, w_copy = load(write_csv, "WRITE_SIZE")
+    nbytes = float(calib_mib << 20)
+    sf, sw = nbytes / f_copy, nbytes / w_copy
+    for stage, kernels in STAGE_KERNELS.items():
+        fb = wb = 0.0
+        found = True
+        for k in kernels:
+            fv = [v for name, vals in fetch.items() if name.startswith(k) for v in vals]
+            wv = [v for name, vals in write.items() if name.startswith(k) for v in vals]
+            if not fv or not wv:
+                found = False
+                break
+            fb += sf * sum(fv) / len(fv)
+            wb += sw * sum(wv) / len(wv)
+        if not found:
+            continue
+        path = os.path.join(ROOT, "profiles", f"{stage}_{workload}_traffic.txt")
+        with open(path, "w") as f:
+            f.write(f"# HBM traffic per launch of stage {stage} ({', '.join(k.rstrip('(') for k in kernels)}), "
+                    "mapping iteration 1200x680, 500K Gaussians\n")
+            f.write("# made by: " + PMC_COMMAND.format(counter="FETCH_SIZE", mib=calib_mib) + "\n")
+            f.write("#     and: " + PMC_COMMAND.format(counter="WRITE_SIZE", mib=calib_mib) + "\n")
+            f.write(f"#     then: python bench.py --summarize-pmc <fetch csv> <write csv> --calib-copy-mib {calib_mib}\n")
+            f.write(f"calibration: copy of {calib_mib} MiB read as FETCH {nbytes / sf / 1024:.0f} KiB, "
+                    f"WRITE {nbytes / sw / 1024:.0f} KiB; scale {sf:.4f} / {sw:.4f}\n")
+            f.write(f"source_sha1: {source_hash(STAGE_SOURCES[stage])}\n")
+            f.write(f"fetch_bytes_per_launch: {fb:.0f}\n")
+            f.write(f"write_bytes_per_launch: {wb:.0f}\n")
+            f.write(f"hbm_bytes_per_launch: {fb + wb:.0f}\n")
+        print("wrote", path, f"{(fb + wb) / 1e6:.1f} MB per launch")
+
+
+def summarize_trace(stats_csv: str, out_name: str, command: str, title: str) -> None:
+    """Writes profiles/<out_name>.txt from a rocprofv3 --kernel-trace --stats
+    kernel_stats.csv (durations in microseconds)."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    path = os.path.join(ROOT, "profiles", out_name + ".txt")
+    with open(path, "w") as f:
+        f.write(f"# rocprofv3 kernel statistics: {title}\n")
+        f.write(f"# command: {command}\n")
+        f.write("# durations in microseconds (kernel_stats.csv of the run)\n")
+        f.write("%-44s %7s %12s %10s %10s %10s %7s\n" % ("kernel", "calls", "total_us", "avg_us", "min_us",
+                                                         "max_us", "pct"))
+        for r in rows:
+            name = r["Name"].replace("gsr::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+            f.write("%-44s %7s %12.1f %10.2f %10.2f %10.2f %7.2f\n" % (
+                name[:44], r["Calls"], float(r["TotalDurationNs"]) / 1e3, float(r["AverageNs"]) / 1e3,
+                float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    print("wrote", path)
 
 
 def cpu_baseline(inp: dict, rows_every: int, threads: int) -> dict:
@@ -331,7 +417,17 @@ def main() -> int:
     ap.add_argument("--initnet-steps", type=int, default=8000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/*_traffic.txt from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("STATS_CSV", "NAME", "COMMAND", "TITLE"),
+                    help="write profiles/NAME.txt from a rocprofv3 kernel_stats.csv and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return 0
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.calib_copy_mib or 256)
+        return 0
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)

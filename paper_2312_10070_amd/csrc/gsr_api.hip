@@ -151,9 +151,9 @@ struct Carver {
 void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, int64_t views, int64_t nm,
              size_t* bytes) {
   Carver c{base};
-  s->rec_uvab = c.take<float4>(n);
-  s->rec_cob = c.take<float4>(n);
-  s->rec_rgbz = c.take<float4>(n);
+  s->rec_uvab = c.take<float4>(gsr::kRec * n);  // interleaved records (see gsr_internal.h)
+  s->rec_cob = s->rec_uvab ? s->rec_uvab + 1 : nullptr;
+  s->rec_rgbz = s->rec_uvab ? s->rec_uvab + 2 : nullptr;
   s->rect = c.take<int4>(n);
   s->counts = c.take<uint32_t>(n);
   s->bin_M = c.take<uint32_t>(nm);

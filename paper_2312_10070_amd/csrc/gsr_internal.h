@@ -13,6 +13,7 @@ namespace gsr {
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kTileThreads = 256;  // one pixel per lane, 4 waves per tile
 constexpr int kWave = 64;
+constexpr int kRec = 4;  // float4s per projected record
 
 
 // Launch constants of one render (by value into every kernel).
@@ -32,6 +33,10 @@ struct Raster {
 // Eq. 4 is stored pre-scaled so that one pair costs three FMAs:
 //   p = pa dx^2 + pb dx dy + pc dy^2 = -sigma * log2(e),   alpha = o * 2^p.
 //   rec_uvab = (u, v, pa, pb), rec_cob = (pc, o, bx, by), rec_rgbz = (r, g, b, z_cam)
+// The three float4s of a record are interleaved in one 64-byte slot (kRec
+// float4s, the fourth unused): a record gathered by its index touches one
+// cache line instead of three. rec_uvab[kRec i], rec_cob[kRec i], ... address
+// record i.
 // where bx / by carry the pixel support box as bit patterns px0 | px1 << 16 and
 // py0 | py1 << 16 (a wave skips records whose box misses its pixels).
 struct PairEval {

@@ -156,10 +156,10 @@ __global__ __launch_bounds__(256) void k_project(Raster Rr, ProjectArgs a) {
           rect = make_int4(px0 >> Rr.tw_log2, py0 / Rr.th, px1 >> Rr.tw_log2, py1 / Rr.th);
           count = (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1));
           const float s = -0.5f * kLog2e;
-          a.rec_uvab[o] = make_float4(g.u, g.v, s * ca, -kLog2e * cb);
-          a.rec_cob[o] = make_float4(s * cc, op, __uint_as_float((uint32_t)px0 | ((uint32_t)px1 << 16)),
+          a.rec_uvab[kRec * o] = make_float4(g.u, g.v, s * ca, -kLog2e * cb);
+          a.rec_cob[kRec * o] = make_float4(s * cc, op, __uint_as_float((uint32_t)px0 | ((uint32_t)px1 << 16)),
                                      __uint_as_float((uint32_t)py0 | ((uint32_t)py1 << 16)));
-          a.rec_rgbz[o] = make_float4(a.colors[3 * k], a.colors[3 * k + 1], a.colors[3 * k + 2], g.x[2]);
+          a.rec_rgbz[kRec * o] = make_float4(a.colors[3 * k], a.colors[3 * k + 1], a.colors[3 * k + 2], g.x[2]);
         }
       }
     }

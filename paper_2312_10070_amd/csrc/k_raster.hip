@@ -115,9 +115,9 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
     const int i = base + tid;
     if (i < end) {
       const uint32_t gid = a.ids[i];
-      sm.uvab[tid] = a.rec_uvab[gid];
-      sm.cob[tid] = a.rec_cob[gid];
-      sm.rgbz[tid] = a.rec_rgbz[gid];
+      sm.uvab[tid] = a.rec_uvab[kRec * gid];
+      sm.cob[tid] = a.rec_cob[kRec * gid];
+      sm.rgbz[tid] = a.rec_rgbz[kRec * gid];
     }
     __syncthreads();
     if (!__any(T > 0.f)) continue;
@@ -228,9 +228,9 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
     if (i < bend) {
       const uint32_t gid = a.ids[i];
       sm.gid[tid] = gid;
-      sm.uvab[tid] = a.rec_uvab[gid];
-      sm.cob[tid] = a.rec_cob[gid];
-      sm.rgbz[tid] = a.rec_rgbz[gid];
+      sm.uvab[tid] = a.rec_uvab[kRec * gid];
+      sm.cob[tid] = a.rec_cob[kRec * gid];
+      sm.rgbz[tid] = a.rec_rgbz[kRec * gid];
     }
     __syncthreads();
     const int cnt = min(bend, start + wmax) - bstart;  // records this wave may need
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kTileThreads) void k_count_bwd_pairs(Raster Rr, Fwd
   unsigned long long n = 0;
   for (int base = rg.x; base < rg.y; base += kTileThreads) {
     __syncthreads();
-    if (base + (int)threadIdx.x < rg.y) s_cob[threadIdx.x] = a.rec_cob[a.ids[base + threadIdx.x]];
+    if (base + (int)threadIdx.x < rg.y) s_cob[threadIdx.x] = a.rec_cob[kRec * a.ids[base + threadIdx.x]];
     __syncthreads();
     const int cnt = min(kTileThreads, rg.y - base);
     for (int j = 0; j < cnt; ++j)

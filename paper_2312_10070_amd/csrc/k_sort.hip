@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_bin_place(Raster Rr, BinArgs a) {
     const int64_t o = view * a.n + g;
     if (a.counts[o] == 0) continue;
     const int4 r = a.rect[o];
-    const uint64_t key = ((uint64_t)__float_as_uint(a.rec_rgbz[o].w) << 32) | (uint64_t)(uint32_t)o;
+    const uint64_t key = ((uint64_t)__float_as_uint(a.rec_rgbz[kRec * o].w) << 32) | (uint64_t)(uint32_t)o;
     for (int ty = r.y; ty <= r.w; ++ty)
       for (int tx = r.x; tx <= r.z; ++tx) {
         const int t = ty * Rr.ntx + tx - c.t0;
