@@ -258,6 +258,7 @@ int make_raster(gsr_ctx* c, const gsr_camera* cam, const gsr_opts* o, gsr::Raste
   r.near_z = cam->near_z;
   r.lowpass = o->lowpass;
   r.amin = o->alpha_min;
+  r.log2_amin = std::log2(o->alpha_min);
   r.amax = o->alpha_max;
   r.tmin = o->T_min;
   r.limx = o->guard * std::max(cam->cx, (float)cam->width - cam->cx) / cam->fx;

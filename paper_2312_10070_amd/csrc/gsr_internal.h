@@ -25,6 +25,7 @@ struct Raster {
   int n_tiles;        // ntx * nty (per view)
   float fx, fy, cx, cy, near_z;
   float lowpass, amin, amax, tmin;
+  float log2_amin;    // log2(amin)
   float limx, limy;   // guard band on x/z and y/z inside the Jacobian
   float bg0, bg1, bg2;
 };

@@ -76,6 +76,36 @@ __device__ __forceinline__ bool box_meets(float fbx, float fby, const Block& s) 
   return (x0 <= s.x1) & (x1 >= s.x0) & (y0 <= s.y1) & (y1 >= s.y0);  // no short-circuit branches
 }
 
+// Can the record reach alpha >= alpha_min anywhere in the block? alpha = o 2^p
+// with p = pa dx^2 + pb dx dy + pc dy^2 <= 0 (pa, pc < 0), so it needs
+// max over the block of p >= log2(alpha_min / o). If the centre lies in the
+// block the maximum is 0; otherwise it lies on the block edge(s) facing the
+// centre, where p restricted to the edge is a 1D concave quadratic whose
+// maximiser is clamped to the edge. The continuous block contains every pixel
+// centre, and the threshold carries a margin of 1e-3 (FP32 rounding of p is
+// ~1e-6), so a skipped record has alpha < alpha_min at every pixel: the
+// result cannot change, only the work.
+__device__ __forceinline__ bool ellipse_meets(const float4& g, const float4& cb, const Block& s, float log2_amin) {
+  const float u = g.x, v = g.y, pa = g.z, pb = g.w, pc = cb.x;
+  const float thr = log2_amin - __builtin_amdgcn_logf(cb.y) - 1e-3f;  // log2(alpha_min / o)
+  const float X0 = (float)s.x0, X1 = (float)s.x1, Y0 = (float)s.y0, Y1 = (float)s.y1;
+  const float cx = fminf(fmaxf(u, X0), X1), cy = fminf(fmaxf(v, Y0), Y1);
+  float best = (cx == u && cy == v) ? 0.f : -INFINITY;
+  if (cx != u) {  // edge x = cx: maximise over y
+    const float dX = cx - u;
+    const float y = fminf(fmaxf(v - pb * dX * __builtin_amdgcn_rcpf(2.f * pc), Y0), Y1);
+    const float dy = y - v;
+    best = fmaxf(best, fmaf(pa * dX, dX, fmaf(pb * dX, dy, pc * dy * dy)));
+  }
+  if (cy != v) {  // edge y = cy: maximise over x
+    const float dY = cy - v;
+    const float x = fminf(fmaxf(u - pb * dY * __builtin_amdgcn_rcpf(2.f * pa), X0), X1);
+    const float dx = x - u;
+    best = fmaxf(best, fmaf(pa * dx, dx, fmaf(pb * dx, dY, pc * dY * dY)));
+  }
+  return best >= thr;
+}
+
 __device__ __forceinline__ bool box_holds(float fbx, float fby, int px, int py) {
   const uint32_t bx = __float_as_uint(fbx), by = __float_as_uint(fby);
   return (px >= (int)(bx & 0xffffu)) & (px <= (int)(bx >> 16)) & (py >= (int)(by & 0xffffu)) & (py <= (int)(by >> 16));
@@ -128,7 +158,7 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
       bool meets = false;
       if (r < cnt) {
         const float4 cb = sm.cob[r];
-        meets = box_meets(cb.z, cb.w, q.blk);
+        meets = box_meets(cb.z, cb.w, q.blk) && ellipse_meets(sm.uvab[r], cb, q.blk, Rr.log2_amin);
       }
       uint64_t m = __ballot(meets);
       while (m) {
@@ -239,7 +269,7 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
       bool meets = false;
       if (r < cnt) {
         const float4 cb = sm.cob[r];
-        meets = box_meets(cb.z, cb.w, q.blk);
+        meets = box_meets(cb.z, cb.w, q.blk) && ellipse_meets(sm.uvab[r], cb, q.blk, Rr.log2_amin);
       }
       uint64_t m = __ballot(meets);
       while (m) {
