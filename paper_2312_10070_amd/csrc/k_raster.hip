@@ -1,25 +1,37 @@
 // Per-tile compositing. One 256-thread workgroup per (view, tile) item, one
-// pixel per lane, one 8x8 pixel block per wave. Gaussian records of the item's depth-sorted list are staged
-// through LDS in batches of 256 (one coalesced fetch per record per
-// workgroup). Each wave then ballots, 64 records at a time, which records'
-// support boxes overlap its own pixel block, and visits only those, in list
-// order, with the record broadcast from LDS. Skipping a record whose box
-// misses the block cannot change the result: outside its box a Gaussian has
-// alpha < alpha_min.
+// pixel per lane: each wave covers an 8x8 pixel block of the tile and each
+// 16-lane row of a wave (one DPP row) a 4x4 quadrant of that block. Gaussian
+// records of the item's depth-sorted list are staged through LDS in batches
+// (one coalesced fetch per record per workgroup). Skipping a record for a
+// block or quadrant cannot change the result: outside its support a Gaussian
+// has alpha < alpha_min.
 //
-// Forward: front to back (Eq. 3 colour, Eq. 4 alpha, Eq. 6 depth). A lane
-// stops before the Gaussian that would take its transmittance below T_min; a
+// Forward: front to back (Eq. 3 colour, Eq. 4 alpha, Eq. 6 depth), batches of
+// 512 records. Each wave tests, 64 records at a time, which records can reach
+// alpha >= alpha_min in its block (support box, then an exact
+// ellipse-versus-rectangle test) and in which of its quadrants (support box),
+// and appends their LDS offsets to one visit list per quadrant. The four rows
+// of the wave then walk their own lists side by side, each lane reading its
+// row's record from LDS, so a record is visited only by the quadrants it can
+// reach; a row whose list has ended reads an all-zero record (alpha = 0). A
+// lane stops before the Gaussian that would take its transmittance below
+// T_min; a quadrant whose lanes have all stopped gets no further entries, a
 // wave leaves the batch as soon as all its lanes have stopped, and the
 // workgroup stops fetching batches once all four waves have.
 //
-// Backward: back to front from each pixel's last composited Gaussian. The
-// transmittance in front of Gaussian j is recomputed as T_j = T_{j+1} /
-// (1 - alpha_j) instead of being stored; suffix sums of c alpha T and z alpha T
-// give the second terms of dC/dalpha and Eq. 8. The ten per-Gaussian partials
-// (sums of q (dx, dy, dx^2, dx dy, dy^2) with q = dL/dp / ln 2 for alpha =
-// o 2^p, then opacity, colour, direct depth) of a wave are summed with a field-splitting
-// butterfly and added to the [V n, 10] gradient buffer with one 10-lane
-// atomic per (Gaussian, wave).
+// Backward: back to front from each pixel's last composited Gaussian, batches
+// of 256 records, one visit list per wave (records reaching the 8x8 block,
+// walked with the record broadcast from LDS). The transmittance in front of
+// Gaussian j is recomputed as T_j = T_{j+1} / (1 - alpha_j) instead of being
+// stored; suffix sums of c alpha T and z alpha T give the second terms of
+// dC/dalpha and Eq. 8. The ten per-Gaussian partials (sums of q (dx, dy,
+// dx^2, dx dy, dy^2) with q = dL/dp / ln 2 for alpha = o 2^p, then opacity,
+// colour, direct depth) of a wave are summed with a field-splitting butterfly
+// and added to the [V n, 10] gradient buffer with one 10-lane atomic per
+// (Gaussian, wave). (Per-quadrant lists would also shorten the backward walk,
+// but they multiply the partial sums to add: 2.4 per (Gaussian, block) on the
+// headline scene, and float atomics, in L2 or LDS, then cost more than the
+// walk saves.)
 //
 // Launch shapes: one workgroup per item (items dealt to XCDs in contiguous
 // runs), or a persistent grid whose workgroups pull items from a counter in
@@ -30,6 +42,15 @@ namespace gsr {
 
 namespace {
 
+// Records staged in LDS per batch (forward, backward), capacity of a
+// quadrant's visit list, and the LDS slot of an all-zero record (u = v = 0,
+// zero conic, o = 0: alpha = 0 at every pixel), which a row reads once its
+// list has ended.
+constexpr int kFwdBatch = 512;
+constexpr int kListCap = 128;
+constexpr int kWavesPerTile = kTileThreads / kWave;
+static_assert(kFwdBatch % kWave == 0 && kListCap >= kWave, "batch / list shape");
+
 struct Block {
   int x0, x1, y0, y1;  // inclusive pixel rectangle of a wave (8x8)
 };
@@ -37,6 +58,7 @@ struct Block {
 struct Pixel {
   int tile, view;
   int px, py;
+  int quad;     // 4x4 quadrant of the block (row-major) = DPP row of the lane
   bool inside;
   float fpx, fpy;
   int64_t p;    // pixel index inside the view
@@ -45,8 +67,9 @@ struct Pixel {
 };
 
 // Each wave covers one 8x8 pixel block of the tile (a square block meets fewer
-// support boxes than a 16x4 or 32x2 strip); the four blocks are row-major in
-// the tile, lanes row-major in the block.
+// support boxes than a 16x4 or 32x2 strip), the four blocks row-major in the
+// tile; lane row r = lane / 16 covers quadrant r of the block (row-major),
+// lanes row-major in the quadrant.
 __device__ __forceinline__ Pixel item_pixel(const Raster& Rr, int item) {
   Pixel q;
   q.view = item / Rr.n_tiles;
@@ -59,21 +82,15 @@ __device__ __forceinline__ Pixel item_pixel(const Raster& Rr, int item) {
   q.blk.x1 = q.blk.x0 + 7;
   q.blk.y0 = tyi * Rr.th + 8 * by;
   q.blk.y1 = q.blk.y0 + 7;
-  q.px = q.blk.x0 + (l & 7);
-  q.py = q.blk.y0 + (l >> 3);
+  q.quad = l >> 4;
+  q.px = q.blk.x0 + 4 * (q.quad & 1) + (l & 3);
+  q.py = q.blk.y0 + 4 * (q.quad >> 1) + ((l >> 2) & 3);
   q.inside = q.px < Rr.W && q.py < Rr.H;
   q.fpx = (float)q.px;
   q.fpy = (float)q.py;
   q.p = (int64_t)q.py * Rr.W + q.px;
   q.off = (int64_t)q.view * Rr.W * Rr.H;
   return q;
-}
-
-// Does the packed support box (bx = x0 | x1 << 16, by = y0 | y1 << 16) meet the block?
-__device__ __forceinline__ bool box_meets(float fbx, float fby, const Block& s) {
-  const uint32_t bx = __float_as_uint(fbx), by = __float_as_uint(fby);
-  const int x0 = (int)(bx & 0xffffu), x1 = (int)(bx >> 16), y0 = (int)(by & 0xffffu), y1 = (int)(by >> 16);
-  return (x0 <= s.x1) & (x1 >= s.x0) & (y0 <= s.y1) & (y1 >= s.y0);  // no short-circuit branches
 }
 
 // Can the record reach alpha >= alpha_min anywhere in the block? alpha = o 2^p
@@ -106,15 +123,56 @@ __device__ __forceinline__ bool ellipse_meets(const float4& g, const float4& cb,
   return best >= thr;
 }
 
+// Quadrants of the block (bit k = quadrant k, row-major) the record may reach:
+// the packed support box (x0 | x1 << 16, y0 | y1 << 16) must meet the block
+// and, if EXACT, the record must pass the ellipse test on the block; a
+// quadrant must also meet the support box.
+template <bool EXACT>
+__device__ __forceinline__ uint32_t quad_mask(const float4& g, const float4& cb, const Block& s, float log2_amin) {
+  const uint32_t bx = __float_as_uint(cb.z), by = __float_as_uint(cb.w);
+  const int x0 = (int)(bx & 0xffffu), x1 = (int)(bx >> 16), y0 = (int)(by & 0xffffu), y1 = (int)(by >> 16);
+  bool meets = (x0 <= s.x1) & (x1 >= s.x0) & (y0 <= s.y1) & (y1 >= s.y0);  // no short-circuit branches
+  if (EXACT) meets = meets && ellipse_meets(g, cb, s, log2_amin);
+  const uint32_t L = x0 <= s.x0 + 3, R = x1 >= s.x0 + 4, T = y0 <= s.y0 + 3, B = y1 >= s.y0 + 4;
+  const uint32_t m = (L & T) | ((R & T) << 1) | ((L & B) << 2) | ((R & B) << 3);
+  return meets ? m : 0u;
+}
+
+// Can the record reach alpha >= alpha_min anywhere in the block (support box,
+// then the ellipse test)?
+__device__ __forceinline__ bool block_meets(const float4& g, const float4& cb, const Block& s, float log2_amin) {
+  const uint32_t bx = __float_as_uint(cb.z), by = __float_as_uint(cb.w);
+  const int x0 = (int)(bx & 0xffffu), x1 = (int)(bx >> 16), y0 = (int)(by & 0xffffu), y1 = (int)(by >> 16);
+  return ((x0 <= s.x1) & (x1 >= s.x0) & (y0 <= s.y1) & (y1 >= s.y0)) && ellipse_meets(g, cb, s, log2_amin);
+}
+
 __device__ __forceinline__ bool box_holds(float fbx, float fby, int px, int py) {
   const uint32_t bx = __float_as_uint(fbx), by = __float_as_uint(fby);
   return (px >= (int)(bx & 0xffffu)) & (px <= (int)(bx >> 16)) & (py >= (int)(by & 0xffffu)) & (py <= (int)(by >> 16));
 }
 
+// Lanes whose bit is set in the wave-uniform mask m append `val` to `list`
+// after its first `len` entries: in lane order (ascending) or in reverse lane
+// order (descending).
+template <bool DESCENDING>
+__device__ __forceinline__ void list_append(uint16_t* list, int len, uint64_t m, int lane, int val) {
+  if ((m >> lane) & 1ull) {
+    const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    list[len + (DESCENDING ? __popcll(m) - 1 - below : below)] = (uint16_t)val;
+  }
+}
+
+// The float4 at byte offset `boff` of an LDS array.
+__device__ __forceinline__ float4 lds_at(const float4* arr, int boff) {
+  return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(arr) + boff);
+}
+
 struct FwdSmem {
-  float4 uvab[kTileThreads];
-  float4 cob[kTileThreads];
-  float4 rgbz[kTileThreads];
+  static constexpr int kBatch = kFwdBatch, kDummy = kFwdBatch;
+  float4 uvab[kBatch + 1];
+  float4 cob[kBatch + 1];
+  float4 rgbz[kBatch + 1];
+  uint16_t list[kWavesPerTile][4][kListCap + 2];
 };
 
 struct BwdSmem {
@@ -125,69 +183,109 @@ struct BwdSmem {
   int max_last;
 };
 
+// The all-zero record; written once per workgroup before its first barrier.
+__device__ __forceinline__ void init_smem(FwdSmem& sm) {
+  if (threadIdx.x == 0) {
+    sm.uvab[FwdSmem::kDummy] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sm.cob[FwdSmem::kDummy] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sm.rgbz[FwdSmem::kDummy] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
 // STATS = true: instead of writing outputs, count the algorithmic work (for the
 // benchmark's roofline): pairs whose pixel lies in the Gaussian's support box
-// before the pixel stops, and pairs composited.
+// before the pixel stops, and pairs composited. The lists then come from the
+// support boxes alone, so every such pair is visited.
 template <bool STATS>
 __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int item, FwdSmem& sm) {
-  const int tid = threadIdx.x, lane = tid & 63;
+  constexpr int kBatch = FwdSmem::kBatch, kDummy = FwdSmem::kDummy;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const Pixel q = item_pixel(Rr, item);
   const int2 rg = a.ranges[item];
   const int start = rg.x, end = rg.y;
   // T > 0: the lane is compositing; T < 0: it has stopped and -T is its final
   // transmittance (T >= T_min > 0 while compositing, so the sign is free).
   float T = q.inside ? 1.f : -1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
-  int last = 0;
+  int last16 = 0;  // 16 x (list position of the last composited Gaussian + 1)
   uint32_t n_eval = 0, n_comp = 0;
+  const uint16_t* mylist = sm.list[w][q.quad];
 
-  for (int base = start; base < end; base += kTileThreads) {
+  for (int base = start; base < end; base += kBatch) {
     if (__syncthreads_count(T > 0.f) == 0) break;
-    const int i = base + tid;
-    if (i < end) {
-      const uint32_t gid = a.ids[i];
-      sm.uvab[tid] = a.rec_uvab[kRec * gid];
-      sm.cob[tid] = a.rec_cob[kRec * gid];
-      sm.rgbz[tid] = a.rec_rgbz[kRec * gid];
+#pragma unroll
+    for (int h = 0; h < (kBatch + kTileThreads - 1) / kTileThreads; ++h) {
+      const int sl = h * kTileThreads + tid, i = base + sl;
+      if (sl < kBatch && i < end) {
+        const uint32_t gid = a.ids[i];
+        sm.uvab[sl] = a.rec_uvab[kRec * gid];
+        sm.cob[sl] = a.rec_cob[kRec * gid];
+        sm.rgbz[sl] = a.rec_rgbz[kRec * gid];
+      }
     }
     __syncthreads();
-    if (!__any(T > 0.f)) continue;
-    const int cnt = min(kTileThreads, end - base);
-    bool wave_done = false;
-    for (int c = 0; c * kWave < cnt && !wave_done; ++c) {
-      const int r = c * kWave + lane;
-      bool meets = false;
-      if (r < cnt) {
-        const float4 cb = sm.cob[r];
-        meets = box_meets(cb.z, cb.w, q.blk) && ellipse_meets(sm.uvab[r], cb, q.blk, Rr.log2_amin);
+    const int cnt = min(kBatch, end - base);
+    const int nch = (cnt + kWave - 1) / kWave;
+    int k = 0;
+    while (k < nch) {
+      // one segment: append chunks to the quadrant lists until one would overflow
+      const uint64_t alive = __ballot(T > 0.f);
+      if (alive == 0) break;
+      int len0 = 0, len1 = 0, len2 = 0, len3 = 0;
+      for (; k < nch; ++k) {
+        const int r = k * kWave + lane;
+        const uint32_t qm = r < cnt ? quad_mask<!STATS>(sm.uvab[r], sm.cob[r], q.blk, Rr.log2_amin) : 0u;
+        // a quadrant whose lanes have all stopped takes no entries
+        const uint64_t m0 = (alive & 0xffffull) ? __ballot(qm & 1u) : 0ull;
+        const uint64_t m1 = (alive & 0xffff0000ull) ? __ballot(qm & 2u) : 0ull;
+        const uint64_t m2 = (alive & 0xffff00000000ull) ? __ballot(qm & 4u) : 0ull;
+        const uint64_t m3 = (alive & 0xffff000000000000ull) ? __ballot(qm & 8u) : 0ull;
+        const int c0 = __popcll(m0), c1 = __popcll(m1), c2 = __popcll(m2), c3 = __popcll(m3);
+        if (len0 + c0 > kListCap || len1 + c1 > kListCap || len2 + c2 > kListCap || len3 + c3 > kListCap) break;
+        // entries are LDS byte offsets of the slot inside each record array
+        list_append<false>(sm.list[w][0], len0, m0, lane, 16 * r);
+        list_append<false>(sm.list[w][1], len1, m1, lane, 16 * r);
+        list_append<false>(sm.list[w][2], len2, m2, lane, 16 * r);
+        list_append<false>(sm.list[w][3], len3, m3, lane, 16 * r);
+        len0 += c0;
+        len1 += c1;
+        len2 += c2;
+        len3 += c3;
       }
-      uint64_t m = __ballot(meets);
-      while (m) {
-        const int j = c * kWave + __builtin_ctzll(m);
-        m &= m - 1;
+      const int myl = q.quad == 0 ? len0 : (q.quad == 1 ? len1 : (q.quad == 2 ? len2 : len3));
+      const int maxl = __builtin_amdgcn_readfirstlane(max(max(len0, len1), max(len2, len3)));
+      // (list position + 1) * 16 of slot 0: last16 = code + byte offset
+      const int code = 16 * (base - start + 1);
+      __builtin_amdgcn_wave_barrier();
+      // the next entry is read one step ahead (entry kListCap + 1 exists, so
+      // the read stays inside the row's list)
+      int jn = mylist[0];
+      // walk while some lane is compositing and its row's list has not ended
+      for (int t = 0; t < maxl && (__ballot(T > 0.f) & __ballot(t < myl)) != 0; ++t) {
+        const bool pend = t < myl;
+        const int jb = pend ? jn : 16 * kDummy;
+        jn = mylist[t + 1];
         // Every lane runs the same instructions. A skipped pair (alpha <
-        // alpha_min) acts as alpha = 0; a stopped lane has T < 0, so its Tn < T_min
-        // and it adds w = 0 and keeps T.
-        const float4 g = sm.uvab[j];
-        const float4 cb = sm.cob[j];
-        const float4 cz = sm.rgbz[j];
+        // alpha_min, or the all-zero record) acts as alpha = 0; a stopped lane
+        // has T < 0, so its Tn < T_min and it adds w = 0 and keeps T.
+        const float4 g = lds_at(sm.uvab, jb);
+        const float4 cb = lds_at(sm.cob, jb);
+        const float4 cz = lds_at(sm.rgbz, jb);
         const PairEval pe = eval_pair(q.fpx - g.x, q.fpy - g.y, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
-        if (STATS && T > 0.f && box_holds(cb.z, cb.w, q.px, q.py)) ++n_eval;
+        if (STATS && T > 0.f && jb != 16 * kDummy && box_holds(cb.z, cb.w, q.px, q.py)) ++n_eval;
         const float al = pe.use ? pe.alpha : 0.f;
         const float Tn = T * (1.f - al);
         const bool comp = Tn >= Rr.tmin;  // false for a stopped lane and at the stop
-        const float w = comp ? al * T : 0.f;
-        C0 = fmaf(cz.x, w, C0);
-        C1 = fmaf(cz.y, w, C1);
-        C2 = fmaf(cz.z, w, C2);
-        D = fmaf(cz.w, w, D);
-        last = (comp && pe.use) ? base - start + j + 1 : last;
+        const float wt = comp ? al * T : 0.f;
+        C0 = fmaf(cz.x, wt, C0);
+        C1 = fmaf(cz.y, wt, C1);
+        C2 = fmaf(cz.z, wt, C2);
+        D = fmaf(cz.w, wt, D);
+        last16 = (comp && pe.use) ? code + jb : last16;
         if (STATS && comp && pe.use) ++n_comp;
         T = comp ? Tn : -fabsf(T);
-        if (!__any(T > 0.f)) {
-          wave_done = true;
-          break;
-        }
+        asm volatile("" : "+v"(jn));  // keep the read of the next entry in this step
       }
+      __builtin_amdgcn_wave_barrier();
     }
   }
   if (STATS) {
@@ -213,7 +311,7 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
     a.depth[p] = D;
     a.alpha[p] = 1.f - T;
     a.Tfin[p] = T;
-    a.last[p] = last;
+    a.last[p] = last16 >> 4;
   }
 }
 
@@ -269,7 +367,7 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
       bool meets = false;
       if (r < cnt) {
         const float4 cb = sm.cob[r];
-        meets = box_meets(cb.z, cb.w, q.blk) && ellipse_meets(sm.uvab[r], cb, q.blk, Rr.log2_amin);
+        meets = block_meets(sm.uvab[r], cb, q.blk, Rr.log2_amin);
       }
       uint64_t m = __ballot(meets);
       while (m) {
@@ -324,6 +422,7 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
 template <bool STATS>
 __global__ __launch_bounds__(kTileThreads) void k_render_fwd(Raster Rr, FwdArgs a) {
   __shared__ FwdSmem sm;
+  init_smem(sm);
   fwd_item<STATS>(Rr, a, xcd_tile(blockIdx.x, gridDim.x), sm);
 }
 
@@ -347,6 +446,7 @@ __device__ __forceinline__ int next_item(int* queue, const int* order, int n_ite
 __global__ __launch_bounds__(kTileThreads) void k_render_fwd_persistent(Raster Rr, FwdArgs a) {
   __shared__ FwdSmem sm;
   __shared__ int s_item;
+  init_smem(sm);
   for (;;) {
     const int item = next_item(a.queue, a.order, a.n_items, &s_item);
     if (item < 0) break;
