@@ -284,10 +284,17 @@ int gsr_initnet_adam(gsr_ctx *ctx, gsr_initnet *net, float lr, float beta1, floa
 /* Measurement ------------------------------------------------------------ */
 
 /* Stage timing for benchmarks: while enabled, every stage a call enqueues
- * (project, scan, duplicate, radix_sort, tile_ranges, render_fwd, fill,
- * render_bwd, project_bwd, loss_l1, loss_track, adam, ...) is bracketed by a
- * pair of HIP events on the context's stream. */
+ * (project, bin_count, tile_bins, render_fwd, fill, render_bwd, project_bwd,
+ * loss_l1, loss_track, adam, pose_adam, track_graph, initnet_fwd,
+ * initnet_bwd) is bracketed by a pair of HIP events on the context's stream.
+ * The events carry no system-scope fence, so they do not write back or
+ * invalidate caches, but each still costs a few microseconds of stream time. */
 int gsr_profile_enable(gsr_ctx *ctx, int on);
+/* Restricts stage timing to the stage named `stage` (NULL or "" = every
+ * stage), so a timed loop can measure one kernel's duration with one event
+ * pair per launch. The name is copied; GSR_EINVAL if it is 32 bytes or
+ * longer. */
+int gsr_profile_only(gsr_ctx *ctx, const char *stage);
 /* Synchronises, then reports per stage name (NUL-terminated, 32 bytes each in
  * `names`) the summed milliseconds and the number of launches since the last
  * read, and clears the record. *n_stages receives the number of names, which

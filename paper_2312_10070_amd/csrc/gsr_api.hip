@@ -107,6 +107,7 @@ struct gsr_ctx {
     hipEvent_t a, b;
   };
   bool prof = false;
+  std::string prof_only;  // empty: every stage
   std::vector<Rec> recs;
   std::vector<hipEvent_t> spare;
 };
@@ -275,8 +276,10 @@ hipEvent_t take_event(gsr_ctx* c) {
     c->spare.pop_back();
     return e;
   }
+  // Timing-only events: no system-scope fence, whose L2 writeback and
+  // invalidation would otherwise stall the stream at every stage boundary.
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) {
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
     (void)hipGetLastError();
     return nullptr;
   }
@@ -289,7 +292,8 @@ struct Stage {
   const char* name;
   hipEvent_t a = nullptr;
   Stage(gsr_ctx* ctx, const char* nm) : c(ctx), name(nm) {
-    if (c->prof && (a = take_event(c))) (void)hipEventRecord(a, c->stream);
+    if (c->prof && (c->prof_only.empty() || c->prof_only == nm) && (a = take_event(c)))
+      (void)hipEventRecord(a, c->stream);
   }
   ~Stage() {
     if (!a) return;
@@ -648,7 +652,8 @@ int gsr_autotune_batch(gsr_ctx* c, const gsr_gaussians* g, int32_t n_views, cons
   float* depth = buf + 3 * P * n_views;
   float* alpha = depth + P * n_views;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+  if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+      hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(buf);
     return fail(c, GSR_EHIP, "event creation failed");
@@ -894,6 +899,13 @@ int gsr_initnet_adam(gsr_ctx* c, gsr_initnet* net, float lr, float b1, float b2,
 int gsr_profile_enable(gsr_ctx* c, int on) {
   if (!c) return GSR_EINVAL;
   c->prof = on != 0;
+  return GSR_OK;
+}
+
+int gsr_profile_only(gsr_ctx* c, const char* stage) {
+  if (!c) return GSR_EINVAL;
+  if (stage && std::strlen(stage) >= 32) return fail(c, GSR_EINVAL, "stage name too long");
+  c->prof_only = stage ? stage : "";
   return GSR_OK;
 }
 

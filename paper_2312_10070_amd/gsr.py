@@ -103,6 +103,7 @@ _SIGS = {
     "gsr_initnet_backward": (ctypes.c_int, [P, P, ctypes.c_int32, P, P, P, P]),
     "gsr_initnet_adam": (ctypes.c_int, [P, P] + [ctypes.c_float] * 4),
     "gsr_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
+    "gsr_profile_only": (ctypes.c_int, [P, ctypes.c_char_p]),
     "gsr_profile_read": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_char_p, P, P, ctypes.POINTER(ctypes.c_int)]),
     "gsr_state_stats": (ctypes.c_int, [P, P, P]),
 }
@@ -389,6 +390,12 @@ def adam_step(param, exp_avg, exp_avg_sq, grad, step, lr, beta1=0.9, beta2=0.999
 def profile_enable(on: bool = True, ctx: Context | None = None):
     ctx = ctx or Context.get(torch.cuda.current_device())
     ctx.check(ctx.lib.gsr_profile_enable(ctx.h, 1 if on else 0))
+
+
+def profile_only(stage: str | None = None, ctx: Context | None = None):
+    """Restricts stage timing to one stage (None: every stage)."""
+    ctx = ctx or Context.get(torch.cuda.current_device())
+    ctx.check(ctx.lib.gsr_profile_only(ctx.h, stage.encode() if stage else None))
 
 
 def profile_read(ctx: Context | None = None) -> dict:

@@ -314,3 +314,31 @@ def test_fused_adam_groups_match_oracle():
     torch.cuda.synchronize()
     for p, d in zip(ps, pd):
         np.testing.assert_allclose(d.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+
+
+def test_stage_profile_filter():
+    """gsr_profile_only: with a filter only that stage is timed; without, every
+    stage of the call is."""
+    g, _, pose, cam = G.c1_case(0)
+    gsr.profile_read()
+    try:
+        gsr.profile_only("render_fwd")
+        gsr.profile_enable(True)
+        _, st, _, _ = run_fwd(g, pose, cam)
+        st.release()
+        gsr.profile_enable(False)
+        only = gsr.profile_read()
+        assert set(only) == {"render_fwd"} and only["render_fwd"][1] == 1 and only["render_fwd"][0] > 0
+        gsr.profile_only(None)
+        gsr.profile_enable(True)
+        _, st, _, _ = run_fwd(g, pose, cam)
+        st.release()
+        gsr.profile_enable(False)
+        every = gsr.profile_read()
+        assert {"project", "bin_count", "tile_bins", "render_fwd"} <= set(every)
+        with pytest.raises(gsr.GsrError):
+            gsr.profile_only("x" * 40)
+    finally:
+        gsr.profile_enable(False)
+        gsr.profile_only(None)
+        gsr.profile_read()
