@@ -59,7 +59,7 @@ __device__ __forceinline__ PairEval eval_pair(float dx, float dy, float pa, floa
   r.e = __builtin_amdgcn_exp2f(p);
   const float raw = o * r.e;
   r.clamped = raw > amax;
-  r.alpha = r.clamped ? amax : raw;
+  r.alpha = fminf(raw, amax);  // = clamped ? amax : raw (raw is finite: p is)
   r.use = r.alpha >= amin;
   return r;
 }

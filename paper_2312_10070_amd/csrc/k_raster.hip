@@ -370,10 +370,11 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
         meets = block_meets(sm.uvab[r], cb, q.blk, Rr.log2_amin);
       }
       uint64_t m = __ballot(meets);
+      const int cbase = __builtin_amdgcn_readfirstlane(c * kWave);  // keep the index arithmetic scalar
       while (m) {
         const int bit = 63 - __builtin_clzll(m);
         m &= ~(1ull << bit);
-        const int li = c * kWave + bit;
+        const int li = cbase + bit;
         const int pos = bstart + li - start;
         const float4 g = sm.uvab[li];
         const float4 cb = sm.cob[li];
