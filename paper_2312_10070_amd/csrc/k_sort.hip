@@ -108,6 +108,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
 
 constexpr int kSortCap = 2048;  // keys a workgroup sorts in LDS (16 KB)
 constexpr int kBinThreads = 256;
+// Threads of a counting / placing workgroup: each walks a few of its
+// workgroup's Gaussians, so more threads hide more of the memory latency.
+constexpr int kPlaceThreads = 1024;
 
 // Tiles one workgroup's LDS histogram covers (64 KB); more tiles per view are
 // handled in chunks (grid.z).
@@ -129,7 +132,7 @@ __device__ __forceinline__ Chunk bin_chunk(const Raster& Rr, const BinArgs& a) {
 }
 
 // M[(v n_tiles + t) n_wg + w] = pairs of workgroup w's Gaussians on tile t of view v.
-__global__ __launch_bounds__(256) void k_bin_count(Raster Rr, BinArgs a) {
+__global__ __launch_bounds__(kPlaceThreads) void k_bin_count(Raster Rr, BinArgs a) {
   extern __shared__ uint32_t hist[];
   const Chunk c = bin_chunk(Rr, a);
   const int64_t view = blockIdx.y;
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(256) void k_tile_init(const uint32_t* __restrict__ 
 
 // Every (Gaussian, tile) pair of the workgroup takes the next position of its
 // tile's sub-range (LDS counters seeded from S) and writes its key there.
-__global__ __launch_bounds__(256) void k_bin_place(Raster Rr, BinArgs a) {
+__global__ __launch_bounds__(kPlaceThreads) void k_bin_place(Raster Rr, BinArgs a) {
   extern __shared__ uint32_t next[];
   const Chunk c = bin_chunk(Rr, a);
   const int64_t view = blockIdx.y;
@@ -313,7 +316,7 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_
 
 int bin_workgroups(int64_t n) {
   const int64_t w = (n + 1023) / 1024;
-  return (int)(w < 1 ? 1 : (w > 256 ? 256 : w));
+  return (int)(w < 1 ? 1 : (w > 128 ? 128 : w));
 }
 
 namespace {
@@ -325,7 +328,7 @@ size_t bin_lds(const Raster& R) { return sizeof(uint32_t) * (size_t)min(R.n_tile
 
 void launch_bin_count(const Raster& R, const BinArgs& a, hipStream_t s) {
   if (R.n_tiles <= 0 || a.n_views <= 0) return;
-  hipLaunchKernelGGL(k_bin_count, bin_grid(R, a), dim3(256), bin_lds(R), s, R, a);
+  hipLaunchKernelGGL(k_bin_count, bin_grid(R, a), dim3(kPlaceThreads), bin_lds(R), s, R, a);
 }
 
 void launch_tile_bins(const Raster& R, const BinArgs& a, int64_t n_items, int2* ranges, uint64_t* scratch,
@@ -333,7 +336,7 @@ void launch_tile_bins(const Raster& R, const BinArgs& a, int64_t n_items, int2* 
   if (n_items <= 0) return;
   hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, (const uint32_t*)a.M,
                      (const uint32_t*)a.S, n_items, a.n_wg, a.cap, ranges);
-  hipLaunchKernelGGL(k_bin_place, bin_grid(R, a), dim3(256), bin_lds(R), s, R, a);
+  hipLaunchKernelGGL(k_bin_place, bin_grid(R, a), dim3(kPlaceThreads), bin_lds(R), s, R, a);
   hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)n_items), dim3(kBinThreads), 0, s, (const int2*)ranges, a.keys,
                      scratch, ids);
 }
