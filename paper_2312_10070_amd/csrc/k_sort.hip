@@ -5,10 +5,11 @@
 // its sub-range inside every tile's [start, end) range (and the overlap count
 // K). The workgroup then walks its Gaussians again, takes positions from LDS
 // counters seeded with its sub-range starts, and writes the keys (float bits
-// of the camera depth << 32 | record index) in arbitrary order. Finally one
-// workgroup per tile sorts its range by key in LDS (a bitonic network; a
-// range longer than LDS holds is sorted in LDS-sized runs merged pairwise in
-// global memory) and writes the record indices. Keys are unique within a
+// of the camera depth << 32 | record index) in arbitrary order. Finally each
+// tile's range is sorted by key and its record indices written: by one wave
+// in registers (a bitonic network, up to 512 keys), or for longer ranges by a
+// whole workgroup through LDS (runs of 2048 merged pairwise in global
+// memory). Keys are unique within a
 // tile, so the result is the depth order of the "m ordered Gaussians" of
 // Eq. 3 and Eq. 6 with ties broken by index: exactly what a stable sort of
 // (tile, depth) gives. No launch grid depends on K: positions at or beyond
@@ -253,34 +254,99 @@ __device__ void merge_runs(const uint64_t* a, int na, const uint64_t* b, int nb,
   }
 }
 
-// One workgroup per (view, tile) item.
-__global__ __launch_bounds__(kBinThreads) void k_tile_sort(const int2* __restrict__ ranges, uint64_t* __restrict__ keys,
-                                                          uint64_t* __restrict__ scratch, uint32_t* __restrict__ ids) {
-  __shared__ uint64_t s[kSortCap];
-  const int2 rg = ranges[blockIdx.x];
-  const int64_t b = rg.x;
-  const int len = rg.y - rg.x;
-  if (len <= 0) return;
-  if (len <= kSortCap) {
-    sort_run(keys, b, len, s, nullptr, ids);
-    return;
+// Keys a single wave sorts in registers (8 per lane).
+constexpr int kWaveSort = 512;
+
+// Sorts keys[b, b + len) (0 < len <= kWaveSort) with one wave: lane l holds
+// elements 8 l .. 8 l + 7 in registers; a bitonic network whose strides below
+// 8 are compare-exchanges inside a lane and whose larger strides exchange with
+// lane l ^ (stride / 8). Writes the low words (record indices) to ids.
+__device__ void wave_sort(const uint64_t* __restrict__ keys, int64_t b, int len, uint32_t* __restrict__ ids) {
+  const int lane = threadIdx.x & 63;
+  uint64_t e[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int i = 8 * lane + r;
+    e[r] = i < len ? keys[b + i] : ~0ull;  // padding sorts last (keys hold finite depths)
   }
-  // long range: sorted runs of kSortCap, then pairwise merges (ping-pong)
-  for (int c0 = 0; c0 < len; c0 += kSortCap) sort_run(keys, b + c0, min(kSortCap, len - c0), s, keys, nullptr);
-  uint64_t* src = keys + b;
-  uint64_t* dst = scratch + b;
-  for (int w = kSortCap; w < len; w <<= 1) {
-    for (int lo = 0; lo < len; lo += 2 * w) {
-      const int mid = min(lo + w, len), hi = min(lo + 2 * w, len);
-      merge_runs(src + lo, mid - lo, src + mid, hi - mid, dst + lo);
+#pragma unroll
+  for (int k = 2; k <= kWaveSort; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 8) {
+        const int m = j >> 3;
+        const bool upper = (lane & m) != 0;  // this lane holds the larger position of each pair
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const bool asc = ((8 * lane + r) & k) == 0;
+          const uint64_t p = __shfl_xor(e[r], m, 64);
+          // the lower position keeps the minimum of an ascending block, the upper the maximum
+          const bool keep_min = asc != upper;
+          e[r] = ((e[r] < p) == keep_min) ? e[r] : p;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          if ((r & j) == 0) {
+            const bool asc = ((8 * lane + r) & k) == 0;
+            const uint64_t x = e[r], y = e[r | j];
+            const bool sw = (x > y) == asc;
+            e[r] = sw ? y : x;
+            e[r | j] = sw ? x : y;
+          }
+        }
+      }
     }
-    __threadfence_block();
-    __syncthreads();
-    uint64_t* t = src;
-    src = dst;
-    dst = t;
   }
-  for (int i = threadIdx.x; i < len; i += kBinThreads) ids[b + i] = (uint32_t)src[i];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int i = 8 * lane + r;
+    if (i < len) ids[b + i] = (uint32_t)e[r];
+  }
+}
+
+// Four (view, tile) items per workgroup. Each wave sorts one item of at most
+// kWaveSort keys in registers; longer items are then sorted by the whole
+// workgroup through LDS (runs of kSortCap merged pairwise in global memory).
+__global__ __launch_bounds__(kBinThreads) void k_tile_sort(const int2* __restrict__ ranges, int64_t n_items,
+                                                          uint64_t* __restrict__ keys, uint64_t* __restrict__ scratch,
+                                                          uint32_t* __restrict__ ids) {
+  __shared__ uint64_t s[kSortCap];
+  constexpr int kItems = kBinThreads / 64;
+  const int64_t item0 = (int64_t)blockIdx.x * kItems;
+  const int w = threadIdx.x >> 6;
+  if (item0 + w < n_items) {
+    const int2 rg = ranges[item0 + w];
+    const int len = rg.y - rg.x;
+    if (len > 0 && len <= kWaveSort) wave_sort(keys, rg.x, len, ids);
+  }
+  for (int it = 0; it < kItems && item0 + it < n_items; ++it) {
+    const int2 rg = ranges[item0 + it];
+    const int64_t b = rg.x;
+    const int len = rg.y - rg.x;
+    if (len <= kWaveSort) continue;  // uniform across the workgroup
+    if (len <= kSortCap) {
+      sort_run(keys, b, len, s, nullptr, ids);
+      continue;
+    }
+    // long range: sorted runs of kSortCap, then pairwise merges (ping-pong)
+    for (int c0 = 0; c0 < len; c0 += kSortCap) sort_run(keys, b + c0, min(kSortCap, len - c0), s, keys, nullptr);
+    uint64_t* src = keys + b;
+    uint64_t* dst = scratch + b;
+    for (int wd = kSortCap; wd < len; wd <<= 1) {
+      for (int lo = 0; lo < len; lo += 2 * wd) {
+        const int mid = min(lo + wd, len), hi = min(lo + 2 * wd, len);
+        merge_runs(src + lo, mid - lo, src + mid, hi - mid, dst + lo);
+      }
+      __threadfence_block();
+      __syncthreads();
+      uint64_t* t = src;
+      src = dst;
+      dst = t;
+    }
+    for (int i = threadIdx.x; i < len; i += kBinThreads) ids[b + i] = (uint32_t)src[i];
+    __syncthreads();
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
@@ -337,8 +403,8 @@ void launch_tile_bins(const Raster& R, const BinArgs& a, int64_t n_items, int2* 
   hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, (const uint32_t*)a.M,
                      (const uint32_t*)a.S, n_items, a.n_wg, a.cap, ranges);
   hipLaunchKernelGGL(k_bin_place, bin_grid(R, a), dim3(kPlaceThreads), bin_lds(R), s, R, a);
-  hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)n_items), dim3(kBinThreads), 0, s, (const int2*)ranges, a.keys,
-                     scratch, ids);
+  hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)((n_items + kBinThreads / 64 - 1) / (kBinThreads / 64))),
+                     dim3(kBinThreads), 0, s, (const int2*)ranges, n_items, a.keys, scratch, ids);
 }
 
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
