@@ -260,12 +260,18 @@ Proj project_one(int64_t k, const double* means, const double* scales, const dou
   g.o = opac[k];
   for (int i = 0; i < 3; ++i) g.col[i] = colors[3 * k + i];
   // Support: o exp(-sigma) >= alpha_min needs sigma <= ln(o / alpha_min);
-  // for |dx| > sqrt(2 smax Sigma'_xx) the minimum of sigma over dy already
-  // exceeds smax, so the box below is exact-conservative.
+  // for |dx| > sqrt(2 s Sigma'_xx) the minimum of sigma over dy already
+  // exceeds s, so a box of half-widths sqrt(2 s Sigma'_xx), sqrt(2 s Sigma'_yy)
+  // with s >= smax is conservative. The box only selects work (which pixels
+  // and tiles a Gaussian is evaluated on), so any conservative s gives the
+  // same image; s = (1 + 1e-3) smax + 1e-3 keeps alpha below alpha_min by a
+  // factor e^-0.001 outside the box, so binary32 evaluation cannot reach
+  // alpha_min there either.
   if (!(g.o >= opt.amin) || !std::isfinite(g.o)) return g;
   g.smax = std::log(g.o / opt.amin);
-  const double rx = std::sqrt(2.0 * g.smax * g.Sp[0]);
-  const double ry = std::sqrt(2.0 * g.smax * g.Sp[2]);
+  const double sbox = (1.0 + 1e-3) * g.smax + 1e-3;
+  const double rx = std::sqrt(2.0 * sbox * g.Sp[0]);
+  const double ry = std::sqrt(2.0 * sbox * g.Sp[2]);
   const double ex0 = g.u - rx, ex1 = g.u + rx, ey0 = g.v - ry, ey1 = g.v + ry;
   if (!std::isfinite(ex0) || !std::isfinite(ex1) || !std::isfinite(ey0) || !std::isfinite(ey1)) return g;
   const double fx0 = std::max(0.0, std::ceil(ex0));

@@ -14,6 +14,9 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr int kTileThreads = 256;  // one pixel per lane, 4 waves per tile
 constexpr int kWave = 64;
 constexpr int kRec = 4;  // float4s per projected record
+// The support box is taken at level (1 + kBoxSlack) ln(o / alpha_min) + kBoxSlack
+// of sigma instead of ln(o / alpha_min).
+constexpr float kBoxSlack = 1e-3f;
 
 
 // Launch constants of one render (by value into every kernel).

@@ -144,8 +144,12 @@ __global__ __launch_bounds__(256) void k_project(Raster Rr, ProjectArgs a) {
     if (op >= Rr.amin && isfinite(op)) {
       const float idet = 1.f / g.det;
       const float ca = g.Syy * idet, cb = -g.Sxy * idet, cc = g.Sxx * idet;
-      // support: o exp(-sigma) >= alpha_min needs sigma <= ln(o / alpha_min)
-      const float smax = logf(op / Rr.amin);
+      // support: o exp(-sigma) >= alpha_min needs sigma <= ln(o / alpha_min);
+      // the box is taken for a slightly larger level, so outside it alpha stays
+      // below alpha_min by a factor e^-0.001 and no FP32 rounding of alpha can
+      // reach alpha_min there: skipping by box (tiles, blocks, quadrants)
+      // never changes a result
+      const float smax = logf(op / Rr.amin) * (1.f + kBoxSlack) + kBoxSlack;
       const float rx = sqrtf(2.f * smax * g.Sxx), ry = sqrtf(2.f * smax * g.Syy);
       const float ex0 = g.u - rx, ex1 = g.u + rx, ey0 = g.v - ry, ey1 = g.v + ry;
       if (isfinite(ex0) && isfinite(ex1) && isfinite(ey0) && isfinite(ey1)) {

@@ -141,7 +141,8 @@ def test_culling_rules():
 
 
 def test_support_box_is_conservative():
-    """Outside the support box no pixel reaches alpha_min (brute force over pixels)."""
+    """Outside the support box no pixel reaches alpha_min, with the box's slack
+    to spare: alpha < alpha_min e^-0.001 (brute force over pixels)."""
     inp = synth.c1_inputs(0)
     g = inp["gaussians"]
     opts = oracle.Opts()
@@ -153,7 +154,7 @@ def test_support_box_is_conservative():
         sigma = 0.5 * (rec["a"][k] * dx * dx + rec["c"][k] * dy * dy) + rec["b"][k] * dx * dy
         alpha = np.minimum(opts.alpha_max, rec["o"][k] * np.exp(-sigma))
         inside = (xs >= rec["px0"][k]) & (xs <= rec["px1"][k]) & (ys >= rec["py0"][k]) & (ys <= rec["py1"][k])
-        assert np.all(alpha[~inside] < opts.alpha_min)
+        assert np.all(alpha[~inside] < opts.alpha_min * np.exp(-1e-3))
         checked += 1
     assert checked > 50
 
