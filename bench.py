@@ -55,6 +55,9 @@ def stage_work(stage: str, st: dict, n: int, P: int) -> tuple[str, float]:
         return "hbm", n * (56.0 + 64.0 + 16.0)
     if stage == "project_bwd":
         return "hbm", n * (56.0 + 40.0 + 56.0)
+    if stage == "project_bwd_adam":
+        # ten partial sums and the parameters read, Adam moments read and written, parameters written
+        return "hbm", n * (40.0 + 56.0 + 4 * 56.0 + 56.0)
     if stage == "adam":
         return "hbm", 28.0 * 14 * n  # all 14 n parameters in one launch
     if stage == "loss_l1":
@@ -73,7 +76,8 @@ def source_hash(names) -> str:
 STAGE_SOURCES = {"render_fwd": ["k_raster.hip", "gsr_internal.h"], "render_bwd": ["k_raster.hip", "gsr_internal.h"],
                  "adam": ["k_loss.hip"], "loss_l1": ["k_loss.hip"],
                  "tile_bins": ["k_sort.hip"], "bin_count": ["k_sort.hip"], "project": ["k_project.hip", "gsr_internal.h"],
-                 "project_bwd": ["k_project.hip", "gsr_internal.h"]}
+                 "project_bwd": ["k_project.hip", "gsr_internal.h"],
+                 "project_bwd_adam": ["k_project.hip", "gsr_internal.h"]}
 
 
 def read_traffic(stage: str, workload: str):
@@ -99,7 +103,7 @@ def read_traffic(stage: str, workload: str):
 STAGE_KERNELS = {"render_bwd": ["k_render_bwd<false>("], "render_fwd": ["k_render_fwd<false>("],
                  "tile_bins": ["k_tile_init(", "k_bin_place(", "k_tile_sort("],
                  "bin_count": ["k_bin_count(", "k_scan_reduce(", "k_scan_partials(", "k_scan_down("],
-                 "project": ["k_project("], "project_bwd": ["k_project_bwd("]}
+                 "project": ["k_project("], "project_bwd_adam": ["k_project_bwd("]}
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {counter} -d <dir> -o run --output-format csv -- python3 bench.py "
                "--steps 5 --warmup 2 --no-cpu-baseline --no-tracking --no-batched --no-initnet --calib-copy-mib {mib}")
 
@@ -456,11 +460,9 @@ def main() -> int:
         color, depth, alpha, st = gsr.render_fwd(params["means"], params["scales"], params["quats"],
                                                  params["opacities"], params["colors"], pose, camera, opts)
         loss, gC, gD = gsr.loss_l1(color, depth, tgt_c, tgt_d)
-        grads = gsr.render_bwd(st, gC, gD, None, want_params=True, want_pose=False)
         step_no[0] += 1
-        keys = list(params)
-        gsr.adam_groups([params[k] for k in keys], [adam_m[k] for k in keys], [adam_v[k] for k in keys],
-                        [grads[k] for k in keys], [lrs[k] for k in keys], step_no[0])
+        # backward with the Adam step on all parameters fused into its last kernel
+        gsr.render_bwd_adam(st, gC, gD, adam_m, adam_v, lrs, step_no[0])
         st.release()
         return loss
 

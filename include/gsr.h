@@ -134,6 +134,28 @@ int gsr_render_bwd(gsr_ctx *ctx, gsr_state *state, const float *dL_dcolor, const
  * gradients dL_dpose7 [V,7] / dL_dtwist6 [V,6], and runs the compositing
  * backward with the forward's launch shape. */
 
+/* Adam state of the five Gaussian parameter tensors, in the order means,
+ * scales, quats, opacities, colors (device pointers; exp_avg / exp_avg_sq of
+ * the same shapes as the parameters), with per-tensor step sizes lr. step >= 1
+ * is the 1-based step count. */
+typedef struct {
+  float *params[5], *exp_avg[5], *exp_avg_sq[5];
+  float lr[5];
+  int64_t step;
+  float beta1, beta2, eps;
+} gsr_adam5;
+
+/* A mapping optimiser step fused into the backward: the result equals
+ * gsr_render_bwd (parameter gradients, no pose) followed by gsr_adam_groups
+ * on the five parameter tensors, but each Gaussian's gradient is applied by
+ * Adam in the kernel that completes it and is never stored. adam->params must
+ * be the tensors the forward read (checked; GSR_EINVAL otherwise); they and
+ * the moments are updated in place, so the state must not be used for
+ * another backward afterwards. For a batched state the gradient is the sum
+ * over the views. */
+int gsr_render_bwd_adam(gsr_ctx *ctx, gsr_state *state, const float *dL_dcolor, const float *dL_ddepth,
+                        const float *dL_dalpha, const gsr_adam5 *adam);
+
 /* Tile-shape autotuner for the batched path: times forward + backward (reps
  * runs after one warm-up, HIP events) for every tile shape in {16x16, 8x32,
  * 32x8} and blocks_per_cu in {0, 1, 2, 4, 8} with the given upstream
@@ -285,8 +307,8 @@ int gsr_initnet_adam(gsr_ctx *ctx, gsr_initnet *net, float lr, float beta1, floa
 
 /* Stage timing for benchmarks: while enabled, every stage a call enqueues
  * (project, bin_count, tile_bins, render_fwd, fill, render_bwd, project_bwd,
- * loss_l1, loss_track, adam, pose_adam, track_graph, initnet_fwd,
- * initnet_bwd) is bracketed by a pair of HIP events on the context's stream.
+ * project_bwd_adam, loss_l1, loss_track, adam, pose_adam, track_graph,
+ * initnet_fwd, initnet_bwd) is bracketed by a pair of HIP events on the context's stream.
  * The events carry no system-scope fence, so they do not write back or
  * invalidate caches, but each still costs a few microseconds of stream time. */
 int gsr_profile_enable(gsr_ctx *ctx, int on);

@@ -349,7 +349,7 @@ void enqueue_back(gsr_ctx* c, gsr_state* s, hipStream_t st, int64_t cap, float* 
 
 // Backward of the compositing and the projection. grads may be NULL (pose only).
 void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, const float* gD, const float* gA,
-                 const gsr_grads* grads, float* dpose7, float* dtwist6) {
+                 const gsr_grads* grads, float* dpose7, float* dtwist6, const gsr::AdamFused* adam = nullptr) {
   const gsr::Raster& R = s->R;
   const bool want_pose = dpose7 || dtwist6;
   const int n_items = R.n_tiles * s->n_views;
@@ -357,7 +357,7 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
     Stage t(c, "fill");
     gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n * s->n_views, st);
   }
-  const bool geom_only = !grads || (!grads->opacities && !grads->colors);
+  const bool geom_only = !adam && (!grads || (!grads->opacities && !grads->colors));
   gsr::BwdArgs ba{s->ranges, s->ids, s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
                   gC, gD, gA, s->g2d, geom_only, n_items, s->queue, s->blocks > 0 ? s->order : nullptr, s->blocks};
   {
@@ -369,8 +369,9 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
   gsr::ProjectBwdArgs pb{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
                          s->counts, s->g2d, G.means, G.scales, G.quats, G.opacities, G.colors,
                          want_pose ? s->pose_acc : nullptr, s->n_views};
+  if (adam) pb.adam = *adam;
   {
-    Stage t(c, "project_bwd");
+    Stage t(c, adam ? "project_bwd_adam" : "project_bwd");
     gsr::launch_project_bwd(R, pb, st);
     if (want_pose)
       gsr::launch_pose_finalize(s->pose7, s->pose_acc, gsr::project_bwd_blocks(s->n), dpose7, dtwist6, s->n_views,
@@ -574,6 +575,33 @@ int gsr_render_bwd(gsr_ctx* c, gsr_state* s, const float* dL_dcolor, const float
     return fail(c, GSR_EINVAL, "the quaternion gradient must be 16-byte aligned");
   enqueue_bwd(c, s, c->stream, dL_dcolor, dL_ddepth, dL_dalpha, G, dL_dpose7, dL_dtwist6);
   return check_launch(c, "gsr_render_bwd kernels");
+}
+
+int gsr_render_bwd_adam(gsr_ctx* c, gsr_state* s, const float* dL_dcolor, const float* dL_ddepth,
+                        const float* dL_dalpha, const gsr_adam5* adam) {
+  if (!c || !s || !s->in_use || s->ctx != c) return fail(c, GSR_EINVAL, "invalid state");
+  if (!dL_dcolor || !dL_ddepth || !adam) return fail(c, GSR_EINVAL, "dL/dcolor, dL/ddepth and the Adam state are required");
+  const float* read[5] = {s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors};
+  gsr::AdamFused A{};
+  for (int i = 0; i < 5; ++i) {
+    if (adam->params[i] != read[i])
+      return fail(c, GSR_EINVAL, "the Adam parameters must be the tensors the forward read");
+    if (!adam->exp_avg[i] || !adam->exp_avg_sq[i]) return fail(c, GSR_EINVAL, "Adam moments are required");
+    A.p[i] = adam->params[i];
+    A.m[i] = adam->exp_avg[i];
+    A.v[i] = adam->exp_avg_sq[i];
+    A.lr[i] = adam->lr[i];
+  }
+  if (adam->step < 1) return fail(c, GSR_EINVAL, "the Adam step count is 1-based");
+  A.b1 = adam->beta1;
+  A.b2 = adam->beta2;
+  A.eps = adam->eps;
+  A.bc1 = (float)(1.0 - std::pow((double)adam->beta1, (double)adam->step));
+  A.bc2 = (float)(1.0 - std::pow((double)adam->beta2, (double)adam->step));
+  A.on = true;
+  GSR_HIP(c, hipSetDevice(c->device));
+  enqueue_bwd(c, s, c->stream, dL_dcolor, dL_ddepth, dL_dalpha, nullptr, nullptr, nullptr, &A);
+  return check_launch(c, "gsr_render_bwd_adam kernels");
 }
 
 int gsr_state_release(gsr_ctx* c, gsr_state* s) {

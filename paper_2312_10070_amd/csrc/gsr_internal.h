@@ -284,6 +284,16 @@ struct BwdArgs {
 };
 void launch_render_bwd(const Raster& R, const BwdArgs& a, hipStream_t s);
 
+// Adam applied by the projection backward to each Gaussian's gradient as soon
+// as it is complete (groups: means, scales, quats, opacities, colors); p[i]
+// are the parameters the forward read, updated in place.
+struct AdamFused {
+  float *p[5], *m[5], *v[5];
+  float lr[5];
+  float b1, b2, eps, bc1, bc2;
+  bool on;
+};
+
 struct ProjectBwdArgs {
   int64_t n;
   const float *means, *scales, *quats, *opacities, *colors;
@@ -293,6 +303,7 @@ struct ProjectBwdArgs {
   float *g_means, *g_scales, *g_quats, *g_opacities, *g_colors;  // may be NULL; summed over views
   float* pose_acc;  // [n_views][blocks][12] per-workgroup dL/dR_p (9, row-major), dL/dt (3); NULL = skip
   int n_views;
+  AdamFused adam;  // adam.on: apply Adam instead of (or as well as) writing the gradients
 };
 // workgroups of the projection backward (one per 256 Gaussians)
 int64_t project_bwd_blocks(int64_t n);
@@ -322,6 +333,18 @@ void launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float 
 
 void launch_pose_adam(float* pose, float* state, const float* g, float lr_q, float lr_t, float b1, float b2, float eps,
                       hipStream_t s);
+// One bias-corrected Adam step (Kingma & Ba) on one value; bc1 = 1 - b1^t,
+// bc2 = 1 - b2^t. Contraction is pinned so every kernel that applies it (the
+// group step, the single-tensor step and the step fused into the projection
+// backward) rounds identically.
+__device__ __forceinline__ void adam_one(float& p, float& m, float& v, float g, float lr, float b1, float b2,
+                                         float eps, float bc1, float bc2) {
+#pragma clang fp contract(off)
+  m = b1 * m + (1.f - b1) * g;
+  v = b2 * v + (1.f - b2) * g * g;
+  p -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+}
+
 constexpr int kAdamGroups = 8;
 struct AdamGroups {
   float* p[kAdamGroups];

@@ -237,21 +237,12 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
                                              const float* __restrict__ g, int64_t n, float lr, float b1, float b2,
                                              float eps, float bc1, float bc2) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    float pi = p[i], mi = m[i], vi = v[i];
+    adam_one(pi, mi, vi, g[i], lr, b1, b2, eps, bc1, bc2);
+    p[i] = pi;
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
   }
-}
-
-__device__ __forceinline__ float adam_one(float& p, float& m, float& v, float g, float lr, float b1, float b2,
-                                          float eps, float bc1, float bc2) {
-  m = b1 * m + (1.f - b1) * g;
-  v = b2 * v + (1.f - b2) * g * g;
-  p -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
-  return p;
 }
 
 // Adam over up to kAdamGroups parameter tensors in one launch (each with its

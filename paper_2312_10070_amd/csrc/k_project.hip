@@ -300,6 +300,21 @@ __device__ __forceinline__ void chain_one(const Raster& Rr, const PoseF& P, cons
   }
 }
 
+// Adam on cnt consecutive values of parameter group grp starting at base.
+__device__ __forceinline__ void adam_apply(const AdamFused& A, int grp, int64_t base, const float* g, int cnt) {
+  float* __restrict__ P = A.p[grp];
+  float* __restrict__ M = A.m[grp];
+  float* __restrict__ V = A.v[grp];
+#pragma unroll
+  for (int i = 0; i < cnt; ++i) {
+    float p = P[base + i], m = M[base + i], v = V[base + i];
+    adam_one(p, m, v, g[i], A.lr[grp], A.b1, A.b2, A.eps, A.bc1, A.bc2);
+    P[base + i] = p;
+    M[base + i] = m;
+    V[base + i] = v;
+  }
+}
+
 // One thread per Gaussian, looping over the views: parameter gradients are the
 // sum over views; pose partials are reduced per view (workgroup sum + one
 // atomic per value).
@@ -330,6 +345,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a
       }
       __syncthreads();
     }
+  }
+  if (k < a.n && a.adam.on) {
+    adam_apply(a.adam, 0, 3 * k, gm, 3);
+    adam_apply(a.adam, 1, 3 * k, gs, 3);
+    adam_apply(a.adam, 2, 4 * k, gq, 4);
+    adam_apply(a.adam, 3, k, &go, 1);
+    adam_apply(a.adam, 4, 3 * k, gc, 3);
   }
   if (k < a.n) {
     if (a.g_means) {

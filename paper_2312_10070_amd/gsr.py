@@ -48,6 +48,12 @@ class Grads(ctypes.Structure):
                 ("opacities", ctypes.c_void_p), ("colors", ctypes.c_void_p)]
 
 
+class Adam5(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p * 5), ("exp_avg", ctypes.c_void_p * 5), ("exp_avg_sq", ctypes.c_void_p * 5),
+                ("lr", ctypes.c_float * 5), ("step", ctypes.c_int64), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 class TrackOpts(ctypes.Structure):
     _fields_ = [("lambda_c", ctypes.c_float), ("inlier_mult", ctypes.c_float), ("lr_q", ctypes.c_float),
                 ("lr_t", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
@@ -69,6 +75,7 @@ _SIGS = {
     "gsr_render_fwd": (ctypes.c_int, [P, ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), ctypes.POINTER(Opts), P,
                                       P, P, P, ctypes.POINTER(P)]),
     "gsr_render_bwd": (ctypes.c_int, [P, P, P, P, P, ctypes.POINTER(Grads), P, P]),
+    "gsr_render_bwd_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.POINTER(Adam5)]),
     "gsr_render_fwd_batch": (ctypes.c_int, [P, ctypes.POINTER(Gaussians), ctypes.c_int32, ctypes.POINTER(Camera),
                                             ctypes.POINTER(Opts), ctypes.c_int32, P, P, P, P, ctypes.POINTER(P)]),
     "gsr_autotune_batch": (ctypes.c_int, [P, ctypes.POINTER(Gaussians), ctypes.c_int32, ctypes.POINTER(Camera),
@@ -329,6 +336,34 @@ def render_bwd(state: State, dL_dcolor, dL_ddepth, dL_dalpha=None, want_params=T
     ctx.check(ctx.lib.gsr_render_bwd(ctx.h, state.h, _ptr(gC), _ptr(gD), _ptr(gA), ctypes.byref(gr),
                                      _ptr(out.get("pose7")), _ptr(out.get("twist6"))))
     return out
+
+
+PARAM_GROUPS = ("means", "scales", "quats", "opacities", "colors")
+
+
+def render_bwd_adam(state: State, dL_dcolor, dL_ddepth, exp_avg: dict, exp_avg_sq: dict, lrs: dict, step: int,
+                    dL_dalpha=None, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Backward fused with one Adam step on the five parameter tensors the
+    forward read (updated in place, as are the moments; keyed by PARAM_GROUPS)."""
+    ctx = state.ctx
+    ctx.sync_stream()
+    params = dict(zip(PARAM_GROUPS, state.keep[:5]))
+    gC = _f32(dL_dcolor.contiguous(), "dL_dcolor")
+    gD = _f32(dL_ddepth.contiguous(), "dL_ddepth")
+    gA = None if dL_dalpha is None else _f32(dL_dalpha.contiguous(), "dL_dalpha")
+    a = Adam5()
+    for i, k in enumerate(PARAM_GROUPS):
+        for t, nme in ((exp_avg[k], "exp_avg"), (exp_avg_sq[k], "exp_avg_sq")):
+            _f32(t, nme)
+            if t.shape != params[k].shape or not t.is_contiguous():
+                raise ValueError(f"{nme}[{k}] must be a contiguous tensor shaped like the parameter")
+        a.params[i] = _ptr(params[k])
+        a.exp_avg[i] = _ptr(exp_avg[k])
+        a.exp_avg_sq[i] = _ptr(exp_avg_sq[k])
+        a.lr[i] = float(lrs[k])
+    a.step = int(step)
+    a.beta1, a.beta2, a.eps = float(beta1), float(beta2), float(eps)
+    ctx.check(ctx.lib.gsr_render_bwd_adam(ctx.h, state.h, _ptr(gC), _ptr(gD), _ptr(gA), ctypes.byref(a)))
 
 
 def tile_lists(state: State, n_tiles: int):

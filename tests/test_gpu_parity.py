@@ -342,3 +342,50 @@ def test_stage_profile_filter():
         gsr.profile_enable(False)
         gsr.profile_only(None)
         gsr.profile_read()
+
+
+def test_backward_fused_with_adam_matches_separate_calls():
+    """gsr_render_bwd_adam equals gsr_render_bwd followed by gsr_adam_groups
+    (single view and a two-view batch); up to the order of the compositing
+    backward's float atomics, which reaches the update only through rounding."""
+    torch = torch_()
+    g, tg, pose, cam = G.c1_case(0)
+    camera = gsr.make_camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near_z, cam.bg)
+    keys = gsr.PARAM_GROUPS
+    lrs = {"means": 1e-3, "scales": 5e-4, "quats": 2e-3, "opacities": 1e-2, "colors": 5e-3}
+    rng = np.random.default_rng(3)
+    m0 = {k: rng.normal(scale=1e-3, size=np.asarray(g[k]).shape).astype(np.float32) for k in keys}
+    v0 = {k: rng.uniform(1e-8, 1e-6, size=np.asarray(g[k]).shape).astype(np.float32) for k in keys}
+    poses = [np.asarray(pose, np.float32)[None], np.stack([np.asarray(pose, np.float32)] * 2)]
+    poses[1][1, 4] += 0.02  # second view shifted 2 cm
+    for pv in poses:
+        runs = []
+        for fused in (False, True):
+            d = {k: v.clone() for k, v in G.to_dev(g).items()}
+            m = {k: torch.from_numpy(m0[k]).cuda() for k in keys}
+            v = {k: torch.from_numpy(v0[k]).cuda() for k in keys}
+            pd = torch.from_numpy(pv).cuda()
+            if pv.shape[0] == 1:
+                c, dep, _, st = gsr.render_fwd(d["means"], d["scales"], d["quats"], d["opacities"], d["colors"],
+                                               pd[0], camera)
+            else:
+                c, dep, _, st = gsr.render_fwd_batch(d["means"], d["scales"], d["quats"], d["opacities"],
+                                                     d["colors"], pd, camera)
+            gC = torch.full_like(c, 1e-3) * torch.sign(c - 0.3)
+            gD = torch.full_like(dep, 1e-3) * torch.sign(dep - 1.0)
+            if fused:
+                gsr.render_bwd_adam(st, gC, gD, m, v, lrs, 3)
+            else:
+                gr = gsr.render_bwd(st, gC, gD, None, want_params=True, want_pose=False)
+                gsr.adam_groups([d[k] for k in keys], [m[k] for k in keys], [v[k] for k in keys],
+                                [gr[k] for k in keys], [lrs[k] for k in keys], 3)
+            torch.cuda.synchronize()
+            st.release()
+            runs.append({k: (d[k].cpu().numpy(), m[k].cpu().numpy(), v[k].cpu().numpy()) for k in keys})
+        sep, fus = runs
+        for k in keys:
+            moved = np.abs(sep[k][0] - np.asarray(g[k], np.float32)).max()
+            assert moved > 0, k
+            np.testing.assert_allclose(fus[k][0], sep[k][0], rtol=1e-6, atol=1e-7, err_msg=k)
+            np.testing.assert_allclose(fus[k][1], sep[k][1], rtol=1e-4, atol=1e-12, err_msg=k)
+            np.testing.assert_allclose(fus[k][2], sep[k][2], rtol=1e-4, atol=1e-15, err_msg=k)
