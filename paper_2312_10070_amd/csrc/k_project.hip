@@ -300,18 +300,35 @@ __device__ __forceinline__ void chain_one(const Raster& Rr, const PoseF& P, cons
   }
 }
 
-// Adam on cnt consecutive values of parameter group grp starting at base.
-__device__ __forceinline__ void adam_apply(const AdamFused& A, int grp, int64_t base, const float* g, int cnt) {
-  float* __restrict__ P = A.p[grp];
-  float* __restrict__ M = A.m[grp];
-  float* __restrict__ V = A.v[grp];
-#pragma unroll
-  for (int i = 0; i < cnt; ++i) {
-    float p = P[base + i], m = M[base + i], v = V[base + i];
-    adam_one(p, m, v, g[i], A.lr[grp], A.b1, A.b2, A.eps, A.bc1, A.bc2);
-    P[base + i] = p;
-    M[base + i] = m;
-    V[base + i] = v;
+// Adam, by the whole workgroup, on the cnt values of parameter group grp
+// starting at base, with their gradients in LDS (g, 16-byte aligned): float4
+// accesses when the group's arrays allow, then a scalar tail.
+__device__ __forceinline__ void adam_range(const AdamFused& A, int grp, int64_t base, int cnt, const float* g) {
+  float* __restrict__ P = A.p[grp] + base;
+  float* __restrict__ M = A.m[grp] + base;
+  float* __restrict__ V = A.v[grp] + base;
+  const float lr = A.lr[grp];
+  const bool vec = ((reinterpret_cast<uintptr_t>(P) | reinterpret_cast<uintptr_t>(M) | reinterpret_cast<uintptr_t>(V)) &
+                    15u) == 0;
+  const int n4 = vec ? cnt / 4 : 0;
+  for (int i = threadIdx.x; i < n4; i += blockDim.x) {
+    float4 p = reinterpret_cast<float4*>(P)[i], m = reinterpret_cast<float4*>(M)[i];
+    float4 v = reinterpret_cast<float4*>(V)[i];
+    const float4 gg = reinterpret_cast<const float4*>(g)[i];
+    adam_one(p.x, m.x, v.x, gg.x, lr, A.b1, A.b2, A.eps, A.bc1, A.bc2);
+    adam_one(p.y, m.y, v.y, gg.y, lr, A.b1, A.b2, A.eps, A.bc1, A.bc2);
+    adam_one(p.z, m.z, v.z, gg.z, lr, A.b1, A.b2, A.eps, A.bc1, A.bc2);
+    adam_one(p.w, m.w, v.w, gg.w, lr, A.b1, A.b2, A.eps, A.bc1, A.bc2);
+    reinterpret_cast<float4*>(P)[i] = p;
+    reinterpret_cast<float4*>(M)[i] = m;
+    reinterpret_cast<float4*>(V)[i] = v;
+  }
+  for (int i = 4 * n4 + threadIdx.x; i < cnt; i += blockDim.x) {
+    float p = P[i], m = M[i], v = V[i];
+    adam_one(p, m, v, g[i], lr, A.b1, A.b2, A.eps, A.bc1, A.bc2);
+    P[i] = p;
+    M[i] = m;
+    V[i] = v;
   }
 }
 
@@ -346,12 +363,31 @@ __global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a
       __syncthreads();
     }
   }
-  if (k < a.n && a.adam.on) {
-    adam_apply(a.adam, 0, 3 * k, gm, 3);
-    adam_apply(a.adam, 1, 3 * k, gs, 3);
-    adam_apply(a.adam, 2, 4 * k, gq, 4);
-    adam_apply(a.adam, 3, k, &go, 1);
-    adam_apply(a.adam, 4, 3 * k, gc, 3);
+  if (a.adam.on) {
+    // Stage the workgroup's gradients in LDS in parameter order, then run Adam
+    // over each group's contiguous range with 16-byte accesses.
+    __shared__ __align__(16) float sg[14 * 256];
+    const int t = threadIdx.x;
+    sg[3 * t] = gm[0];
+    sg[3 * t + 1] = gm[1];
+    sg[3 * t + 2] = gm[2];
+    sg[768 + 3 * t] = gs[0];
+    sg[768 + 3 * t + 1] = gs[1];
+    sg[768 + 3 * t + 2] = gs[2];
+    sg[1536 + 4 * t] = gq[0];
+    sg[1536 + 4 * t + 1] = gq[1];
+    sg[1536 + 4 * t + 2] = gq[2];
+    sg[1536 + 4 * t + 3] = gq[3];
+    sg[2560 + t] = go;
+    sg[2816 + 3 * t] = gc[0];
+    sg[2816 + 3 * t + 1] = gc[1];
+    sg[2816 + 3 * t + 2] = gc[2];
+    __syncthreads();
+    const int64_t k0 = (int64_t)blockIdx.x * blockDim.x;
+    const int nk = (int)min((int64_t)blockDim.x, a.n - k0);
+    const int width[5] = {3, 3, 4, 1, 3}, soff[5] = {0, 768, 1536, 2560, 2816};
+#pragma unroll
+    for (int grp = 0; grp < 5; ++grp) adam_range(a.adam, grp, k0 * width[grp], nk * width[grp], sg + soff[grp]);
   }
   if (k < a.n) {
     if (a.g_means) {
