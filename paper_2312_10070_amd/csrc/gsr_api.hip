@@ -95,8 +95,9 @@ struct gsr_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   std::vector<gsr_state*> pool;
-  uint32_t* h_K = nullptr;  // pinned host word for the overlap count
-  hipEvent_t k_ev = nullptr;  // recorded after the copy of the overlap count
+  uint32_t* h_K = nullptr;      // pinned host word for the overlap count
+  uint32_t* h_K_dev = nullptr;  // its device-side address (written by the scan kernel)
+  hipEvent_t k_ev = nullptr;  // recorded after the scan that writes the overlap count
   uint32_t* red = nullptr;  // grid-reduction scratch of the L1 loss
   uint32_t* track_temp = nullptr;
   unsigned long long* d_stats = nullptr;
@@ -311,7 +312,7 @@ gsr::BinArgs bin_args(gsr_state* s, int64_t cap) {
 
 // Projection, per-(tile, workgroup) pair counts and their scan (the overlap
 // count K lands in s->d_K).
-void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st) {
+void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st, uint32_t* K_host = nullptr) {
   const int64_t n_items = (int64_t)s->R.n_tiles * s->n_views;
   gsr::ProjectArgs pa{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
                       s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts, s->n_views};
@@ -323,7 +324,7 @@ void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st) {
     Stage t(c, "bin_count");
     s->n_wg = gsr::bin_workgroups(s->n);
     gsr::launch_bin_count(s->R, bin_args(s, 0), st);
-    gsr::launch_exclusive_scan(s->bin_M, s->bin_S, n_items * s->n_wg, s->d_K, s->scan_temp, st);
+    gsr::launch_exclusive_scan(s->bin_M, s->bin_S, n_items * s->n_wg, s->d_K, s->scan_temp, st, K_host);
   }
 }
 
@@ -450,6 +451,11 @@ int gsr_ctx_create(gsr_ctx** out, int device, void* hip_stream) {
     delete c;
     return GSR_ENOMEM;
   }
+  if (hipHostGetDevicePointer((void**)&c->h_K_dev, c->h_K, 0) != hipSuccess || !c->h_K_dev) {
+    (void)hipGetLastError();
+    gsr_ctx_destroy(c);
+    return GSR_EHIP;
+  }
   if (hipEventCreateWithFlags(&c->k_ev, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     gsr_ctx_destroy(c);
@@ -530,8 +536,9 @@ int gsr_render_fwd_batch(gsr_ctx* c, const gsr_gaussians* g, int32_t n_views, co
   s->n_views = n_views;
   s->blocks = blocks_per_cu * c->n_cu;
   hipStream_t st = c->stream;
-  enqueue_front(c, s, st);
-  GSR_HIP(c, hipMemcpyAsync(c->h_K, s->d_K, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  // the scan writes K straight into the pinned host word; the event's
+  // system-scope release makes it visible to the host
+  enqueue_front(c, s, st, c->h_K_dev);
   GSR_HIP(c, hipEventRecord(c->k_ev, st));
   // With a tile-list workspace from an earlier forward, the second half is
   // queued before the overlap count is known (positions beyond the capacity
@@ -540,7 +547,7 @@ int gsr_render_fwd_batch(gsr_ctx* c, const gsr_gaussians* g, int32_t n_views, co
   const bool speculative = s->arenaB != nullptr && s->K_cap > 0;
   if (speculative) enqueue_back(c, s, st, s->K_cap, color, depth, alpha);
   GSR_HIP(c, hipEventSynchronize(c->k_ev));
-  const int64_t K = (int64_t)*c->h_K;
+  const int64_t K = (int64_t)*static_cast<volatile uint32_t*>(c->h_K);
   s->K = K;
   if (!speculative || K > s->K_cap) {
     if (speculative) GSR_HIP(c, hipStreamSynchronize(st));  // before the workspace is replaced

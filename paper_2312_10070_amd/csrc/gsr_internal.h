@@ -219,11 +219,12 @@ struct ProjectArgs {
 };
 void launch_project(const Raster& R, const ProjectArgs& a, hipStream_t s);
 
-// Exclusive scan of n uint32 values; writes the total to *total (device).
+// Exclusive scan of n uint32 values; writes the total to *total (device) and,
+// if total_host is not NULL, to that device-visible pinned host word.
 // temp must hold scan_temp_words(n) uint32.
 int64_t scan_temp_words(int64_t n);
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* temp,
-                           hipStream_t s);
+                           hipStream_t s, uint32_t* total_host = nullptr);
 
 // Tile binning (see k_sort.hip). Workgroup w of view v handles the Gaussians
 // [w c, (w + 1) c) with c = ceil(n / n_wg); M[item][w] counts its pairs per

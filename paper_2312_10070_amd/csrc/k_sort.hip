@@ -60,9 +60,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// One workgroup scans all partials (exclusive, in place) and writes the total.
+// One workgroup scans all partials (exclusive, in place) and writes the total
+// (and, if total_host is set, the same word to pinned host memory).
 __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __restrict__ partials, int64_t np,
-                                                               uint32_t* __restrict__ total) {
+                                                               uint32_t* __restrict__ total,
+                                                               uint32_t* __restrict__ total_host) {
   __shared__ uint32_t s_wave[4];
   uint32_t carry = 0;
   for (int64_t b0 = 0; b0 < np; b0 += kScanTile) {
@@ -84,7 +86,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __rest
     carry += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *total = carry;
+  if (threadIdx.x == 0) {
+    *total = carry;
+    if (total_host) *total_host = carry;
+  }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
@@ -369,14 +374,15 @@ unsigned fill_blocks(int64_t n) {
 int64_t scan_temp_words(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* temp,
-                           hipStream_t s) {
+                           hipStream_t s, uint32_t* total_host) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   if (nb == 0) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, total, 0u, (int64_t)1);
+    if (total_host) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, total_host, 0u, (int64_t)1);
     return;
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, temp);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, temp, nb, total);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, temp, nb, total, total_host);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, (const uint32_t*)temp);
 }
 
