@@ -45,12 +45,13 @@ def stage_work(stage: str, st: dict, n: int, P: int) -> tuple[str, float]:
     if stage == "render_bwd":
         return "alu", FLOPS_EVAL * st["pairs_bwd"] + FLOPS_COMP_BWD * st["pairs_composited"]
     if stage == "bin_count":
-        # rectangles and counts read (20 B per Gaussian); the [tile][workgroup] matrix is written, scanned, read
-        return "hbm", n * 20.0 + st["tiles"] * 256 * 4.0 * 4
+        # packed rectangles read (16 B per Gaussian); the [tile][workgroup] matrix (128 workgroups) is
+        # written, scanned (read twice, written once) and read
+        return "hbm", n * 16.0 + st["tiles"] * 128 * 4.0 * 4
     if stage == "tile_bins":
-        # placement reads rect, count and depth (36 B per Gaussian) and writes an 8-B key per overlap;
-        # the per-tile sort reads the key and writes a 4-B id
-        return "hbm", n * 36.0 + K * (8.0 + 8.0 + 4.0)
+        # placement reads the packed rectangle with the depth (16 B per Gaussian) and writes an 8-B key per
+        # overlap; the per-tile sort reads the key and writes a 4-B id
+        return "hbm", n * 16.0 + K * (8.0 + 8.0 + 4.0)
     if stage == "project":
         return "hbm", n * (56.0 + 64.0 + 16.0)
     if stage == "project_bwd":

@@ -306,7 +306,7 @@ struct Stage {
 };
 
 gsr::BinArgs bin_args(gsr_state* s, int64_t cap) {
-  return gsr::BinArgs{s->n, s->n_views, s->n_wg, s->rect, s->counts, s->rec_rgbz, s->bin_M, s->bin_S,
+  return gsr::BinArgs{s->n, s->n_views, s->n_wg, s->rect, s->bin_M, s->bin_S,
                       cap, s->keys, s->d_overflow};
 }
 

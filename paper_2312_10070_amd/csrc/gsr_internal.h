@@ -213,7 +213,7 @@ struct ProjectArgs {
   float4* rec_uvab;
   float4* rec_cob;
   float4* rec_rgbz;
-  int4* rect;          // tile rectangle (tx0, ty0, tx1, ty1)
+  int4* rect;          // (tx0 | tx1 << 16, ty0 | ty1 << 16, depth bits, tiles); see BinArgs
   uint32_t* counts;    // tiles per Gaussian (0 = culled)
   int n_views;         // outputs are [n_views * n]; view v uses pose7 + 7 v
 };
@@ -229,13 +229,13 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_
 // Tile binning (see k_sort.hip). Workgroup w of view v handles the Gaussians
 // [w c, (w + 1) c) with c = ceil(n / n_wg); M[item][w] counts its pairs per
 // (view, tile) item and S = exclusive scan of M in (item, workgroup) order.
+// rect[o] = (tx0 | tx1 << 16, ty0 | ty1 << 16, float bits of the camera
+// depth, number of tiles; 0 = not binned): everything binning reads, 16 bytes.
 struct BinArgs {
   int64_t n;
   int n_views;
   int n_wg;                // workgroups per view
   const int4* rect;
-  const uint32_t* counts;
-  const float4* rec_rgbz;  // camera depth in .w
   uint32_t* M;             // [n_items][n_wg]
   uint32_t* S;             // [n_items][n_wg]
   int64_t cap;             // positions >= cap are dropped and flagged

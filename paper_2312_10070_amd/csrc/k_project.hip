@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_project(Raster Rr, ProjectArgs a) {
   const PoseF P = load_pose(a.pose7 + 7 * blockIdx.y);
   Geo g;
   uint32_t count = 0;
-  int4 rect = make_int4(0, 0, -1, -1);
+  int4 rect = make_int4(0, 0, 0, 0);  // packed tile rectangle, depth bits, tile count (0: not binned)
   if (project_geo(Rr, P, a.means, a.scales, a.quats, k, g)) {
     const float op = a.opacities[k];
     if (op >= Rr.amin && isfinite(op)) {
@@ -157,8 +157,10 @@ __global__ __launch_bounds__(256) void k_project(Raster Rr, ProjectArgs a) {
         const float fy0 = fmaxf(0.f, ceilf(ey0)), fy1 = fminf((float)(Rr.H - 1), floorf(ey1));
         if (fx0 <= fx1 && fy0 <= fy1) {
           const int px0 = (int)fx0, px1 = (int)fx1, py0 = (int)fy0, py1 = (int)fy1;
-          rect = make_int4(px0 >> Rr.tw_log2, py0 / Rr.th, px1 >> Rr.tw_log2, py1 / Rr.th);
-          count = (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1));
+          const int tx0 = px0 >> Rr.tw_log2, ty0 = py0 / Rr.th, tx1 = px1 >> Rr.tw_log2, ty1 = py1 / Rr.th;
+          count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+          rect = make_int4((int)((uint32_t)tx0 | ((uint32_t)tx1 << 16)), (int)((uint32_t)ty0 | ((uint32_t)ty1 << 16)),
+                           (int)__float_as_uint(g.x[2]), (int)count);
           const float s = -0.5f * kLog2e;
           a.rec_uvab[kRec * o] = make_float4(g.u, g.v, s * ca, -kLog2e * cb);
           a.rec_cob[kRec * o] = make_float4(s * cc, op, __uint_as_float((uint32_t)px0 | ((uint32_t)px1 << 16)),

@@ -146,10 +146,11 @@ __global__ __launch_bounds__(kPlaceThreads) void k_bin_count(Raster Rr, BinArgs 
   __syncthreads();
   for (int64_t g = c.g0 + threadIdx.x; g < c.g1; g += blockDim.x) {
     const int64_t o = view * a.n + g;
-    if (a.counts[o] == 0) continue;
     const int4 r = a.rect[o];
-    for (int ty = r.y; ty <= r.w; ++ty)
-      for (int tx = r.x; tx <= r.z; ++tx) {
+    if (r.w == 0) continue;
+    const int tx0 = r.x & 0xffff, tx1 = (int)((uint32_t)r.x >> 16), ty0 = r.y & 0xffff, ty1 = (int)((uint32_t)r.y >> 16);
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) {
         const int t = ty * Rr.ntx + tx - c.t0;
         if ((unsigned)t < (unsigned)c.nt) atomicAdd(&hist[t], 1u);
       }
@@ -180,11 +181,12 @@ __global__ __launch_bounds__(kPlaceThreads) void k_bin_place(Raster Rr, BinArgs 
   __syncthreads();
   for (int64_t g = c.g0 + threadIdx.x; g < c.g1; g += blockDim.x) {
     const int64_t o = view * a.n + g;
-    if (a.counts[o] == 0) continue;
     const int4 r = a.rect[o];
-    const uint64_t key = ((uint64_t)__float_as_uint(a.rec_rgbz[kRec * o].w) << 32) | (uint64_t)(uint32_t)o;
-    for (int ty = r.y; ty <= r.w; ++ty)
-      for (int tx = r.x; tx <= r.z; ++tx) {
+    if (r.w == 0) continue;
+    const uint64_t key = ((uint64_t)(uint32_t)r.z << 32) | (uint64_t)(uint32_t)o;
+    const int tx0 = r.x & 0xffff, tx1 = (int)((uint32_t)r.x >> 16), ty0 = r.y & 0xffff, ty1 = (int)((uint32_t)r.y >> 16);
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) {
         const int t = ty * Rr.ntx + tx - c.t0;
         if ((unsigned)t >= (unsigned)c.nt) continue;
         const uint32_t pos = atomicAdd(&next[t], 1u);
