@@ -261,31 +261,33 @@ __device__ void merge_runs(const uint64_t* a, int na, const uint64_t* b, int nb,
   }
 }
 
-// Keys a single wave sorts in registers (8 per lane).
-constexpr int kWaveSort = 512;
+// Keys a single wave sorts in registers (up to 32 per lane).
+constexpr int kWaveSort = 2048;
 
-// Sorts keys[b, b + len) (0 < len <= kWaveSort) with one wave: lane l holds
-// elements 8 l .. 8 l + 7 in registers; a bitonic network whose strides below
-// 8 are compare-exchanges inside a lane and whose larger strides exchange with
-// lane l ^ (stride / 8). Writes the low words (record indices) to ids.
+// Sorts keys[b, b + len) (0 < len <= 64 E) with one wave: lane l holds
+// elements E l .. E l + E - 1 in registers; a bitonic network whose strides
+// below E are compare-exchanges inside a lane and whose larger strides
+// exchange with lane l ^ (stride / E). Writes the low words (record indices)
+// to ids.
+template <int E>
 __device__ void wave_sort(const uint64_t* __restrict__ keys, int64_t b, int len, uint32_t* __restrict__ ids) {
   const int lane = threadIdx.x & 63;
-  uint64_t e[8];
+  uint64_t e[E];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int i = 8 * lane + r;
+  for (int r = 0; r < E; ++r) {
+    const int i = E * lane + r;
     e[r] = i < len ? keys[b + i] : ~0ull;  // padding sorts last (keys hold finite depths)
   }
 #pragma unroll
-  for (int k = 2; k <= kWaveSort; k <<= 1) {
+  for (int k = 2; k <= 64 * E; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j >= 8) {
-        const int m = j >> 3;
+      if (j >= E) {
+        const int m = j / E;
         const bool upper = (lane & m) != 0;  // this lane holds the larger position of each pair
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const bool asc = ((8 * lane + r) & k) == 0;
+        for (int r = 0; r < E; ++r) {
+          const bool asc = ((E * lane + r) & k) == 0;
           const uint64_t p = __shfl_xor(e[r], m, 64);
           // the lower position keeps the minimum of an ascending block, the upper the maximum
           const bool keep_min = asc != upper;
@@ -293,9 +295,9 @@ __device__ void wave_sort(const uint64_t* __restrict__ keys, int64_t b, int len,
         }
       } else {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < E; ++r) {
           if ((r & j) == 0) {
-            const bool asc = ((8 * lane + r) & k) == 0;
+            const bool asc = ((E * lane + r) & k) == 0;
             const uint64_t x = e[r], y = e[r | j];
             const bool sw = (x > y) == asc;
             e[r] = sw ? y : x;
@@ -306,15 +308,16 @@ __device__ void wave_sort(const uint64_t* __restrict__ keys, int64_t b, int len,
     }
   }
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int i = 8 * lane + r;
+  for (int r = 0; r < E; ++r) {
+    const int i = E * lane + r;
     if (i < len) ids[b + i] = (uint32_t)e[r];
   }
 }
 
 // Four (view, tile) items per workgroup. Each wave sorts one item of at most
-// kWaveSort keys in registers; longer items are then sorted by the whole
-// workgroup through LDS (runs of kSortCap merged pairwise in global memory).
+// kWaveSort keys in registers (the smallest of the 512 / 1024 / 2048-key
+// networks that holds it); longer items are then sorted by the whole
+// workgroup (LDS runs of kSortCap merged pairwise in global memory).
 __global__ __launch_bounds__(kBinThreads) void k_tile_sort(const int2* __restrict__ ranges, int64_t n_items,
                                                           uint64_t* __restrict__ keys, uint64_t* __restrict__ scratch,
                                                           uint32_t* __restrict__ ids) {
@@ -325,17 +328,19 @@ __global__ __launch_bounds__(kBinThreads) void k_tile_sort(const int2* __restric
   if (item0 + w < n_items) {
     const int2 rg = ranges[item0 + w];
     const int len = rg.y - rg.x;
-    if (len > 0 && len <= kWaveSort) wave_sort(keys, rg.x, len, ids);
+    if (len > 0 && len <= 512) {
+      wave_sort<8>(keys, rg.x, len, ids);
+    } else if (len > 512 && len <= 1024) {
+      wave_sort<16>(keys, rg.x, len, ids);
+    } else if (len > 1024 && len <= kWaveSort) {
+      wave_sort<32>(keys, rg.x, len, ids);
+    }
   }
   for (int it = 0; it < kItems && item0 + it < n_items; ++it) {
     const int2 rg = ranges[item0 + it];
     const int64_t b = rg.x;
     const int len = rg.y - rg.x;
     if (len <= kWaveSort) continue;  // uniform across the workgroup
-    if (len <= kSortCap) {
-      sort_run(keys, b, len, s, nullptr, ids);
-      continue;
-    }
     // long range: sorted runs of kSortCap, then pairwise merges (ping-pong)
     for (int c0 = 0; c0 < len; c0 += kSortCap) sort_run(keys, b + c0, min(kSortCap, len - c0), s, keys, nullptr);
     uint64_t* src = keys + b;
