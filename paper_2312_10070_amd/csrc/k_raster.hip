@@ -489,12 +489,27 @@ __global__ __launch_bounds__(kTileThreads) void k_count_bwd_pairs(Raster Rr, Fwd
 
 // Longest-list-first item order: bucket items by floor(log2(len + 1)) and
 // emit the buckets from the longest down (order inside a bucket is arbitrary).
+// Each wave aggregates its items per bucket (one leader lane per distinct
+// bucket), so the 32 global counters see one atomic per (wave, bucket)
+// instead of one per item.
+__device__ __forceinline__ int order_bucket(const int2* __restrict__ ranges, int i) {
+  const int2 r = ranges[i];
+  return 31 - __clz(r.y - r.x + 1);
+}
+
 __global__ void k_order_hist(const int2* __restrict__ ranges, int n_items, int* __restrict__ temp) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_items) return;
-  const int2 r = ranges[i];
-  const int b = 31 - __clz(r.y - r.x + 1);
-  atomicAdd(&temp[b], 1);
+  const int lane = threadIdx.x & 63;
+  const bool valid = i < n_items;
+  const int b = valid ? order_bucket(ranges, i) : -1;
+  uint64_t remaining = __ballot(valid);
+  while (remaining) {
+    const int leader = __builtin_ctzll(remaining);
+    const int lb = __shfl(b, leader, 64);
+    const uint64_t same = __ballot(valid && b == lb);
+    if (lane == leader) atomicAdd(&temp[lb], __popcll(same));
+    remaining &= ~same;
+  }
 }
 
 __global__ void k_order_scan(int* temp) {
@@ -510,11 +525,23 @@ __global__ void k_order_scan(int* temp) {
 __global__ void k_order_scatter(const int2* __restrict__ ranges, int n_items, int* __restrict__ temp,
                                 int* __restrict__ order) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_items) return;
-  const int2 r = ranges[i];
-  const int b = 31 - __clz(r.y - r.x + 1);
-  const int pos = atomicAdd(&temp[32 + b], 1);
-  order[pos] = i;
+  const int lane = threadIdx.x & 63;
+  const bool valid = i < n_items;
+  const int b = valid ? order_bucket(ranges, i) : -1;
+  uint64_t remaining = __ballot(valid);
+  while (remaining) {
+    const int leader = __builtin_ctzll(remaining);
+    const int lb = __shfl(b, leader, 64);
+    const uint64_t same = __ballot(valid && b == lb);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&temp[32 + lb], __popcll(same));
+    base = __shfl(base, leader, 64);
+    if (valid && b == lb) {
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+      order[base + rank] = i;
+    }
+    remaining &= ~same;
+  }
 }
 
 }  // namespace

@@ -218,6 +218,27 @@ def test_tile_ranges_longer_than_lds_are_merged():
     G.compare_images(out, oracle.render(g, pose, cam, opts), TOL, max_unverifiable=0.06)
 
 
+def test_register_sorts_of_long_tile_lists():
+    """Tile lists of 513..1024 and 1025..2048 keys, sorted by one wave in
+    registers (16 and 32 keys per lane): bit-exact, including depth ties."""
+    rng = np.random.default_rng(12)
+    n = 1500
+    g = dict(means=np.stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.25, 0.25, n), rng.uniform(2, 6, n)], 1),
+             scales=np.exp(rng.normal(-2.2, 0.3, (n, 3))), quats=rng.normal(size=(n, 4)),
+             opacities=rng.uniform(0.2, 0.9, n), colors=rng.uniform(0, 1, (n, 3)))
+    g["means"][50:150, 2] = 3.0  # exact depth ties: order by index
+    cam = oracle.Camera(48, 40, 40.0, 40.0, 24.0, 20.0)
+    pose = np.array([1, 0, 0, 0, 0, 0, 0], np.float64)
+    g = G.certify(g, pose, cam, 1e-4)
+    tl = oracle.tile_lists(g, pose, cam, oracle.Opts())
+    lens = tl["ranges"][:, 1] - tl["ranges"][:, 0]
+    assert ((lens > 512) & (lens <= 1024)).any() and ((lens > 1024) & (lens <= 2048)).any(), lens
+    _, st, _, _ = run_fwd(g, pose, cam)
+    K, ranges, ids = gsr.tile_lists(st, tl["ranges"].shape[0])
+    assert K == tl["K"]
+    G.compare_tile_lists(ranges.cpu().numpy(), ids.cpu().numpy(), tl, None)
+
+
 def test_workspace_growth_between_calls():
     """A forward whose overlap count exceeds the tile-list workspace left by the
     previous forward on the same (reused) state: the speculatively queued
