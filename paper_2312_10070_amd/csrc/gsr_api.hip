@@ -202,6 +202,10 @@ int ensure_A(gsr_ctx* c, gsr_state* s, int64_t n, int64_t P, int64_t tiles, int6
   }
   s->arenaA = p;
   carve_A(s, (char*)p, nn, PP, tt, vv, nm, &bytes);
+  // The per-Gaussian backward sums start at zero and every backward leaves them
+  // at zero (the projection backward clears what it reads), so they are
+  // cleared only here, when the workspace is allocated.
+  gsr::launch_fill_f32(s->g2d, 0.f, 10 * nn, c->stream);
   s->bin_cap = nm;
   s->n_cap = nn;
   s->P_cap = PP;
@@ -354,10 +358,8 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
   const gsr::Raster& R = s->R;
   const bool want_pose = dpose7 || dtwist6;
   const int n_items = R.n_tiles * s->n_views;
-  {
-    Stage t(c, "fill");
-    gsr::launch_fill_f32(s->g2d, 0.f, 10 * s->n * s->n_views, st);
-  }
+  // s->g2d is zero here: cleared when allocated, and each projection backward
+  // clears the sums it reads
   const bool geom_only = !adam && (!grads || (!grads->opacities && !grads->colors));
   gsr::BwdArgs ba{s->ranges, s->ids, s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
                   gC, gD, gA, s->g2d, geom_only, n_items, s->queue, s->blocks > 0 ? s->order : nullptr, s->blocks};

@@ -300,7 +300,7 @@ struct ProjectBwdArgs {
   const float *means, *scales, *quats, *opacities, *colors;
   const float* pose7;
   const uint32_t* counts;
-  const float* g2d;
+  float* g2d;  // read, then cleared (zero again for the next backward)
   float *g_means, *g_scales, *g_quats, *g_opacities, *g_colors;  // may be NULL; summed over views
   float* pose_acc;  // [n_views][blocks][12] per-workgroup dL/dR_p (9, row-major), dL/dt (3); NULL = skip
   int n_views;

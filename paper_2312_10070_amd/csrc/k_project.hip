@@ -348,7 +348,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a
 #pragma unroll
     for (int i = 0; i < 12; ++i) pacc[i] = 0.f;
     const int64_t o = (int64_t)v * a.n + k;
-    if (k < a.n && a.counts[o] > 0) chain_one(Rr, P, a, k, a.g2d + 10 * o, gm, gs, gq, go, gc, pacc);
+    if (k < a.n && a.counts[o] > 0) {
+      float* g2 = a.g2d + 10 * o;
+      chain_one(Rr, P, a, k, g2, gm, gs, gq, go, gc, pacc);
+      // leave the sums at zero for the next backward (the compositing backward
+      // only adds to Gaussians with tiles, i.e. the ones cleared here)
+#pragma unroll
+      for (int i = 0; i < 10; ++i) g2[i] = 0.f;
+    }
     if (a.pose_acc) {
 #pragma unroll
       for (int i = 0; i < 12; ++i) {
