@@ -53,12 +53,15 @@ def stage_work(stage: str, st: dict, n: int, P: int) -> tuple[str, float]:
         # overlap; the per-tile sort reads the key and writes a 4-B id
         return "hbm", n * 16.0 + K * (8.0 + 8.0 + 4.0)
     if stage == "project":
-        return "hbm", n * (56.0 + 64.0 + 16.0)
+        # parameters read; the 64-byte record slot, the packed rectangle word and the tile count written
+        return "hbm", n * (56.0 + 64.0 + 16.0 + 4.0)
     if stage == "project_bwd":
-        return "hbm", n * (56.0 + 40.0 + 56.0)
+        # parameters and the ten sums read, gradients written, the sums cleared
+        return "hbm", n * (56.0 + 40.0 + 56.0 + 40.0)
     if stage == "project_bwd_adam":
-        # ten partial sums and the parameters read, Adam moments read and written, parameters written
-        return "hbm", n * (40.0 + 56.0 + 4 * 56.0 + 56.0)
+        # ten partial sums and the parameters read, Adam moments read and written, parameters written,
+        # the sums cleared
+        return "hbm", n * (40.0 + 56.0 + 4 * 56.0 + 56.0 + 40.0)
     if stage == "adam":
         return "hbm", 28.0 * 14 * n  # all 14 n parameters in one launch
     if stage == "loss_l1":
