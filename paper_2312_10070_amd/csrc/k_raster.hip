@@ -7,9 +7,10 @@
 // has alpha < alpha_min.
 //
 // Forward: front to back (Eq. 3 colour, Eq. 4 alpha, Eq. 6 depth), batches of
-// 512 records. Each wave tests, 64 records at a time, which records can reach
-// alpha >= alpha_min in its block (support box, then an exact
-// ellipse-versus-rectangle test) and in which of its quadrants (support box),
+// 448 records (the largest that keeps six workgroups per CU in LDS). Each
+// wave tests, 64 records at a time, which records can reach alpha >=
+// alpha_min in its block (support box, then an exact ellipse-versus-rectangle
+// test) and in which of its quadrants (support box),
 // and appends their LDS offsets to one visit list per quadrant. The four rows
 // of the wave then walk their own lists side by side, each lane reading its
 // row's record from LDS, so a record is visited only by the quadrants it can
@@ -20,7 +21,7 @@
 // workgroup stops fetching batches once all four waves have.
 //
 // Backward: back to front from each pixel's last composited Gaussian, batches
-// of 256 records, one visit list per wave (records reaching the 8x8 block,
+// of 512 records, one visit list per wave (records reaching the 8x8 block,
 // walked with the record broadcast from LDS). The transmittance in front of
 // Gaussian j is recomputed as T_j = T_{j+1} / (1 - alpha_j) instead of being
 // stored; suffix sums of c alpha T and z alpha T give the second terms of
@@ -46,10 +47,11 @@ namespace {
 // quadrant's visit list, and the LDS slot of an all-zero record (u = v = 0,
 // zero conic, o = 0: alpha = 0 at every pixel), which a row reads once its
 // list has ended.
-constexpr int kFwdBatch = 512;
+constexpr int kFwdBatch = 448;
+constexpr int kBwdBatch = 512;
 constexpr int kListCap = 128;
 constexpr int kWavesPerTile = kTileThreads / kWave;
-static_assert(kFwdBatch % kWave == 0 && kListCap >= kWave, "batch / list shape");
+static_assert(kFwdBatch % kWave == 0 && kBwdBatch % kWave == 0 && kListCap >= kWave, "batch / list shape");
 
 struct Block {
   int x0, x1, y0, y1;  // inclusive pixel rectangle of a wave (8x8)
@@ -176,10 +178,11 @@ struct FwdSmem {
 };
 
 struct BwdSmem {
-  float4 uvab[kTileThreads];
-  float4 cob[kTileThreads];
-  float4 rgbz[kTileThreads];
-  uint32_t gid[kTileThreads];
+  static constexpr int kBatch = kBwdBatch;
+  float4 uvab[kBatch];
+  float4 cob[kBatch];
+  float4 rgbz[kBatch];
+  uint32_t gid[kBatch];
   int max_last;
 };
 
@@ -349,16 +352,20 @@ __device__ __forceinline__ void bwd_item(const Raster& Rr, const BwdArgs& a, int
   const int bmax = sm.max_last;
   const int start = a.ranges[item].x;
 
-  for (int bend = start + bmax; bend > start; bend -= kTileThreads) {
-    const int bstart = max(start, bend - kTileThreads);
+  constexpr int kBatch = BwdSmem::kBatch;
+  for (int bend = start + bmax; bend > start; bend -= kBatch) {
+    const int bstart = max(start, bend - kBatch);
     __syncthreads();
-    const int i = bstart + tid;
-    if (i < bend) {
-      const uint32_t gid = a.ids[i];
-      sm.gid[tid] = gid;
-      sm.uvab[tid] = a.rec_uvab[kRec * gid];
-      sm.cob[tid] = a.rec_cob[kRec * gid];
-      sm.rgbz[tid] = a.rec_rgbz[kRec * gid];
+#pragma unroll
+    for (int h = 0; h < (kBatch + kTileThreads - 1) / kTileThreads; ++h) {
+      const int sl = h * kTileThreads + tid, i = bstart + sl;
+      if (sl < kBatch && i < bend) {
+        const uint32_t gid = a.ids[i];
+        sm.gid[sl] = gid;
+        sm.uvab[sl] = a.rec_uvab[kRec * gid];
+        sm.cob[sl] = a.rec_cob[kRec * gid];
+        sm.rgbz[sl] = a.rec_rgbz[kRec * gid];
+      }
     }
     __syncthreads();
     const int cnt = min(bend, start + wmax) - bstart;  // records this wave may need
