@@ -410,3 +410,35 @@ def test_backward_fused_with_adam_matches_separate_calls():
             np.testing.assert_allclose(fus[k][0], sep[k][0], rtol=1e-6, atol=1e-7, err_msg=k)
             np.testing.assert_allclose(fus[k][1], sep[k][1], rtol=1e-4, atol=1e-12, err_msg=k)
             np.testing.assert_allclose(fus[k][2], sep[k][2], rtol=1e-4, atol=1e-15, err_msg=k)
+
+
+def test_backward_fused_with_adam_rejects_other_parameters():
+    """gsr_render_bwd_adam checks that the Adam parameters are the tensors the
+    forward read (GSR_EINVAL otherwise) and that the step count is 1-based."""
+    import ctypes
+    torch = torch_()
+    g, _, pose, cam = G.c1_case(0)
+    out, st, d, pose_d = run_fwd(g, pose, cam)
+    gC = torch.full((3, cam.height, cam.width), 1e-3, device="cuda")
+    gD = torch.full((cam.height, cam.width), 1e-3, device="cuda")
+    m = {k: torch.zeros_like(d[k]) for k in gsr.PARAM_GROUPS}
+    v = {k: torch.zeros_like(d[k]) for k in gsr.PARAM_GROUPS}
+    other = d["means"].clone()
+    a = gsr.Adam5()
+    for i, k in enumerate(gsr.PARAM_GROUPS):
+        a.params[i] = (other if k == "means" else st.keep[i]).data_ptr()
+        a.exp_avg[i] = m[k].data_ptr()
+        a.exp_avg_sq[i] = v[k].data_ptr()
+        a.lr[i] = 1e-3
+    a.step, a.beta1, a.beta2, a.eps = 1, 0.9, 0.999, 1e-8
+    lib, h = st.ctx.lib, st.ctx.h
+    rc = lib.gsr_render_bwd_adam(h, st.h, ctypes.c_void_p(gC.data_ptr()), ctypes.c_void_p(gD.data_ptr()), None,
+                                 ctypes.byref(a))
+    assert rc != 0
+    a.params[0] = st.keep[0].data_ptr()
+    a.step = 0
+    rc = lib.gsr_render_bwd_adam(h, st.h, ctypes.c_void_p(gC.data_ptr()), ctypes.c_void_p(gD.data_ptr()), None,
+                                 ctypes.byref(a))
+    assert rc != 0
+    torch.cuda.synchronize()
+    st.release()
