@@ -3,15 +3,16 @@
 // 16-lane row of a wave (one DPP row) a 4x4 quadrant of that block. Gaussian
 // records of the item's depth-sorted list are staged through LDS in batches
 // (one coalesced fetch per record per workgroup). Skipping a record for a
-// block or quadrant cannot change the result: outside its support a Gaussian
-// has alpha < alpha_min.
+// block or quadrant cannot change the result: outside its support box (taken
+// with a small slack) a Gaussian's alpha stays below alpha_min by more than
+// FP32 rounding, and the ellipse test keeps a margin too.
 //
 // Forward: front to back (Eq. 3 colour, Eq. 4 alpha, Eq. 6 depth), batches of
 // 448 records (the largest that keeps six workgroups per CU in LDS). Each
 // wave tests, 64 records at a time, which records can reach alpha >=
 // alpha_min in its block (support box, then an exact ellipse-versus-rectangle
-// test) and in which of its quadrants (support box),
-// and appends their LDS offsets to one visit list per quadrant. The four rows
+// test) and in which of its quadrants (support box), and appends their LDS
+// offsets to one visit list per quadrant. The four rows
 // of the wave then walk their own lists side by side, each lane reading its
 // row's record from LDS, so a record is visited only by the quadrants it can
 // reach; a row whose list has ended reads an all-zero record (alpha = 0). A
@@ -154,13 +155,11 @@ __device__ __forceinline__ bool box_holds(float fbx, float fby, int px, int py) 
 }
 
 // Lanes whose bit is set in the wave-uniform mask m append `val` to `list`
-// after its first `len` entries: in lane order (ascending) or in reverse lane
-// order (descending).
-template <bool DESCENDING>
+// after its first `len` entries, in lane order.
 __device__ __forceinline__ void list_append(uint16_t* list, int len, uint64_t m, int lane, int val) {
   if ((m >> lane) & 1ull) {
     const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    list[len + (DESCENDING ? __popcll(m) - 1 - below : below)] = (uint16_t)val;
+    list[len + below] = (uint16_t)val;
   }
 }
 
@@ -245,10 +244,10 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
         const int c0 = __popcll(m0), c1 = __popcll(m1), c2 = __popcll(m2), c3 = __popcll(m3);
         if (len0 + c0 > kListCap || len1 + c1 > kListCap || len2 + c2 > kListCap || len3 + c3 > kListCap) break;
         // entries are LDS byte offsets of the slot inside each record array
-        list_append<false>(sm.list[w][0], len0, m0, lane, 16 * r);
-        list_append<false>(sm.list[w][1], len1, m1, lane, 16 * r);
-        list_append<false>(sm.list[w][2], len2, m2, lane, 16 * r);
-        list_append<false>(sm.list[w][3], len3, m3, lane, 16 * r);
+        list_append(sm.list[w][0], len0, m0, lane, 16 * r);
+        list_append(sm.list[w][1], len1, m1, lane, 16 * r);
+        list_append(sm.list[w][2], len2, m2, lane, 16 * r);
+        list_append(sm.list[w][3], len3, m3, lane, 16 * r);
         len0 += c0;
         len1 += c1;
         len2 += c2;
