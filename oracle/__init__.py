@@ -4,7 +4,7 @@ Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. It shares no code with the HIP library
 (``paper_2312_10070_amd``) and never imports it.
 
-The native part (``gsr_oracle.cpp``, ``cnn_oracle.cpp``) is plain C++17 in
+The native part (``gsr_oracle.cpp``, ``cnn_oracle.cpp``, ``ssim_oracle.cpp``) is plain C++17 in
 double precision; :func:`build` compiles it with g++ into ``liboracle.so``
 beside the sources. Every function here only marshals numpy arrays.
 """
@@ -18,7 +18,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SOURCES = ["gsr_oracle.cpp", "cnn_oracle.cpp"]
+_SOURCES = ["gsr_oracle.cpp", "cnn_oracle.cpp", "ssim_oracle.cpp"]
 _LIB_PATH = os.environ.get("GSR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -62,6 +62,8 @@ def _load():
     lib.orc_pose_apply_twist.argtypes = [P, P, P]
     if hasattr(lib, "orc_conv2d_fwd"):
         _bind_cnn(lib)
+    if hasattr(lib, "orc_ssim"):
+        lib.orc_ssim.argtypes = [ctypes.c_int] * 3 + [P] * 5
     _lib = lib
     return lib
 
@@ -225,6 +227,21 @@ def loss_track(C, D, A, Ct, Dt, lambda_c=0.5, inlier_mult=50.0):
     lib.orc_loss_track(P, _p(C), _p(D), _p(A), _p(Ct), _p(Dt), lambda_c, inlier_mult, _p(loss), _p(gC),
                        _p(gD), _p(med), _p(ni))
     return dict(loss=float(loss[0]), gC=gC, gD=gD, median=float(med[0]), n_inlier=int(ni[0]))
+
+
+def ssim(X, Y, want_grad: bool = True):
+    """SSIM(X, Y) of Eq. 10 (Wang et al.'s 11x11 Gaussian window, sigma 1.5,
+    zero padding, C1 = 1e-4, C2 = 9e-4) on [C, H, W] images.
+    Returns (mean, map[C,H,W], d mean / d X or None)."""
+    lib = _load()
+    X = _d(X); Y = _d(Y)
+    assert X.shape == Y.shape and X.ndim == 3
+    Cc, Hh, Ww = X.shape
+    mp = np.zeros(X.shape); mean = np.zeros(1)
+    g = np.zeros(X.shape) if want_grad else None
+    rc = lib.orc_ssim(Cc, Hh, Ww, _p(X), _p(Y), _p(mp), _p(mean), _p(g))
+    assert rc == 0
+    return float(mean[0]), mp, g
 
 
 def adam(param, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
