@@ -9,7 +9,10 @@ L1 depth loss, the hand-written backward to every Gaussian parameter, and Adam
 on all 14 N parameters. `value` is iterations per second with all inputs
 resident in HBM. Prints ONE JSON line (rank 0) with a roofline entry for the
 dominant kernel (stage times from HIP events inside the timed region) and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+FP64 CPU oracle timed on a bounded sample of the same workload. A second
+timed loop runs the same iteration with the paper's full colour loss (Eq. 10:
+L1 and SSIM, lambda = 0.2) and reports it, and the SSIM kernel's roofline,
+beside the headline.
 """
 from __future__ import annotations
 
@@ -34,6 +37,11 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (256 CU x 2.4 GHz, packed FMA)
 FLOPS_EVAL = 15      # offset, quadratic form, exp2, opacity, clamp and skip tests
 FLOPS_COMP_FWD = 12  # transmittance update, stop test, colour + depth accumulation
 FLOPS_COMP_BWD = 48  # T recovery, dC/dalpha, dD/dalpha (Eq. 8), dA/dalpha, suffix sums, 10 partials
+# Algorithmic FP32 operations of the SSIM term per (pixel, channel): the products x^2, y^2, xy (3), five
+# moments by two 11-tap passes (220), SSIM and its partials (30), three partial maps by two 11-tap passes
+# (132) and the gradient (7).
+FLOPS_SSIM = 390
+SSIM_LAMBDA = 0.2  # Eq. 10
 
 
 def stage_work(stage: str, st: dict, n: int, P: int) -> tuple[str, float]:
@@ -66,6 +74,8 @@ def stage_work(stage: str, st: dict, n: int, P: int) -> tuple[str, float]:
         return "hbm", 28.0 * 14 * n  # all 14 n parameters in one launch
     if stage == "loss_l1":
         return "hbm", P * 8 * 4.0 * 2
+    if stage == "loss_ssim":
+        return "alu", FLOPS_SSIM * 3.0 * P
     return "hbm", 0.0
 
 
@@ -81,7 +91,8 @@ STAGE_SOURCES = {"render_fwd": ["k_raster.hip", "gsr_internal.h"], "render_bwd":
                  "adam": ["k_loss.hip"], "loss_l1": ["k_loss.hip"],
                  "tile_bins": ["k_sort.hip"], "bin_count": ["k_sort.hip"], "project": ["k_project.hip", "gsr_internal.h"],
                  "project_bwd": ["k_project.hip", "gsr_internal.h"],
-                 "project_bwd_adam": ["k_project.hip", "gsr_internal.h"]}
+                 "project_bwd_adam": ["k_project.hip", "gsr_internal.h"],
+                 "loss_ssim": ["k_loss.hip", "gsr_internal.h"]}
 
 
 def read_traffic(stage: str, workload: str):
@@ -107,7 +118,8 @@ def read_traffic(stage: str, workload: str):
 STAGE_KERNELS = {"render_bwd": ["k_render_bwd<false>("], "render_fwd": ["k_render_fwd<false>("],
                  "tile_bins": ["k_tile_init(", "k_bin_place(", "k_tile_sort("],
                  "bin_count": ["k_bin_count(", "k_scan_reduce(", "k_scan_partials(", "k_scan_down("],
-                 "project": ["k_project("], "project_bwd_adam": ["k_project_bwd("]}
+                 "project": ["k_project("], "project_bwd_adam": ["k_project_bwd("],
+                 "loss_ssim": ["k_loss_ssim("]}
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {counter} -d <dir> -o run --output-format csv -- python3 bench.py "
                "--steps 5 --warmup 2 --no-cpu-baseline --no-tracking --no-batched --no-initnet --calib-copy-mib {mib}")
 
@@ -414,6 +426,7 @@ def main() -> int:
     ap.add_argument("--gaussians", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows-every", type=int, default=68)
+    ap.add_argument("--no-ssim", action="store_true", help="skip the loop with the full Eq. 10 colour loss")
     ap.add_argument("--no-tracking", action="store_true")
     ap.add_argument("--tracking-frames", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
@@ -460,10 +473,13 @@ def main() -> int:
     opts = gsr.RasterOpts()
     step_no = [0]
 
-    def step():
+    def step(lam: float = 0.0):
         color, depth, alpha, st = gsr.render_fwd(params["means"], params["scales"], params["quats"],
                                                  params["opacities"], params["colors"], pose, camera, opts)
-        loss, gC, gD = gsr.loss_l1(color, depth, tgt_c, tgt_d)
+        if lam:
+            loss, gC, gD = gsr.loss_map(color, depth, tgt_c, tgt_d, lam=lam)
+        else:
+            loss, gC, gD = gsr.loss_l1(color, depth, tgt_c, tgt_d)
         step_no[0] += 1
         # backward with the Adam step on all parameters fused into its last kernel
         gsr.render_bwd_adam(st, gC, gD, adam_m, adam_v, lrs, step_no[0])
@@ -524,6 +540,35 @@ def main() -> int:
     roof["kernel"] = dom
     roof["avg_ms"] = round(avg_ms, 4)
 
+    ssim = None
+    if not args.no_ssim:
+        # the same iteration with the full colour loss of Eq. 10 (after the headline's timed region)
+        k = max(5, min(args.steps, 20))
+        for _ in range(2):
+            step(SSIM_LAMBDA)
+        torch.cuda.synchronize()
+        gsr.profile_read()
+        gsr.profile_only("loss_ssim")
+        gsr.profile_enable(True)
+        e0.record()
+        for _ in range(k):
+            loss_s = step(SSIM_LAMBDA)
+        e1.record()
+        torch.cuda.synchronize()
+        gsr.profile_enable(False)
+        gsr.profile_only(None)
+        rec = gsr.profile_read()["loss_ssim"]
+        ms_s = e0.elapsed_time(e1) / k
+        ssim_ms = rec[0] / rec[1]
+        _, w_ssim = stage_work("loss_ssim", stats, n, P)
+        ach = w_ssim / (ssim_ms * 1e-3) / 1e12
+        ssim = {"workload": f"mapping iteration with the Eq. 10 colour loss (L1 + SSIM, lambda {SSIM_LAMBDA})",
+                "steps": k, "ms_per_step": round(ms_s, 4), "it_per_s": round(1000.0 / ms_s, 3),
+                "loss_ssim_ms": round(ssim_ms, 4), "loss": float(loss_s.item()),
+                "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": read_traffic("loss_ssim", "H"),
+                             "kernel": "loss_ssim", "avg_ms": round(ssim_ms, 4)}}
+
     if args.calib_copy_mib > 0:
         nbytes = args.calib_copy_mib << 20
         a = torch.empty(nbytes // 4, device=dev, dtype=torch.float32).fill_(1.0)
@@ -570,6 +615,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: round(v[0] / n_stage_steps, 4) for k, v in sorted(stage_pass.items())},
         "work": stats,
+        "mapping_full_colour_loss": ssim,
         "tracking": track,
         "batched_mapping": batched,
         "learned_init": learned,

@@ -6,9 +6,9 @@
  * 2312.10070): projection of Gaussians (Sec. 3.1, Eq. 1) with the EWA 2D
  * covariance (Eq. 2), front-to-back alpha compositing of colour (Eq. 3, 4)
  * and depth (Eq. 6), their explicit gradients (Sec. 3.3, Eq. 7-8 and the
- * colour/opacity/covariance analogues), the L1 mapping losses (Eq. 9, Eq. 10
- * without SSIM) and the masked tracking loss (Eq. 15) with the pose gradient
- * the tracking optimisation (Eq. 14) needs.
+ * colour/opacity/covariance analogues), the mapping losses (Eq. 9, Eq. 10
+ * with its L1 and SSIM terms) and the masked tracking loss (Eq. 15) with the
+ * pose gradient the tracking optimisation (Eq. 14) needs.
  *
  * Conventions shared by every call
  *  - All array arguments are DEVICE pointers to contiguous float32 (unless
@@ -184,6 +184,20 @@ int gsr_loss_l1(gsr_ctx *ctx, const float *color, const float *depth, const floa
                 const float *tgt_depth, int64_t n_pixels, float w_color, float w_depth, float *loss,
                 float *dL_dcolor, float *dL_ddepth);
 
+/* SSIM term of the mapping colour loss (Eq. 10: L_color = (1 - lambda) L1 +
+ * lambda (1 - SSIM)), with SSIM as Wang et al. 2004 define it and the paper
+ * cites: per channel, an 11x11 Gaussian window (sigma 1.5, weights summing to
+ * one), zero padding at the image border, C1 = 1e-4 and C2 = 9e-4 for values
+ * in [0, 1], averaged over the 3 channels and all pixels.
+ * ACCUMULATES: *loss += weight (1 - SSIM(color, tgt_color)) and
+ * dL_dcolor += weight d(1 - SSIM)/d color, so it runs after gsr_loss_l1 (which
+ * overwrites both) with w_color = 1 - lambda and weight = lambda.
+ * color, tgt_color, dL_dcolor: device float [3, height, width]; loss: device
+ * float[1]. 0 <= width, height <= 65535 (GSR_EINVAL otherwise); an empty image
+ * adds nothing. The gradient is with respect to color only. */
+int gsr_loss_ssim(gsr_ctx *ctx, const float *color, const float *tgt_color, int32_t width, int32_t height,
+                  float weight, float *loss, float *dL_dcolor);
+
 /* Tracking loss (Eq. 15 with the supplement's masks): valid = observed depth
  * > 0; e = |D - D*|; m = lower median of e over valid pixels (exact, radix
  * select on the device); inlier = valid and e <= inlier_mult * m; weight =
@@ -307,7 +321,7 @@ int gsr_initnet_adam(gsr_ctx *ctx, gsr_initnet *net, float lr, float beta1, floa
 
 /* Stage timing for benchmarks: while enabled, every stage a call enqueues
  * (project, bin_count, tile_bins, render_fwd, fill, render_bwd, project_bwd,
- * project_bwd_adam, loss_l1, loss_track, adam, pose_adam, track_graph,
+ * project_bwd_adam, loss_l1, loss_ssim, loss_track, adam, pose_adam, track_graph,
  * initnet_fwd, initnet_bwd) is bracketed by a pair of HIP events on the context's stream.
  * The events carry no system-scope fence, so they do not write back or
  * invalidate caches, but each still costs a few microseconds of stream time. */

@@ -644,6 +644,18 @@ int gsr_loss_l1(gsr_ctx* c, const float* color, const float* depth, const float*
   return check_launch(c, "gsr_loss_l1");
 }
 
+int gsr_loss_ssim(gsr_ctx* c, const float* color, const float* tgt_color, int32_t width, int32_t height, float weight,
+                  float* loss, float* dL_dcolor) {
+  if (!c) return GSR_EINVAL;
+  if (width < 0 || height < 0 || width > 65535 || height > 65535 || !loss || !std::isfinite(weight) ||
+      ((int64_t)width * height > 0 && (!color || !tgt_color || !dL_dcolor)))
+    return fail(c, GSR_EINVAL, "bad SSIM loss arguments");
+  GSR_HIP(c, hipSetDevice(c->device));
+  Stage t(c, "loss_ssim");
+  gsr::launch_loss_ssim(color, tgt_color, height, width, weight, loss, dL_dcolor, c->red, c->stream);
+  return check_launch(c, "gsr_loss_ssim");
+}
+
 int gsr_loss_track(gsr_ctx* c, const float* color, const float* depth, const float* alpha, const float* tgt_color,
                    const float* tgt_depth, int64_t P, float lambda_c, float inlier_mult, float* loss, float* dL_dcolor,
                    float* dL_ddepth, float* median) {

@@ -324,6 +324,9 @@ void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 int64_t reduce_temp_words();
 void launch_loss_l1(const float* C, const float* D, const float* Ct, const float* Dt, int64_t P, float wc, float wd,
                     float* loss, float* gC, float* gD, uint32_t* red, hipStream_t s);
+// Adds weight (1 - SSIM(X, Y)) to *loss and its gradient to gX ([3,H,W]).
+void launch_loss_ssim(const float* X, const float* Y, int H, int W, float weight, float* loss, float* gX,
+                      uint32_t* red, hipStream_t s);
 // temp: track_temp_words() uint32, zero before its first use
 int64_t track_temp_words();
 void launch_loss_track(const float* C, const float* D, const float* A, const float* Ct, const float* Dt, int64_t P,

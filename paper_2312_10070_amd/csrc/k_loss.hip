@@ -1,6 +1,8 @@
-// Losses and their upstream gradients (Eq. 9, the L1 part of Eq. 10, and the
-// masked tracking loss of Eq. 15), the exact median the inlier mask needs
-// (radix select on float bits, all on the device), and Adam.
+// Losses and their upstream gradients (Eq. 9, Eq. 10 with its L1 and SSIM
+// terms, and the masked tracking loss of Eq. 15), the exact median the inlier
+// mask needs (radix select on float bits, all on the device), and Adam.
+#include <cmath>
+
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -44,8 +46,10 @@ __device__ __forceinline__ bool publish_and_count(float* slot, float value, uint
 // L2): every workgroup publishes its partial; the last of each group of
 // kRedGroup workgroups sums the group's partials and publishes that; the last
 // group sums the group sums. Tickets return to zero. red: kRedWords words,
-// zero before the first launch.
-__device__ __forceinline__ void grid_sum(float v, float* out, uint32_t* red) {
+// zero before the first launch. With `accumulate`, *out becomes
+// *out + (offset + scale * total) instead.
+__device__ __forceinline__ void grid_sum(float v, float* out, uint32_t* red, bool accumulate = false,
+                                         float scale = 1.f, float offset = 0.f) {
   __shared__ bool go;
   float* f = reinterpret_cast<float*>(red);
   const uint32_t b = blockIdx.x, n = gridDim.x;
@@ -66,7 +70,7 @@ __device__ __forceinline__ void grid_sum(float v, float* out, uint32_t* red) {
             ? __hip_atomic_load(f + kRedSums + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
             : 0.f;
   const float total = block_sum(acc);
-  if (threadIdx.x == 0) *out = total;
+  if (threadIdx.x == 0) *out = accumulate ? *out + (offset + scale * total) : total;
 }
 
 __device__ __forceinline__ float4 ld4(const float* p, int64_t i) { return reinterpret_cast<const float4*>(p)[i]; }
@@ -233,6 +237,184 @@ __global__ __launch_bounds__(256) void k_loss_track(const float* __restrict__ C,
   grid_sum(acc, loss, red);
 }
 
+// ---- SSIM term of the mapping colour loss (Eq. 10) ------------------------
+// SSIM after Wang et al. 2004: per channel, an 11x11 Gaussian window (sigma
+// 1.5, unit sum, applied as two 11-tap passes), zero padding, C1 = 1e-4,
+// C2 = 9e-4 for values in [0, 1]. A workgroup takes one 32x32 block of one
+// channel at a time and keeps everything in LDS: the five windowed moments
+// (mu_x, mu_y, E[x^2], E[y^2], E[xy]) over the block and a 5-pixel apron, the
+// partials of SSIM(p) with respect to them on that apron (zero outside the
+// image), and the windowed sums of those partials over the block, which give
+//   d mean SSIM / d x_q = (1/n) sum_p w(q - p) (A_p + 2 x_q B_p + y_q C_p)
+// with A = dS/dmu_x, B = dS/dE[x^2], C = dS/dE[xy] (the moments taken as
+// independent: sigma_x^2 = E[x^2] - mu_x^2, sigma_xy = E[xy] - mu_x mu_y).
+// Global memory sees the two images (with a 10-pixel apron, mostly from L2),
+// the gradient read-modify-write and one partial per workgroup.
+constexpr int kSsR = 5;                // window half-width
+constexpr int kSsT = 32;               // output block edge
+constexpr int kSsS = kSsT + 2 * kSsR;  // 42: moments and partials edge
+constexpr int kSsI = kSsT + 4 * kSsR;  // 52: input edge
+constexpr int kSsTaps = 2 * kSsR + 1;
+static_assert(kSsS % 3 == 0 && kSsT % 2 == 0 && kSsT * 8 == 256, "SSIM work split");
+
+struct SsimWin {
+  float w[kSsTaps];
+};
+
+struct SsimSmem {
+  union {
+    struct {
+      float x[kSsI * kSsI], y[kSsI * kSsI];  // inputs (steps 1-2)
+    } in;
+    float part[3][kSsS * kSsS];  // A, B, C on the apron (steps 3-4)
+  } a;
+  union {
+    float hm[5][kSsI * kSsS];  // row sums of the five moments, 52 rows x 42 (steps 2-3)
+    float hp[3][kSsS * kSsT];  // row sums of A, B, C, 42 rows x 32 (steps 4-5)
+  } b;
+};
+
+// lsum accumulates SSIM(p) over the pixels of the blocks this workgroup owns;
+// *loss += loffset + lscale * (sum over the grid); gX += gscale * d(sum SSIM)/dx.
+__global__ __launch_bounds__(256, 2) void k_loss_ssim(const float* __restrict__ X, const float* __restrict__ Y, int H,
+                                                      int W, int tiles_x, int n_tiles, SsimWin win, float gscale,
+                                                      float lscale, float loffset, float* __restrict__ loss,
+                                                      float* __restrict__ gX, uint32_t* __restrict__ red) {
+  __shared__ SsimSmem sm;
+  constexpr float c1 = 1e-4f, c2 = 9e-4f;
+  const int tid = threadIdx.x;
+  const int64_t plane = (int64_t)H * W;
+  float lsum = 0.f;
+  for (int item = blockIdx.x; item < 3 * n_tiles; item += gridDim.x) {
+    const int ch = item / n_tiles, tile = item - ch * n_tiles;
+    const int ty0 = (tile / tiles_x) * kSsT, tx0 = (tile % tiles_x) * kSsT;
+    const float* x = X + ch * plane;
+    const float* y = Y + ch * plane;
+    __syncthreads();  // the previous block's last step still reads sm.b
+    // 1: inputs over the block and a 10-pixel apron, zero outside the image
+    for (int i = tid; i < kSsI * kSsI; i += 256) {
+      const int r = i / kSsI, c = i - r * kSsI;
+      const int gy = ty0 - 2 * kSsR + r, gx = tx0 - 2 * kSsR + c;
+      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      const int64_t o = in ? (int64_t)gy * W + gx : 0;
+      sm.a.in.x[i] = in ? x[o] : 0.f;
+      sm.a.in.y[i] = in ? y[o] : 0.f;
+    }
+    __syncthreads();
+    // 2: row sums of x, y, x^2, y^2, xy (three adjacent outputs per thread)
+    for (int i = tid; i < kSsI * (kSsS / 3); i += 256) {
+      const int r = i / (kSsS / 3), c0 = 3 * (i - r * (kSsS / 3));
+      float acc[5][3] = {};
+#pragma unroll
+      for (int k = 0; k < kSsTaps + 2; ++k) {
+        const float xv = sm.a.in.x[r * kSsI + c0 + k], yv = sm.a.in.y[r * kSsI + c0 + k];
+        const float m[5] = {xv, yv, xv * xv, yv * yv, xv * yv};
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+          const int t = k - o;
+          if (t < 0 || t >= kSsTaps) continue;
+#pragma unroll
+          for (int q = 0; q < 5; ++q) acc[q][o] = fmaf(win.w[t], m[q], acc[q][o]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int o = 0; o < 3; ++o) sm.b.hm[q][r * kSsS + c0 + o] = acc[q][o];
+    }
+    __syncthreads();
+    // 3: column sums give the moments at apron position (r, c), pixel
+    //    (ty0 - 5 + r, tx0 - 5 + c); then SSIM and its partials there
+    for (int i = tid; i < kSsS * (kSsS / 3); i += 256) {
+      const int sg = i / kSsS, c = i - sg * kSsS, r0 = 3 * sg;
+      float acc[5][3] = {};
+#pragma unroll
+      for (int k = 0; k < kSsTaps + 2; ++k) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const float v = sm.b.hm[q][(r0 + k) * kSsS + c];
+#pragma unroll
+          for (int o = 0; o < 3; ++o) {
+            const int t = k - o;
+            if (t >= 0 && t < kSsTaps) acc[q][o] = fmaf(win.w[t], v, acc[q][o]);
+          }
+        }
+      }
+      const int gx = tx0 - kSsR + c;
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        const int r = r0 + o, gy = ty0 - kSsR + r;
+        float pa = 0.f, pb = 0.f, pc = 0.f;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+          const float mx = acc[0][o], my = acc[1][o];
+          const float vx = acc[2][o] - mx * mx, vy = acc[3][o] - my * my, cxy = acc[4][o] - mx * my;
+          const float a1 = 2.f * mx * my + c1, a2 = 2.f * cxy + c2;
+          const float b1 = mx * mx + my * my + c1, b2 = vx + vy + c2;
+          const float s = (a1 * a2) / (b1 * b2);
+          if (r >= kSsR && r < kSsR + kSsT && c >= kSsR && c < kSsR + kSsT) lsum += s;
+          pb = -s / b2;        // dS/dsigma_x^2 = dS/dE[x^2]
+          pc = 2.f * s / a2;   // dS/dsigma_xy = dS/dE[xy]
+          pa = s * (2.f * my / a1 - 2.f * mx / b1) - 2.f * mx * pb - my * pc;  // total dS/dmu_x
+        }
+        sm.a.part[0][r * kSsS + c] = pa;
+        sm.a.part[1][r * kSsS + c] = pb;
+        sm.a.part[2][r * kSsS + c] = pc;
+      }
+    }
+    __syncthreads();
+    // 4: row sums of A, B, C for output column c (pixel tx0 + c), two per thread
+    for (int i = tid; i < kSsS * (kSsT / 2); i += 256) {
+      const int r = i / (kSsT / 2), c0 = 2 * (i - r * (kSsT / 2));
+      float acc[3][2] = {};
+#pragma unroll
+      for (int k = 0; k < kSsTaps + 1; ++k) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const float v = sm.a.part[q][r * kSsS + c0 + k];
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+            const int t = k - o;
+            if (t >= 0 && t < kSsTaps) acc[q][o] = fmaf(win.w[t], v, acc[q][o]);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) sm.b.hp[q][r * kSsT + c0 + o] = acc[q][o];
+    }
+    __syncthreads();
+    // 5: column sums; gradient at pixel (ty0 + r0 + o, tx0 + c), four rows per thread
+    {
+      const int c = tid & (kSsT - 1), r0 = 4 * (tid >> 5);
+      float acc[3][4] = {};
+#pragma unroll
+      for (int k = 0; k < kSsTaps + 3; ++k) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const float v = sm.b.hp[q][(r0 + k) * kSsT + c];
+#pragma unroll
+          for (int o = 0; o < 4; ++o) {
+            const int t = k - o;
+            if (t >= 0 && t < kSsTaps) acc[q][o] = fmaf(win.w[t], v, acc[q][o]);
+          }
+        }
+      }
+      const int gx = tx0 + c;
+      float* g = gX + ch * plane;
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        const int gy = ty0 + r0 + o;
+        if (gy < H && gx < W) {
+          const int64_t q = (int64_t)gy * W + gx;
+          g[q] += gscale * (acc[0][o] + 2.f * x[q] * acc[1][o] + y[q] * acc[2][o]);
+        }
+      }
+    }
+  }
+  grid_sum(lsum, loss, red, true, lscale, loffset);
+}
+
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
                                              const float* __restrict__ g, int64_t n, float lr, float b1, float b2,
                                              float eps, float bc1, float bc2) {
@@ -368,6 +550,25 @@ void launch_loss_l1(const float* C, const float* D, const float* Ct, const float
   const int64_t P4 = vec ? P / 4 : 0;
   hipLaunchKernelGGL(k_loss_l1, dim3(grid_for(vec ? P4 : P, kRedSlots)), dim3(256), 0, s, C, D, Ct, Dt, P, P4,
                      wc / (3.f * (float)P), wd / (float)P, loss, gC, gD, red);
+}
+
+void launch_loss_ssim(const float* X, const float* Y, int H, int W, float weight, float* loss, float* gX,
+                      uint32_t* red, hipStream_t s) {
+  if (H <= 0 || W <= 0) return;  // an empty image adds nothing
+  SsimWin win;
+  double g[kSsTaps], sum = 0.0;
+  for (int k = 0; k < kSsTaps; ++k) {
+    const double d = k - kSsR;
+    g[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
+    sum += g[k];
+  }
+  for (int k = 0; k < kSsTaps; ++k) win.w[k] = (float)(g[k] / sum);
+  const int tiles_x = (W + kSsT - 1) / kSsT, tiles_y = (H + kSsT - 1) / kSsT;
+  const int n_tiles = tiles_x * tiles_y;
+  const double n = 3.0 * (double)H * (double)W;
+  const int grid = 3 * n_tiles < kRedSlots ? 3 * n_tiles : kRedSlots;
+  hipLaunchKernelGGL(k_loss_ssim, dim3(grid), dim3(256), 0, s, X, Y, H, W, tiles_x, n_tiles, win,
+                     (float)(-weight / n), (float)(-weight / n), weight, loss, gX, red);
 }
 
 int64_t track_temp_words() { return kSelWords + kRedWords; }

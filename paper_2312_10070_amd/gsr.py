@@ -84,6 +84,7 @@ _SIGS = {
     "gsr_state_release": (ctypes.c_int, [P, P]),
     "gsr_tile_lists": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_int64), P, P]),
     "gsr_loss_l1": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P]),
+    "gsr_loss_ssim": (ctypes.c_int, [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P, P]),
     "gsr_loss_track": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P, P]),
     "gsr_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float]),
@@ -391,6 +392,32 @@ def loss_l1(color, depth, tgt_color, tgt_depth, w_color=1.0, w_depth=1.0, ctx: C
     gD = torch.empty_like(depth)
     ctx.check(ctx.lib.gsr_loss_l1(ctx.h, _ptr(color), _ptr(depth), _ptr(tgt_color), _ptr(tgt_depth), P_,
                                   float(w_color), float(w_depth), _ptr(loss), _ptr(gC), _ptr(gD)))
+    return loss, gC, gD
+
+
+def loss_ssim(color, tgt_color, weight, loss, dL_dcolor, ctx: Context | None = None):
+    """SSIM term of Eq. 10, in place: loss [1] += weight (1 - SSIM(color, tgt_color)),
+    dL_dcolor += its gradient. color, tgt_color, dL_dcolor: [3, H, W]."""
+    ctx = ctx or Context.get(color.device.index or 0)
+    ctx.sync_stream()
+    for t, nme in ((color, "color"), (tgt_color, "tgt_color"), (loss, "loss"), (dL_dcolor, "dL_dcolor")):
+        _f32(t, nme)
+    if color.dim() != 3 or color.shape[0] != 3 or tgt_color.shape != color.shape or dL_dcolor.shape != color.shape:
+        raise ValueError("color, tgt_color and dL_dcolor must share one [3, H, W] shape")
+    if loss.numel() != 1:
+        raise ValueError("loss must hold one float")
+    ctx.check(ctx.lib.gsr_loss_ssim(ctx.h, _ptr(color), _ptr(tgt_color), int(color.shape[2]), int(color.shape[1]),
+                                    float(weight), _ptr(loss), _ptr(dL_dcolor)))
+    return loss, dL_dcolor
+
+
+def loss_map(color, depth, tgt_color, tgt_depth, lam=0.2, w_color=1.0, w_depth=1.0, ctx: Context | None = None):
+    """Mapping loss of Eq. 10 and Eq. 12 without the regulariser:
+    w_color ((1 - lam) mean|C - C*| + lam (1 - SSIM(C, C*))) + w_depth mean|D - D*|.
+    Returns (loss [1] device, dL/dcolor, dL/ddepth)."""
+    loss, gC, gD = loss_l1(color, depth, tgt_color, tgt_depth, w_color * (1.0 - lam), w_depth, ctx=ctx)
+    if lam != 0.0:
+        loss_ssim(color, tgt_color, w_color * lam, loss, gC, ctx=ctx)
     return loss, gC, gD
 
 

@@ -343,6 +343,19 @@ def mapping_inputs(seed: int = 0, n: int = 200_000, cam: Intrinsics = MAPPING_CA
     return dict(gaussians=g, pose7=pose, camera=cam, target_color=color, target_depth=depth)
 
 
+def image_pair(seed: int = 0, cam: Intrinsics = MAPPING_CAMERA, noise: float = 0.02):
+    """Two colour images [3,H,W] of the room for the mapping colour loss: the
+    ground-truth frame at a view, and a stand-in for a render (the frame at that
+    view moved by 2 cm / 1 degree, plus N(0, noise) clipped to [0, 1])."""
+    rng = np.random.default_rng(seed)
+    room = make_room(seed)
+    pose = open_view(room, rng, MAPPING_CAMERA)  # the view is chosen at a fixed probe size
+    tgt, _ = render_frame(room, cam, pose)
+    near, _ = render_frame(room, cam, perturb_pose(pose, rng, 0.02, 1.0))
+    ren = np.clip(near + rng.normal(0.0, noise, near.shape), 0.0, 1.0).astype(np.float32)
+    return ren, tgt
+
+
 def tracking_inputs(seed: int = 0, n: int = 500_000, cam: Intrinsics = TRACKING_CAMERA, n_views: int = 5,
                     trans_m: float = 0.02, rot_deg: float = 1.0) -> dict:
     """C3: sub-map seeded from views near the ground-truth pose, GT pose, perturbed init."""
