@@ -11,7 +11,7 @@ namespace {
 
 __device__ __forceinline__ float sgnf(float r) { return (float)((r > 0.f) - (r < 0.f)); }
 
-constexpr int kRedSlots = 1024;  // most workgroups a grid_sum launch may have
+constexpr int kRedSlots = 4096;  // most workgroups a grid_sum launch may have
 constexpr int kRedGroup = 32;    // workgroups per first-level ticket
 constexpr int kRedGroups = kRedSlots / kRedGroup;
 constexpr int kLine = 16;        // words per 64-byte line: one ticket per line
@@ -274,8 +274,38 @@ struct SsimSmem {
   } b;
 };
 
+constexpr int kSsLd = (kSsI * kSsI + 255) / 256;  // input elements per thread and image
+
+// One block's inputs (block and 10-pixel apron) into registers: element
+// threadIdx.x + 256 j of the 52 x 52 window goes to v[j], read at the nearest
+// in-image pixel; bit j of the result says whether it lies in the image (else
+// it counts as zero). The loads are unconditional so that nothing waits for
+// them before the values are stored.
+__device__ __forceinline__ uint32_t ssim_load(const float* __restrict__ X, const float* __restrict__ Y, int H, int W,
+                                              int tiles_x, int n_tiles, int item, float (&vx)[kSsLd],
+                                              float (&vy)[kSsLd]) {
+  const int ch = item / n_tiles, tile = item - ch * n_tiles;
+  const int ty0 = (tile / tiles_x) * kSsT, tx0 = (tile % tiles_x) * kSsT;
+  const int64_t base = (int64_t)ch * H * W;
+  uint32_t in_mask = 0;
+#pragma unroll
+  for (int j = 0; j < kSsLd; ++j) {
+    const int i = threadIdx.x + 256 * j;
+    const int r = i / kSsI, c = i - r * kSsI;
+    const int gy = ty0 - 2 * kSsR + r, gx = tx0 - 2 * kSsR + c;
+    in_mask |= (uint32_t)(i < kSsI * kSsI && gy >= 0 && gy < H && gx >= 0 && gx < W) << j;
+    const int64_t o = base + (int64_t)min(max(gy, 0), H - 1) * W + min(max(gx, 0), W - 1);
+    vx[j] = X[o];
+    vy[j] = Y[o];
+  }
+  return in_mask;
+}
+
 // lsum accumulates SSIM(p) over the pixels of the blocks this workgroup owns;
 // *loss += loffset + lscale * (sum over the grid); gX += gscale * d(sum SSIM)/dx.
+// A workgroup normally owns one block (the grid has one workgroup per block up
+// to the reduction's limit), so the other workgroup on its CU hides its input
+// latency; the gradient step's own global reads are issued a step early.
 __global__ __launch_bounds__(256, 2) void k_loss_ssim(const float* __restrict__ X, const float* __restrict__ Y, int H,
                                                       int W, int tiles_x, int n_tiles, SsimWin win, float gscale,
                                                       float lscale, float loffset, float* __restrict__ loss,
@@ -284,33 +314,35 @@ __global__ __launch_bounds__(256, 2) void k_loss_ssim(const float* __restrict__ 
   constexpr float c1 = 1e-4f, c2 = 9e-4f;
   const int tid = threadIdx.x;
   const int64_t plane = (int64_t)H * W;
+  const int n_items = 3 * n_tiles;
   float lsum = 0.f;
-  for (int item = blockIdx.x; item < 3 * n_tiles; item += gridDim.x) {
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const int ch = item / n_tiles, tile = item - ch * n_tiles;
     const int ty0 = (tile / tiles_x) * kSsT, tx0 = (tile % tiles_x) * kSsT;
-    const float* x = X + ch * plane;
-    const float* y = Y + ch * plane;
+    float vx[kSsLd], vy[kSsLd];
+    const uint32_t in_mask = ssim_load(X, Y, H, W, tiles_x, n_tiles, item, vx, vy);
     __syncthreads();  // the previous block's last step still reads sm.b
-    // 1: inputs over the block and a 10-pixel apron, zero outside the image
-    for (int i = tid; i < kSsI * kSsI; i += 256) {
-      const int r = i / kSsI, c = i - r * kSsI;
-      const int gy = ty0 - 2 * kSsR + r, gx = tx0 - 2 * kSsR + c;
-      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-      const int64_t o = in ? (int64_t)gy * W + gx : 0;
-      sm.a.in.x[i] = in ? x[o] : 0.f;
-      sm.a.in.y[i] = in ? y[o] : 0.f;
+    // 1: the inputs to LDS
+#pragma unroll
+    for (int j = 0; j < kSsLd; ++j) {
+      const int i = tid + 256 * j;
+      if (i < kSsI * kSsI) {
+        const bool in = (in_mask >> j) & 1u;
+        sm.a.in.x[i] = in ? vx[j] : 0.f;
+        sm.a.in.y[i] = in ? vy[j] : 0.f;
+      }
     }
     __syncthreads();
-    // 2: row sums of x, y, x^2, y^2, xy (three adjacent outputs per thread)
-    for (int i = tid; i < kSsI * (kSsS / 3); i += 256) {
-      const int r = i / (kSsS / 3), c0 = 3 * (i - r * (kSsS / 3));
-      float acc[5][3] = {};
+    // 2: row sums of x, y, x^2, y^2, xy; 14 adjacent outputs per thread (156 threads)
+    if (tid < kSsI * 3) {
+      const int r = tid / 3, c0 = 14 * (tid - 3 * r);
+      float acc[5][14] = {};
 #pragma unroll
-      for (int k = 0; k < kSsTaps + 2; ++k) {
+      for (int k = 0; k < kSsTaps + 13; ++k) {
         const float xv = sm.a.in.x[r * kSsI + c0 + k], yv = sm.a.in.y[r * kSsI + c0 + k];
         const float m[5] = {xv, yv, xv * xv, yv * yv, xv * yv};
 #pragma unroll
-        for (int o = 0; o < 3; ++o) {
+        for (int o = 0; o < 14; ++o) {
           const int t = k - o;
           if (t < 0 || t >= kSsTaps) continue;
 #pragma unroll
@@ -320,21 +352,22 @@ __global__ __launch_bounds__(256, 2) void k_loss_ssim(const float* __restrict__ 
 #pragma unroll
       for (int q = 0; q < 5; ++q)
 #pragma unroll
-        for (int o = 0; o < 3; ++o) sm.b.hm[q][r * kSsS + c0 + o] = acc[q][o];
+        for (int o = 0; o < 14; ++o) sm.b.hm[q][r * kSsS + c0 + o] = acc[q][o];
     }
     __syncthreads();
     // 3: column sums give the moments at apron position (r, c), pixel
     //    (ty0 - 5 + r, tx0 - 5 + c); then SSIM and its partials there
-    for (int i = tid; i < kSsS * (kSsS / 3); i += 256) {
-      const int sg = i / kSsS, c = i - sg * kSsS, r0 = 3 * sg;
-      float acc[5][3] = {};
+    //    (7 rows per thread, 252 threads)
+    if (tid < kSsS * 6) {
+      const int sg = tid / kSsS, c = tid - sg * kSsS, r0 = 7 * sg;
+      float acc[5][7] = {};
 #pragma unroll
-      for (int k = 0; k < kSsTaps + 2; ++k) {
+      for (int k = 0; k < kSsTaps + 6; ++k) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
           const float v = sm.b.hm[q][(r0 + k) * kSsS + c];
 #pragma unroll
-          for (int o = 0; o < 3; ++o) {
+          for (int o = 0; o < 7; ++o) {
             const int t = k - o;
             if (t >= 0 && t < kSsTaps) acc[q][o] = fmaf(win.w[t], v, acc[q][o]);
           }
@@ -342,37 +375,53 @@ __global__ __launch_bounds__(256, 2) void k_loss_ssim(const float* __restrict__ 
       }
       const int gx = tx0 - kSsR + c;
 #pragma unroll
-      for (int o = 0; o < 3; ++o) {
+      for (int o = 0; o < 7; ++o) {
         const int r = r0 + o, gy = ty0 - kSsR + r;
         float pa = 0.f, pb = 0.f, pc = 0.f;
         if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
           const float mx = acc[0][o], my = acc[1][o];
-          const float vx = acc[2][o] - mx * mx, vy = acc[3][o] - my * my, cxy = acc[4][o] - mx * my;
+          const float vxx = acc[2][o] - mx * mx, vyy = acc[3][o] - my * my, cxy = acc[4][o] - mx * my;
           const float a1 = 2.f * mx * my + c1, a2 = 2.f * cxy + c2;
-          const float b1 = mx * mx + my * my + c1, b2 = vx + vy + c2;
-          const float s = (a1 * a2) / (b1 * b2);
+          const float rb1 = __builtin_amdgcn_rcpf(mx * mx + my * my + c1);
+          const float rb2 = __builtin_amdgcn_rcpf(vxx + vyy + c2);
+          const float s = a1 * a2 * (rb1 * rb2);
           if (r >= kSsR && r < kSsR + kSsT && c >= kSsR && c < kSsR + kSsT) lsum += s;
-          pb = -s / b2;        // dS/dsigma_x^2 = dS/dE[x^2]
-          pc = 2.f * s / a2;   // dS/dsigma_xy = dS/dE[xy]
-          pa = s * (2.f * my / a1 - 2.f * mx / b1) - 2.f * mx * pb - my * pc;  // total dS/dmu_x
+          // partials of s = a1 a2 / (b1 b2), written without dividing by a1 or a2
+          pb = -s * rb2;                // dS/dsigma_x^2 = dS/dE[x^2]
+          pc = 2.f * a1 * rb1 * rb2;    // dS/dsigma_xy = dS/dE[xy]
+          pa = 2.f * rb1 * (my * a2 * rb2 - mx * s) - 2.f * mx * pb - my * pc;  // total dS/dmu_x
         }
         sm.a.part[0][r * kSsS + c] = pa;
         sm.a.part[1][r * kSsS + c] = pb;
         sm.a.part[2][r * kSsS + c] = pc;
       }
     }
-    __syncthreads();
-    // 4: row sums of A, B, C for output column c (pixel tx0 + c), two per thread
-    for (int i = tid; i < kSsS * (kSsT / 2); i += 256) {
-      const int r = i / (kSsT / 2), c0 = 2 * (i - r * (kSsT / 2));
-      float acc[3][2] = {};
+    // the gradient step's pixels (ty0 + r5 + o, tx0 + c5), read a step early at
+    // the nearest in-image pixel (only in-image ones are used)
+    const int c5 = tid & (kSsT - 1), r5 = 4 * (tid >> 5);
+    const float* x = X + ch * plane;
+    const float* y = Y + ch * plane;
+    float* g = gX + ch * plane;
+    float xs[4], ys[4], gs[4];
 #pragma unroll
-      for (int k = 0; k < kSsTaps + 1; ++k) {
+    for (int o = 0; o < 4; ++o) {
+      const int64_t q = (int64_t)min(ty0 + r5 + o, H - 1) * W + min(tx0 + c5, W - 1);
+      xs[o] = x[q];
+      ys[o] = y[q];
+      gs[o] = g[q];
+    }
+    __syncthreads();
+    // 4: row sums of A, B, C for output column c (pixel tx0 + c); 8 per thread (168 threads)
+    if (tid < kSsS * 4) {
+      const int r = tid >> 2, c0 = 8 * (tid & 3);
+      float acc[3][8] = {};
+#pragma unroll
+      for (int k = 0; k < kSsTaps + 7; ++k) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           const float v = sm.a.part[q][r * kSsS + c0 + k];
 #pragma unroll
-          for (int o = 0; o < 2; ++o) {
+          for (int o = 0; o < 8; ++o) {
             const int t = k - o;
             if (t >= 0 && t < kSsTaps) acc[q][o] = fmaf(win.w[t], v, acc[q][o]);
           }
@@ -381,18 +430,17 @@ __global__ __launch_bounds__(256, 2) void k_loss_ssim(const float* __restrict__ 
 #pragma unroll
       for (int q = 0; q < 3; ++q)
 #pragma unroll
-        for (int o = 0; o < 2; ++o) sm.b.hp[q][r * kSsT + c0 + o] = acc[q][o];
+        for (int o = 0; o < 8; ++o) sm.b.hp[q][r * kSsT + c0 + o] = acc[q][o];
     }
     __syncthreads();
-    // 5: column sums; gradient at pixel (ty0 + r0 + o, tx0 + c), four rows per thread
+    // 5: column sums; gradient at pixel (ty0 + r5 + o, tx0 + c5), four rows per thread
     {
-      const int c = tid & (kSsT - 1), r0 = 4 * (tid >> 5);
       float acc[3][4] = {};
 #pragma unroll
       for (int k = 0; k < kSsTaps + 3; ++k) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          const float v = sm.b.hp[q][(r0 + k) * kSsT + c];
+          const float v = sm.b.hp[q][(r5 + k) * kSsT + c5];
 #pragma unroll
           for (int o = 0; o < 4; ++o) {
             const int t = k - o;
@@ -400,15 +448,12 @@ __global__ __launch_bounds__(256, 2) void k_loss_ssim(const float* __restrict__ 
           }
         }
       }
-      const int gx = tx0 + c;
-      float* g = gX + ch * plane;
+      const int gx = tx0 + c5;
 #pragma unroll
       for (int o = 0; o < 4; ++o) {
-        const int gy = ty0 + r0 + o;
-        if (gy < H && gx < W) {
-          const int64_t q = (int64_t)gy * W + gx;
-          g[q] += gscale * (acc[0][o] + 2.f * x[q] * acc[1][o] + y[q] * acc[2][o]);
-        }
+        const int gy = ty0 + r5 + o;
+        if (gy < H && gx < W)
+          g[(int64_t)gy * W + gx] = gs[o] + gscale * (acc[0][o] + 2.f * xs[o] * acc[1][o] + ys[o] * acc[2][o]);
       }
     }
   }
