@@ -316,7 +316,14 @@ __global__ __launch_bounds__(256, 2) void k_loss_ssim(const float* __restrict__ 
   const int64_t plane = (int64_t)H * W;
   const int n_items = 3 * n_tiles;
   float lsum = 0.f;
-  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+  // Workgroups are dealt to the 8 XCDs in turn (b mod 8), each with its own L2:
+  // XCD x takes the x-th contiguous eighth of the blocks, so neighbouring
+  // blocks, which share their aprons, meet in one L2. A bijection on
+  // [0, n_items) whenever the grid is n_items or a multiple of 8.
+  const int xq = n_items >> 3, xr = n_items & 7;
+  for (int v = blockIdx.x; v < n_items; v += gridDim.x) {
+    const int xcd = v & 7, local = v >> 3;
+    const int item = xcd * xq + min(xcd, xr) + local;
     const int ch = item / n_tiles, tile = item - ch * n_tiles;
     const int ty0 = (tile / tiles_x) * kSsT, tx0 = (tile % tiles_x) * kSsT;
     float vx[kSsLd], vy[kSsLd];
