@@ -56,6 +56,7 @@ def _load():
     lib.orc_backward.restype = i64
     lib.orc_tile_lists.argtypes = [i64] + [P] * 8 + [P, P, P, P, i64]
     lib.orc_loss_l1.argtypes = [i64, P, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
+    lib.orc_loss_reg.argtypes = [i64, P, P, P]
     lib.orc_loss_track.argtypes = [i64, P, P, P, P, P, ctypes.c_double, ctypes.c_float, P, P, P, P, P]
     lib.orc_adam.argtypes = [i64, P, P, P, P, i64] + [ctypes.c_double] * 4
     lib.orc_pose_const_velocity.argtypes = [P, P, P]
@@ -214,6 +215,16 @@ def loss_l1(C, D, Ct, Dt, w_color=1.0, w_depth=1.0):
     loss = np.zeros(1); gC = np.zeros(C.shape); gD = np.zeros(D.shape)
     lib.orc_loss_l1(P, _p(C), _p(D), _p(Ct), _p(Dt), w_color, w_depth, _p(loss), _p(gC), _p(gD))
     return float(loss[0]), gC, gD
+
+
+def loss_reg(scales):
+    """Eq. 11 on [N,3] scales: (L_reg, dL_reg/dscales [N,3])."""
+    lib = _load()
+    s = _d(scales)
+    assert s.ndim == 2 and s.shape[1] == 3
+    loss = np.zeros(1); g = np.zeros(s.shape)
+    lib.orc_loss_reg(s.shape[0], _p(s), _p(loss), _p(g))
+    return float(loss[0]), g
 
 
 def loss_track(C, D, A, Ct, Dt, lambda_c=0.5, inlier_mult=50.0):

@@ -20,8 +20,9 @@
 //     alpha and direct-depth analogues) chained to means, scales, quaternions,
 //     opacities, colours and the camera pose (quaternion + translation, and a
 //     left-perturbation twist);
-//   * the L1 mapping loss (Eq. 9, L1 part of Eq. 10) and the masked tracking
-//     loss (Eq. 15, with the inlier and alpha^3 masks of the supplement);
+//   * the L1 mapping loss (Eq. 9, L1 part of Eq. 10), the isotropic scale
+//     regulariser (Eq. 11) and the masked tracking loss (Eq. 15, with the
+//     inlier and alpha^3 masks of the supplement);
 //   * one Adam step (Kingma & Ba), the optimiser both loops use.
 //
 // "Several results are correct" handling: a discrete decision whose FP64
@@ -1030,6 +1031,31 @@ int orc_loss_l1(int64_t P, const float* C, const float* D, const float* Ct, cons
     gD[i] = wd * ((r > 0) - (r < 0)) / (double)P;
   }
   *loss = wc * lc / (3.0 * P) + wd * ld / (double)P;
+  return 0;
+}
+
+// Isotropic regularisation of the scales (Eq. 11):
+//   L_reg = (1/N) sum_k |s_k - sbar_k 1|_1, sbar_k = (s_k,x + s_k,y + s_k,z) / 3,
+// the mean of Gaussian k's own three scales (the reading of "mean scale" that
+// makes the term isotropic). With sign(0) = 0, its gradient is
+//   dL/ds_k,j = (1/N) (sign(r_j) - (1/3) sum_i sign(r_i)),  r_i = s_k,i - sbar_k.
+// scales: [N,3]; grad: [N,3] (overwritten) or NULL; *loss = L_reg (0 if N = 0).
+int orc_loss_reg(int64_t N, const double* scales, double* loss, double* grad) {
+  double total = 0.0;
+  for (int64_t k = 0; k < N; ++k) {
+    const double* s = scales + 3 * k;
+    const double sbar = (s[0] + s[1] + s[2]) / 3.0;
+    double sg[3], sgsum = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      const double r = s[i] - sbar;
+      total += std::fabs(r);
+      sg[i] = (double)((r > 0) - (r < 0));
+      sgsum += sg[i];
+    }
+    if (grad)
+      for (int j = 0; j < 3; ++j) grad[3 * k + j] = (sg[j] - sgsum / 3.0) / (double)N;
+  }
+  *loss = N > 0 ? total / (double)N : 0.0;
   return 0;
 }
 

@@ -1,0 +1,53 @@
+"""Pins of the oracle's isotropic scale regulariser (Eq. 11; sbar_k = the mean of
+Gaussian k's own three scales) against hand-derived values, invariances and
+finite differences."""
+import numpy as np
+
+import oracle
+
+
+def test_closed_forms():
+    s = np.array([[1.0, 2.0, 3.0], [1.0, 1.0, 4.0], [2.0, 2.0, 2.0], [0.5, 0.2, 0.2]])
+    L, g = oracle.loss_reg(s)
+    # |r| sums: (1, 0, 1) -> 2; (1, 1, 2) -> 4; 0; sbar = 0.3: (0.2, 0.1, 0.1) -> 0.4
+    assert abs(L - (2 + 4 + 0 + 0.4) / 4) < 1e-15
+    ref = np.array([[-1, 0, 1], [-2 / 3, -2 / 3, 4 / 3], [0, 0, 0], [4 / 3, -2 / 3, -2 / 3]]) / 4
+    np.testing.assert_allclose(g, ref, rtol=0, atol=1e-15)
+
+
+def test_isotropic_is_zero_and_empty():
+    # dyadic scales, so that (a + a + a) / 3 == a exactly and every r is 0
+    s = np.repeat(np.random.default_rng(0).integers(1, 64, (50, 1)) / 64.0, 3, axis=1)
+    L, g = oracle.loss_reg(s)
+    assert L == 0.0 and not g.any()
+    # any isotropic scales: only the rounding of sbar remains
+    s = np.repeat(np.random.default_rng(0).uniform(0.01, 1, (50, 1)), 3, axis=1)
+    assert oracle.loss_reg(s)[0] < 1e-15
+    L, g = oracle.loss_reg(np.zeros((0, 3)))
+    assert L == 0.0 and g.shape == (0, 3)
+
+
+def test_homogeneous_and_axis_symmetric():
+    rng = np.random.default_rng(1)
+    s = np.exp(rng.normal(-3, 0.3, (200, 3)))
+    L, g = oracle.loss_reg(s)
+    L2, g2 = oracle.loss_reg(2.5 * s)
+    assert abs(L2 - 2.5 * L) < 1e-15 * max(1, L2) * 10
+    np.testing.assert_array_equal(g2, g)
+    perm = [2, 0, 1]
+    L3, g3 = oracle.loss_reg(s[:, perm])
+    assert abs(L3 - L) < 1e-15
+    np.testing.assert_array_equal(g3, g[:, perm])
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(2)
+    s = np.exp(rng.normal(-3, 0.3, (40, 3)))
+    _, g = oracle.loss_reg(s)
+    h = 1e-9
+    fd = np.empty_like(s)
+    for i in np.ndindex(s.shape):
+        sp = s.copy(); sp[i] += h
+        sm = s.copy(); sm[i] -= h
+        fd[i] = (oracle.loss_reg(sp)[0] - oracle.loss_reg(sm)[0]) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=0, atol=1e-6 * np.abs(fd).max())
