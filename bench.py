@@ -10,9 +10,10 @@ on all 14 N parameters. `value` is iterations per second with all inputs
 resident in HBM. Prints ONE JSON line (rank 0) with a roofline entry for the
 dominant kernel (stage times from HIP events inside the timed region) and the
 FP64 CPU oracle timed on a bounded sample of the same workload. A second
-timed loop runs the same iteration with the paper's full colour loss (Eq. 10:
-L1 and SSIM, lambda = 0.2) and reports it, and the SSIM kernel's roofline,
-beside the headline.
+timed loop runs the same iteration with the paper's whole mapping loss (Eq. 12:
+the Eq. 10 colour loss with its SSIM term, lambda = 0.2, the depth L1 and the
+Eq. 11 scale regulariser, all weights 1) and reports it, and the SSIM kernel's
+roofline, beside the headline.
 """
 from __future__ import annotations
 
@@ -42,6 +43,7 @@ FLOPS_COMP_BWD = 48  # T recovery, dC/dalpha, dD/dalpha (Eq. 8), dA/dalpha, suff
 # (132) and the gradient (7).
 FLOPS_SSIM = 390
 SSIM_LAMBDA = 0.2  # Eq. 10
+REG_LAMBDA = 1.0   # Eq. 12 (lambda_color = lambda_depth = lambda_reg = 1)
 
 
 def stage_work(stage: str, st: dict, n: int, P: int) -> tuple[str, float]:
@@ -426,7 +428,7 @@ def main() -> int:
     ap.add_argument("--gaussians", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows-every", type=int, default=68)
-    ap.add_argument("--no-ssim", action="store_true", help="skip the loop with the full Eq. 10 colour loss")
+    ap.add_argument("--no-ssim", action="store_true", help="skip the loop with the whole Eq. 12 mapping loss")
     ap.add_argument("--no-tracking", action="store_true")
     ap.add_argument("--tracking-frames", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
@@ -473,16 +475,18 @@ def main() -> int:
     opts = gsr.RasterOpts()
     step_no = [0]
 
-    def step(lam: float = 0.0):
+    def step(lam: float = 0.0, reg: float = 0.0):
         color, depth, alpha, st = gsr.render_fwd(params["means"], params["scales"], params["quats"],
                                                  params["opacities"], params["colors"], pose, camera, opts)
         if lam:
             loss, gC, gD = gsr.loss_map(color, depth, tgt_c, tgt_d, lam=lam)
         else:
             loss, gC, gD = gsr.loss_l1(color, depth, tgt_c, tgt_d)
+        if reg:
+            gsr.loss_reg(params["scales"], reg, loss)  # its value; the gradient joins the fused step below
         step_no[0] += 1
         # backward with the Adam step on all parameters fused into its last kernel
-        gsr.render_bwd_adam(st, gC, gD, adam_m, adam_v, lrs, step_no[0])
+        gsr.render_bwd_adam(st, gC, gD, adam_m, adam_v, lrs, step_no[0], scale_reg=reg)
         st.release()
         return loss
 
@@ -542,17 +546,17 @@ def main() -> int:
 
     ssim = None
     if not args.no_ssim:
-        # the same iteration with the full colour loss of Eq. 10 (after the headline's timed region)
+        # the same iteration with the whole mapping loss of Eq. 12 (after the headline's timed region)
         k = max(5, min(args.steps, 20))
         for _ in range(2):
-            step(SSIM_LAMBDA)
+            step(SSIM_LAMBDA, REG_LAMBDA)
         torch.cuda.synchronize()
         gsr.profile_read()
         gsr.profile_only("loss_ssim")
         gsr.profile_enable(True)
         e0.record()
         for _ in range(k):
-            loss_s = step(SSIM_LAMBDA)
+            loss_s = step(SSIM_LAMBDA, REG_LAMBDA)
         e1.record()
         torch.cuda.synchronize()
         gsr.profile_enable(False)
@@ -562,7 +566,8 @@ def main() -> int:
         ssim_ms = rec[0] / rec[1]
         _, w_ssim = stage_work("loss_ssim", stats, n, P)
         ach = w_ssim / (ssim_ms * 1e-3) / 1e12
-        ssim = {"workload": f"mapping iteration with the Eq. 10 colour loss (L1 + SSIM, lambda {SSIM_LAMBDA})",
+        ssim = {"workload": f"mapping iteration with the Eq. 12 loss: Eq. 10 colour (L1 + SSIM, lambda {SSIM_LAMBDA}), "
+                            f"depth L1, Eq. 11 scale regulariser (lambda_reg {REG_LAMBDA})",
                 "steps": k, "ms_per_step": round(ms_s, 4), "it_per_s": round(1000.0 / ms_s, 3),
                 "loss_ssim_ms": round(ssim_ms, 4), "loss": float(loss_s.item()),
                 "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -615,7 +620,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: round(v[0] / n_stage_steps, 4) for k, v in sorted(stage_pass.items())},
         "work": stats,
-        "mapping_full_colour_loss": ssim,
+        "mapping_full_loss": ssim,
         "tracking": track,
         "batched_mapping": batched,
         "learned_init": learned,

@@ -143,6 +143,8 @@ typedef struct {
   float lr[5];
   int64_t step;
   float beta1, beta2, eps;
+  float scale_reg; /* lambda_reg of Eq. 12: the gradient of lambda_reg * L_reg (Eq. 11, as
+                      gsr_loss_reg defines it) joins the scale gradient before the step; 0 = none */
 } gsr_adam5;
 
 /* A mapping optimiser step fused into the backward: the result equals
@@ -183,6 +185,15 @@ int gsr_tile_lists(gsr_ctx *ctx, const gsr_state *state, int64_t *K, int32_t *ra
 int gsr_loss_l1(gsr_ctx *ctx, const float *color, const float *depth, const float *tgt_color,
                 const float *tgt_depth, int64_t n_pixels, float w_color, float w_depth, float *loss,
                 float *dL_dcolor, float *dL_ddepth);
+
+/* Isotropic scale regulariser (Eq. 11): L_reg = (1/N) sum_k |s_k - sbar_k|_1
+ * with sbar_k = (s_k,x + s_k,y + s_k,z) / 3, the mean of Gaussian k's own
+ * scales (activated scales; sign(0) = 0 in the gradient).
+ * ACCUMULATES: *loss += weight L_reg and, if dL_dscales != NULL,
+ * dL_dscales += weight dL_reg/dscales, so it runs after gsr_render_bwd (which
+ * overwrites the parameter gradients). scales, dL_dscales: device float [n,3];
+ * loss: device float[1]; n >= 0 (n = 0 adds nothing); weight finite. */
+int gsr_loss_reg(gsr_ctx *ctx, const float *scales, int64_t n, float weight, float *loss, float *dL_dscales);
 
 /* SSIM term of the mapping colour loss (Eq. 10: L_color = (1 - lambda) L1 +
  * lambda (1 - SSIM)), with SSIM as Wang et al. 2004 define it and the paper
@@ -321,7 +332,7 @@ int gsr_initnet_adam(gsr_ctx *ctx, gsr_initnet *net, float lr, float beta1, floa
 
 /* Stage timing for benchmarks: while enabled, every stage a call enqueues
  * (project, bin_count, tile_bins, render_fwd, fill, render_bwd, project_bwd,
- * project_bwd_adam, loss_l1, loss_ssim, loss_track, adam, pose_adam, track_graph,
+ * project_bwd_adam, loss_l1, loss_reg, loss_ssim, loss_track, adam, pose_adam, track_graph,
  * initnet_fwd, initnet_bwd) is bracketed by a pair of HIP events on the context's stream.
  * The events carry no system-scope fence, so they do not write back or
  * invalidate caches, but each still costs a few microseconds of stream time. */

@@ -607,6 +607,8 @@ int gsr_render_bwd_adam(gsr_ctx* c, gsr_state* s, const float* dL_dcolor, const 
   A.eps = adam->eps;
   A.bc1 = (float)(1.0 - std::pow((double)adam->beta1, (double)adam->step));
   A.bc2 = (float)(1.0 - std::pow((double)adam->beta2, (double)adam->step));
+  if (!std::isfinite(adam->scale_reg)) return fail(c, GSR_EINVAL, "scale_reg must be finite");
+  A.reg_w = s->g.n > 0 ? (float)((double)adam->scale_reg / (double)s->g.n) : 0.f;
   A.on = true;
   GSR_HIP(c, hipSetDevice(c->device));
   enqueue_bwd(c, s, c->stream, dL_dcolor, dL_ddepth, dL_dalpha, nullptr, nullptr, nullptr, &A);
@@ -642,6 +644,16 @@ int gsr_loss_l1(gsr_ctx* c, const float* color, const float* depth, const float*
   gsr::launch_loss_l1(color, depth, tgt_color, tgt_depth, P, w_color, w_depth, loss, dL_dcolor, dL_ddepth, c->red,
                       c->stream);
   return check_launch(c, "gsr_loss_l1");
+}
+
+int gsr_loss_reg(gsr_ctx* c, const float* scales, int64_t n, float weight, float* loss, float* dL_dscales) {
+  if (!c) return GSR_EINVAL;
+  if (n < 0 || !loss || !std::isfinite(weight) || (n > 0 && !scales))
+    return fail(c, GSR_EINVAL, "bad regulariser arguments");
+  GSR_HIP(c, hipSetDevice(c->device));
+  Stage t(c, "loss_reg");
+  gsr::launch_loss_reg(scales, n, weight, loss, dL_dscales, c->red, c->stream);
+  return check_launch(c, "gsr_loss_reg");
 }
 
 int gsr_loss_ssim(gsr_ctx* c, const float* color, const float* tgt_color, int32_t width, int32_t height, float weight,

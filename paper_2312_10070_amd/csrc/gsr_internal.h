@@ -292,8 +292,26 @@ struct AdamFused {
   float *p[5], *m[5], *v[5];
   float lr[5];
   float b1, b2, eps, bc1, bc2;
+  float reg_w;  // Eq. 11 weight lambda_reg / N added to the scale gradient before the step; 0 = none
   bool on;
 };
+
+// Isotropic scale regulariser (Eq. 11) of one Gaussian: returns
+// sum_i |s_i - sbar| with sbar = (s0 + s1 + s2) / 3, and writes
+// d[j] = w (sign(r_j) - mean_i sign(r_i)), r = s - sbar, sign(0) = 0.
+// Contraction is pinned so every kernel that applies it rounds alike.
+__device__ __forceinline__ float reg_term(float s0, float s1, float s2, float w, float d[3]) {
+#pragma clang fp contract(off)
+  const float sbar = (s0 + s1 + s2) / 3.f;
+  const float r0 = s0 - sbar, r1 = s1 - sbar, r2 = s2 - sbar;
+  const float g0 = (float)((r0 > 0.f) - (r0 < 0.f)), g1 = (float)((r1 > 0.f) - (r1 < 0.f)),
+              g2 = (float)((r2 > 0.f) - (r2 < 0.f));
+  const float gm = (g0 + g1 + g2) / 3.f;
+  d[0] = w * (g0 - gm);
+  d[1] = w * (g1 - gm);
+  d[2] = w * (g2 - gm);
+  return fabsf(r0) + fabsf(r1) + fabsf(r2);
+}
 
 struct ProjectBwdArgs {
   int64_t n;
@@ -324,6 +342,10 @@ void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 int64_t reduce_temp_words();
 void launch_loss_l1(const float* C, const float* D, const float* Ct, const float* Dt, int64_t P, float wc, float wd,
                     float* loss, float* gC, float* gD, uint32_t* red, hipStream_t s);
+// Adds weight * L_reg (Eq. 11) of scales [n,3] to *loss and, if g != NULL, its
+// gradient to g [n,3].
+void launch_loss_reg(const float* scales, int64_t n, float weight, float* loss, float* g, uint32_t* red,
+                     hipStream_t s);
 // Adds weight (1 - SSIM(X, Y)) to *loss and its gradient to gX ([3,H,W]).
 void launch_loss_ssim(const float* X, const float* Y, int H, int W, float weight, float* loss, float* gX,
                       uint32_t* red, hipStream_t s);

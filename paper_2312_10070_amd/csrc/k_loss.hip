@@ -467,6 +467,25 @@ __global__ __launch_bounds__(256, 2) void k_loss_ssim(const float* __restrict__ 
   grid_sum(lsum, loss, red, true, lscale, loffset);
 }
 
+// ---- isotropic scale regulariser (Eq. 11) -----------------------------------
+// *loss += lscale * sum_k sum_i |s_k,i - sbar_k|; g (if non-NULL) += the gradient
+// with weight w per Gaussian (the same reg_term the fused mapping step applies).
+__global__ __launch_bounds__(256) void k_loss_reg(const float* __restrict__ S, int64_t n, float w, float lscale,
+                                                 float* __restrict__ loss, float* __restrict__ g,
+                                                 uint32_t* __restrict__ red) {
+  float acc = 0.f;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    float d[3];
+    acc += reg_term(S[3 * k], S[3 * k + 1], S[3 * k + 2], w, d);
+    if (g) {
+      g[3 * k] += d[0];
+      g[3 * k + 1] += d[1];
+      g[3 * k + 2] += d[2];
+    }
+  }
+  grid_sum(acc, loss, red, true, lscale, 0.f);
+}
+
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
                                              const float* __restrict__ g, int64_t n, float lr, float b1, float b2,
                                              float eps, float bc1, float bc2) {
@@ -621,6 +640,13 @@ void launch_loss_ssim(const float* X, const float* Y, int H, int W, float weight
   const int grid = 3 * n_tiles < kRedSlots ? 3 * n_tiles : kRedSlots;
   hipLaunchKernelGGL(k_loss_ssim, dim3(grid), dim3(256), 0, s, X, Y, H, W, tiles_x, n_tiles, win,
                      (float)(-weight / n), (float)(-weight / n), weight, loss, gX, red);
+}
+
+void launch_loss_reg(const float* scales, int64_t n, float weight, float* loss, float* g, uint32_t* red,
+                     hipStream_t s) {
+  if (n <= 0) return;  // nothing to add
+  const float w = (float)((double)weight / (double)n);
+  hipLaunchKernelGGL(k_loss_reg, dim3(grid_for(n, 2048)), dim3(256), 0, s, scales, n, w, w, loss, g, red);
 }
 
 int64_t track_temp_words() { return kSelWords + kRedWords; }

@@ -375,6 +375,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a
       __syncthreads();
     }
   }
+  if (a.adam.on && a.adam.reg_w != 0.f && k < a.n) {
+    float d[3];
+    (void)reg_term(a.scales[3 * k], a.scales[3 * k + 1], a.scales[3 * k + 2], a.adam.reg_w, d);
+    gs[0] += d[0];
+    gs[1] += d[1];
+    gs[2] += d[2];
+  }
   if (a.adam.on) {
     // Stage the workgroup's gradients in LDS in parameter order, then run Adam
     // over each group's contiguous range with 16-byte accesses.

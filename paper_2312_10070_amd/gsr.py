@@ -51,7 +51,7 @@ class Grads(ctypes.Structure):
 class Adam5(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p * 5), ("exp_avg", ctypes.c_void_p * 5), ("exp_avg_sq", ctypes.c_void_p * 5),
                 ("lr", ctypes.c_float * 5), ("step", ctypes.c_int64), ("beta1", ctypes.c_float),
-                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("scale_reg", ctypes.c_float)]
 
 
 class TrackOpts(ctypes.Structure):
@@ -84,6 +84,7 @@ _SIGS = {
     "gsr_state_release": (ctypes.c_int, [P, P]),
     "gsr_tile_lists": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_int64), P, P]),
     "gsr_loss_l1": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P]),
+    "gsr_loss_reg": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_float, P, P]),
     "gsr_loss_ssim": (ctypes.c_int, [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P, P]),
     "gsr_loss_track": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P, P]),
     "gsr_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
@@ -343,9 +344,10 @@ PARAM_GROUPS = ("means", "scales", "quats", "opacities", "colors")
 
 
 def render_bwd_adam(state: State, dL_dcolor, dL_ddepth, exp_avg: dict, exp_avg_sq: dict, lrs: dict, step: int,
-                    dL_dalpha=None, beta1=0.9, beta2=0.999, eps=1e-8):
+                    dL_dalpha=None, beta1=0.9, beta2=0.999, eps=1e-8, scale_reg=0.0):
     """Backward fused with one Adam step on the five parameter tensors the
-    forward read (updated in place, as are the moments; keyed by PARAM_GROUPS)."""
+    forward read (updated in place, as are the moments; keyed by PARAM_GROUPS).
+    scale_reg = lambda_reg adds the Eq. 11 regulariser's gradient to the scales'."""
     ctx = state.ctx
     ctx.sync_stream()
     params = dict(zip(PARAM_GROUPS, state.keep[:5]))
@@ -364,6 +366,7 @@ def render_bwd_adam(state: State, dL_dcolor, dL_ddepth, exp_avg: dict, exp_avg_s
         a.lr[i] = float(lrs[k])
     a.step = int(step)
     a.beta1, a.beta2, a.eps = float(beta1), float(beta2), float(eps)
+    a.scale_reg = float(scale_reg)
     ctx.check(ctx.lib.gsr_render_bwd_adam(ctx.h, state.h, _ptr(gC), _ptr(gD), _ptr(gA), ctypes.byref(a)))
 
 
@@ -393,6 +396,22 @@ def loss_l1(color, depth, tgt_color, tgt_depth, w_color=1.0, w_depth=1.0, ctx: C
     ctx.check(ctx.lib.gsr_loss_l1(ctx.h, _ptr(color), _ptr(depth), _ptr(tgt_color), _ptr(tgt_depth), P_,
                                   float(w_color), float(w_depth), _ptr(loss), _ptr(gC), _ptr(gD)))
     return loss, gC, gD
+
+
+def loss_reg(scales, weight, loss, dL_dscales=None, ctx: Context | None = None):
+    """Isotropic scale regulariser (Eq. 11), in place: loss [1] += weight L_reg and,
+    if given, dL_dscales [n,3] += its gradient."""
+    ctx = ctx or Context.get(scales.device.index or 0)
+    ctx.sync_stream()
+    _f32(scales, "scales")
+    _f32(loss, "loss")
+    if scales.dim() != 2 or scales.shape[1] != 3 or loss.numel() != 1:
+        raise ValueError("scales must be [n, 3] and loss must hold one float")
+    if dL_dscales is not None:
+        _f32(dL_dscales, "dL_dscales", tuple(scales.shape))
+    ctx.check(ctx.lib.gsr_loss_reg(ctx.h, _ptr(scales), int(scales.shape[0]), float(weight), _ptr(loss),
+                                   _ptr(dL_dscales)))
+    return loss
 
 
 def loss_ssim(color, tgt_color, weight, loss, dL_dcolor, ctx: Context | None = None):

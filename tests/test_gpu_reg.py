@@ -1,0 +1,121 @@
+"""Isotropic scale regulariser (Eq. 11) on the HIP path vs the FP64 oracle, and
+its gradient fused into the mapping step's Adam (gsr_render_bwd_adam with
+scale_reg) vs the separate calls.
+
+Bar: value within 1e-5 relative; gradient within 1e-6 relative per element
+(its values are w times one of 0, 1/3, 2/3, 1, 4/3 in magnitude), except where r = s - sbar is
+within rounding of zero (|r| < 1e-6 sbar), where FP32 and FP64 may take the
+sign differently: those elements are only checked to be one of the valid values."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_10070_amd import gsr
+from tests import gpu_cases as G
+
+pytestmark = pytest.mark.gpu
+
+
+def torch_():
+    import torch
+    return torch
+
+
+def scales_case(n, seed=0):
+    rng = np.random.default_rng(seed)
+    s = np.exp(rng.normal(-3.0, 0.3, (n, 3))).astype(np.float32)
+    m = min(n, 7)
+    s[:m] = np.repeat(rng.integers(1, 64, (m, 1)) / 64.0, 3, axis=1)  # exactly isotropic
+    if n > 7:
+        s[7] = (0.01, 0.02, 0.03)
+    return s
+
+
+@pytest.mark.parametrize("n", [1, 255, 100_003])
+def test_loss_reg_matches_oracle_and_accumulates(n):
+    torch = torch_()
+    s = scales_case(n)
+    L_ref, g_ref = oracle.loss_reg(s)
+    lam = 0.7
+    w = lam / n
+    rng = np.random.default_rng(n)
+    g0 = (rng.normal(0, w, s.shape)).astype(np.float32)
+    sd = torch.from_numpy(s).cuda()
+    loss = torch.full((1,), 0.25, device="cuda")
+    gd = torch.from_numpy(g0).cuda()
+    gsr.loss_reg(sd, lam, loss, gd)
+    torch.cuda.synchronize()
+    assert abs((loss.item() - 0.25) - lam * L_ref) <= 1e-5 * lam * L_ref + 1e-7
+    got = gd.cpu().numpy().astype(np.float64) - g0
+    ref = lam * g_ref
+    s64 = s.astype(np.float64)
+    amb = np.abs(s64 - s64.mean(1, keepdims=True)) < 1e-6 * s64.mean(1, keepdims=True)
+    amb = np.repeat(amb.any(1, keepdims=True), 3, axis=1)  # one ambiguous sign moves the whole row
+    ok = ~amb
+    np.testing.assert_allclose(got[ok], ref[ok], rtol=1e-6, atol=1e-6 * w)
+    valid = np.array([0, 1 / 3, 2 / 3, 1, 4 / 3]) * w
+    dist = np.min(np.abs(np.abs(got[amb])[:, None] - valid[None, :]), axis=1)
+    assert (dist <= 1e-6 * w).all()
+    # value only, and an empty set
+    loss.zero_()
+    gsr.loss_reg(sd, lam, loss)
+    gsr.loss_reg(sd[:0], lam, loss)
+    torch.cuda.synchronize()
+    assert abs(loss.item() - lam * L_ref) <= 1e-5 * lam * L_ref + 1e-7
+
+
+def test_fused_regulariser_matches_separate_calls():
+    """gsr_render_bwd_adam with scale_reg equals gsr_render_bwd, then
+    gsr_loss_reg into the scale gradient, then gsr_adam_groups (up to the order
+    of the compositing backward's float atomics)."""
+    torch = torch_()
+    g, _, pose, cam = G.c1_case(0)
+    camera = gsr.make_camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near_z, cam.bg)
+    keys = gsr.PARAM_GROUPS
+    lrs = {"means": 1e-3, "scales": 5e-4, "quats": 2e-3, "opacities": 1e-2, "colors": 5e-3}
+    lam = 1.0
+    runs = []
+    for fused in (False, True):
+        d = {k: v.clone() for k, v in G.to_dev(g).items()}
+        m = {k: torch.zeros_like(d[k]) for k in keys}
+        v = {k: torch.zeros_like(d[k]) for k in keys}
+        pd = torch.from_numpy(np.asarray(pose, np.float32)).cuda()
+        c, dep, _, st = gsr.render_fwd(d["means"], d["scales"], d["quats"], d["opacities"], d["colors"], pd, camera)
+        gC = torch.full_like(c, 1e-3) * torch.sign(c - 0.3)
+        gD = torch.full_like(dep, 1e-3) * torch.sign(dep - 1.0)
+        if fused:
+            gsr.render_bwd_adam(st, gC, gD, m, v, lrs, 1, scale_reg=lam)
+        else:
+            gr = gsr.render_bwd(st, gC, gD, None, want_params=True, want_pose=False)
+            loss = torch.zeros(1, device="cuda")
+            gsr.loss_reg(d["scales"], lam, loss, gr["scales"])
+            gsr.adam_groups([d[k] for k in keys], [m[k] for k in keys], [v[k] for k in keys],
+                            [gr[k] for k in keys], [lrs[k] for k in keys], 1)
+        torch.cuda.synchronize()
+        st.release()
+        runs.append({k: (d[k].cpu().numpy(), m[k].cpu().numpy(), v[k].cpu().numpy()) for k in keys})
+    sep, fus = runs
+    for k in keys:
+        np.testing.assert_allclose(fus[k][0], sep[k][0], rtol=1e-6, atol=1e-7, err_msg=k)
+        np.testing.assert_allclose(fus[k][1], sep[k][1], rtol=1e-4, atol=1e-12, err_msg=k)
+        np.testing.assert_allclose(fus[k][2], sep[k][2], rtol=1e-4, atol=1e-15, err_msg=k)
+    # the regulariser reached every Gaussian, visible or not: the scale moments carry its gradient
+    _, g_reg = oracle.loss_reg(np.asarray(g["scales"], np.float32))
+    m_s = fus["scales"][1]
+    far = np.abs(g_reg) > 0
+    assert (m_s[far] != 0).all()
+
+
+def test_loss_reg_bad_arguments():
+    import ctypes
+    torch = torch_()
+    ctx = gsr.Context.get(0)
+    loss = torch.zeros(1, device="cuda")
+    s = torch.ones((4, 3), device="cuda")
+    lp, sp = ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(s.data_ptr())
+    assert ctx.lib.gsr_loss_reg(ctx.h, sp, -1, 1.0, lp, None) == gsr.GSR_EINVAL
+    assert ctx.lib.gsr_loss_reg(ctx.h, None, 4, 1.0, lp, None) == gsr.GSR_EINVAL
+    assert ctx.lib.gsr_loss_reg(ctx.h, sp, 4, float("inf"), lp, None) == gsr.GSR_EINVAL
+    assert ctx.lib.gsr_loss_reg(ctx.h, sp, 4, 1.0, None, None) == gsr.GSR_EINVAL
+    with pytest.raises(ValueError):
+        gsr.loss_reg(torch.ones((4, 2), device="cuda"), 1.0, loss)
