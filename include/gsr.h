@@ -186,6 +186,19 @@ int gsr_loss_l1(gsr_ctx *ctx, const float *color, const float *depth, const floa
                 const float *tgt_depth, int64_t n_pixels, float w_color, float w_depth, float *loss,
                 float *dL_dcolor, float *dL_ddepth);
 
+/* Opacity pruning (supplement, mapping: at the middle and the end of a new
+ * keyframe's iterations, Gaussians with opacity below o_thre are removed;
+ * o_thre = 0.1 on Replica-like data, 0.5 otherwise). Stable compaction:
+ * Gaussian i is kept iff opacities[i] >= o_thre (NaN is removed) and the kept
+ * ones are written, in their order, to rows 0..n_kept-1 of the outputs.
+ * in[0..4] = means [n,3], scales [n,3], quats [n,4], opacities [n], colors [n,3];
+ * in[5..9] and in[10..14] = the matching Adam exp_avg / exp_avg_sq tensors,
+ * each entry NULL if absent (out[t] must be NULL exactly where in[t] is).
+ * Outputs are device buffers of the inputs' shapes (n rows), not aliased with
+ * any input. *n_kept (host) receives the count. Allocates temporary device
+ * memory and synchronises the context's stream. 0 <= n < 2^31. */
+int gsr_prune(gsr_ctx *ctx, int64_t n, float o_thre, const float *const *in, float *const *out, int64_t *n_kept);
+
 /* Isotropic scale regulariser (Eq. 11): L_reg = (1/N) sum_k |s_k - sbar_k|_1
  * with sbar_k = (s_k,x + s_k,y + s_k,z) / 3, the mean of Gaussian k's own
  * scales (activated scales; sign(0) = 0 in the gradient).
@@ -332,7 +345,7 @@ int gsr_initnet_adam(gsr_ctx *ctx, gsr_initnet *net, float lr, float beta1, floa
 
 /* Stage timing for benchmarks: while enabled, every stage a call enqueues
  * (project, bin_count, tile_bins, render_fwd, fill, render_bwd, project_bwd,
- * project_bwd_adam, loss_l1, loss_reg, loss_ssim, loss_track, adam, pose_adam, track_graph,
+ * project_bwd_adam, loss_l1, loss_reg, loss_ssim, loss_track, prune, adam, pose_adam, track_graph,
  * initnet_fwd, initnet_bwd) is bracketed by a pair of HIP events on the context's stream.
  * The events carry no system-scope fence, so they do not write back or
  * invalidate caches, but each still costs a few microseconds of stream time. */

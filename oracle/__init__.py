@@ -217,6 +217,17 @@ def loss_l1(C, D, Ct, Dt, w_color=1.0, w_depth=1.0):
     return float(loss[0]), gC, gD
 
 
+def prune(groups, o_thre: float):
+    """Opacity pruning (supplement, mapping): Gaussian i is kept iff its opacity
+    >= o_thre (NaN is not), and the kept rows stay in their order. groups: a
+    list of dicts of arrays with N rows, the first holding "opacities"; the
+    decision is taken in binary32, the precision the opacities are stored in.
+    Returns (n_kept, [dict of kept rows per group])."""
+    o = np.asarray(groups[0]["opacities"], np.float32)
+    keep = o >= np.float32(o_thre)
+    return int(keep.sum()), [{k: np.asarray(v)[keep] for k, v in g.items()} for g in groups]
+
+
 def loss_reg(scales):
     """Eq. 11 on [N,3] scales: (L_reg, dL_reg/dscales [N,3])."""
     lib = _load()

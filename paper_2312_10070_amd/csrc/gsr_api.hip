@@ -646,6 +646,40 @@ int gsr_loss_l1(gsr_ctx* c, const float* color, const float* depth, const float*
   return check_launch(c, "gsr_loss_l1");
 }
 
+int gsr_prune(gsr_ctx* c, int64_t n, float o_thre, const float* const* in, float* const* out, int64_t* n_kept) {
+  if (!c) return GSR_EINVAL;
+  if (n < 0 || n > (int64_t)0x7fffffff || !in || !out || !n_kept || std::isnan(o_thre))
+    return fail(c, GSR_EINVAL, "bad prune arguments");
+  gsr::PruneArgs a{};
+  for (int t = 0; t < 15; ++t) {
+    if ((in[t] == nullptr) != (out[t] == nullptr)) return fail(c, GSR_EINVAL, "prune: in[t] and out[t] must both be set or both be NULL");
+    if (t < 5 && n > 0 && !in[t]) return fail(c, GSR_EINVAL, "prune: the five parameter tensors are required");
+    a.in[t] = in[t];
+    a.out[t] = out[t];
+  }
+  GSR_HIP(c, hipSetDevice(c->device));
+  uint32_t* temp = nullptr;
+  uint32_t* kept = nullptr;
+  GSR_HIP(c, hipMalloc((void**)&temp, sizeof(uint32_t) * gsr::prune_temp_words(n)));
+  if (hipHostMalloc((void**)&kept, sizeof(uint32_t), hipHostMallocMapped) != hipSuccess) {
+    (void)hipFree(temp);
+    return fail(c, GSR_ENOMEM, "prune: pinned count");
+  }
+  uint32_t* kept_dev = nullptr;
+  hipError_t e = hipHostGetDevicePointer((void**)&kept_dev, kept, 0);
+  if (e == hipSuccess) {
+    Stage t(c, "prune");
+    gsr::launch_prune(a, n, o_thre, temp, kept_dev, c->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) *n_kept = (int64_t)*(volatile uint32_t*)kept;
+  (void)hipFree(temp);
+  (void)hipHostFree(kept);
+  if (e != hipSuccess) return fail(c, GSR_EHIP, hipGetErrorString(e));
+  return GSR_OK;
+}
+
 int gsr_loss_reg(gsr_ctx* c, const float* scales, int64_t n, float weight, float* loss, float* dL_dscales) {
   if (!c) return GSR_EINVAL;
   if (n < 0 || !loss || !std::isfinite(weight) || (n > 0 && !scales))

@@ -430,4 +430,40 @@ void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_f32, dim3(fill_blocks(n)), dim3(256), 0, s, p, v, n);
 }
 
+// ---- opacity pruning: stable compaction of the Gaussians kept -------------
+namespace {
+__global__ __launch_bounds__(256) void k_prune_flag(const float* __restrict__ o, int64_t n, float thre,
+                                                  uint32_t* __restrict__ keep) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) keep[i] = o[i] >= thre ? 1u : 0u;  // NaN is not kept
+}
+
+__global__ __launch_bounds__(256) void k_prune_scatter(PruneArgs a, int64_t n, const uint32_t* __restrict__ keep,
+                                                     const uint32_t* __restrict__ off) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !keep[i]) return;
+  const int64_t j = off[i];
+  constexpr int width[5] = {3, 3, 4, 1, 3};
+#pragma unroll
+  for (int t = 0; t < 15; ++t) {
+    if (!a.in[t]) continue;
+    const int w = width[t % 5];
+    for (int c = 0; c < w; ++c) a.out[t][w * j + c] = a.in[t][w * i + c];
+  }
+}
+}  // namespace
+
+int64_t prune_temp_words(int64_t n) { return 2 * n + scan_temp_words(n) + 1; }
+
+void launch_prune(const PruneArgs& a, int64_t n, float thre, uint32_t* temp, uint32_t* kept_host, hipStream_t s) {
+  uint32_t* keep = temp;
+  uint32_t* off = temp + n;
+  uint32_t* total = temp + 2 * n;
+  uint32_t* scan_tmp = total + 1;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (n > 0) hipLaunchKernelGGL(k_prune_flag, dim3(g), dim3(256), 0, s, a.in[3], n, thre, keep);
+  launch_exclusive_scan(keep, off, n, total, scan_tmp, s, kept_host);
+  if (n > 0) hipLaunchKernelGGL(k_prune_scatter, dim3(g), dim3(256), 0, s, a, n, keep, off);
+}
+
 }  // namespace gsr

@@ -85,6 +85,7 @@ _SIGS = {
     "gsr_tile_lists": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_int64), P, P]),
     "gsr_loss_l1": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P]),
     "gsr_loss_reg": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_float, P, P]),
+    "gsr_prune": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_float, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_loss_ssim": (ctypes.c_int, [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P, P]),
     "gsr_loss_track": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P, P]),
     "gsr_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
@@ -396,6 +397,35 @@ def loss_l1(color, depth, tgt_color, tgt_depth, w_color=1.0, w_depth=1.0, ctx: C
     ctx.check(ctx.lib.gsr_loss_l1(ctx.h, _ptr(color), _ptr(depth), _ptr(tgt_color), _ptr(tgt_depth), P_,
                                   float(w_color), float(w_depth), _ptr(loss), _ptr(gC), _ptr(gD)))
     return loss, gC, gD
+
+
+def prune(params: dict, o_thre: float, exp_avg: dict | None = None, exp_avg_sq: dict | None = None,
+          ctx: Context | None = None):
+    """Opacity pruning (stable compaction of the Gaussians with opacity >= o_thre).
+    params (and the optional Adam moments) are keyed by PARAM_GROUPS; returns
+    (n_kept, params, exp_avg, exp_avg_sq) as new tensors of n_kept rows."""
+    ctx = ctx or Context.get(params["means"].device.index or 0)
+    ctx.sync_stream()
+    n = params["opacities"].shape[0]
+    groups = [params, exp_avg, exp_avg_sq]
+    ins = (P * 15)()
+    outs = (P * 15)()
+    res = [None, None, None]
+    for gi, grp in enumerate(groups):
+        if grp is None:
+            continue
+        res[gi] = {}
+        for i, k in enumerate(PARAM_GROUPS):
+            t = _f32(grp[k], k, tuple(params[k].shape))
+            o = torch.empty_like(t)
+            ins[5 * gi + i] = _ptr(t)
+            outs[5 * gi + i] = _ptr(o)
+            res[gi][k] = o
+    kept = ctypes.c_int64()
+    ctx.check(ctx.lib.gsr_prune(ctx.h, n, float(o_thre), ins, outs, ctypes.byref(kept)))
+    m = kept.value
+    res = [None if r is None else {k: v[:m] for k, v in r.items()} for r in res]
+    return m, res[0], res[1], res[2]
 
 
 def loss_reg(scales, weight, loss, dL_dscales=None, ctx: Context | None = None):

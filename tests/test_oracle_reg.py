@@ -51,3 +51,17 @@ def test_gradient_matches_central_differences():
         sm = s.copy(); sm[i] -= h
         fd[i] = (oracle.loss_reg(sp)[0] - oracle.loss_reg(sm)[0]) / (2 * h)
     np.testing.assert_allclose(g, fd, rtol=0, atol=1e-6 * np.abs(fd).max())
+
+
+def test_prune_definition():
+    # supplement: Gaussians with opacity below the threshold are removed
+    o = np.array([0.05, 0.1, 0.5, np.nan, 0.0999999, 1.0], np.float32)
+    means = np.arange(18, dtype=np.float32).reshape(6, 3)
+    n, (kept,) = oracle.prune([{"opacities": o, "means": means}], 0.1)
+    assert n == 3
+    np.testing.assert_array_equal(kept["opacities"], np.array([0.1, 0.5, 1.0], np.float32))
+    np.testing.assert_array_equal(kept["means"], means[[1, 2, 5]])
+    n2, (again,) = oracle.prune([kept], 0.1)  # idempotent
+    assert n2 == 3 and all(np.array_equal(again[k], kept[k]) for k in kept)
+    assert oracle.prune([{"opacities": o}], float("inf"))[0] == 0
+    assert oracle.prune([{"opacities": o}], -float("inf"))[0] == 5  # NaN still removed
