@@ -428,7 +428,7 @@ def main() -> int:
     ap.add_argument("--gaussians", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows-every", type=int, default=68)
-    ap.add_argument("--no-ssim", action="store_true", help="skip the loop with the whole Eq. 12 mapping loss")
+    ap.add_argument("--no-full-loss", action="store_true", help="skip the loop with the whole Eq. 12 mapping loss")
     ap.add_argument("--no-tracking", action="store_true")
     ap.add_argument("--tracking-frames", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
@@ -545,7 +545,7 @@ def main() -> int:
     roof["avg_ms"] = round(avg_ms, 4)
 
     ssim = None
-    if not args.no_ssim:
+    if not args.no_full_loss:
         # the same iteration with the whole mapping loss of Eq. 12 (after the headline's timed region)
         k = max(5, min(args.steps, 20))
         for _ in range(2):
