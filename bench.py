@@ -429,6 +429,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows-every", type=int, default=68)
     ap.add_argument("--no-full-loss", action="store_true", help="skip the loop with the whole Eq. 12 mapping loss")
+    ap.add_argument("--no-seed", action="store_true", help="skip the seeding neighbour-query measurement")
     ap.add_argument("--no-tracking", action="store_true")
     ap.add_argument("--tracking-frames", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
@@ -574,6 +575,42 @@ def main() -> int:
                              "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": read_traffic("loss_ssim", "H"),
                              "kernel": "loss_ssim", "avg_ms": round(ssim_ms, 4)}}
 
+    seed = None
+    if not args.no_seed:
+        # seeding neighbour queries (radius test rho = 1 cm, nearest-neighbour scale up to 5 cm) of 100,000
+        # candidate points near the surface (sub-map means moved by N(0, 1 cm)) against the 500K sub-map
+        g_seed = torch.Generator(device="cpu").manual_seed(args.seed)
+        m_q = 100_000
+        pick = torch.randint(0, n, (m_q,), generator=g_seed)
+        cand = (params["means"].cpu()[pick] + 0.01 * torch.randn(m_q, 3, generator=g_seed)).to(dev).contiguous()
+        gsr.seed_query(params["means"], cand, 0.01, 0.05)
+        gsr.profile_read()
+        gsr.profile_only("seed_query")
+        gsr.profile_enable(True)
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            nn_d2, keep = gsr.seed_query(params["means"], cand, 0.01, 0.05)
+        t1 = time.perf_counter()
+        gsr.profile_enable(False)
+        gsr.profile_only(None)
+        rec = gsr.profile_read()["seed_query"]
+        dev_ms = rec[0] / rec[1]
+        T = 1024
+        while T < 2 * n:
+            T *= 2
+        # means read twice and written once into the grid (12 + 12 + 16 B), four words per bucket, candidates
+        # read and both outputs written (12 + 8 B)
+        seed_bytes = n * 40.0 + T * 16.0 + m_q * 20.0
+        ach = seed_bytes / (dev_ms * 1e-3) / 1e9
+        seed = {"workload": "seeding neighbour queries: 100,000 candidates vs the 500K sub-map, rho 1 cm, "
+                            "nearest-neighbour scale up to 5 cm, spatial hash grid built per call",
+                "device_ms": round(dev_ms, 4), "call_ms": round((t1 - t0) / reps * 1000.0, 3),
+                "queries_per_s": round(m_q / (dev_ms * 1e-3), 1), "kept": int(keep.sum().item()),
+                "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "seed_query",
+                             "avg_ms": round(dev_ms, 4)}}
+
     if args.calib_copy_mib > 0:
         nbytes = args.calib_copy_mib << 20
         a = torch.empty(nbytes // 4, device=dev, dtype=torch.float32).fill_(1.0)
@@ -621,6 +658,7 @@ def main() -> int:
         "stages_ms_per_step": {k: round(v[0] / n_stage_steps, 4) for k, v in sorted(stage_pass.items())},
         "work": stats,
         "mapping_full_loss": ssim,
+        "seeding_query": seed,
         "tracking": track,
         "batched_mapping": batched,
         "learned_init": learned,

@@ -186,6 +186,23 @@ int gsr_loss_l1(gsr_ctx *ctx, const float *color, const float *depth, const floa
                 const float *tgt_depth, int64_t n_pixels, float w_color, float w_depth, float *loss,
                 float *dL_dcolor, float *dL_ddepth);
 
+/* Neighbour queries of the seeding step (Sec. 3.2: a sampled point becomes a
+ * new Gaussian only if the active sub-map has no Gaussian within the search
+ * radius rho; the supplement sets a new Gaussian's scale from its
+ * nearest-neighbour distance in the sub-map). For each query point q_j:
+ *   nn_d2[j] = min(r_max^2, min_i d2(q_j, p_i)),  keep[j] = (nn_d2[j] >= rho^2),
+ * with d2 = (dx^2 + dy^2) + dz^2 in FP32 without contraction, r_max^2 and rho^2
+ * rounded to FP32, and p_i the n sub-map means. The nearest-neighbour distance
+ * is searched up to r_max (distances beyond it read as r_max^2).
+ * means [n,3], points [m,3]: device float; nn_d2 [m] float and keep [m] int32
+ * (device; either may be NULL). 0 < rho <= r_max, both finite;
+ * 0 <= n <= 2^27, 0 <= m <= 2^31; coordinates within +-8000 r_max of the
+ * origin (beyond that FP32 cell indices lose the precision the exact search
+ * relies on). Builds a spatial hash grid in temporary device memory and
+ * synchronises the context's stream. */
+int gsr_seed_query(gsr_ctx *ctx, const float *means, int64_t n, const float *points, int64_t m, float rho,
+                   float r_max, float *nn_d2, int32_t *keep);
+
 /* Opacity pruning (supplement, mapping: at the middle and the end of a new
  * keyframe's iterations, Gaussians with opacity below o_thre are removed;
  * o_thre = 0.1 on Replica-like data, 0.5 otherwise). Stable compaction:
@@ -345,7 +362,7 @@ int gsr_initnet_adam(gsr_ctx *ctx, gsr_initnet *net, float lr, float beta1, floa
 
 /* Stage timing for benchmarks: while enabled, every stage a call enqueues
  * (project, bin_count, tile_bins, render_fwd, fill, render_bwd, project_bwd,
- * project_bwd_adam, loss_l1, loss_reg, loss_ssim, loss_track, prune, adam, pose_adam, track_graph,
+ * project_bwd_adam, loss_l1, loss_reg, loss_ssim, loss_track, prune, seed_query, adam, pose_adam, track_graph,
  * initnet_fwd, initnet_bwd) is bracketed by a pair of HIP events on the context's stream.
  * The events carry no system-scope fence, so they do not write back or
  * invalidate caches, but each still costs a few microseconds of stream time. */

@@ -217,6 +217,28 @@ def loss_l1(C, D, Ct, Dt, w_color=1.0, w_depth=1.0):
     return float(loss[0]), gC, gD
 
 
+def seed_query(means, points, rho: float, r_max: float, chunk: int = 128):
+    """Neighbour queries of the seeding step (Sec. 3.2 radius test, the
+    supplement's nearest-neighbour scale), by brute force over every mean:
+    nn_d2[j] = min(r_max^2, min_i d2(q_j, p_i)) with d2 = (dx^2 + dy^2) + dz^2
+    in binary32 (the precision of the stored coordinates; numpy does not fuse),
+    keep[j] = nn_d2[j] >= rho^2. Returns (nn_d2 float32 [m], keep int32 [m])."""
+    p = np.asarray(means, np.float32).reshape(-1, 3)
+    q = np.asarray(points, np.float32).reshape(-1, 3)
+    r2max = np.float32(r_max) * np.float32(r_max)
+    rho2 = np.float32(rho) * np.float32(rho)
+    nn = np.full(q.shape[0], r2max, np.float32)
+    if p.shape[0] > 0:
+        for s in range(0, q.shape[0], chunk):
+            qq = q[s:s + chunk]
+            dx = qq[:, None, 0] - p[None, :, 0]
+            dy = qq[:, None, 1] - p[None, :, 1]
+            dz = qq[:, None, 2] - p[None, :, 2]
+            d2 = (dx * dx + dy * dy) + dz * dz
+            nn[s:s + chunk] = np.minimum(r2max, d2.min(axis=1))
+    return nn, (nn >= rho2).astype(np.int32)
+
+
 def prune(groups, o_thre: float):
     """Opacity pruning (supplement, mapping): Gaussian i is kept iff its opacity
     >= o_thre (NaN is not), and the kept rows stay in their order. groups: a

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgsr.so")
 SOURCES = ["gsr_api.hip", "k_project.hip", "k_sort.hip", "k_raster.hip", "k_loss.hip"]
-EXTRA_SOURCES = ["k_batch.hip", "k_graph.hip", "k_initnet.hip"]
+EXTRA_SOURCES = ["k_batch.hip", "k_graph.hip", "k_initnet.hip", "k_seed.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [

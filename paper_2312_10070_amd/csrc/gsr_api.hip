@@ -646,6 +646,27 @@ int gsr_loss_l1(gsr_ctx* c, const float* color, const float* depth, const float*
   return check_launch(c, "gsr_loss_l1");
 }
 
+int gsr_seed_query(gsr_ctx* c, const float* means, int64_t n, const float* points, int64_t m, float rho, float r_max,
+                   float* nn_d2, int32_t* keep) {
+  if (!c) return GSR_EINVAL;
+  if (n < 0 || n > ((int64_t)1 << 27) || m < 0 || m > ((int64_t)1 << 31) || (n > 0 && !means) ||
+      (m > 0 && !points) || !std::isfinite(rho) || !std::isfinite(r_max) || !(rho > 0.f) || !(r_max >= rho))
+    return fail(c, GSR_EINVAL, "bad seeding query arguments (0 < rho <= r_max, finite)");
+  GSR_HIP(c, hipSetDevice(c->device));
+  uint32_t* temp = nullptr;
+  GSR_HIP(c, hipMalloc((void**)&temp, sizeof(uint32_t) * gsr::seed_temp_words(n)));
+  hipError_t e;
+  {
+    Stage t(c, "seed_query");
+    gsr::launch_seed_query(means, n, points, m, rho, r_max, nn_d2, keep, temp, c->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(temp);
+  if (e != hipSuccess) return fail(c, GSR_EHIP, hipGetErrorString(e));
+  return GSR_OK;
+}
+
 int gsr_prune(gsr_ctx* c, int64_t n, float o_thre, const float* const* in, float* const* out, int64_t* n_kept) {
   if (!c) return GSR_EINVAL;
   if (n < 0 || n > (int64_t)0x7fffffff || !in || !out || !n_kept || std::isnan(o_thre))

@@ -226,6 +226,14 @@ int64_t scan_temp_words(int64_t n);
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* temp,
                            hipStream_t s, uint32_t* total_host = nullptr);
 
+// Seeding neighbour queries (k_seed.hip): nn_d2[j] = min(r_max^2, min_i |q_j - p_i|^2),
+// keep[j] = nn_d2[j] >= rho^2 (either output may be NULL); rho <= r_max.
+// temp: seed_temp_words(n) uint32, 16-byte aligned.
+uint32_t seed_buckets(int64_t n);
+int64_t seed_temp_words(int64_t n);
+void launch_seed_query(const float* means, int64_t n, const float* points, int64_t m, float rho, float r_max,
+                       float* nn_d2, int32_t* keep, uint32_t* temp, hipStream_t s);
+
 // Opacity pruning: in[0..4] = means, scales, quats, opacities, colors
 // (widths 3, 3, 4, 1, 3), in[5..9] / in[10..14] their Adam moments (NULL =
 // absent; out[t] NULL exactly where in[t] is). Keeps the Gaussians with

@@ -1,0 +1,115 @@
+// Neighbour queries of the seeding step (Sec. 3.2: a sampled point becomes a
+// new Gaussian only if no Gaussian of the active sub-map lies within the
+// search radius rho; the supplement sets the new Gaussian's scale from its
+// nearest-neighbour distance in the sub-map).
+//
+// A spatial hash grid over the sub-map's means answers both with one search:
+// the cell edge h is r_max (1 + 1e-3), so every mean within r_max of a query
+// lies in the 27 cells around the query's cell, whatever the rounding of the
+// cell index (cell coordinates below 8192 in magnitude keep that rounding
+// under 1e-3 of a cell). The squared distance (dx^2 + dy^2) + dz^2 is evaluated without
+// contraction, and the minimum is exact, so results do not depend on the
+// order in which the grid is filled.
+#include "gsr_internal.h"
+
+namespace gsr {
+
+namespace {
+
+__device__ __forceinline__ int cell_of(float x, float inv_h) {
+  return (int)floorf(fminf(fmaxf(x * inv_h, -1.0e9f), 1.0e9f));
+}
+
+__device__ __forceinline__ uint32_t bucket_of(int cx, int cy, int cz, uint32_t mask) {
+  const uint32_t h = (uint32_t)cx * 73856093u ^ (uint32_t)cy * 19349663u ^ (uint32_t)cz * 83492791u;
+  return (h ^ (h >> 15)) & mask;
+}
+
+__device__ __forceinline__ float dist2(float ax, float ay, float az, float bx, float by, float bz) {
+#pragma clang fp contract(off)
+  const float dx = ax - bx, dy = ay - by, dz = az - bz;
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+__global__ __launch_bounds__(256) void k_grid_count(const float* __restrict__ p, int64_t n, float inv_h,
+                                                  uint32_t mask, uint32_t* __restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t b = bucket_of(cell_of(p[3 * i], inv_h), cell_of(p[3 * i + 1], inv_h), cell_of(p[3 * i + 2], inv_h),
+                               mask);
+  atomicAdd(&counts[b], 1u);
+}
+
+// cursor: zero on entry; pts[offsets[b] + k] = the k-th mean that reached bucket b
+__global__ __launch_bounds__(256) void k_grid_fill(const float* __restrict__ p, int64_t n, float inv_h, uint32_t mask,
+                                                 const uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor,
+                                                 float4* __restrict__ pts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
+  const uint32_t b = bucket_of(cell_of(x, inv_h), cell_of(y, inv_h), cell_of(z, inv_h), mask);
+  const uint32_t slot = offsets[b] + atomicAdd(&cursor[b], 1u);
+  pts[slot] = make_float4(x, y, z, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_seed_query(const float* __restrict__ q, int64_t m, float inv_h, uint32_t mask,
+                                                  const uint32_t* __restrict__ offsets,
+                                                  const uint32_t* __restrict__ counts, const float4* __restrict__ pts,
+                                                  float r2max, float rho2, float* __restrict__ nn_d2,
+                                                  int32_t* __restrict__ keep) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const float x = q[3 * j], y = q[3 * j + 1], z = q[3 * j + 2];
+  const int cx = cell_of(x, inv_h), cy = cell_of(y, inv_h), cz = cell_of(z, inv_h);
+  float best = r2max;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const uint32_t b = bucket_of(cx + dx, cy + dy, cz + dz, mask);
+        const uint32_t s = offsets[b], e = s + counts[b];
+        for (uint32_t k = s; k < e; ++k) {
+          const float4 pk = pts[k];
+          best = fminf(best, dist2(x, y, z, pk.x, pk.y, pk.z));
+        }
+      }
+  if (nn_d2) nn_d2[j] = best;
+  if (keep) keep[j] = best < rho2 ? 0 : 1;
+}
+
+}  // namespace
+
+uint32_t seed_buckets(int64_t n) {
+  uint32_t t = 1024;
+  while ((int64_t)t < 2 * n && t < (1u << 30)) t <<= 1;
+  return t;
+}
+
+// words before the float4 point array, rounded up to 16 bytes
+static int64_t seed_pts_offset(int64_t T) { return (3 * T + 1 + scan_temp_words(T) + 3) & ~(int64_t)3; }
+
+int64_t seed_temp_words(int64_t n) { return seed_pts_offset(seed_buckets(n)) + 4 * n; }
+
+void launch_seed_query(const float* means, int64_t n, const float* points, int64_t m, float rho, float r_max,
+                       float* nn_d2, int32_t* keep, uint32_t* temp, hipStream_t s) {
+  const uint32_t T = seed_buckets(n);
+  uint32_t* counts = temp;
+  uint32_t* offsets = temp + T;
+  uint32_t* cursor = temp + 2 * (int64_t)T;
+  uint32_t* total = temp + 3 * (int64_t)T;
+  uint32_t* scan_tmp = total + 1;
+  float4* pts = reinterpret_cast<float4*>(temp + seed_pts_offset(T));
+  const float inv_h = (float)(1.0 / ((double)r_max * 1.001));
+  const uint32_t mask = T - 1;
+  launch_fill_u32(counts, 0u, T, s);
+  launch_fill_u32(cursor, 0u, T, s);
+  const unsigned gn = (unsigned)((n + 255) / 256), gm = (unsigned)((m + 255) / 256);
+  if (n > 0) hipLaunchKernelGGL(k_grid_count, dim3(gn), dim3(256), 0, s, means, n, inv_h, mask, counts);
+  launch_exclusive_scan(counts, offsets, T, total, scan_tmp, s);
+  if (n > 0) hipLaunchKernelGGL(k_grid_fill, dim3(gn), dim3(256), 0, s, means, n, inv_h, mask, offsets, cursor, pts);
+  const float r2max = r_max * r_max, rho2 = rho * rho;
+  if (m > 0)
+    hipLaunchKernelGGL(k_seed_query, dim3(gm), dim3(256), 0, s, points, m, inv_h, mask, offsets, counts,
+                       (const float4*)pts, r2max, rho2, nn_d2, keep);
+}
+
+}  // namespace gsr

@@ -85,6 +85,7 @@ _SIGS = {
     "gsr_tile_lists": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_int64), P, P]),
     "gsr_loss_l1": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P]),
     "gsr_loss_reg": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_float, P, P]),
+    "gsr_seed_query": (ctypes.c_int, [P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P]),
     "gsr_prune": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_float, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_loss_ssim": (ctypes.c_int, [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P, P]),
     "gsr_loss_track": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P, P]),
@@ -397,6 +398,23 @@ def loss_l1(color, depth, tgt_color, tgt_depth, w_color=1.0, w_depth=1.0, ctx: C
     ctx.check(ctx.lib.gsr_loss_l1(ctx.h, _ptr(color), _ptr(depth), _ptr(tgt_color), _ptr(tgt_depth), P_,
                                   float(w_color), float(w_depth), _ptr(loss), _ptr(gC), _ptr(gD)))
     return loss, gC, gD
+
+
+def seed_query(means, points, rho: float, r_max: float, ctx: Context | None = None):
+    """Seeding neighbour queries: (nn_d2 [m] float32, keep [m] int32) of the
+    query points [m,3] against the sub-map means [n,3] (see gsr_seed_query)."""
+    ctx = ctx or Context.get(points.device.index or 0)
+    ctx.sync_stream()
+    for t, nme in ((means, "means"), (points, "points")):
+        _f32(t, nme)
+        if t.dim() != 2 or t.shape[1] != 3:
+            raise ValueError(f"{nme} must be [k, 3]")
+    m = points.shape[0]
+    nn = torch.empty(m, device=points.device, dtype=torch.float32)
+    keep = torch.empty(m, device=points.device, dtype=torch.int32)
+    ctx.check(ctx.lib.gsr_seed_query(ctx.h, _ptr(means), int(means.shape[0]), _ptr(points), m, float(rho),
+                                     float(r_max), _ptr(nn), _ptr(keep)))
+    return nn, keep
 
 
 def prune(params: dict, o_thre: float, exp_avg: dict | None = None, exp_avg_sq: dict | None = None,

@@ -1,0 +1,70 @@
+"""Seeding neighbour queries (Sec. 3.2 radius test, the supplement's
+nearest-neighbour scale) on the HIP hash grid vs the oracle's brute force:
+a minimum of FP32 distances and a comparison, so bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_10070_amd import gsr
+
+pytestmark = pytest.mark.gpu
+
+
+def torch_():
+    import torch
+    return torch
+
+
+def dev(a):
+    torch = torch_()
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def run(p, q, rho, r_max):
+    torch = torch_()
+    nn, keep = gsr.seed_query(dev(p), dev(q), rho, r_max)
+    torch.cuda.synchronize()
+    return nn.cpu().numpy(), keep.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,m,rho,r_max", [(20000, 5003, 0.01, 0.05), (1, 7, 0.5, 0.5), (0, 100, 0.01, 0.02),
+                                           (3000, 0, 0.01, 0.02), (50000, 4000, 0.002, 0.2)])
+def test_seed_query_matches_oracle(n, m, rho, r_max):
+    rng = np.random.default_rng(n + m)
+    p = rng.uniform(-1.5, 1.5, (n, 3)).astype(np.float32)
+    near = p[rng.integers(0, max(n, 1), m // 2)] + rng.normal(0, rho, (m // 2, 3)) if n else rng.normal(size=(m // 2, 3))
+    q = np.concatenate([near, rng.uniform(-2, 2, (m - m // 2, 3))]).astype(np.float32)
+    if n and m > 3:
+        q[0] = p[0]           # distance 0: not kept
+        q[1] = p[min(1, n - 1)] + np.float32(r_max) * 3  # beyond r_max
+    nn_ref, keep_ref = oracle.seed_query(p, q, rho, r_max)
+    nn, keep = run(p, q, rho, r_max)
+    np.testing.assert_array_equal(nn, nn_ref)
+    np.testing.assert_array_equal(keep, keep_ref)
+
+
+def test_seed_query_room_scale_sampled():
+    # sub-map of 500,000 means on the surfaces of a room (the mapping workload's
+    # density), 100,000 candidates; the oracle checks a sample of 1,000
+    from paper_2312_10070_amd import synth
+    rng = np.random.default_rng(0)
+    inp = synth.mapping_inputs(0, 500_000)
+    p = inp["gaussians"]["means"].astype(np.float32)
+    q = (p[rng.integers(0, len(p), 100_000)] + rng.normal(0, 0.01, (100_000, 3))).astype(np.float32)
+    rho, r_max = 0.01, 0.1
+    nn, keep = run(p, q, rho, r_max)
+    idx = rng.choice(len(q), 1000, replace=False)
+    nn_ref, keep_ref = oracle.seed_query(p, q[idx], rho, r_max)
+    np.testing.assert_array_equal(nn[idx], nn_ref)
+    np.testing.assert_array_equal(keep[idx], keep_ref)
+    assert 0 < keep.sum() < len(q)
+
+
+def test_seed_query_bad_arguments():
+    torch = torch_()
+    p = dev(np.zeros((4, 3)))
+    for rho, r_max in [(0.0, 1.0), (0.2, 0.1), (float("nan"), 1.0), (0.1, float("inf"))]:
+        with pytest.raises(gsr.GsrError):
+            gsr.seed_query(p, p, rho, r_max)
+    with pytest.raises(ValueError):
+        gsr.seed_query(dev(np.zeros((4, 2))), p, 0.1, 0.2)

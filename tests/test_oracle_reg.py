@@ -65,3 +65,31 @@ def test_prune_definition():
     assert n2 == 3 and all(np.array_equal(again[k], kept[k]) for k in kept)
     assert oracle.prune([{"opacities": o}], float("inf"))[0] == 0
     assert oracle.prune([{"opacities": o}], -float("inf"))[0] == 5  # NaN still removed
+
+
+def test_seed_query_definition():
+    # Sec. 3.2 radius test and the supplement's nearest-neighbour distance
+    p = np.array([[0, 0, 0], [1, 0, 0], [0, 0.5, 0]], np.float32)
+    q = np.array([[0.1, 0, 0], [0, 0.5, 0.004], [5, 5, 5], [0.5, 0.25, 0]], np.float32)
+    nn, keep = oracle.seed_query(p, q, rho=0.01, r_max=0.3)
+    np.testing.assert_allclose(nn, [0.01, 0.004 ** 2, 0.09, 0.09], rtol=1e-6)
+    np.testing.assert_array_equal(keep, [1, 0, 1, 1])
+    nn0, keep0 = oracle.seed_query(np.zeros((0, 3)), q, 0.01, 0.3)
+    assert (nn0 == np.float32(0.3) * np.float32(0.3)).all() and keep0.all()
+
+
+def test_seed_query_matches_kdtree():
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(5)
+    p = rng.uniform(-1, 1, (3000, 3)).astype(np.float32)
+    q = np.concatenate([p[:500] + rng.normal(0, 0.01, (500, 3)), rng.uniform(-1.2, 1.2, (500, 3))]).astype(np.float32)
+    r_max = 0.08
+    nn, keep = oracle.seed_query(p, q, 0.02, r_max)
+    d, _ = cKDTree(p.astype(np.float64)).query(q.astype(np.float64))
+    ref = np.minimum(d, r_max)
+    np.testing.assert_allclose(np.sqrt(nn.astype(np.float64)), ref, rtol=1e-6, atol=1e-7)
+    clear = np.abs(d - 0.02) > 1e-6
+    np.testing.assert_array_equal(keep[clear], (d[clear] >= 0.02).astype(np.int32))
+    perm = rng.permutation(len(p))  # order of the means does not matter
+    nn2, _ = oracle.seed_query(p[perm], q, 0.02, r_max)
+    np.testing.assert_array_equal(nn2, nn)
