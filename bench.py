@@ -123,7 +123,8 @@ STAGE_KERNELS = {"render_bwd": ["k_render_bwd<false>("], "render_fwd": ["k_rende
                  "project": ["k_project("], "project_bwd_adam": ["k_project_bwd("],
                  "loss_ssim": ["k_loss_ssim("]}
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {counter} -d <dir> -o run --output-format csv -- python3 bench.py "
-               "--steps 5 --warmup 2 --no-cpu-baseline --no-tracking --no-batched --no-initnet --calib-copy-mib {mib}")
+               "--steps 5 --warmup 2 --no-cpu-baseline --no-tracking --no-batched --no-initnet --no-seed "
+               "--calib-copy-mib {mib}")
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str, calib_mib: int, workload: str = "H") -> None:
