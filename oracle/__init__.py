@@ -217,6 +217,44 @@ def loss_l1(C, D, Ct, Dt, w_color=1.0, w_depth=1.0):
     return float(loss[0]), gC, gD
 
 
+def seed_candidates(color, depth, alpha, u, pose7, cam: Camera, p_uniform: float, p_grad: float = 0.0,
+                    grad_thre: float = 0.0, alpha_n: float = 0.6):
+    """Candidate points for new Gaussians (Sec. 3.2 with the supplement's alpha_n).
+    A pixel needs a positive observed depth. For a sub-map's first keyframe
+    (alpha None) it is chosen iff u < p_uniform + p_grad * [edge], where edge
+    means the grey image's central-difference gradient exceeds grad_thre
+    (gx^2 + gy^2 > grad_thre^2; grey = ((r + g) + b) / 3; border pixels have no
+    gradient); for later keyframes iff alpha < alpha_n and u < p_uniform. The
+    random numbers u are inputs. These decisions are taken in binary32 (the
+    precision of the images). A chosen pixel (x, y) with depth d back-projects to
+    X_c = ((x - cx) d / fx, (y - cy) d / fy, d) and X_w = R^T (X_c - t) for the
+    world-to-camera pose (q normalised, t), in FP64. Returns (points [m,3],
+    colours [m,3]) in row-major pixel order."""
+    f = np.float32
+    C = np.asarray(color, f); D = np.asarray(depth, f); U = np.asarray(u, f)
+    H, W = D.shape
+    gray = ((C[0] + C[1]) + C[2]) / f(3)
+    gx = np.zeros((H, W), f); gy = np.zeros((H, W), f)
+    gx[1:-1, 1:-1] = gray[1:-1, 2:] - gray[1:-1, :-2]
+    gy[1:-1, 1:-1] = gray[2:, 1:-1] - gray[:-2, 1:-1]
+    edge = (gx * gx + gy * gy) > f(grad_thre) * f(grad_thre)
+    if alpha is None:
+        pick = (D > 0) & (U < np.where(edge, f(p_uniform) + f(p_grad), f(p_uniform)))
+    else:
+        pick = (D > 0) & (np.asarray(alpha, f) < f(alpha_n)) & (U < f(p_uniform))
+    ys, xs = np.nonzero(pick)
+    d = D[ys, xs].astype(np.float64)
+    Xc = np.stack([(xs - cam.cx) * d / cam.fx, (ys - cam.cy) * d / cam.fy, d], 1)
+    q = np.asarray(pose7[:4], np.float64)
+    q = q / np.linalg.norm(q)
+    w, x, y, z = q
+    R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                  [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                  [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+    Xw = (Xc - np.asarray(pose7[4:7], np.float64)) @ R  # rows: R^T (X_c - t)
+    return Xw, C[:, ys, xs].T.astype(np.float64)
+
+
 def seed_query(means, points, rho: float, r_max: float, chunk: int = 128):
     """Neighbour queries of the seeding step (Sec. 3.2 radius test, the
     supplement's nearest-neighbour scale), by brute force over every mean:

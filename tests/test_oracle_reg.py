@@ -93,3 +93,45 @@ def test_seed_query_matches_kdtree():
     perm = rng.permutation(len(p))  # order of the means does not matter
     nn2, _ = oracle.seed_query(p[perm], q, 0.02, r_max)
     np.testing.assert_array_equal(nn2, nn)
+
+
+def test_seed_candidates_definition():
+    from scipy.spatial.transform import Rotation
+    cam = oracle.Camera(4, 3, 2.0, 2.5, 1.5, 1.0)
+    D = np.array([[1, 2, 0, 1], [1, 1, 3, 1], [2, 1, 1, 1]], np.float32)
+    C = np.zeros((3, 3, 4), np.float32)
+    ident = np.array([1, 0, 0, 0, 0, 0, 0.0])
+    # p = 1: every pixel with depth; back-projection by the pinhole model
+    P, _ = oracle.seed_candidates(C, D, None, np.zeros((3, 4)), ident, cam, 1.0)
+    assert len(P) == 11
+    np.testing.assert_allclose(P[0], [(0 - 1.5) * 1 / 2.0, (0 - 1.0) * 1 / 2.5, 1.0])
+    np.testing.assert_allclose(P[1], [(1 - 1.5) * 2 / 2.0, (0 - 1.0) * 2 / 2.5, 2.0])
+    # p = 0 and the alpha mask
+    assert len(oracle.seed_candidates(C, D, None, np.full((3, 4), 0.5), ident, cam, 0.0)[0]) == 0
+    A = np.full((3, 4), 0.9, np.float32); A[1, 1] = 0.5
+    P, _ = oracle.seed_candidates(C, D, A, np.zeros((3, 4)), ident, cam, 1.0)
+    np.testing.assert_allclose(P, [[(1 - 1.5) * 1 / 2.0, 0.0, 1.0]])
+    # a posed camera: the points project back to their pixels and depths
+    rng = np.random.default_rng(0)
+    q = rng.normal(size=4); q /= np.linalg.norm(q)
+    pose = np.concatenate([q, [0.3, -0.2, 1.0]])
+    P, _ = oracle.seed_candidates(C, D, None, np.zeros((3, 4)), pose, cam, 1.0)
+    Rm = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    Xc = P @ Rm.T + pose[4:]
+    ys, xs = np.nonzero(D > 0)
+    np.testing.assert_allclose(Xc[:, 2], D[ys, xs], atol=1e-12)
+    np.testing.assert_allclose(cam.fx * Xc[:, 0] / Xc[:, 2] + cam.cx, xs, atol=1e-12)
+    np.testing.assert_allclose(cam.fy * Xc[:, 1] / Xc[:, 2] + cam.cy, ys, atol=1e-12)
+
+
+def test_seed_candidates_colour_gradient():
+    # a vertical step edge: only the interior pixels next to it have a gradient
+    cam = oracle.Camera(6, 5, 3.0, 3.0, 3.0, 2.5)
+    C = np.zeros((3, 5, 6), np.float32); C[:, :, 3:] = 0.9
+    D = np.ones((5, 6), np.float32)
+    P, col = oracle.seed_candidates(C, D, None, np.full((5, 6), 0.5), np.array([1, 0, 0, 0, 0, 0, 0.0]), cam,
+                                    0.0, 1.0, grad_thre=0.5)
+    xs = np.round(P[:, 0] / P[:, 2] * cam.fx + cam.cx).astype(int)
+    ys = np.round(P[:, 1] / P[:, 2] * cam.fy + cam.cy).astype(int)
+    assert sorted(zip(ys.tolist(), xs.tolist())) == [(y, x) for y in (1, 2, 3) for x in (2, 3)]
+    np.testing.assert_allclose(col[xs == 3], 0.9, atol=1e-7)
