@@ -186,6 +186,26 @@ int gsr_loss_l1(gsr_ctx *ctx, const float *color, const float *depth, const floa
                 const float *tgt_depth, int64_t n_pixels, float w_color, float w_depth, float *loss,
                 float *dL_dcolor, float *dL_ddepth);
 
+/* Candidate points of the seeding step (Sec. 3.2; alpha_n from the
+ * supplement): Bernoulli thinning of a keyframe's pixels with caller-supplied
+ * uniform random numbers u [H,W]. A pixel with positive depth is chosen
+ *   - alpha == NULL (a sub-map's first keyframe): iff u < p_uniform, or
+ *     u < p_uniform + p_grad where the grey image's gradient is an edge:
+ *     grey = ((r + g) + b) / 3, gx / gy = central differences (none on the
+ *     border), gx^2 + gy^2 > grad_thre^2;
+ *   - else (later keyframes; alpha = the rendered alpha [H,W]): iff
+ *     alpha < alpha_n and u < p_uniform.
+ * These decisions are taken in FP32 without contraction. Chosen pixel (x, y)
+ * with depth d back-projects to X_c = ((x - cx) d / fx, (y - cy) d / fy, d)
+ * and X_w = R^T (X_c - t) for the world-to-camera pose7 (device, q normalised
+ * inside). points and colors (device float [W H, 3] capacity) receive the
+ * chosen ones in row-major pixel order; *n_out (host) their count. color
+ * [3,H,W], depth [H,W]; camera by pointer as for rendering. Allocates
+ * temporary device memory and synchronises the context's stream. */
+int gsr_seed_candidates(gsr_ctx *ctx, const gsr_camera *cam, const float *pose7, const float *color,
+                        const float *depth, const float *alpha, const float *u, float p_uniform, float p_grad,
+                        float grad_thre, float alpha_n, float *points, float *colors, int64_t *n_out);
+
 /* Neighbour queries of the seeding step (Sec. 3.2: a sampled point becomes a
  * new Gaussian only if the active sub-map has no Gaussian within the search
  * radius rho; the supplement sets a new Gaussian's scale from its
@@ -362,7 +382,7 @@ int gsr_initnet_adam(gsr_ctx *ctx, gsr_initnet *net, float lr, float beta1, floa
 
 /* Stage timing for benchmarks: while enabled, every stage a call enqueues
  * (project, bin_count, tile_bins, render_fwd, fill, render_bwd, project_bwd,
- * project_bwd_adam, loss_l1, loss_reg, loss_ssim, loss_track, prune, seed_query, adam, pose_adam, track_graph,
+ * project_bwd_adam, loss_l1, loss_reg, loss_ssim, loss_track, prune, seed_candidates, seed_query, adam, pose_adam, track_graph,
  * initnet_fwd, initnet_bwd) is bracketed by a pair of HIP events on the context's stream.
  * The events carry no system-scope fence, so they do not write back or
  * invalidate caches, but each still costs a few microseconds of stream time. */

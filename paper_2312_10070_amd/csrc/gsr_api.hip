@@ -646,6 +646,44 @@ int gsr_loss_l1(gsr_ctx* c, const float* color, const float* depth, const float*
   return check_launch(c, "gsr_loss_l1");
 }
 
+int gsr_seed_candidates(gsr_ctx* c, const gsr_camera* cam, const float* pose7, const float* color,
+                        const float* depth, const float* alpha, const float* u, float p_uniform, float p_grad,
+                        float grad_thre, float alpha_n, float* points, float* colors, int64_t* n_out) {
+  if (!c) return GSR_EINVAL;
+  if (!cam || !pose7 || !color || !depth || !u || !points || !colors || !n_out)
+    return fail(c, GSR_EINVAL, "bad seeding candidate arguments");
+  if (cam->width <= 0 || cam->height <= 0 || cam->width > 65535 || cam->height > 65535 || !std::isfinite(cam->fx) ||
+      !std::isfinite(cam->fy) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy) || cam->fx == 0.f ||
+      cam->fy == 0.f)
+    return fail(c, GSR_EINVAL, "camera: positive size up to 65535 and finite, non-zero focal lengths");
+  if (!std::isfinite(p_uniform) || !std::isfinite(p_grad) || !std::isfinite(grad_thre) || !std::isfinite(alpha_n))
+    return fail(c, GSR_EINVAL, "seeding probabilities and thresholds must be finite");
+  gsr::SeedSample a{color, depth, alpha, u, pose7, cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy,
+                    p_uniform, p_grad, grad_thre * grad_thre, alpha_n};
+  const int64_t P = (int64_t)cam->width * cam->height;
+  GSR_HIP(c, hipSetDevice(c->device));
+  uint32_t* temp = nullptr;
+  uint32_t* cnt = nullptr;
+  GSR_HIP(c, hipMalloc((void**)&temp, sizeof(uint32_t) * gsr::seed_sample_temp_words(P)));
+  if (hipHostMalloc((void**)&cnt, sizeof(uint32_t), hipHostMallocMapped) != hipSuccess) {
+    (void)hipFree(temp);
+    return fail(c, GSR_ENOMEM, "seeding: pinned count");
+  }
+  uint32_t* cnt_dev = nullptr;
+  hipError_t e = hipHostGetDevicePointer((void**)&cnt_dev, cnt, 0);
+  if (e == hipSuccess) {
+    Stage t(c, "seed_candidates");
+    gsr::launch_seed_sample(a, points, colors, temp, cnt_dev, c->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) *n_out = (int64_t)*(volatile uint32_t*)cnt;
+  (void)hipFree(temp);
+  (void)hipHostFree(cnt);
+  if (e != hipSuccess) return fail(c, GSR_EHIP, hipGetErrorString(e));
+  return GSR_OK;
+}
+
 int gsr_seed_query(gsr_ctx* c, const float* means, int64_t n, const float* points, int64_t m, float rho, float r_max,
                    float* nn_d2, int32_t* keep) {
   if (!c) return GSR_EINVAL;

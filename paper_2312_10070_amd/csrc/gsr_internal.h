@@ -226,6 +226,19 @@ int64_t scan_temp_words(int64_t n);
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* temp,
                            hipStream_t s, uint32_t* total_host = nullptr);
 
+// Seeding candidates (k_seed.hip): chosen pixels back-projected to world
+// points [m,3] with their colours [m,3], in pixel order; the count goes to
+// count_host (pinned, device-visible). temp: seed_sample_temp_words(W H) uint32.
+struct SeedSample {
+  const float *color, *depth, *alpha, *u, *pose7;  // alpha NULL: a sub-map's first keyframe
+  int W, H;
+  float fx, fy, cx, cy;
+  float p_uniform, p_grad, g2thre, alpha_n;
+};
+int64_t seed_sample_temp_words(int64_t P);
+void launch_seed_sample(const SeedSample& a, float* points, float* colors, uint32_t* temp, uint32_t* count_host,
+                        hipStream_t s);
+
 // Seeding neighbour queries (k_seed.hip): nn_d2[j] = min(r_max^2, min_i |q_j - p_i|^2),
 // keep[j] = nn_d2[j] >= rho^2 (either output may be NULL); rho <= r_max.
 // temp: seed_temp_words(n) uint32, 16-byte aligned.

@@ -1,3 +1,13 @@
+// Seeding (Sec. 3.2): candidate points sampled from a keyframe, and the
+// neighbour queries that decide which become new Gaussians.
+//
+// Candidates: a pixel with positive depth is chosen by Bernoulli thinning with
+// caller-supplied random numbers u: for a sub-map's first keyframe iff
+// u < p_uniform (+ p_grad where the grey image's central-difference gradient
+// exceeds a threshold), afterwards iff the rendered alpha < alpha_n and
+// u < p_uniform; chosen pixels are back-projected through the pinhole and the
+// inverse of the world-to-camera pose, and compacted in pixel order.
+//
 // Neighbour queries of the seeding step (Sec. 3.2: a sampled point becomes a
 // new Gaussian only if no Gaussian of the active sub-map lies within the
 // search radius rho; the supplement sets the new Gaussian's scale from its
@@ -76,7 +86,72 @@ __global__ __launch_bounds__(256) void k_seed_query(const float* __restrict__ q,
   if (keep) keep[j] = best < rho2 ? 0 : 1;
 }
 
+__device__ __forceinline__ float grey(const float* C, int64_t P, int64_t i) {
+#pragma clang fp contract(off)
+  return __fdiv_rn((C[i] + C[P + i]) + C[2 * P + i], 3.f);
+}
+
+__device__ __forceinline__ bool seed_pick(const SeedSample& a, int64_t i) {
+#pragma clang fp contract(off)
+  if (!(a.depth[i] > 0.f)) return false;
+  if (a.alpha) return a.alpha[i] < a.alpha_n && a.u[i] < a.p_uniform;
+  const int y = (int)(i / a.W), x = (int)(i - (int64_t)y * a.W);
+  bool edge = false;
+  if (x > 0 && x < a.W - 1 && y > 0 && y < a.H - 1) {
+    const int64_t P = (int64_t)a.W * a.H;
+    const float gx = grey(a.color, P, i + 1) - grey(a.color, P, i - 1);
+    const float gy = grey(a.color, P, i + a.W) - grey(a.color, P, i - a.W);
+    edge = gx * gx + gy * gy > a.g2thre;
+  }
+  return a.u[i] < (edge ? a.p_uniform + a.p_grad : a.p_uniform);
+}
+
+__global__ __launch_bounds__(256) void k_seed_flag(SeedSample a, uint32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)a.W * a.H) flag[i] = seed_pick(a, i) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_seed_emit(SeedSample a, const uint32_t* __restrict__ flag,
+                                                 const uint32_t* __restrict__ off, float* __restrict__ points,
+                                                 float* __restrict__ colors) {
+  const int64_t P = (int64_t)a.W * a.H;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P || !flag[i]) return;
+  const int y = (int)(i / a.W), x = (int)(i - (int64_t)y * a.W);
+  const float d = a.depth[i];
+  const float xc = ((float)x - a.cx) * d / a.fx, yc = ((float)y - a.cy) * d / a.fy;
+  // world-to-camera (q, t): X_w = R^T (X_c - t)
+  float qw = a.pose7[0], qx = a.pose7[1], qy = a.pose7[2], qz = a.pose7[3];
+  const float inv = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= inv; qx *= inv; qy *= inv; qz *= inv;
+  const float r00 = 1.f - 2.f * (qy * qy + qz * qz), r01 = 2.f * (qx * qy - qw * qz), r02 = 2.f * (qx * qz + qw * qy);
+  const float r10 = 2.f * (qx * qy + qw * qz), r11 = 1.f - 2.f * (qx * qx + qz * qz), r12 = 2.f * (qy * qz - qw * qx);
+  const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx), r22 = 1.f - 2.f * (qx * qx + qy * qy);
+  const float vx = xc - a.pose7[4], vy = yc - a.pose7[5], vz = d - a.pose7[6];
+  const int64_t j = off[i];
+  points[3 * j] = r00 * vx + r10 * vy + r20 * vz;
+  points[3 * j + 1] = r01 * vx + r11 * vy + r21 * vz;
+  points[3 * j + 2] = r02 * vx + r12 * vy + r22 * vz;
+  colors[3 * j] = a.color[i];
+  colors[3 * j + 1] = a.color[P + i];
+  colors[3 * j + 2] = a.color[2 * P + i];
+}
+
 }  // namespace
+
+int64_t seed_sample_temp_words(int64_t P) { return 2 * P + 1 + scan_temp_words(P); }
+
+void launch_seed_sample(const SeedSample& a, float* points, float* colors, uint32_t* temp, uint32_t* count_host,
+                        hipStream_t s) {
+  const int64_t P = (int64_t)a.W * a.H;
+  uint32_t* flag = temp;
+  uint32_t* off = temp + P;
+  uint32_t* total = temp + 2 * P;
+  const unsigned g = (unsigned)((P + 255) / 256);
+  if (P > 0) hipLaunchKernelGGL(k_seed_flag, dim3(g), dim3(256), 0, s, a, flag);
+  launch_exclusive_scan(flag, off, P, total, total + 1, s, count_host);
+  if (P > 0) hipLaunchKernelGGL(k_seed_emit, dim3(g), dim3(256), 0, s, a, flag, off, points, colors);
+}
 
 uint32_t seed_buckets(int64_t n) {
   uint32_t t = 1024;

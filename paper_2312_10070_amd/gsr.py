@@ -85,6 +85,8 @@ _SIGS = {
     "gsr_tile_lists": (ctypes.c_int, [P, P, ctypes.POINTER(ctypes.c_int64), P, P]),
     "gsr_loss_l1": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P]),
     "gsr_loss_reg": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_float, P, P]),
+    "gsr_seed_candidates": (ctypes.c_int, [P, ctypes.POINTER(Camera), P, P, P, P, P, ctypes.c_float, ctypes.c_float,
+                                           ctypes.c_float, ctypes.c_float, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_seed_query": (ctypes.c_int, [P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P]),
     "gsr_prune": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_float, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_loss_ssim": (ctypes.c_int, [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P, P]),
@@ -398,6 +400,25 @@ def loss_l1(color, depth, tgt_color, tgt_depth, w_color=1.0, w_depth=1.0, ctx: C
     ctx.check(ctx.lib.gsr_loss_l1(ctx.h, _ptr(color), _ptr(depth), _ptr(tgt_color), _ptr(tgt_depth), P_,
                                   float(w_color), float(w_depth), _ptr(loss), _ptr(gC), _ptr(gD)))
     return loss, gC, gD
+
+
+def seed_candidates(color, depth, u, pose7, camera: Camera, p_uniform: float, p_grad: float = 0.0,
+                    grad_thre: float = 0.0, alpha=None, alpha_n: float = 0.6, ctx: Context | None = None):
+    """Seeding candidates (see gsr_seed_candidates): (points [m,3], colours [m,3])."""
+    ctx = ctx or Context.get(depth.device.index or 0)
+    ctx.sync_stream()
+    H, W = int(camera.height), int(camera.width)
+    _f32(color, "color", (3, H, W)); _f32(depth, "depth", (H, W)); _f32(u, "u", (H, W))
+    _f32(pose7, "pose7", (7,))
+    if alpha is not None:
+        _f32(alpha, "alpha", (H, W))
+    pts = torch.empty((H * W, 3), device=depth.device, dtype=torch.float32)
+    cols = torch.empty((H * W, 3), device=depth.device, dtype=torch.float32)
+    n = ctypes.c_int64()
+    ctx.check(ctx.lib.gsr_seed_candidates(ctx.h, ctypes.byref(camera), _ptr(pose7), _ptr(color), _ptr(depth),
+                                          _ptr(alpha), _ptr(u), float(p_uniform), float(p_grad), float(grad_thre),
+                                          float(alpha_n), _ptr(pts), _ptr(cols), ctypes.byref(n)))
+    return pts[:n.value], cols[:n.value]
 
 
 def seed_query(means, points, rho: float, r_max: float, ctx: Context | None = None):

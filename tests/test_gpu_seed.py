@@ -68,3 +68,38 @@ def test_seed_query_bad_arguments():
             gsr.seed_query(p, p, rho, r_max)
     with pytest.raises(ValueError):
         gsr.seed_query(dev(np.zeros((4, 2))), p, 0.1, 0.2)
+
+
+def seed_frame(W, Hh, seed):
+    from paper_2312_10070_amd import synth
+    rng = np.random.default_rng(seed)
+    cam_i = synth.Intrinsics(W, Hh, 0.9 * W, 0.9 * W, W / 2 + 0.3, Hh / 2 - 0.2)
+    room = synth.make_room(seed)
+    pose = synth.open_view(room, rng, synth.MAPPING_CAMERA)
+    C, D = synth.render_frame(room, cam_i, pose)
+    D[rng.uniform(size=D.shape) < 0.05] = 0.0  # holes in the observed depth
+    A = rng.uniform(0, 1, D.shape).astype(np.float32)
+    U = rng.uniform(0, 1, D.shape).astype(np.float32)
+    return cam_i, np.asarray(pose, np.float32), C, D, A, U
+
+
+@pytest.mark.parametrize("W,Hh,first", [(70, 45, True), (70, 45, False), (1200, 680, True), (1200, 680, False),
+                                        (1, 1, True), (3, 200, True)])
+def test_seed_candidates_match_oracle(W, Hh, first):
+    torch = torch_()
+    cam_i, pose, C, D, A, U = seed_frame(W, Hh, W + Hh)
+    cam_o = oracle.Camera(W, Hh, cam_i.fx, cam_i.fy, np.float32(cam_i.cx), np.float32(cam_i.cy))
+    pu, pg, thre = (0.05, 0.5, 0.05) if first else (0.3, 0.0, 0.0)
+    P_ref, col_ref = oracle.seed_candidates(C, D, None if first else A, U, pose.astype(np.float64), cam_o, pu, pg,
+                                            thre, 0.6)
+    camera = gsr.camera_from(cam_i)
+    pts, cols = gsr.seed_candidates(dev(C), dev(D), dev(U), dev(pose), camera, pu, pg, thre,
+                                    alpha=None if first else dev(A), alpha_n=0.6)
+    torch.cuda.synchronize()
+    assert pts.shape[0] == len(P_ref)
+    np.testing.assert_array_equal(cols.cpu().numpy(), col_ref.astype(np.float32))
+    got = pts.cpu().numpy().astype(np.float64)
+    scale = np.abs(P_ref).max() if len(P_ref) else 0.0
+    np.testing.assert_allclose(got.reshape(-1, 3), P_ref.reshape(-1, 3), rtol=0, atol=2e-6 * (1 + scale))
+    if W * Hh > 1000:
+        assert 0 < len(P_ref) < W * Hh
