@@ -7,8 +7,11 @@
  * covariance (Eq. 2), front-to-back alpha compositing of colour (Eq. 3, 4)
  * and depth (Eq. 6), their explicit gradients (Sec. 3.3, Eq. 7-8 and the
  * colour/opacity/covariance analogues), the mapping losses (Eq. 9, Eq. 10
- * with its L1 and SSIM terms) and the masked tracking loss (Eq. 15) with the
- * pose gradient the tracking optimisation (Eq. 14) needs.
+ * with its L1 and SSIM terms, the Eq. 11 scale regulariser of Eq. 12) and the
+ * masked tracking loss (Eq. 15) with the pose gradient the tracking
+ * optimisation (Eq. 14) needs; around them, the map upkeep of Sec. 3.2 and
+ * the supplement: seeding candidates and their neighbour queries, and opacity
+ * pruning.
  *
  * Conventions shared by every call
  *  - All array arguments are DEVICE pointers to contiguous float32 (unless
