@@ -209,6 +209,23 @@ int gsr_seed_candidates(gsr_ctx *ctx, const gsr_camera *cam, const float *pose7,
                         const float *depth, const float *alpha, const float *u, float p_uniform, float p_grad,
                         float grad_thre, float alpha_n, float *points, float *colors, int64_t *n_out);
 
+/* Stable compaction by a mask: as gsr_prune, but Gaussian i is kept iff
+ * keep[i] != 0 (device int32 [n]); with gsr_seed_query's keep output it is the
+ * supplement's merge of a sub-map into the global map (a Gaussian joins if the
+ * map so far has none within rho). Synchronises. */
+int gsr_compact(gsr_ctx *ctx, int64_t n, const int32_t *keep, const float *const *in, float *const *out,
+                int64_t *n_kept);
+
+/* Sub-map creation rule (Sec. 3.2): a new sub-map starts when the current
+ * frame's camera centre is more than d_thre from that of the active sub-map's
+ * first frame, or the rotation between the two frames exceeds theta_thre
+ * (radians; the angle of the relative rotation); the paper uses 0.5 m and 50
+ * degrees. pose_first7, pose_cur7: HOST float[7] world-to-camera poses (q
+ * normalised inside). *start_new = 1 or 0. Pure host computation (FP64);
+ * returns GSR_EINVAL for a zero quaternion or non-finite thresholds. */
+int gsr_submap_trigger(const float *pose_first7, const float *pose_cur7, float d_thre, float theta_thre,
+                       int32_t *start_new);
+
 /* Neighbour queries of the seeding step (Sec. 3.2: a sampled point becomes a
  * new Gaussian only if the active sub-map has no Gaussian within the search
  * radius rho; the supplement sets a new Gaussian's scale from its
@@ -385,7 +402,7 @@ int gsr_initnet_adam(gsr_ctx *ctx, gsr_initnet *net, float lr, float beta1, floa
 
 /* Stage timing for benchmarks: while enabled, every stage a call enqueues
  * (project, bin_count, tile_bins, render_fwd, fill, render_bwd, project_bwd,
- * project_bwd_adam, loss_l1, loss_reg, loss_ssim, loss_track, prune, seed_candidates, seed_query, adam, pose_adam, track_graph,
+ * project_bwd_adam, loss_l1, loss_reg, loss_ssim, loss_track, prune, compact, seed_candidates, seed_query, adam, pose_adam, track_graph,
  * initnet_fwd, initnet_bwd) is bracketed by a pair of HIP events on the context's stream.
  * The events carry no system-scope fence, so they do not write back or
  * invalidate caches, but each still costs a few microseconds of stream time. */

@@ -217,6 +217,41 @@ def loss_l1(C, D, Ct, Dt, w_color=1.0, w_depth=1.0):
     return float(loss[0]), gC, gD
 
 
+def _quat_R(q):
+    q = np.asarray(q, np.float64)
+    q = q / np.linalg.norm(q)
+    w, x, y, z = q
+    return q, np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def submap_trigger(pose_first7, pose_cur7, d_thre=0.5, theta_thre=np.deg2rad(50.0)) -> bool:
+    """Sub-map creation rule (Sec. 3.2): the camera centres (c = -R^T t of the
+    world-to-camera poses) more than d_thre apart, or the relative rotation's
+    angle above theta_thre (radians)."""
+    qa, Ra = _quat_R(np.asarray(pose_first7, np.float64)[:4])
+    qb, Rb = _quat_R(np.asarray(pose_cur7, np.float64)[:4])
+    ca = -Ra.T @ np.asarray(pose_first7, np.float64)[4:7]
+    cb = -Rb.T @ np.asarray(pose_cur7, np.float64)[4:7]
+    angle = 2.0 * np.arccos(min(1.0, abs(float(qa @ qb))))
+    return bool(np.linalg.norm(ca - cb) > d_thre or angle > theta_thre)
+
+
+def compact(groups, keep):
+    """Stable compaction: the rows with keep != 0 of every array of every group."""
+    k = np.asarray(keep) != 0
+    return int(k.sum()), [{n: np.asarray(v)[k] for n, v in g.items()} for g in groups]
+
+
+def merge_submap(global_params: dict, sub_params: dict, rho: float = 0.01) -> dict:
+    """The supplement's merge of a sub-map into the global map: its Gaussians
+    with no global mean within rho (the seeding rule) are appended."""
+    _, keep = seed_query(global_params["means"], sub_params["means"], rho, rho)
+    _, (kept,) = compact([sub_params], keep)
+    return {k: np.concatenate([np.asarray(global_params[k]), kept[k]]) for k in global_params}
+
+
 def seed_candidates(color, depth, alpha, u, pose7, cam: Camera, p_uniform: float, p_grad: float = 0.0,
                     grad_thre: float = 0.0, alpha_n: float = 0.6):
     """Candidate points for new Gaussians (Sec. 3.2 with the supplement's alpha_n).

@@ -3,6 +3,7 @@
 // every step of the hot path is one of the kernels in k_*.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -705,13 +706,17 @@ int gsr_seed_query(gsr_ctx* c, const float* means, int64_t n, const float* point
   return GSR_OK;
 }
 
-int gsr_prune(gsr_ctx* c, int64_t n, float o_thre, const float* const* in, float* const* out, int64_t* n_kept) {
-  if (!c) return GSR_EINVAL;
-  if (n < 0 || n > (int64_t)0x7fffffff || !in || !out || !n_kept || std::isnan(o_thre))
-    return fail(c, GSR_EINVAL, "bad prune arguments");
+namespace {
+// Shared body of gsr_prune and gsr_compact: stable compaction of the Gaussians
+// kept by mask (if given) or by opacity >= o_thre.
+int compact_impl(gsr_ctx* c, int64_t n, float o_thre, const int32_t* mask, const float* const* in, float* const* out,
+                 int64_t* n_kept, const char* stage) {
+  if (n < 0 || n > (int64_t)0x7fffffff || !in || !out || !n_kept || (!mask && std::isnan(o_thre)))
+    return fail(c, GSR_EINVAL, "bad prune / compact arguments");
   gsr::PruneArgs a{};
   for (int t = 0; t < 15; ++t) {
-    if ((in[t] == nullptr) != (out[t] == nullptr)) return fail(c, GSR_EINVAL, "prune: in[t] and out[t] must both be set or both be NULL");
+    if ((in[t] == nullptr) != (out[t] == nullptr))
+      return fail(c, GSR_EINVAL, "prune: in[t] and out[t] must both be set or both be NULL");
     if (t < 5 && n > 0 && !in[t]) return fail(c, GSR_EINVAL, "prune: the five parameter tensors are required");
     a.in[t] = in[t];
     a.out[t] = out[t];
@@ -727,8 +732,8 @@ int gsr_prune(gsr_ctx* c, int64_t n, float o_thre, const float* const* in, float
   uint32_t* kept_dev = nullptr;
   hipError_t e = hipHostGetDevicePointer((void**)&kept_dev, kept, 0);
   if (e == hipSuccess) {
-    Stage t(c, "prune");
-    gsr::launch_prune(a, n, o_thre, temp, kept_dev, c->stream);
+    Stage t(c, stage);
+    gsr::launch_prune(a, n, o_thre, mask, temp, kept_dev, c->stream);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -736,6 +741,58 @@ int gsr_prune(gsr_ctx* c, int64_t n, float o_thre, const float* const* in, float
   (void)hipFree(temp);
   (void)hipHostFree(kept);
   if (e != hipSuccess) return fail(c, GSR_EHIP, hipGetErrorString(e));
+  return GSR_OK;
+}
+}  // namespace
+
+int gsr_prune(gsr_ctx* c, int64_t n, float o_thre, const float* const* in, float* const* out, int64_t* n_kept) {
+  if (!c) return GSR_EINVAL;
+  if (std::isnan(o_thre)) return fail(c, GSR_EINVAL, "prune: o_thre is NaN");
+  return compact_impl(c, n, o_thre, nullptr, in, out, n_kept, "prune");
+}
+
+int gsr_compact(gsr_ctx* c, int64_t n, const int32_t* keep, const float* const* in, float* const* out,
+                int64_t* n_kept) {
+  if (!c) return GSR_EINVAL;
+  if (n > 0 && !keep) return fail(c, GSR_EINVAL, "compact: keep mask required");
+  return compact_impl(c, n, 0.f, keep ? keep : (const int32_t*)nullptr, in, out, n_kept, "compact");
+}
+
+int gsr_submap_trigger(const float* pose_first7, const float* pose_cur7, float d_thre, float theta_thre,
+                       int32_t* start_new) {
+  if (!pose_first7 || !pose_cur7 || !start_new || !std::isfinite(d_thre) || !std::isfinite(theta_thre))
+    return GSR_EINVAL;
+  // camera centres c = -R^T t of the world-to-camera poses; relative rotation angle 2 acos |<q_a, q_b>|
+  double qa[4], qb[4], na = 0, nb = 0;
+  for (int i = 0; i < 4; ++i) {
+    qa[i] = pose_first7[i];
+    qb[i] = pose_cur7[i];
+    na += qa[i] * qa[i];
+    nb += qb[i] * qb[i];
+  }
+  if (!(na > 0) || !(nb > 0)) return GSR_EINVAL;
+  na = std::sqrt(na);
+  nb = std::sqrt(nb);
+  double dot = 0;
+  for (int i = 0; i < 4; ++i) {
+    qa[i] /= na;
+    qb[i] /= nb;
+    dot += qa[i] * qb[i];
+  }
+  auto centre = [](const double* q, const float* p7, double* cpos) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z),     2 * (x * z + w * y),
+                         2 * (x * y + w * z),     1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                         2 * (x * z - w * y),     2 * (y * z + w * x),     1 - 2 * (x * x + y * y)};
+    for (int j = 0; j < 3; ++j) cpos[j] = -(R[j] * p7[4] + R[3 + j] * p7[5] + R[6 + j] * p7[6]);
+  };
+  double ca[3], cb[3];
+  centre(qa, pose_first7, ca);
+  centre(qb, pose_cur7, cb);
+  const double d = std::sqrt((ca[0] - cb[0]) * (ca[0] - cb[0]) + (ca[1] - cb[1]) * (ca[1] - cb[1]) +
+                             (ca[2] - cb[2]) * (ca[2] - cb[2]));
+  const double angle = 2.0 * std::acos(std::min(1.0, std::fabs(dot)));
+  *start_new = (d > d_thre || angle > theta_thre) ? 1 : 0;
   return GSR_OK;
 }
 

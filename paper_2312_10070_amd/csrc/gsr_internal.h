@@ -247,17 +247,19 @@ int64_t seed_temp_words(int64_t n);
 void launch_seed_query(const float* means, int64_t n, const float* points, int64_t m, float rho, float r_max,
                        float* nn_d2, int32_t* keep, uint32_t* temp, hipStream_t s);
 
-// Opacity pruning: in[0..4] = means, scales, quats, opacities, colors
-// (widths 3, 3, 4, 1, 3), in[5..9] / in[10..14] their Adam moments (NULL =
-// absent; out[t] NULL exactly where in[t] is). Keeps the Gaussians with
-// opacity >= thre, in their order, at the front of out; the count goes to
-// kept_host (pinned, device-visible). temp: prune_temp_words(n) uint32.
+// Opacity pruning / compaction: in[0..4] = means, scales, quats, opacities,
+// colors (widths 3, 3, 4, 1, 3), in[5..9] / in[10..14] their Adam moments
+// (NULL = absent; out[t] NULL exactly where in[t] is). Keeps the Gaussians
+// with mask[i] != 0 (mask given) or opacity >= thre (mask NULL), in their
+// order, at the front of out; the count goes to kept_host (pinned,
+// device-visible). temp: prune_temp_words(n) uint32.
 struct PruneArgs {
   const float* in[15];
   float* out[15];
 };
 int64_t prune_temp_words(int64_t n);
-void launch_prune(const PruneArgs& a, int64_t n, float thre, uint32_t* temp, uint32_t* kept_host, hipStream_t s);
+void launch_prune(const PruneArgs& a, int64_t n, float thre, const int32_t* mask, uint32_t* temp, uint32_t* kept_host,
+                  hipStream_t s);
 
 // Tile binning (see k_sort.hip). Workgroup w of view v handles the Gaussians
 // [w c, (w + 1) c) with c = ceil(n / n_wg); M[item][w] counts its pairs per

@@ -432,10 +432,11 @@ void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
 
 // ---- opacity pruning: stable compaction of the Gaussians kept -------------
 namespace {
-__global__ __launch_bounds__(256) void k_prune_flag(const float* __restrict__ o, int64_t n, float thre,
-                                                  uint32_t* __restrict__ keep) {
+// keep[i] = mask[i] != 0 when a mask is given, else opacity o[i] >= thre (NaN is not kept)
+__global__ __launch_bounds__(256) void k_prune_flag(const float* __restrict__ o, const int32_t* __restrict__ mask,
+                                                  int64_t n, float thre, uint32_t* __restrict__ keep) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) keep[i] = o[i] >= thre ? 1u : 0u;  // NaN is not kept
+  if (i < n) keep[i] = (mask ? mask[i] != 0 : o[i] >= thre) ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(256) void k_prune_scatter(PruneArgs a, int64_t n, const uint32_t* __restrict__ keep,
@@ -455,13 +456,14 @@ __global__ __launch_bounds__(256) void k_prune_scatter(PruneArgs a, int64_t n, c
 
 int64_t prune_temp_words(int64_t n) { return 2 * n + scan_temp_words(n) + 1; }
 
-void launch_prune(const PruneArgs& a, int64_t n, float thre, uint32_t* temp, uint32_t* kept_host, hipStream_t s) {
+void launch_prune(const PruneArgs& a, int64_t n, float thre, const int32_t* mask, uint32_t* temp, uint32_t* kept_host,
+                  hipStream_t s) {
   uint32_t* keep = temp;
   uint32_t* off = temp + n;
   uint32_t* total = temp + 2 * n;
   uint32_t* scan_tmp = total + 1;
   const unsigned g = (unsigned)((n + 255) / 256);
-  if (n > 0) hipLaunchKernelGGL(k_prune_flag, dim3(g), dim3(256), 0, s, a.in[3], n, thre, keep);
+  if (n > 0) hipLaunchKernelGGL(k_prune_flag, dim3(g), dim3(256), 0, s, a.in[3], mask, n, thre, keep);
   launch_exclusive_scan(keep, off, n, total, scan_tmp, s, kept_host);
   if (n > 0) hipLaunchKernelGGL(k_prune_scatter, dim3(g), dim3(256), 0, s, a, n, keep, off);
 }

@@ -8,6 +8,7 @@ device is present, calls raise instead of falling back to anything else.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import threading
 from dataclasses import dataclass
@@ -88,6 +89,8 @@ _SIGS = {
     "gsr_seed_candidates": (ctypes.c_int, [P, ctypes.POINTER(Camera), P, P, P, P, P, ctypes.c_float, ctypes.c_float,
                                            ctypes.c_float, ctypes.c_float, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_seed_query": (ctypes.c_int, [P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P]),
+    "gsr_compact": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_int64)]),
+    "gsr_submap_trigger": (ctypes.c_int, [P, P, ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_int32)]),
     "gsr_prune": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_float, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_loss_ssim": (ctypes.c_int, [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P, P]),
     "gsr_loss_track": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P, P]),
@@ -436,6 +439,61 @@ def seed_query(means, points, rho: float, r_max: float, ctx: Context | None = No
     ctx.check(ctx.lib.gsr_seed_query(ctx.h, _ptr(means), int(means.shape[0]), _ptr(points), m, float(rho),
                                      float(r_max), _ptr(nn), _ptr(keep)))
     return nn, keep
+
+
+def _compact_call(params, exp_avg, exp_avg_sq, call):
+    groups = [params, exp_avg, exp_avg_sq]
+    ins = (P * 15)()
+    outs = (P * 15)()
+    res = [None, None, None]
+    for gi, grp in enumerate(groups):
+        if grp is None:
+            continue
+        res[gi] = {}
+        for i, k in enumerate(PARAM_GROUPS):
+            t = _f32(grp[k], k, tuple(params[k].shape))
+            o = torch.empty_like(t)
+            ins[5 * gi + i] = _ptr(t)
+            outs[5 * gi + i] = _ptr(o)
+            res[gi][k] = o
+    kept = ctypes.c_int64()
+    call(ins, outs, ctypes.byref(kept))
+    m = kept.value
+    res = [None if r is None else {k: v[:m] for k, v in r.items()} for r in res]
+    return m, res[0], res[1], res[2]
+
+
+def compact(params: dict, keep, exp_avg: dict | None = None, exp_avg_sq: dict | None = None,
+            ctx: Context | None = None):
+    """Stable compaction of the Gaussians with keep != 0 (int32 [n] device);
+    returns (n_kept, params, exp_avg, exp_avg_sq) as new tensors."""
+    ctx = ctx or Context.get(params["means"].device.index or 0)
+    ctx.sync_stream()
+    n = params["opacities"].shape[0]
+    if keep.dtype != torch.int32 or not keep.is_cuda or not keep.is_contiguous() or keep.shape != (n,):
+        raise ValueError("keep must be a contiguous int32 device tensor of n entries")
+    return _compact_call(params, exp_avg, exp_avg_sq,
+                         lambda i, o, k: ctx.check(ctx.lib.gsr_compact(ctx.h, n, _ptr(keep), i, o, k)))
+
+
+def merge_submap(global_params: dict, sub_params: dict, rho: float = 0.01, ctx: Context | None = None):
+    """The supplement's merge: the sub-map's Gaussians with no global-map mean
+    within rho are appended to the global map; returns the merged parameters."""
+    _, keep = seed_query(global_params["means"], sub_params["means"], rho, rho, ctx=ctx)
+    _, kept, _, _ = compact(sub_params, keep, ctx=ctx)
+    return {k: torch.cat([global_params[k], kept[k]]) for k in PARAM_GROUPS}
+
+
+def submap_trigger(pose_first7, pose_cur7, d_thre: float = 0.5, theta_thre_deg: float = 50.0) -> bool:
+    """Sub-map creation rule of Sec. 3.2 (host poses, 7 floats each)."""
+    lib = load()
+    a = (ctypes.c_float * 7)(*[float(v) for v in pose_first7])
+    b = (ctypes.c_float * 7)(*[float(v) for v in pose_cur7])
+    out = ctypes.c_int32()
+    rc = lib.gsr_submap_trigger(a, b, float(d_thre), float(math.radians(theta_thre_deg)), ctypes.byref(out))
+    if rc != GSR_OK:
+        raise GsrError(rc, "invalid poses or thresholds")
+    return bool(out.value)
 
 
 def prune(params: dict, o_thre: float, exp_avg: dict | None = None, exp_avg_sq: dict | None = None,

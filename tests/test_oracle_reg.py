@@ -135,3 +135,34 @@ def test_seed_candidates_colour_gradient():
     ys = np.round(P[:, 1] / P[:, 2] * cam.fy + cam.cy).astype(int)
     assert sorted(zip(ys.tolist(), xs.tolist())) == [(y, x) for y in (1, 2, 3) for x in (2, 3)]
     np.testing.assert_allclose(col[xs == 3], 0.9, atol=1e-7)
+
+
+def test_submap_trigger_definition():
+    from scipy.spatial.transform import Rotation
+    I = np.array([1, 0, 0, 0, 0, 0, 0.0])
+    assert oracle.submap_trigger(I, [1, 0, 0, 0, 0.6, 0, 0])
+    assert not oracle.submap_trigger(I, [1, 0, 0, 0, 0.4, 0, 0])
+
+    def rot(deg, axis, t=(0, 0, 0)):
+        q = Rotation.from_rotvec(np.deg2rad(deg) * np.asarray(axis, float)).as_quat()  # x, y, z, w
+        return np.concatenate([[q[3], q[0], q[1], q[2]], t])
+
+    assert oracle.submap_trigger(I, rot(60, [0, 1, 0]))
+    assert not oracle.submap_trigger(I, rot(40, [1, 1, 0] / np.sqrt(2)))
+    assert not oracle.submap_trigger(rot(10, [0, 0, 1]), rot(-10, [0, 0, 1]))  # 20 degrees apart
+    # same t, but a 40-degree turn moves the camera centre c = -R^T t by 2 sin(20 deg) |t| = 0.68 m
+    t = (1.0, 0.0, 0.0)
+    assert oracle.submap_trigger(rot(0, [0, 1, 0], t), rot(40, [0, 1, 0], t))
+    # a 40-degree turn about the camera centre: t changes, the centre does not
+    Rm = Rotation.from_rotvec(np.deg2rad(40) * np.array([0, 1, 0])).as_matrix()
+    c = np.array([2.0, 0.5, -1.0])
+    assert not oracle.submap_trigger(np.concatenate([[1, 0, 0, 0], -c]), rot(40, [0, 1, 0], -Rm @ c))
+
+
+def test_merge_definition():
+    g = {"means": np.array([[0, 0, 0], [1, 0, 0]], np.float32), "opacities": np.array([0.5, 0.6], np.float32)}
+    s = {"means": np.array([[0.005, 0, 0], [0.5, 0, 0], [1, 0.02, 0]], np.float32),
+         "opacities": np.array([0.1, 0.2, 0.3], np.float32)}
+    m = oracle.merge_submap(g, s, rho=0.01)
+    np.testing.assert_array_equal(m["means"], np.concatenate([g["means"], s["means"][1:]]))
+    np.testing.assert_array_equal(m["opacities"], np.array([0.5, 0.6, 0.2, 0.3], np.float32))
