@@ -8,7 +8,8 @@
 // library: every formula here is written out from the paper's definitions in
 // plain double precision, with no blocking, fusion or reordering.
 //
-// What it computes (per the paper, with the readings listed in the design doc):
+// What it computes (per the paper; where the paper is silent, the reading taken
+// is stated beside the code that applies it):
 //   * projection of each Gaussian: camera-space mean (Eq. 1, world-to-camera
 //     pose), EWA 2D covariance Sigma' = J R Sigma R^T J^T + h I (Eq. 2) with
 //     Sigma = R S S^T R^T (Sec. 3.1), its inverse (the conic) and a support box
