@@ -182,6 +182,100 @@ def summarize_pmc(fetch_csv: str, write_csv: str, calib_mib: int, workload: str 
         print("wrote", path, f"{(fb + wb) / 1e6:.1f} MB per launch")
 
 
+# Two counter passes for the VALU / LDS utilisation of the compositing kernels
+# (at most 8 SQ counters and 2 GRBM counters per pass).
+VALU_PASSES = [
+    "SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_INSTS_SALU SQ_BUSY_CU_CYCLES SQ_WAVE_CYCLES "
+    "GRBM_GUI_ACTIVE",
+    "SQ_INSTS_LDS SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT SQ_LDS_ADDR_CONFLICT SQ_WAIT_INST_LDS "
+    "SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_VMEM GRBM_GUI_ACTIVE",
+]
+N_CU = 256  # MI355X compute units
+# kernels of the tracking iteration, as rocprofv3 names them
+TRACK_KERNELS = {"render_bwd": ["k_render_bwd<true>("], "render_fwd": ["k_render_fwd<false>("],
+                 "project": ["k_project("], "project_bwd": ["k_project_bwd("],
+                 "loss_track": ["k_select_init(", "k_select_hist(", "k_loss_track("]}
+PROFILE_COMMANDS = {
+    "H": ("python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-full-loss --no-tracking --no-batched "
+          "--no-initnet --no-seed"),
+    "C3": "python3 bench.py --profile-tracking 5",
+}
+
+
+def summarize_valu(csvs: list, workload: str) -> None:
+    """Writes profiles/<stage>_<workload>_valu.txt from rocprofv3 --pmc runs of
+    VALU_PASSES: per-dispatch averages of the counters and the utilisation
+    figures rocprofv3's own derived metrics define (VALUBusy,
+    VALUUtilization, LDSBankConflict), plus instruction issue rates per CU
+    cycle (a CU issues at most one wave64 VALU instruction per cycle: four
+    16-lane SIMDs, four cycles each)."""
+    import csv
+    import collections
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"].replace("gsr::(anonymous namespace)::", "").replace("void ", "")
+            vals[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    kernels = STAGE_KERNELS if workload == "H" else TRACK_KERNELS
+    title = ("mapping iteration 1200x680, 500K Gaussians" if workload == "H"
+             else "tracking iteration 640x480, 500K Gaussians")
+    for stage, prefixes in kernels.items():
+        if stage not in ("render_fwd", "render_bwd", "loss_ssim"):
+            continue
+        name = next((nm for nm in vals if any(nm.startswith(k) for k in prefixes)), None)
+        if name is None:
+            continue
+        avg = {c: sum(v) / len(v) for c, v in vals[name].items()}
+        cyc = avg.get("GRBM_GUI_ACTIVE", 0.0)
+        if cyc <= 0:
+            continue
+        per_cu = lambda c: avg.get(c, 0.0) / (N_CU * cyc)
+        act = avg.get("SQ_ACTIVE_INST_VALU", 0.0)
+        derived = {
+            "valu_insts_per_cu_cycle": per_cu("SQ_INSTS_VALU"),
+            "VALUBusy": per_cu("SQ_ACTIVE_INST_VALU"),
+            "VALUUtilization": avg.get("SQ_THREAD_CYCLES_VALU", 0.0) / (act * 64) if act else 0.0,
+            "salu_insts_per_cu_cycle": per_cu("SQ_INSTS_SALU"),
+            "lds_insts_per_cu_cycle": per_cu("SQ_INSTS_LDS"),
+            "LDSBankConflict": per_cu("SQ_LDS_BANK_CONFLICT"),
+            "lds_active_per_cu_cycle": per_cu("SQ_ACTIVE_INST_LDS"),
+            "trans_insts_per_cu_cycle": per_cu("SQ_INSTS_VALU_TRANS_F32"),
+        }
+        path = os.path.join(ROOT, "profiles", f"{stage}_{workload}_valu.txt")
+        with open(path, "w") as f:
+            f.write(f"# VALU / LDS counters per dispatch of {name.split('(')[0]}, {title}\n")
+            for i, counters in enumerate(VALU_PASSES):
+                f.write(f"# pass {i + 1}: cd /tmp && rocprofv3 --pmc {counters} -d <dir> -o run --output-format csv "
+                        f"-- {PROFILE_COMMANDS[workload]}\n")
+            f.write(f"#   then: python bench.py --summarize-valu {workload} <pass csvs>\n")
+            f.write("# ratios per CU cycle divide by 256 CUs x GRBM_GUI_ACTIVE; VALUBusy, VALUUtilization and\n"
+                    "# LDSBankConflict follow rocprofv3's derived-metric definitions (as fractions, not percent)\n")
+            f.write(f"source_sha1: {source_hash(STAGE_SOURCES[stage])}\n")
+            f.write(f"dispatches: {len(vals[name].get('GRBM_GUI_ACTIVE', []))}\n")
+            for c in sorted(avg):
+                f.write(f"{c}: {avg[c]:.0f}\n")
+            for k, v in derived.items():
+                f.write(f"{k}: {v:.4f}\n")
+        print("wrote", path)
+
+
+def read_valu(stage: str, workload: str):
+    """Derived utilisation figures of a committed *_valu.txt taken on the
+    current kernel source, else None."""
+    path = os.path.join(ROOT, "profiles", f"{stage}_{workload}_valu.txt")
+    if not os.path.exists(path) or stage not in STAGE_SOURCES:
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha1") != source_hash(STAGE_SOURCES[stage]):
+        return None
+    keys = ("valu_insts_per_cu_cycle", "VALUBusy", "VALUUtilization", "lds_insts_per_cu_cycle", "LDSBankConflict")
+    return {k: float(kv[k]) for k in keys if k in kv}
+
+
 def summarize_trace(stats_csv: str, out_name: str, command: str, title: str) -> None:
     """Writes profiles/<out_name>.txt from a rocprofv3 --kernel-trace --stats
     kernel_stats.csv (durations in microseconds)."""
@@ -263,6 +357,24 @@ def bench_tracking(seed: int, n: int, frames: int) -> dict:
             "ms_per_frame": round(ms, 3), "ms_per_iteration": round(ms / 100, 4), "frames": frames,
             "init_error_cm_deg": [round(100 * e0[0], 3), round(e0[1], 3)],
             "final_error_cm_deg": [round(100 * e1[0], 4), round(e1[1], 4)]}
+
+
+def profile_tracking(seed: int, n: int, iters: int) -> int:
+    """A few eager tracking iterations of the C3 frame (the graph's kernels,
+    launched one by one), for counter runs."""
+    import torch
+    from paper_2312_10070_amd import gsr, synth, tracking
+    inp = synth.tracking_inputs(seed, n)
+    cam = gsr.camera_from(inp["camera"])
+    g = {k: torch.from_numpy(v).cuda() for k, v in inp["gaussians"].items()}
+    args = (g["means"], g["scales"], g["quats"], g["opacities"], g["colors"])
+    color, depth, _, st = gsr.render_fwd(*args, torch.from_numpy(inp["gt_pose7"]).cuda(), cam)
+    st.release()
+    pose, losses = tracking.track_eager(*args, cam, color.clone(), depth.clone(),
+                                        torch.from_numpy(inp["init_pose7"]).cuda(), n_iters=iters)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_tracking_iters": iters, "last_loss": float(losses[-1].item())}), flush=True)
+    return 0
 
 
 def bench_batched(seed: int, n: int, reps: int) -> dict:
@@ -446,9 +558,16 @@ def main() -> int:
                     help="write profiles/*_traffic.txt from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--summarize-trace", nargs=4, metavar=("STATS_CSV", "NAME", "COMMAND", "TITLE"),
                     help="write profiles/NAME.txt from a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--summarize-valu", nargs="+", metavar=("WORKLOAD", "CSV"),
+                    help="write profiles/*_<WORKLOAD>_valu.txt (WORKLOAD H or C3) from rocprofv3 --pmc runs and exit")
+    ap.add_argument("--profile-tracking", type=int, default=0, metavar="ITERS",
+                    help="only run ITERS eager tracking iterations (640x480, 500K Gaussians) for profiling, then exit")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return 0
+    if args.summarize_valu:
+        summarize_valu(args.summarize_valu[1:], args.summarize_valu[0])
         return 0
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.calib_copy_mib or 256)
@@ -460,6 +579,9 @@ def main() -> int:
 
     import torch
     from paper_2312_10070_amd import gsr, synth
+
+    if args.profile_tracking:
+        return profile_tracking(args.seed, args.gaussians, args.profile_tracking)
 
     t_gen = time.perf_counter()
     inp = synth.mapping_inputs(args.seed, args.gaussians)

@@ -52,7 +52,7 @@ def _load():
     i64 = ctypes.c_int64
     lib.orc_project.argtypes = [i64] + [P] * 9
     lib.orc_render.argtypes = [i64] + [P] * 8 + [ctypes.c_int, i64, P, ctypes.c_int] + [P] * 10
-    lib.orc_backward.argtypes = [i64] + [P] * 8 + [ctypes.c_int, i64, P, ctypes.c_int] + [P] * 7
+    lib.orc_backward.argtypes = [i64] + [P] * 8 + [ctypes.c_int, i64, P, ctypes.c_int] + [P] * 8
     lib.orc_backward.restype = i64
     lib.orc_tile_lists.argtypes = [i64] + [P] * 8 + [P, P, P, P, i64]
     lib.orc_loss_l1.argtypes = [i64, P, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
@@ -168,12 +168,14 @@ def split_flat(flat: np.ndarray, n: int) -> dict:
 
 def backward(g: dict, pose7, cam: Camera, opts: Opts, gC, gD, gA=None, mode: int = 1, pixels=None,
              nthreads: int | None = None, with_g2d: bool = False) -> dict:
-    """Analytic FP64 backward; returns grads, aref, slack (dicts) and n_unverifiable."""
+    """Analytic FP64 backward; returns grads, aref, aref_plain, slack (dicts) and n_unverifiable.
+    aref: per element, the summed magnitudes of its per-pixel terms (before cancellation), each pixel's
+    scaled by that pixel's transmittance condition number kappa; aref_plain: the same without kappa."""
     lib = _load()
     m, s, q, o, c = _params(g)
     n = m.shape[0]
     total = 14 * n + 13
-    gflat = np.zeros(total); aref = np.zeros(total); slack = np.zeros(total)
+    gflat = np.zeros(total); aref = np.zeros(total); slack = np.zeros(total); aplain = np.zeros(total)
     g2d = np.zeros((n, 10)) if with_g2d else None
     pix = None if pixels is None else np.ascontiguousarray(np.asarray(pixels, np.int64))
     npix = 0 if pix is None else pix.shape[0]
@@ -181,9 +183,9 @@ def backward(g: dict, pose7, cam: Camera, opts: Opts, gC, gD, gA=None, mode: int
     gCd = _d(gC); gDd = _d(gD); gAd = None if gA is None else _d(gA)
     nu = lib.orc_backward(n, _p(m), _p(s), _p(q), _p(o), _p(c), _p(_d(pose7)), _p(cam.packed()),
                           _p(opts.packed()), mode, npix, _p(pix), nt, _p(gCd), _p(gDd), _p(gAd), _p(gflat),
-                          _p(aref), _p(slack), _p(g2d))
-    out = dict(grads=split_flat(gflat, n), aref=split_flat(aref, n), slack=split_flat(slack, n),
-               n_unverifiable=int(nu))
+                          _p(aref), _p(slack), _p(g2d), _p(aplain))
+    out = dict(grads=split_flat(gflat, n), aref=split_flat(aref, n), aref_plain=split_flat(aplain, n),
+               slack=split_flat(slack, n), n_unverifiable=int(nu))
     if with_g2d:
         out["g2d"] = g2d
     return out

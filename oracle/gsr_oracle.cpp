@@ -472,10 +472,11 @@ void screen_delta(const Scene& S, const Proj& g, double& du, double& dv) {
 // With `mag` non-NULL it also receives, per pair, the same ten terms with every
 // factor replaced by its magnitude and every sum (in particular the two terms
 // of dC/dalpha and Eq. 8, which nearly cancel where a Gaussian matches what
-// lies behind it) by the sum of magnitudes, times the pixel's transmittance
-// condition number kappa = 1 + sum_k alpha_k / (1 - alpha_k) (a relative
-// error e in every alpha_k moves every T_j by at most kappa e): the scale
-// FP32 rounding acts on.
+// lies behind it) by the sum of magnitudes: the scale FP32 rounding acts on.
+// *kappa_out receives the pixel's transmittance condition number
+// kappa = 1 + sum_k alpha_k / (1 - alpha_k): a relative error e in every
+// alpha_k moves every T_j = prod_{k<j} (1 - alpha_k) by at most kappa e, since
+// d(1 - alpha_k) / (1 - alpha_k) = -alpha_k e / (1 - alpha_k).
 //
 // With `pos` non-NULL it receives, per pair, a first-order bound of how much
 // the ten terms move when the Gaussian's screen position (u, v) carries the
@@ -483,7 +484,8 @@ void screen_delta(const Scene& S, const Proj& g, double& du, double& dv) {
 // next to a Gaussian's centre, dx = px - u is small and that rounding is a
 // large part of it.
 void pixel_backward(const Scene& S, const PixResult& r, const double gC[3], double gD, double gA,
-                    std::vector<G2>& out, std::vector<G2>* mag = nullptr, std::vector<G2>* pos = nullptr) {
+                    std::vector<G2>& out, std::vector<G2>* mag = nullptr, std::vector<G2>* pos = nullptr,
+                    double* kappa_out = nullptr) {
   out.clear();
   if (mag) mag->clear();
   if (pos) pos->clear();
@@ -493,8 +495,11 @@ void pixel_backward(const Scene& S, const PixResult& r, const double gC[3], doub
     MC[ch] = std::fabs(SC[ch]);
   }
   const double Tfin = r.T;
-  double kappa = 1.0;
-  for (const Pair& p : r.pairs) kappa += p.alpha / (1.0 - p.alpha);
+  if (kappa_out) {
+    double kappa = 1.0;
+    for (const Pair& p : r.pairs) kappa += p.alpha / (1.0 - p.alpha);
+    *kappa_out = kappa;
+  }
   for (int j = (int)r.pairs.size() - 1; j >= 0; --j) {
     const Pair& p = r.pairs[j];
     const Proj& g = S.proj[p.id];
@@ -541,7 +546,6 @@ void pixel_backward(const Scene& S, const PixResult& r, const double gC[3], doub
     out.push_back(c);
     if (mag) {
       for (int f = 6; f < 10; ++f) m.g[f] = std::fabs(c.g[f]);
-      for (int f = 0; f < 10; ++f) m.g[f] *= kappa;
       mag->push_back(m);
     }
     if (pos) {
@@ -813,8 +817,10 @@ int orc_render(int64_t n, const double* means, const double* scales, const doubl
 // gflat / aref / slack / g2d use the flat layout
 //   means 3n | scales 3n | quats 4n | opacities n | colors 3n | pose7 | twist6
 // (g2d: [n,10]). aref = sum over pixels of the per-pixel term magnitudes of
-// pixel_backward (sums of magnitudes before any cancellation), chained with
-// absolute Jacobians: the scale of FP32 rounding, used as a tolerance floor. slack =
+// pixel_backward (sums of magnitudes before any cancellation) times the
+// pixel's transmittance condition number kappa, chained with absolute
+// Jacobians: the scale of FP32 rounding, used as a tolerance floor;
+// aref_plain (may be NULL) is the same without kappa. slack =
 // sum over pixels of the per-element maximum |branch - primary| over every
 // decision path of the pixel, plus the FP32 screen-position bound of
 // pixel_backward (absolute Jacobians again).
@@ -826,7 +832,7 @@ int64_t orc_backward(int64_t n, const double* means, const double* scales, const
                      const double* opac, const double* colors, const double* pose7, const double* cam,
                      const double* opt, int mode, int64_t npix, const int64_t* pix, int nthreads,
                      const double* gC, const double* gD, const double* gA, double* gflat, double* aref,
-                     double* slack, double* g2d_out) {
+                     double* slack, double* g2d_out, double* aref_plain) {
   Scene S;
   scene_from_args(S, n, means, scales, quats, opac, colors, pose7, cam, opt);
   build_scene(S, nthreads);
@@ -834,11 +840,12 @@ int64_t orc_backward(int64_t n, const double* means, const double* scales, const
   const int64_t P = (int64_t)W * H;
   const int64_t cnt = pix ? npix : P;
   if (nthreads < 1) nthreads = 1;
-  std::vector<std::vector<double>> acc(nthreads), aabs(nthreads), aslk(nthreads);
+  std::vector<std::vector<double>> acc(nthreads), aabs(nthreads), aplain(nthreads), aslk(nthreads);
   std::vector<int64_t> unver(nthreads, 0);
   for (int t = 0; t < nthreads; ++t) {
     acc[t].assign(10 * n, 0.0);
     aabs[t].assign(10 * n, 0.0);
+    aplain[t].assign(10 * n, 0.0);
     aslk[t].assign(10 * n, 0.0);
   }
   parallel_for(cnt, nthreads, [&](int t, int64_t b, int64_t e) {
@@ -851,11 +858,13 @@ int64_t orc_backward(int64_t n, const double* means, const double* scales, const
       const double gd = gD[p], ga = gA ? gA[p] : 0.0;
       if (g3[0] == 0 && g3[1] == 0 && g3[2] == 0 && gd == 0 && ga == 0) continue;
       composite_pixel(S, px, py, mode == 1, 0, true, r);
-      pixel_backward(S, r, g3, gd, ga, c1, &cm, &cpos);
+      double kappa = 1.0;
+      pixel_backward(S, r, g3, gd, ga, c1, &cm, &cpos, &kappa);
       for (size_t q = 0; q < c1.size(); ++q)
         for (int f = 0; f < 10; ++f) {
           acc[t][10 * c1[q].id + f] += c1[q].g[f];
-          aabs[t][10 * c1[q].id + f] += cm[q].g[f];
+          aabs[t][10 * c1[q].id + f] += kappa * cm[q].g[f];
+          aplain[t][10 * c1[q].id + f] += cm[q].g[f];
           aslk[t][10 * c1[q].id + f] += cpos[q].g[f];
         }
       if (r.events == 0) continue;
@@ -913,11 +922,12 @@ int64_t orc_backward(int64_t n, const double* means, const double* scales, const
       }
     }
   });
-  std::vector<double> g2(10 * n, 0.0), ab2(10 * n, 0.0), sl2(10 * n, 0.0);
+  std::vector<double> g2(10 * n, 0.0), ab2(10 * n, 0.0), ap2(10 * n, 0.0), sl2(10 * n, 0.0);
   for (int t = 0; t < nthreads; ++t)
     for (int64_t i = 0; i < 10 * n; ++i) {
       g2[i] += acc[t][i];
       ab2[i] += aabs[t][i];
+      ap2[i] += aplain[t][i];
       sl2[i] += aslk[t][i];
     }
   if (g2d_out)
@@ -927,6 +937,7 @@ int64_t orc_backward(int64_t n, const double* means, const double* scales, const
   for (int64_t i = 0; i < total; ++i) {
     gflat[i] = 0;
     if (aref) aref[i] = 0;
+    if (aref_plain) aref_plain[i] = 0;
     if (slack) slack[i] = 0;
   }
   for (int64_t k = 0; k < n; ++k) {
@@ -945,7 +956,7 @@ int64_t orc_backward(int64_t n, const double* means, const double* scales, const
       for (int i = 0; i < 6; ++i) dst[off_p + 7 + i] += scale * (absval ? std::fabs(vt[i]) : vt[i]);
     };
     scatter(gflat, o3, p7, t6, false, 1.0);
-    if (aref || slack) {
+    if (aref || aref_plain || slack) {
       // absolute-Jacobian propagation, one unit 2D direction at a time
       for (int f = 0; f < 10; ++f) {
         if (ab2[10 * k + f] == 0 && sl2[10 * k + f] == 0) continue;
@@ -954,6 +965,7 @@ int64_t orc_backward(int64_t n, const double* means, const double* scales, const
         double u3[14], up[7], ut[6];
         chain_3d(S, k, unit, u3, up, ut);
         if (aref) scatter(aref, u3, up, ut, true, ab2[10 * k + f]);
+        if (aref_plain) scatter(aref_plain, u3, up, ut, true, ap2[10 * k + f]);
         if (slack) scatter(slack, u3, up, ut, true, sl2[10 * k + f]);
       }
     }

@@ -16,8 +16,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgsr.so")
-SOURCES = ["gsr_api.hip", "k_project.hip", "k_sort.hip", "k_raster.hip", "k_loss.hip"]
-EXTRA_SOURCES = ["k_batch.hip", "k_graph.hip", "k_initnet.hip", "k_seed.hip"]
+SOURCES = ["gsr_api.hip", "k_project.hip", "k_sort.hip", "k_raster.hip", "k_loss.hip", "k_initnet.hip", "k_seed.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [
@@ -34,9 +33,7 @@ CFLAGS = [
 
 
 def sources():
-    out = [s for s in SOURCES]
-    out += [s for s in EXTRA_SOURCES if os.path.exists(os.path.join(HERE, s))]
-    return out
+    return list(SOURCES)
 
 
 def _compile(src: str) -> str:

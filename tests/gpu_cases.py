@@ -90,9 +90,10 @@ def compare_images(gpu: dict, orc: dict, tol: dict, max_unverifiable: float = 1e
     return report
 
 
-def grads_check(gpu: dict, ref: dict, rel=1e-3, floor=1e-5, keys=("means", "scales", "quats", "opacities", "colors")):
-    for k in keys:
-        H.check_grad(k, gpu[k], ref["grads"][k], ref["aref"][k], ref["slack"][k], rel=rel, floor=floor)
+def grads_check(gpu: dict, ref: dict, rel=1e-3, floor=1e-5, keys=("means", "scales", "quats", "opacities", "colors"),
+                case=None) -> dict:
+    """check_grad of every listed group; returns {group: audit}."""
+    return {k: H.check_grad_ref(k, gpu[k], ref, case=case, rel=rel, floor=floor) for k in keys}
 
 
 def c1_case(seed: int = 0, n: int = 1000):

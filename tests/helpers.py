@@ -123,10 +123,41 @@ def left_perturb_pose(pose7, xi):
     return np.concatenate([q * np.linalg.norm(pose7[:4]), tn])
 
 
-def check_grad(name, got, ref, aref, slack=None, rel=1e-3, floor=1e-5, block_floor=1e-6, max_bad=0):
+# Admission categories of the gradient bar, in the order the tolerance terms are
+# added: plain relative error, then the floor of summed term magnitudes
+# (without, then with the transmittance condition number kappa), then the
+# slack of ambiguous decisions and screen-position rounding, then the block
+# floor. Each element is counted in the first category whose cumulative
+# tolerance admits it.
+AUDIT_KEYS = ("rel", "floor_plain", "floor_kappa", "slack", "block", "fail")
+AUDIT_LOG: list = []
+
+
+def grad_audit(got, ref, aref, aref_plain=None, slack=None, rel=1e-3, floor=1e-5, block_floor=1e-6) -> dict:
+    """Per-category element counts of the gradient bar (see AUDIT_KEYS)."""
+    got = np.asarray(got, np.float64); ref = np.asarray(ref, np.float64)
+    err = np.abs(got - ref)
+    aref = np.asarray(aref, np.float64)
+    aplain = aref if aref_plain is None else np.asarray(aref_plain, np.float64)
+    t = [rel * np.abs(ref)]
+    t.append(t[0] + floor * aplain)
+    t.append(t[0] + floor * aref)
+    t.append(t[2] + (0.0 if slack is None else np.asarray(slack, np.float64)))
+    t.append(t[3] + (block_floor * np.abs(ref).max() if ref.size else 0.0))
+    cat = np.full(err.shape, len(t), np.int64)
+    for i in range(len(t) - 1, -1, -1):
+        cat = np.where(err <= t[i], i, cat)
+    counts = {k: int((cat == i).sum()) for i, k in enumerate(AUDIT_KEYS)}
+    counts["n"] = int(err.size)
+    return counts
+
+
+def check_grad(name, got, ref, aref, slack=None, rel=1e-3, floor=1e-5, block_floor=1e-6, max_bad=0,
+               aref_plain=None, case=None):
     """|got - ref| <= rel |ref| + floor * aref + block_floor * max|ref| + slack,
     elementwise. The block floor covers FP32 rounding in chains that cancel
-    exactly in FP64 (e.g. the quaternion gradient of an isotropic Gaussian)."""
+    exactly in FP64 (e.g. the quaternion gradient of an isotropic Gaussian).
+    Returns the audit of the bar (grad_audit) and records it in AUDIT_LOG."""
     got = np.asarray(got, np.float64); ref = np.asarray(ref, np.float64)
     tol = rel * np.abs(ref) + floor * np.asarray(aref, np.float64)
     if ref.size:
@@ -136,8 +167,16 @@ def check_grad(name, got, ref, aref, slack=None, rel=1e-3, floor=1e-5, block_flo
     err = np.abs(got - ref)
     bad = err > tol
     nbad = int(bad.sum())
+    audit = grad_audit(got, ref, aref, aref_plain, slack, rel, floor, block_floor)
+    AUDIT_LOG.append(dict(case=case, group=name, **audit))
     if nbad > max_bad:
         i = np.unravel_index(np.argmax(np.where(bad, err / np.maximum(tol, 1e-300), 0)), err.shape)
         raise AssertionError(f"{name}: {nbad} elements out of tolerance; worst at {i}: got {got[i]!r} "
                              f"ref {ref[i]!r} tol {tol[i]!r}")
-    return nbad
+    return audit
+
+
+def check_grad_ref(name, got, ref: dict, case=None, **kw):
+    """check_grad of one parameter group against an oracle.backward result."""
+    return check_grad(name, got, ref["grads"][name], ref["aref"][name], ref["slack"][name],
+                      aref_plain=ref.get("aref_plain", {}).get(name), case=case, **kw)

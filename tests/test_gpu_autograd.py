@@ -1,0 +1,127 @@
+"""The autograd path (render.GaussRender and the loss Functions): gradients
+reach every leaf through loss.backward() and match the FP64 oracle at C1 and
+at a posed, ragged 70 x 50 case; the autograd gradients equal those of a
+direct gsr.render_bwd call; an in-place change of a saved input between
+forward and backward is rejected; a tracking loop written with autograd and a
+torch optimiser tracks like the library's eager loop. Sec. 3.3 (explicit
+gradients), Sec. 3.4 (tracking)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_10070_amd import gsr, render, synth, tracking
+from tests import gpu_cases as G
+from tests import helpers as H
+from tests.test_gpu_parity import C1_OPTS, posed_case
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("means", "scales", "quats", "opacities", "colors")
+
+
+def leaves(g: dict, pose):
+    import torch
+    d = {k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).cuda().requires_grad_(True) for k, v in g.items()}
+    p = torch.tensor(np.asarray(pose, np.float32), device="cuda", requires_grad=True)
+    return d, p
+
+
+def autograd_grads(g, pose, cam: oracle.Camera, gC, gD, gA):
+    """render() on leaves, L = <C, gC> + <D, gD> + <A, gA>, L.backward()."""
+    import torch
+    d, p = leaves(g, pose)
+    camera = gsr.make_camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near_z, cam.bg)
+    C, D, A = render.render(*(d[k] for k in NAMES), p, camera)
+    L = (C * torch.from_numpy(gC).cuda()).sum() + (D * torch.from_numpy(gD).cuda()).sum() \
+        + (A * torch.from_numpy(gA).cuda()).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    out = {k: d[k].grad.cpu().numpy().astype(np.float64) for k in NAMES}
+    out["pose7"] = p.grad.cpu().numpy().astype(np.float64)
+    return out
+
+
+@pytest.mark.parametrize("which", ["C1", "posed"])
+def test_autograd_gradients_match_oracle(which):
+    rng = np.random.default_rng(4)
+    if which == "C1":
+        g, _, pose, cam = G.c1_case(0)
+        opts = C1_OPTS
+    else:
+        g, pose, cam = posed_case()
+        opts = oracle.Opts(amb_rel=1e-4)
+    gC = (rng.normal(size=(3, cam.height, cam.width)) * 1e-3).astype(np.float32)
+    gD = (rng.normal(size=(cam.height, cam.width)) * 1e-3).astype(np.float32)
+    gA = (rng.normal(size=(cam.height, cam.width)) * 1e-4).astype(np.float32)
+    got = autograd_grads(g, pose, cam, gC, gD, gA)
+    ref = oracle.backward(g, np.asarray(pose, np.float64), cam, opts, gC.astype(np.float64), gD.astype(np.float64),
+                          gA.astype(np.float64))
+    case = f"autograd {which}"
+    G.grads_check(got, ref, case=case)
+    H.check_grad_ref("pose7", got["pose7"], ref, case=case)
+
+
+def test_autograd_equals_direct_backward_and_l1_loss():
+    """loss = render.loss_l1(render(...)) through autograd against the same
+    forward + gsr.loss_l1 + gsr.render_bwd issued directly."""
+    import torch
+    g, tg, pose, cam = G.c1_case(1)
+    camera = gsr.make_camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near_z, cam.bg)
+    tgt = {k: torch.from_numpy(v).cuda() for k, v in G.f32(tg).items()}
+    pose_d = torch.tensor(np.asarray(pose, np.float32), device="cuda")
+    tc, td, _, st = gsr.render_fwd(*(tgt[k] for k in NAMES), pose_d, camera)
+    st.release()
+    d, p = leaves(g, pose)
+    C, D, A = render.render(*(d[k] for k in NAMES), p, camera)
+    loss = render.loss_l1(C, D, tc, td)
+    loss.backward()
+    plain = {k: v.detach().clone() for k, v in d.items()}
+    c2, d2, _, st2 = gsr.render_fwd(*(plain[k] for k in NAMES), pose_d, camera)
+    l2, gC, gD = gsr.loss_l1(c2, d2, tc, td)
+    ref = gsr.render_bwd(st2, gC, gD)
+    torch.cuda.synchronize()
+    assert loss.item() == l2.item()
+    for k in NAMES:
+        a, b = d[k].grad.cpu().numpy(), ref[k].cpu().numpy()
+        # the two backwards add the same terms; only the order of the float
+        # atomics between waves may differ
+        np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-6 * np.abs(b).max())
+    np.testing.assert_allclose(p.grad.cpu().numpy(), ref["pose7"].cpu().numpy(), rtol=1e-4,
+                               atol=1e-6 * np.abs(ref["pose7"].cpu().numpy()).max())
+
+
+def test_inplace_change_before_backward_is_rejected():
+    import torch
+    g, _, pose, cam = G.c1_case(2)
+    camera = gsr.make_camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near_z, cam.bg)
+    d, p = leaves(g, pose)
+    params = {k: v.detach().clone().requires_grad_(False) for k, v in d.items()}
+    params["means"].requires_grad_(True)
+    C, D, A = render.render(*(params[k] for k in NAMES), p, camera)
+    with torch.no_grad():
+        params["means"].add_(1e-3)  # the backward would re-read the changed buffer
+    with pytest.raises(RuntimeError):
+        (C.sum() + D.sum()).backward()
+
+
+def test_autograd_tracking_loop_tracks_like_the_eager_loop():
+    import torch
+    cam_i = synth.Intrinsics(320, 240, 262.5, 262.5, 160.0, 120.0)
+    inp = synth.tracking_inputs(5, 60_000, cam_i, n_views=3)
+    cam = gsr.camera_from(cam_i)
+    g = {k: torch.from_numpy(v).cuda() for k, v in inp["gaussians"].items()}
+    args = tuple(g[k] for k in NAMES)
+    obs_c, obs_d, _, st = gsr.render_fwd(*args, torch.from_numpy(inp["gt_pose7"]).cuda(), cam)
+    st.release()
+    init = torch.from_numpy(inp["init_pose7"]).cuda()
+    n_it = 30
+    pose_a, losses_a = tracking.track_autograd(*args, cam, obs_c, obs_d, init, n_iters=n_it)
+    pose_e, losses_e = tracking.track_eager(*args, cam, obs_c, obs_d, init, n_iters=n_it)
+    torch.cuda.synchronize()
+    la, le = losses_a.cpu().numpy(), losses_e.cpu().numpy()
+    assert abs(la[0] - le[0]) <= 1e-6 * abs(le[0])  # the same first render and loss
+    np.testing.assert_allclose(la, le, rtol=2e-2)
+    np.testing.assert_allclose(pose_a.cpu().numpy(), pose_e.cpu().numpy(), atol=2e-4)
+    e0 = synth.pose_error(inp["init_pose7"], inp["gt_pose7"])[0]
+    e1 = synth.pose_error(pose_a.cpu().numpy(), inp["gt_pose7"])[0]
+    assert e1 < 0.6 * e0

@@ -86,12 +86,13 @@ def test_batch_matches_oracle():
                          orc, {"color": 1e-4, "depth": 1e-4, "alpha": 1e-4})
         refs.append(oracle.backward(g, pose, cam, opts, gC[v].astype(np.float64), gD[v].astype(np.float64)))
         H.check_grad(f"pose{v}", out["pose7"][v].cpu().numpy(), refs[v]["grads"]["pose7"], refs[v]["aref"]["pose7"],
-                     refs[v]["slack"]["pose7"])
+                     refs[v]["slack"]["pose7"], aref_plain=refs[v]["aref_plain"]["pose7"], case="batch 2 views")
     for k in ("means", "scales", "quats", "opacities", "colors"):
         ref = refs[0]["grads"][k] + refs[1]["grads"][k]
         aref = refs[0]["aref"][k] + refs[1]["aref"][k]
+        aplain = refs[0]["aref_plain"][k] + refs[1]["aref_plain"][k]
         slack = refs[0]["slack"][k] + refs[1]["slack"][k]
-        H.check_grad(k, out[k].cpu().numpy(), ref, aref, slack)
+        H.check_grad(k, out[k].cpu().numpy(), ref, aref, slack, aref_plain=aplain, case="batch 2 views")
 
 
 def test_autotune_picks_a_timed_configuration():

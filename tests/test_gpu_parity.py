@@ -87,9 +87,10 @@ def test_c1_backward_parity(seed):
                          torch.from_numpy(gA32).cuda())
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
-    G.grads_check(got, ref)
-    H.check_grad("pose7", got["pose7"], ref["grads"]["pose7"], ref["aref"]["pose7"], ref["slack"]["pose7"])
-    H.check_grad("twist6", got["twist6"], ref["grads"]["twist6"], ref["aref"]["twist6"], ref["slack"]["twist6"])
+    case = f"C1 seed {seed}"
+    G.grads_check(got, ref, case=case)
+    H.check_grad_ref("pose7", got["pose7"], ref, case=case)
+    H.check_grad_ref("twist6", got["twist6"], ref, case=case)
 
 
 def posed_case(seed=3, n=2000, W=70, Hh=50):
@@ -127,15 +128,16 @@ def test_posed_ragged_forward_backward_and_tiles():
     out = gsr.render_bwd(st, torch.from_numpy(gC).cuda(), torch.from_numpy(gD).cuda())
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
-    G.grads_check(got, ref)
-    H.check_grad("pose7", got["pose7"], ref["grads"]["pose7"], ref["aref"]["pose7"], ref["slack"]["pose7"])
-    H.check_grad("twist6", got["twist6"], ref["grads"]["twist6"], ref["aref"]["twist6"], ref["slack"]["twist6"])
+    case = "posed 70x50"
+    G.grads_check(got, ref, case=case)
+    H.check_grad_ref("pose7", got["pose7"], ref, case=case)
+    H.check_grad_ref("twist6", got["twist6"], ref, case=case)
     # pose only: the six-field reduction (no opacity / colour fields)
     out_p = gsr.render_bwd(st, torch.from_numpy(gC).cuda(), torch.from_numpy(gD).cuda(), want_params=False)
     torch.cuda.synchronize()
     for k in ("pose7", "twist6"):
         gp = out_p[k].cpu().numpy().astype(np.float64)
-        H.check_grad(k, gp, ref["grads"][k], ref["aref"][k], ref["slack"][k])
+        H.check_grad_ref(k, gp, ref, case=case + " six-field")
 
 
 def test_empty_and_fully_culled_inputs_render_background():
@@ -190,7 +192,7 @@ def test_long_lists_and_early_termination():
     ref = oracle.backward(g, pose, cam, opts, gC.astype(np.float64), gD.astype(np.float64))
     b = gsr.render_bwd(st, torch.from_numpy(gC).cuda(), torch.from_numpy(gD).cuda())
     torch.cuda.synchronize()
-    G.grads_check({k: v.cpu().numpy().astype(np.float64) for k, v in b.items()}, ref)
+    G.grads_check({k: v.cpu().numpy().astype(np.float64) for k, v in b.items()}, ref, case="long lists 48x40")
 
 
 def test_tile_ranges_longer_than_lds_are_merged():
