@@ -42,10 +42,11 @@ def pytest_terminal_summary(terminalreporter, exitstatus, config):
         return
     tr = terminalreporter
     tr.write_sep("-", "gradient bar audit (elements admitted per tolerance term)")
-    tr.write_line("%-28s %-9s %8s %8s %8s %8s %8s %8s %6s" % ("case", "group", "n", *helpers.AUDIT_KEYS))
+    tr.write_line("%-28s %-9s %8s %8s %8s %8s %8s %8s %8s %6s" % ("case", "group", "n", "nonzero",
+                                                                 *helpers.AUDIT_KEYS))
     for r in log:
-        tr.write_line("%-28s %-9s %8d %8d %8d %8d %8d %8d %6d" % (
-            str(r["case"])[:28], r["group"], r["n"], *[r[k] for k in helpers.AUDIT_KEYS]))
+        tr.write_line("%-28s %-9s %8d %8d %8d %8d %8d %8d %8d %6d" % (
+            str(r["case"])[:28], r["group"], r["n"], r.get("nz", r["n"]), *[r[k] for k in helpers.AUDIT_KEYS]))
     path = os.environ.get("GSR_AUDIT_OUT")
     if path:
         import json

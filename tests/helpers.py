@@ -149,6 +149,9 @@ def grad_audit(got, ref, aref, aref_plain=None, slack=None, rel=1e-3, floor=1e-5
         cat = np.where(err <= t[i], i, cat)
     counts = {k: int((cat == i).sum()) for i, k in enumerate(AUDIT_KEYS)}
     counts["n"] = int(err.size)
+    # elements where either side is non-zero (an element both sides leave at
+    # exactly zero passes the relative bar trivially)
+    counts["nz"] = int(((ref != 0) | (got != 0)).sum())
     return counts
 
 

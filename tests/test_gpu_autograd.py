@@ -114,14 +114,17 @@ def test_autograd_tracking_loop_tracks_like_the_eager_loop():
     obs_c, obs_d, _, st = gsr.render_fwd(*args, torch.from_numpy(inp["gt_pose7"]).cuda(), cam)
     st.release()
     init = torch.from_numpy(inp["init_pose7"]).cuda()
-    n_it = 30
+    n_it = 100
     pose_a, losses_a = tracking.track_autograd(*args, cam, obs_c, obs_d, init, n_iters=n_it)
     pose_e, losses_e = tracking.track_eager(*args, cam, obs_c, obs_d, init, n_iters=n_it)
     torch.cuda.synchronize()
     la, le = losses_a.cpu().numpy(), losses_e.cpu().numpy()
     assert abs(la[0] - le[0]) <= 1e-6 * abs(le[0])  # the same first render and loss
-    np.testing.assert_allclose(la, le, rtol=2e-2)
-    np.testing.assert_allclose(pose_a.cpu().numpy(), pose_e.cpu().numpy(), atol=2e-4)
-    e0 = synth.pose_error(inp["init_pose7"], inp["gt_pose7"])[0]
-    e1 = synth.pose_error(pose_a.cpu().numpy(), inp["gt_pose7"])[0]
-    assert e1 < 0.6 * e0
+    # the float atomics of the two backwards add in different orders, so the
+    # two iterations drift apart slowly: the first 25 losses are compared
+    # closely, the end by the outcome (as the captured graph's test does)
+    np.testing.assert_allclose(la[:25], le[:25], rtol=2e-2)
+    e0 = synth.pose_error(inp["init_pose7"], inp["gt_pose7"])
+    for pose in (pose_a, pose_e):
+        et, er = synth.pose_error(pose.cpu().numpy(), inp["gt_pose7"])
+        assert et < 0.3 * e0[0] and er < 0.3 * e0[1], (e0, (et, er))
