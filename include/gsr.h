@@ -31,7 +31,8 @@
  *    the forward's Gaussian and pose inputs.
  *  - Errors: every call returns GSR_OK (0) or a negative code; no exception
  *    crosses the ABI. gsr_last_error() gives a message for the last failure
- *    on that context. A degenerate Gaussian (non-finite parameters, zero
+ *    on that context (with NULL: of the calling thread's last failed
+ *    context-free call). A degenerate Gaussian (non-finite parameters, zero
  *    quaternion, depth <= near_z, singular 2D covariance, opacity below
  *    alpha_min, support box off the image) is not an error: it is culled and
  *    receives zero gradient.
@@ -288,6 +289,26 @@ int gsr_loss_ssim(gsr_ctx *ctx, const float *color, const float *tgt_color, int3
 int gsr_loss_track(gsr_ctx *ctx, const float *color, const float *depth, const float *alpha,
                    const float *tgt_color, const float *tgt_depth, int64_t n_pixels, float lambda_c,
                    float inlier_mult, float *loss, float *dL_dcolor, float *dL_ddepth, float *median);
+
+/* gsr_loss_track without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): no context is needed, and the call makes no
+ * hipMalloc, hipFree or other allocating call. Same arguments, result and
+ * layout as gsr_loss_track; work is enqueued on hip_stream (NULL = the null
+ * stream) of the CURRENT device and not waited for.
+ * Scratch: the median's histograms and the loss reduction use a 32 KiB
+ * static device array of the library (one per device, held until the
+ * process ends), cleared by a fill kernel at the start of every call. Every
+ * call on one device shares it: calls that overlap on one device (other
+ * streams or threads without ordering between them) race and give wrong
+ * results. n_pixels <= GSR_NOALLOC_MAX_PIXELS (the histogram counts are
+ * 32-bit); larger is GSR_EINVAL. Errors: GSR_EINVAL (NULL required pointer,
+ * n_pixels out of range), GSR_EHIP (device lookup or launch failed); the
+ * message is gsr_last_error(NULL) on the calling thread. */
+#define GSR_NOALLOC_MAX_PIXELS 4294967295LL
+int gsr_loss_track_noalloc(void *hip_stream, const float *color, const float *depth, const float *alpha,
+                           const float *tgt_color, const float *tgt_depth, int64_t n_pixels, float lambda_c,
+                           float inlier_mult, float *loss, float *dL_dcolor, float *dL_ddepth, float *median);
 
 /* Optimiser --------------------------------------------------------------- */
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -412,7 +413,16 @@ const char* gsr_strerror(int code) {
   }
 }
 
-const char* gsr_last_error(gsr_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+namespace {
+// message of the calling thread's last failed context-free call
+thread_local std::string t_err;
+}  // namespace
+
+const char* gsr_last_error(gsr_ctx* ctx) {
+  if (ctx) return ctx->err.c_str();
+  return t_err.empty() ? "no context" : t_err.c_str();
+}
+
 
 void gsr_default_opts(gsr_opts* o) {
   if (!o) return;
@@ -830,6 +840,76 @@ int gsr_loss_track(gsr_ctx* c, const float* color, const float* depth, const flo
   gsr::launch_loss_track(color, depth, alpha, tgt_color, tgt_depth, P, lambda_c, inlier_mult, loss, dL_dcolor,
                          dL_ddepth, median, c->track_temp, c->stream);
   return check_launch(c, "gsr_loss_track");
+}
+
+// ---- tracking loss without allocation ---------------------------------------
+// The radix-select histograms, the grid-reduction partials and tickets of
+// gsr_loss_track_noalloc live in this file-scope device array (one copy per
+// device, held until the process ends). Host code never passes `scratch`
+// itself to a kernel: that name is a host-side stand-in. Its device address
+// is looked up once per device with hipGetSymbolAddress, with that device
+// current, and that address is what the kernels get.
+namespace {
+constexpr int64_t kNoAllocScratchWords = 8192;  // 32 KiB
+__device__ __align__(256) uint32_t scratch[kNoAllocScratchWords];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_dev[kMaxDevices] = {};
+
+int noalloc_fail(int code, const std::string& msg) {
+  t_err = msg;
+  return code;
+}
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there); NULL with t_err set on failure.
+uint32_t* noalloc_scratch(int* code) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    *code = noalloc_fail(GSR_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      *code = noalloc_fail(GSR_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_dev[dev] = static_cast<uint32_t*>(ptr);
+  }
+  return g_scratch_dev[dev];
+}
+}  // namespace
+
+int gsr_loss_track_noalloc(void* hip_stream, const float* color, const float* depth, const float* alpha,
+                           const float* tgt_color, const float* tgt_depth, int64_t P, float lambda_c,
+                           float inlier_mult, float* loss, float* dL_dcolor, float* dL_ddepth, float* median) {
+  if (P < 0 || !loss ||
+      (P > 0 && (!color || !depth || !alpha || !tgt_color || !tgt_depth || !dL_dcolor || !dL_ddepth)))
+    return noalloc_fail(GSR_EINVAL, "gsr_loss_track_noalloc: bad loss arguments");
+  if (P > (int64_t)GSR_NOALLOC_MAX_PIXELS)
+    return noalloc_fail(GSR_EINVAL, "gsr_loss_track_noalloc: more than GSR_NOALLOC_MAX_PIXELS pixels "
+                                    "(the median's histogram counts are 32-bit)");
+  const int64_t words = gsr::track_temp_words();
+  if (words > kNoAllocScratchWords)
+    return noalloc_fail(GSR_EINVAL, "gsr_loss_track_noalloc: the loss needs more scratch than the static array holds");
+  int code = GSR_OK;
+  uint32_t* temp = noalloc_scratch(&code);
+  if (!temp) return code;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // the previous call (on any stream) leaves its histograms and tickets behind:
+  // clear them with a fill kernel (no memset node, so the call can be captured)
+  gsr::launch_fill_u32(temp, 0u, words, s);
+  gsr::launch_loss_track(color, depth, alpha, tgt_color, tgt_depth, P, lambda_c, inlier_mult, loss, dL_dcolor,
+                         dL_ddepth, median, temp, s);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return noalloc_fail(GSR_EHIP, std::string("gsr_loss_track_noalloc: ") + hipGetErrorString(e));
+  return GSR_OK;
 }
 
 int gsr_adam(gsr_ctx* c, float* param, float* m, float* v, const float* grad, int64_t n, int64_t step, float lr,

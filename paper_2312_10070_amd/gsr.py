@@ -94,6 +94,8 @@ _SIGS = {
     "gsr_prune": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_float, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_loss_ssim": (ctypes.c_int, [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P, P]),
     "gsr_loss_track": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P, P, P]),
+    "gsr_loss_track_noalloc": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P,
+                                              P, P]),
     "gsr_adam": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float]),
     "gsr_adam_groups": (ctypes.c_int, [P, ctypes.c_int32, P, P, P, P, P, P, ctypes.c_int64, ctypes.c_float,
@@ -583,6 +585,32 @@ def loss_track(color, depth, alpha, tgt_color, tgt_depth, lambda_c=0.5, inlier_m
                                      P_, float(lambda_c), float(inlier_mult), _ptr(loss), _ptr(gC), _ptr(gD),
                                      _ptr(med)))
     return loss, gC, gD, med
+
+
+def loss_track_noalloc(color, depth, alpha, tgt_color, tgt_depth, loss, dL_dcolor, dL_ddepth, median=None,
+                       lambda_c=0.5, inlier_mult=50.0):
+    """gsr_loss_track_noalloc: the tracking loss (Eq. 15) into caller-given
+    outputs (loss [1], dL/dcolor, dL/ddepth, median [1] or None) on torch's
+    current stream of the tensors' device; the library allocates nothing and
+    needs no context (its scratch is a static device array shared by every
+    call on the device)."""
+    lib = load()
+    P_ = depth.numel()
+    for t, nme in ((color, "color"), (depth, "depth"), (alpha, "alpha"), (tgt_color, "tgt_color"),
+                   (tgt_depth, "tgt_depth"), (loss, "loss"), (dL_dcolor, "dL_dcolor"), (dL_ddepth, "dL_ddepth")):
+        _f32(t, nme)
+    if median is not None:
+        _f32(median, "median")
+    if dL_dcolor.numel() != color.numel() or dL_ddepth.numel() != P_ or loss.numel() < 1:
+        raise ValueError("output sizes do not match the inputs")
+    with torch.cuda.device(color.device):
+        stream = ctypes.c_void_p(torch.cuda.current_stream(color.device).cuda_stream)
+        rc = lib.gsr_loss_track_noalloc(stream, _ptr(color), _ptr(depth), _ptr(alpha), _ptr(tgt_color),
+                                        _ptr(tgt_depth), P_, float(lambda_c), float(inlier_mult), _ptr(loss),
+                                        _ptr(dL_dcolor), _ptr(dL_ddepth), _ptr(median))
+    if rc != 0:
+        raise GsrError(rc, f"gsr_loss_track_noalloc: {lib.gsr_strerror(rc).decode()}: "
+                           f"{lib.gsr_last_error(None).decode()}")
 
 
 def adam_step(param, exp_avg, exp_avg_sq, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,

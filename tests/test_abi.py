@@ -52,3 +52,7 @@ def test_host_only_calls():
     # a NULL context is rejected without touching a device
     assert lib.gsr_set_stream(None, None) == gsr.GSR_EINVAL
     assert lib.gsr_ctx_create(None, 0, None) == gsr.GSR_EINVAL
+    # the context-free loss checks its arguments before any device call
+    assert lib.gsr_loss_track_noalloc(None, None, None, None, None, None, 4, 0.5, 50.0, None, None, None,
+                                      None) == gsr.GSR_EINVAL
+    assert b"bad loss arguments" in lib.gsr_last_error(None)
