@@ -117,7 +117,7 @@ def read_traffic(stage: str, workload: str):
 
 
 # kernels of each stage, as rocprofv3 names them (prefix after the namespace)
-STAGE_KERNELS = {"render_bwd": ["k_render_bwd<false>("], "render_fwd": ["k_render_fwd<false>("],
+STAGE_KERNELS = {"render_bwd": ["k_render_bwd_block<false>("], "render_fwd": ["k_render_fwd<false>("],
                  "tile_bins": ["k_tile_init(", "k_bin_place(", "k_tile_sort("],
                  "bin_count": ["k_bin_count(", "k_scan_reduce(", "k_scan_partials(", "k_scan_down("],
                  "project": ["k_project("], "project_bwd_adam": ["k_project_bwd("],
@@ -192,7 +192,7 @@ VALU_PASSES = [
 ]
 N_CU = 256  # MI355X compute units
 # kernels of the tracking iteration, as rocprofv3 names them
-TRACK_KERNELS = {"render_bwd": ["k_render_bwd<true>("], "render_fwd": ["k_render_fwd<false>("],
+TRACK_KERNELS = {"render_bwd": ["k_render_bwd_quad<false>("], "render_fwd": ["k_render_fwd<false>("],
                  "project": ["k_project("], "project_bwd": ["k_project_bwd("],
                  "loss_track": ["k_select_init(", "k_select_hist(", "k_loss_track("]}
 PROFILE_COMMANDS = {
@@ -202,13 +202,21 @@ PROFILE_COMMANDS = {
 }
 
 
+N_XCD = 8   # accelerator complex dies, each with its own GRBM
+
+
 def summarize_valu(csvs: list, workload: str) -> None:
     """Writes profiles/<stage>_<workload>_valu.txt from rocprofv3 --pmc runs of
-    VALU_PASSES: per-dispatch averages of the counters and the utilisation
-    figures rocprofv3's own derived metrics define (VALUBusy,
-    VALUUtilization, LDSBankConflict), plus instruction issue rates per CU
-    cycle (a CU issues at most one wave64 VALU instruction per cycle: four
-    16-lane SIMDs, four cycles each)."""
+    VALU_PASSES: per-dispatch averages of the counters and utilisation
+    figures per CU cycle. rocprofv3 reports GRBM_GUI_ACTIVE summed over the 8
+    XCDs, so the kernel's cycles are GRBM_GUI_ACTIVE / 8 (at 2.4 GHz this
+    reproduces the kernel trace's durations). A CU issues at most one wave64
+    VALU instruction per cycle (four 16-lane SIMDs, four cycles each), so
+    valu_issue = SQ_INSTS_VALU / (256 CUs x cycles) is the fraction of the
+    chip's VALU issue slots used; lanes_per_valu is the fraction of the 64
+    lanes enabled per VALU instruction (SQ_THREAD_CYCLES_VALU /
+    (64 SQ_ACTIVE_INST_VALU)); the LDS figures are instructions per CU
+    cycle."""
     import csv
     import collections
     vals = collections.defaultdict(lambda: collections.defaultdict(list))
@@ -226,20 +234,22 @@ def summarize_valu(csvs: list, workload: str) -> None:
         if name is None:
             continue
         avg = {c: sum(v) / len(v) for c, v in vals[name].items()}
-        cyc = avg.get("GRBM_GUI_ACTIVE", 0.0)
+        cyc = avg.get("GRBM_GUI_ACTIVE", 0.0) / N_XCD
         if cyc <= 0:
             continue
         per_cu = lambda c: avg.get(c, 0.0) / (N_CU * cyc)
         act = avg.get("SQ_ACTIVE_INST_VALU", 0.0)
         derived = {
-            "valu_insts_per_cu_cycle": per_cu("SQ_INSTS_VALU"),
-            "VALUBusy": per_cu("SQ_ACTIVE_INST_VALU"),
-            "VALUUtilization": avg.get("SQ_THREAD_CYCLES_VALU", 0.0) / (act * 64) if act else 0.0,
+            "cycles": cyc,
+            "us_at_2.4GHz": cyc / 2400.0,
+            "valu_issue": per_cu("SQ_INSTS_VALU"),
+            "lanes_per_valu": avg.get("SQ_THREAD_CYCLES_VALU", 0.0) / (act * 64) if act else 0.0,
             "salu_insts_per_cu_cycle": per_cu("SQ_INSTS_SALU"),
             "lds_insts_per_cu_cycle": per_cu("SQ_INSTS_LDS"),
-            "LDSBankConflict": per_cu("SQ_LDS_BANK_CONFLICT"),
+            "lds_bank_conflict_per_cu_cycle": per_cu("SQ_LDS_BANK_CONFLICT"),
             "lds_active_per_cu_cycle": per_cu("SQ_ACTIVE_INST_LDS"),
             "trans_insts_per_cu_cycle": per_cu("SQ_INSTS_VALU_TRANS_F32"),
+            "vmem_insts_per_cu_cycle": per_cu("SQ_INSTS_VMEM"),
         }
         path = os.path.join(ROOT, "profiles", f"{stage}_{workload}_valu.txt")
         with open(path, "w") as f:
@@ -248,8 +258,9 @@ def summarize_valu(csvs: list, workload: str) -> None:
                 f.write(f"# pass {i + 1}: cd /tmp && rocprofv3 --pmc {counters} -d <dir> -o run --output-format csv "
                         f"-- {PROFILE_COMMANDS[workload]}\n")
             f.write(f"#   then: python bench.py --summarize-valu {workload} <pass csvs>\n")
-            f.write("# ratios per CU cycle divide by 256 CUs x GRBM_GUI_ACTIVE; VALUBusy, VALUUtilization and\n"
-                    "# LDSBankConflict follow rocprofv3's derived-metric definitions (as fractions, not percent)\n")
+            f.write("# cycles = GRBM_GUI_ACTIVE / 8 (summed over the 8 XCDs); valu_issue = SQ_INSTS_VALU / (256 CUs x\n"
+                    "# cycles), the fraction of VALU issue slots used (one wave64 instruction per CU per cycle);\n"
+                    "# lanes_per_valu = SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU); other ratios per CU cycle\n")
             f.write(f"source_sha1: {source_hash(STAGE_SOURCES[stage])}\n")
             f.write(f"dispatches: {len(vals[name].get('GRBM_GUI_ACTIVE', []))}\n")
             for c in sorted(avg):
@@ -272,7 +283,7 @@ def read_valu(stage: str, workload: str):
             kv[k.strip()] = v.strip()
     if kv.get("source_sha1") != source_hash(STAGE_SOURCES[stage]):
         return None
-    keys = ("valu_insts_per_cu_cycle", "VALUBusy", "VALUUtilization", "lds_insts_per_cu_cycle", "LDSBankConflict")
+    keys = ("valu_issue", "lanes_per_valu", "lds_insts_per_cu_cycle", "lds_bank_conflict_per_cu_cycle")
     return {k: float(kv[k]) for k in keys if k in kv}
 
 

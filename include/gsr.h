@@ -67,7 +67,7 @@ typedef struct {
 } gsr_camera;
 
 /* Rasterizer constants (host struct). Defaults: lowpass 0.3 px^2, alpha_min
- * 1/255, alpha_max 0.99, T_min 1e-4, guard 1.3, tile 16x16. */
+ * 1/255, alpha_max 0.99, T_min 1e-4, guard 1.3, tile 16x16, deterministic 0. */
 typedef struct {
   float lowpass;   /* h added to both diagonal entries of Sigma' */
   float alpha_min; /* pairs with alpha < alpha_min are skipped */
@@ -75,6 +75,18 @@ typedef struct {
   float T_min;     /* a pixel stops before the Gaussian that would take T below it */
   float guard;     /* lateral clamp of x/z, y/z inside J: guard * max(c, size-c) / f */
   int32_t tile_w, tile_h; /* 16x16, 8x32 or 32x8 */
+  /* 0: the backward adds per-tile partial sums with float atomics (fastest;
+   *    the order of those additions, and so the last bits of the gradients,
+   *    varies between runs).
+   * 1: the backward stores every (Gaussian, tile, 8x8 pixel block) partial
+   *    sum (4x4 quadrant when only the pose gradient is wanted) and adds them
+   *    per Gaussian in a fixed order (tiles in row-major order of its tile
+   *    rectangle, blocks in order), so
+   *    gradients are bitwise reproducible; it needs 648 bytes per tile
+   *    overlap and 4 per Gaussian and view more device memory, allocated by
+   *    the first such backward of a state (synchronises), and is slower.
+   *    Not supported by the tracking graph (GSR_EINVAL). */
+  int32_t deterministic;
 } gsr_opts;
 
 typedef struct {
@@ -216,6 +228,20 @@ int gsr_seed_candidates(gsr_ctx *ctx, const gsr_camera *cam, const float *pose7,
  * map so far has none within rho). Synchronises. */
 int gsr_compact(gsr_ctx *ctx, int64_t n, const int32_t *keep, const float *const *in, float *const *out,
                 int64_t *n_kept);
+
+/* Sub-map offload and restore (Sec. 3.2: only the active sub-map is kept in
+ * GPU memory; a finished one is stored away until the global map is built).
+ * Offload copies the n Gaussians' five parameter arrays in[0..4] (device:
+ * means, scales, quats, opacities, colors) into one host buffer laid out
+ * [means 3n | scales 3n | quats 4n | opacities n | colors 3n] (14 n floats);
+ * restore copies such a buffer into the device arrays out[0..4]. Both
+ * enqueue copies on the context's stream and return without waiting: the
+ * host buffer must stay alive (and, for restore, unchanged) until the stream
+ * has passed the call. With pinned host memory (hipHostMalloc) the copies
+ * are asynchronous DMA; with pageable memory HIP may stage them. n >= 0
+ * (n = 0 copies nothing). GSR_EINVAL for NULL arrays or host buffer. */
+int gsr_submap_offload(gsr_ctx *ctx, int64_t n, const float *const *in, float *host);
+int gsr_submap_restore(gsr_ctx *ctx, int64_t n, const float *host, float *const *out);
 
 /* Sub-map creation rule (Sec. 3.2): a new sub-map starts when the current
  * frame's camera centre is more than d_thre from that of the active sub-map's

@@ -51,6 +51,17 @@ struct gsr_state {
   uint64_t* keys = nullptr;     // [K] (depth bits << 32 | record index), slot order
   uint64_t* scratch = nullptr;  // [K] merge buffer for tile ranges longer than LDS holds
   uint32_t* ids = nullptr;      // [K] record indices, per tile in depth order
+  // deterministic backward (opts.deterministic): arena D, allocated by the
+  // first such backward of the state
+  bool det = false;
+  void* arenaD = nullptr;
+  int64_t det_K_cap = -1, det_n_cap = -1;
+  uint32_t* det_goff = nullptr;   // [V n] exclusive scan of the records' tile counts
+  uint32_t* det_total = nullptr;  // [1]
+  uint32_t* det_scan = nullptr;   // scan temp
+  uint32_t* det_rev = nullptr;    // [K] list position of each (record, tile of its rectangle)
+  uint32_t* det_mask = nullptr;   // [K] quadrants that stored a sum
+  float* det_part = nullptr;      // [K, 16, 10] per (list position, quadrant) sums
 };
 
 struct gsr_track_graph {
@@ -234,6 +245,37 @@ int ensure_B(gsr_ctx* c, gsr_state* s, int64_t K) {
   return GSR_OK;
 }
 
+// Arena D of a deterministic backward: sized for the state's current overlap
+// count and records (allocation synchronises the device).
+int ensure_D(gsr_ctx* c, gsr_state* s) {
+  const int64_t n_rec = s->n * s->n_views, K = s->K;
+  if (s->arenaD && K <= s->det_K_cap && n_rec <= s->det_n_cap) return GSR_OK;
+  if (s->arenaD) GSR_HIP(c, hipFree(s->arenaD));
+  s->arenaD = nullptr;
+  const int64_t kk = std::max<int64_t>(K + K / 4, 4096), nn = std::max<int64_t>(n_rec + n_rec / 4, 1024);
+  Carver cv{nullptr};
+  for (int pass = 0; pass < 2; ++pass) {
+    s->det_goff = cv.take<uint32_t>(nn);
+    s->det_total = cv.take<uint32_t>(1);
+    s->det_scan = cv.take<uint32_t>(gsr::scan_temp_words(nn));
+    s->det_rev = cv.take<uint32_t>(kk);
+    s->det_mask = cv.take<uint32_t>(kk);
+    s->det_part = cv.take<float>(kk * 16 * 10);
+    if (pass == 0) {
+      void* p = nullptr;
+      if (hipMalloc(&p, cv.off) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, GSR_ENOMEM, "device allocation of the deterministic backward's workspace failed");
+      }
+      s->arenaD = p;
+      cv = Carver{(char*)p};
+    }
+  }
+  s->det_K_cap = kk;
+  s->det_n_cap = nn;
+  return GSR_OK;
+}
+
 int make_raster(gsr_ctx* c, const gsr_camera* cam, const gsr_opts* o, gsr::Raster* R) {
   if (!cam || !o) return fail(c, GSR_EINVAL, "camera and opts are required");
   if (cam->width <= 0 || cam->height <= 0) return fail(c, GSR_EINVAL, "image size must be positive");
@@ -364,8 +406,21 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
   // clears the sums it reads
   const bool geom_only = !adam && (!grads || (!grads->opacities && !grads->colors));
   gsr::BwdArgs ba{s->ranges, s->ids, s->rec_uvab, s->rec_cob, s->rec_rgbz, s->Tfin, s->last,
-                  gC, gD, gA, s->g2d, geom_only, n_items, s->queue, s->blocks > 0 ? s->order : nullptr, s->blocks};
-  {
+                  gC, gD, gA, s->g2d, geom_only, n_items, s->queue, s->blocks > 0 ? s->order : nullptr, s->blocks,
+                  nullptr, nullptr};
+  if (s->det) {
+    // arena D is in place (ensure_D): list positions of every (record, tile),
+    // then the stored quadrant sums, then their fixed-order totals
+    const int64_t n_rec = s->n * s->n_views;
+    Stage t(c, "render_bwd");
+    gsr::launch_exclusive_scan(s->counts, s->det_goff, n_rec, s->det_total, s->det_scan, st);
+    gsr::launch_det_rev(R, s->ranges, s->ids, s->rect, s->det_goff, s->det_rev, n_items, st);
+    gsr::launch_fill_u32(s->det_mask, 0u, s->K, st);
+    ba.part = s->det_part;
+    ba.mask = s->det_mask;
+    gsr::launch_render_bwd(R, ba, st);
+    gsr::launch_det_reduce(s->rect, s->det_goff, s->det_rev, s->det_mask, s->det_part, n_rec, geom_only, s->g2d, st);
+  } else {
     Stage t(c, "render_bwd");
     gsr::launch_render_bwd(R, ba, st);
   }
@@ -423,7 +478,6 @@ const char* gsr_last_error(gsr_ctx* ctx) {
   return t_err.empty() ? "no context" : t_err.c_str();
 }
 
-
 void gsr_default_opts(gsr_opts* o) {
   if (!o) return;
   o->lowpass = 0.3f;
@@ -433,6 +487,7 @@ void gsr_default_opts(gsr_opts* o) {
   o->guard = 1.3f;
   o->tile_w = 16;
   o->tile_h = 16;
+  o->deterministic = 0;
 }
 
 int gsr_ctx_create(gsr_ctx** out, int device, void* hip_stream) {
@@ -492,6 +547,7 @@ int gsr_ctx_destroy(gsr_ctx* c) {
   for (gsr_state* s : c->pool) {
     if (s->arenaA) (void)hipFree(s->arenaA);
     if (s->arenaB) (void)hipFree(s->arenaB);
+    if (s->arenaD) (void)hipFree(s->arenaD);
     delete s;
   }
   if (c->h_K) (void)hipHostFree(c->h_K);
@@ -548,6 +604,7 @@ int gsr_render_fwd_batch(gsr_ctx* c, const gsr_gaussians* g, int32_t n_views, co
   s->pose7 = poses7;
   s->n_views = n_views;
   s->blocks = blocks_per_cu * c->n_cu;
+  s->det = opts->deterministic != 0;
   hipStream_t st = c->stream;
   // the scan writes K straight into the pinned host word; the event's
   // system-scope release makes it visible to the host
@@ -593,6 +650,10 @@ int gsr_render_bwd(gsr_ctx* c, gsr_state* s, const float* dL_dcolor, const float
   const gsr_grads* G = grads;
   if (G && G->quats && (reinterpret_cast<uintptr_t>(G->quats) & 15u) != 0)
     return fail(c, GSR_EINVAL, "the quaternion gradient must be 16-byte aligned");
+  if (s->det) {
+    const int rc = ensure_D(c, s);
+    if (rc) return rc;
+  }
   enqueue_bwd(c, s, c->stream, dL_dcolor, dL_ddepth, dL_dalpha, G, dL_dpose7, dL_dtwist6);
   return check_launch(c, "gsr_render_bwd kernels");
 }
@@ -622,6 +683,10 @@ int gsr_render_bwd_adam(gsr_ctx* c, gsr_state* s, const float* dL_dcolor, const 
   A.reg_w = s->g.n > 0 ? (float)((double)adam->scale_reg / (double)s->g.n) : 0.f;
   A.on = true;
   GSR_HIP(c, hipSetDevice(c->device));
+  if (s->det) {
+    const int rc = ensure_D(c, s);
+    if (rc) return rc;
+  }
   enqueue_bwd(c, s, c->stream, dL_dcolor, dL_ddepth, dL_dalpha, nullptr, nullptr, nullptr, &A);
   return check_launch(c, "gsr_render_bwd_adam kernels");
 }
@@ -766,6 +831,42 @@ int gsr_compact(gsr_ctx* c, int64_t n, const int32_t* keep, const float* const* 
   if (!c) return GSR_EINVAL;
   if (n > 0 && !keep) return fail(c, GSR_EINVAL, "compact: keep mask required");
   return compact_impl(c, n, 0.f, keep ? keep : (const int32_t*)nullptr, in, out, n_kept, "compact");
+}
+
+namespace {
+// Copies the five parameter arrays of n Gaussians between device arrays and
+// one host buffer [means 3n | scales 3n | quats 4n | opacities n | colors 3n].
+int submap_copy(gsr_ctx* c, int64_t n, const float* const* dev_in, float* const* dev_out, const float* host_in,
+                float* host_out, const char* what) {
+  if (!c) return GSR_EINVAL;
+  if (n < 0 || (n > 0 && !(host_in || host_out))) return fail(c, GSR_EINVAL, std::string(what) + ": bad arguments");
+  if (n == 0) return GSR_OK;
+  static constexpr int kWidth[5] = {3, 3, 4, 1, 3};
+  for (int i = 0; i < 5; ++i)
+    if ((dev_in && !dev_in[i]) || (dev_out && !dev_out[i]))
+      return fail(c, GSR_EINVAL, std::string(what) + ": all five parameter arrays are required");
+  GSR_HIP(c, hipSetDevice(c->device));
+  int64_t off = 0;
+  for (int i = 0; i < 5; ++i) {
+    const size_t bytes = sizeof(float) * (size_t)(kWidth[i] * n);
+    if (dev_in)
+      GSR_HIP(c, hipMemcpyAsync(host_out + off, dev_in[i], bytes, hipMemcpyDeviceToHost, c->stream));
+    else
+      GSR_HIP(c, hipMemcpyAsync(dev_out[i], host_in + off, bytes, hipMemcpyHostToDevice, c->stream));
+    off += kWidth[i] * n;
+  }
+  return GSR_OK;
+}
+}  // namespace
+
+int gsr_submap_offload(gsr_ctx* c, int64_t n, const float* const* in, float* host) {
+  if (!in) return fail(c, GSR_EINVAL, "submap offload: parameter arrays required");
+  return submap_copy(c, n, in, nullptr, nullptr, host, "submap offload");
+}
+
+int gsr_submap_restore(gsr_ctx* c, int64_t n, const float* host, float* const* out) {
+  if (!out) return fail(c, GSR_EINVAL, "submap restore: parameter arrays required");
+  return submap_copy(c, n, nullptr, out, host, nullptr, "submap restore");
 }
 
 int gsr_submap_trigger(const float* pose_first7, const float* pose_cur7, float d_thre, float theta_thre,
@@ -1350,6 +1451,7 @@ int gsr_track_graph_create(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera*
   gsr::Raster R;
   int rc = make_raster(c, cam, opts, &R);
   if (rc) return rc;
+  if (opts->deterministic) return fail(c, GSR_EINVAL, "the tracking graph has no deterministic backward");
   GSR_HIP(c, hipSetDevice(c->device));
   gsr_track_graph* tg = new (std::nothrow) gsr_track_graph();
   if (!tg) return fail(c, GSR_ENOMEM, "host allocation failed");

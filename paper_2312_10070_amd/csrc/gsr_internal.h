@@ -76,24 +76,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return x * q + (x < r ? x : r) + i;
 }
 
-// Sum over the 64 lanes with DPP row operations; the total lands in lane 63.
-__device__ __forceinline__ float wave_sum_lane63(float v) {
-  int x = __float_as_int(v);
-#define GSR_DPP_ADD(ctrl)                                                                  \
-  x = __float_as_int(__int_as_float(x) +                                                   \
-                     __int_as_float(__builtin_amdgcn_update_dpp(0, x, ctrl, 0xf, 0xf, false)))
-  GSR_DPP_ADD(0xb1);   // quad_perm [1,0,3,2]
-  GSR_DPP_ADD(0x4e);   // quad_perm [2,3,0,1]
-  GSR_DPP_ADD(0x124);  // row_ror:4
-  GSR_DPP_ADD(0x128);  // row_ror:8
-  GSR_DPP_ADD(0x142);  // row_bcast:15
-  GSR_DPP_ADD(0x143);  // row_bcast:31
-#undef GSR_DPP_ADD
-  return __int_as_float(x);
-}
-
-// Adds the wave-wide sums of ten per-lane values to dst[0..9] with one
-// 10-lane atomic. Field-splitting butterfly: at each of four exchange steps a
+// Wave-wide sums of ten per-lane values: returns the sum the lane ends with
+// and sets *f to its field, or -1 (ten lanes end with one field each).
+// Field-splitting butterfly: at each of four exchange steps a
 // lane keeps half of its remaining fields and hands the other half to its
 // partner (v_permlane32_swap across the 32-lane halves, v_permlane16_swap
 // across rows, then DPP row_mirror / row_half_mirror inside rows), so the ten
@@ -112,7 +97,7 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
-__device__ __forceinline__ void wave_add10(const float v[10], float* __restrict__ dst, int lane) {
+__device__ __forceinline__ float wave_reduce10(const float v[10], int lane, int* f) {
   // step 1 (lane bit 5): pairs of fields (2k, 2k+1)
   const float r10 = perm_add32(v[0], v[1]);
   const float r11 = perm_add32(v[2], v[3]);
@@ -136,31 +121,9 @@ __device__ __forceinline__ void wave_add10(const float v[10], float* __restrict_
   // steps 5-6: sum the quad
   r4 += dpp_f<0xb1>(r4);                                   // quad_perm [1,0,3,2]
   r4 += dpp_f<0x4e>(r4);                                   // quad_perm [2,3,0,1]
-  const int f = 8 * ((lane >> 2) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
-  if ((lane & 3) == 0 && f < 10) atomicAdd(dst + f, r4);
-}
-
-// The same for the six fields the mean, scale, rotation and camera-pose
-// gradients need (v[0..4] and v[9]; opacity and colour are not reduced): three exchange steps, then the
-// 8-lane sum. Lane L with (L & 7) == 0 ends with field 2 b4 + b5 (b3 = 0) or,
-// for b3 = 1 and b4 = 0, field 4 + b5 (v[4] or v[9]).
-__device__ __forceinline__ void wave_add6(const float v[10], float* __restrict__ dst, int lane) {
-  const float r10 = perm_add32(v[0], v[1]);
-  const float r11 = perm_add32(v[2], v[3]);
-  const float r12 = perm_add32(v[4], v[9]);
-  const float r20 = perm_add16(r10, r11);
-  const float r21 = perm_add16(r12, 0.f);
-  const bool b3 = (lane >> 3) & 1;
-  const float a0 = b3 ? r21 : r20, c0 = b3 ? r20 : r21;
-  float r = a0 + dpp_f<0x140>(c0);  // row_mirror
-  r += dpp_f<0x141>(r);             // row_half_mirror
-  r += dpp_f<0xb1>(r);              // quad_perm [1,0,3,2]
-  r += dpp_f<0x4e>(r);              // quad_perm [2,3,0,1]
-  const int b4 = (lane >> 4) & 1, b5 = (lane >> 5) & 1;
-  if ((lane & 7) == 0) {
-    if (!b3) atomicAdd(dst + 2 * b4 + b5, r);
-    else if (!b4) atomicAdd(dst + (b5 ? 9 : 4), r);
-  }
+  const int fld = 8 * ((lane >> 2) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
+  *f = ((lane & 3) == 0 && fld < 10) ? fld : -1;
+  return r4;
 }
 
 __device__ __forceinline__ int wave_max_int(int v) {
@@ -317,8 +280,19 @@ struct BwdArgs {
   int* queue;
   const int* order;
   int blocks;
+  // deterministic backward (both NULL otherwise): per (list position,
+  // quadrant of the tile) sums [K, 16, 10 or 6] and per list position the
+  // 16-bit mask of the quadrants that stored one (zero before the launch)
+  float* part;
+  uint32_t* mask;
 };
 void launch_render_bwd(const Raster& R, const BwdArgs& a, hipStream_t s);
+// Deterministic backward: list positions of each record's tiles (before the
+// compositing pass), and the fixed-order sums into g2d (after it).
+void launch_det_rev(const Raster& R, const int2* ranges, const uint32_t* ids, const int4* rect, const uint32_t* goff,
+                    uint32_t* rev, int n_items, hipStream_t s);
+void launch_det_reduce(const int4* rect, const uint32_t* goff, const uint32_t* rev, const uint32_t* mask,
+                       const float* part, int64_t n_rec, bool geom_only, float* g2d, hipStream_t s);
 
 // Adam applied by the projection backward to each Gaussian's gradient as soon
 // as it is complete (groups: means, scales, quats, opacities, colors); p[i]

@@ -36,7 +36,7 @@ class Camera(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("lowpass", ctypes.c_float), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_min", ctypes.c_float), ("guard", ctypes.c_float), ("tile_w", ctypes.c_int32),
-                ("tile_h", ctypes.c_int32)]
+                ("tile_h", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 class Gaussians(ctypes.Structure):
@@ -90,6 +90,8 @@ _SIGS = {
                                            ctypes.c_float, ctypes.c_float, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_seed_query": (ctypes.c_int, [P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P]),
     "gsr_compact": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_int64)]),
+    "gsr_submap_offload": (ctypes.c_int, [P, ctypes.c_int64, P, P]),
+    "gsr_submap_restore": (ctypes.c_int, [P, ctypes.c_int64, P, P]),
     "gsr_submap_trigger": (ctypes.c_int, [P, P, ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_int32)]),
     "gsr_prune": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_float, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_loss_ssim": (ctypes.c_int, [P, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P, P]),
@@ -175,9 +177,11 @@ class RasterOpts:
     guard: float = 1.3
     tile_w: int = 16
     tile_h: int = 16
+    deterministic: int = 0  # 1: bitwise reproducible backward (fixed-order sums, more memory, slower)
 
     def c(self) -> Opts:
-        return Opts(self.lowpass, self.alpha_min, self.alpha_max, self.T_min, self.guard, self.tile_w, self.tile_h)
+        return Opts(self.lowpass, self.alpha_min, self.alpha_max, self.T_min, self.guard, self.tile_w, self.tile_h,
+                    int(self.deterministic))
 
 
 def make_camera(width, height, fx, fy, cx, cy, near_z=0.2, bg=(0.0, 0.0, 0.0)) -> Camera:
@@ -315,15 +319,17 @@ def autotune_batch(means, scales, quats, opacities, colors, poses7, camera: Came
                                          _ptr(poses7), _ptr(_f32(dL_dcolor, "dL_dcolor")),
                                          _ptr(_f32(dL_ddepth, "dL_ddepth")), int(reps), ctypes.byref(bpc),
                                          table.ctypes.data_as(P)))
-    best = RasterOpts(opts.lowpass, opts.alpha_min, opts.alpha_max, opts.T_min, opts.guard, oc.tile_w, oc.tile_h)
+    best = RasterOpts(opts.lowpass, opts.alpha_min, opts.alpha_max, opts.T_min, opts.guard, oc.tile_w, oc.tile_h,
+                      opts.deterministic)
     shapes = [(16, 16), (8, 32), (32, 8)]
     bpcs = [0, 1, 2, 4, 8]
     timings = {(shapes[i // 5][0], shapes[i // 5][1], bpcs[i % 5]): float(table[i]) for i in range(15)}
     return best, int(bpc.value), timings
 
 
-def render_bwd(state: State, dL_dcolor, dL_ddepth, dL_dalpha=None, want_params=True, want_pose=True):
-    """Backward; returns dict of gradients (means, scales, quats, opacities, colors, pose7, twist6)."""
+def render_bwd(state: State, dL_dcolor, dL_ddepth, dL_dalpha=None, want_params=True, want_pose=True, groups=None):
+    """Backward; returns dict of gradients (means, scales, quats, opacities, colors, pose7, twist6).
+    groups: the parameter groups wanted (default: all five when want_params)."""
     ctx = state.ctx
     ctx.sync_stream()
     means, scales, quats, opacities, colors, pose7 = state.keep
@@ -334,10 +340,12 @@ def render_bwd(state: State, dL_dcolor, dL_ddepth, dL_dalpha=None, want_params=T
     gA = None if dL_dalpha is None else _f32(dL_dalpha.contiguous(), "dL_dalpha")
     out = {}
     if want_params:
+        wanted = PARAM_GROUPS if groups is None else tuple(groups)
         for k, shape in (("means", (n, 3)), ("scales", (n, 3)), ("quats", (n, 4)), ("opacities", (n,)),
                          ("colors", (n, 3))):
-            out[k] = torch.empty(shape, device=dev, dtype=torch.float32)
-        gr = Grads(*[_ptr(out[k]) for k in ("means", "scales", "quats", "opacities", "colors")])
+            if k in wanted:
+                out[k] = torch.empty(shape, device=dev, dtype=torch.float32)
+        gr = Grads(*[_ptr(out.get(k)) for k in ("means", "scales", "quats", "opacities", "colors")])
     else:
         gr = Grads()
     if want_pose:
@@ -484,6 +492,37 @@ def merge_submap(global_params: dict, sub_params: dict, rho: float = 0.01, ctx: 
     _, keep = seed_query(global_params["means"], sub_params["means"], rho, rho, ctx=ctx)
     _, kept, _, _ = compact(sub_params, keep, ctx=ctx)
     return {k: torch.cat([global_params[k], kept[k]]) for k in PARAM_GROUPS}
+
+
+def offload_submap(params: dict, ctx: Context | None = None):
+    """Copies a finished sub-map's parameters (PARAM_GROUPS, device) into one
+    pinned host tensor of 14 n floats [means | scales | quats | opacities |
+    colors] (gsr_submap_offload); the copy is enqueued on the current stream
+    and complete once that stream is synchronised."""
+    ctx = ctx or Context.get(params["means"].device.index or 0)
+    ctx.sync_stream()
+    n = params["opacities"].shape[0]
+    for k, w in zip(PARAM_GROUPS, (3, 3, 4, 1, 3)):
+        _f32(params[k], k, (n, w) if w > 1 else (n,))
+    host = torch.empty(14 * n, dtype=torch.float32, pin_memory=True)
+    arr = (P * 5)(*[params[k].data_ptr() for k in PARAM_GROUPS])
+    ctx.check(ctx.lib.gsr_submap_offload(ctx.h, n, arr, ctypes.c_void_p(host.data_ptr())))
+    return host
+
+
+def restore_submap(host, n: int, device=None, ctx: Context | None = None) -> dict:
+    """The inverse of offload_submap: new device tensors keyed by PARAM_GROUPS
+    (gsr_submap_restore), enqueued on the current stream."""
+    device = torch.device(device if device is not None else "cuda")
+    ctx = ctx or Context.get(device.index or 0)
+    ctx.sync_stream()
+    if host.dtype != torch.float32 or host.is_cuda or not host.is_contiguous() or host.numel() != 14 * n:
+        raise ValueError("host must be a contiguous float32 CPU tensor of 14 n values")
+    out = {k: torch.empty((n, w) if w > 1 else (n,), device=device, dtype=torch.float32)
+           for k, w in zip(PARAM_GROUPS, (3, 3, 4, 1, 3))}
+    arr = (P * 5)(*[out[k].data_ptr() for k in PARAM_GROUPS])
+    ctx.check(ctx.lib.gsr_submap_restore(ctx.h, n, ctypes.c_void_p(host.data_ptr()), arr))
+    return out
 
 
 def submap_trigger(pose_first7, pose_cur7, d_thre: float = 0.5, theta_thre_deg: float = 50.0) -> bool:

@@ -64,53 +64,78 @@ def test_loss_reg_matches_oracle_and_accumulates(n):
     assert abs(loss.item() - lam * L_ref) <= 1e-5 * lam * L_ref + 1e-7
 
 
-def test_fused_regulariser_matches_separate_calls():
-    """gsr_render_bwd_adam with scale_reg equals gsr_render_bwd, then
-    gsr_loss_reg into the scale gradient, then gsr_adam_groups, up to the order
-    of the compositing backward's float atomics. As in the test without the
-    regulariser, the moments start non-zero, so that this order (which moves a
-    cancelling gradient element by more than 1e-4 of itself) reaches them only
-    through rounding."""
+def run_fused_and_separate(m0: dict, v0: dict, opts=None, step: int = 3):
+    """One mapping step on C1 (seed 0), as gsr_render_bwd_adam with scale_reg,
+    and as gsr_render_bwd, gsr_loss_reg into the scale gradient, then
+    gsr_adam_groups; returns both outcomes {group: (params, m, v)}."""
     torch = torch_()
     g, _, pose, cam = G.c1_case(0)
     camera = gsr.make_camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.near_z, cam.bg)
     keys = gsr.PARAM_GROUPS
     lrs = {"means": 1e-3, "scales": 5e-4, "quats": 2e-3, "opacities": 1e-2, "colors": 5e-3}
     lam = 1.0
-    rng = np.random.default_rng(3)
-    m0 = {k: rng.normal(scale=1e-3, size=np.asarray(g[k]).shape).astype(np.float32) for k in keys}
-    v0 = {k: rng.uniform(1e-8, 1e-6, size=np.asarray(g[k]).shape).astype(np.float32) for k in keys}
     runs = []
     for fused in (False, True):
         d = {k: v.clone() for k, v in G.to_dev(g).items()}
         m = {k: torch.from_numpy(m0[k]).cuda() for k in keys}
         v = {k: torch.from_numpy(v0[k]).cuda() for k in keys}
         pd = torch.from_numpy(np.asarray(pose, np.float32)).cuda()
-        c, dep, _, st = gsr.render_fwd(d["means"], d["scales"], d["quats"], d["opacities"], d["colors"], pd, camera)
+        c, dep, _, st = gsr.render_fwd(d["means"], d["scales"], d["quats"], d["opacities"], d["colors"], pd, camera,
+                                       opts)
         gC = torch.full_like(c, 1e-3) * torch.sign(c - 0.3)
         gD = torch.full_like(dep, 1e-3) * torch.sign(dep - 1.0)
         if fused:
-            gsr.render_bwd_adam(st, gC, gD, m, v, lrs, 3, scale_reg=lam)
+            gsr.render_bwd_adam(st, gC, gD, m, v, lrs, step, scale_reg=lam)
         else:
             gr = gsr.render_bwd(st, gC, gD, None, want_params=True, want_pose=False)
             loss = torch.zeros(1, device="cuda")
             gsr.loss_reg(d["scales"], lam, loss, gr["scales"])
             gsr.adam_groups([d[k] for k in keys], [m[k] for k in keys], [v[k] for k in keys],
-                            [gr[k] for k in keys], [lrs[k] for k in keys], 3)
+                            [gr[k] for k in keys], [lrs[k] for k in keys], step)
         torch.cuda.synchronize()
         st.release()
         runs.append({k: (d[k].cpu().numpy(), m[k].cpu().numpy(), v[k].cpu().numpy()) for k in keys})
-    sep, fus = runs
+    return g, runs
+
+
+def test_fused_regulariser_matches_separate_calls_bitwise_when_deterministic():
+    """With the deterministic backward both paths see the same gradient bits,
+    and the fused step adds the regulariser and applies Adam with the same
+    operations as the separate calls: the results agree bit for bit, from
+    zero moments (the first Adam step, where a gradient's sign alone decides
+    the update)."""
+    keys = gsr.PARAM_GROUPS
+    g0, _, _, _ = G.c1_case(0)
+    m0 = {k: np.zeros(np.asarray(g0[k]).shape, np.float32) for k in keys}
+    v0 = {k: np.zeros(np.asarray(g0[k]).shape, np.float32) for k in keys}
+    g, (sep, fus) = run_fused_and_separate(m0, v0, gsr.RasterOpts(deterministic=1), step=1)
+    for k in keys:
+        for i in range(3):
+            np.testing.assert_array_equal(fus[k][i], sep[k][i], err_msg=f"{k}[{i}]")
+    # the regulariser reached every Gaussian, visible or not: the scales' first
+    # moment is (1 - b1) times a gradient that holds w (sign(r) - mean sign(r))
+    # wherever that is non-zero
+    _, g_reg = oracle.loss_reg(np.asarray(g["scales"], np.float32))
+    far = np.abs(g_reg) > 0
+    assert (np.abs(fus["scales"][1][far]) > 0).all()
+
+
+def test_fused_regulariser_matches_separate_calls():
+    """The same comparison with the default backward, whose float atomics add
+    in a run-dependent order. From zero moments the first step moves a
+    parameter by about lr sign(g), so an element whose gradient cancels to
+    ~0 can move either way; the moments therefore start non-zero here, and the
+    bitwise comparison of the step is the deterministic test above."""
+    keys = gsr.PARAM_GROUPS
+    g0, _, _, _ = G.c1_case(0)
+    rng = np.random.default_rng(3)
+    m0 = {k: rng.normal(scale=1e-3, size=np.asarray(g0[k]).shape).astype(np.float32) for k in keys}
+    v0 = {k: rng.uniform(1e-8, 1e-6, size=np.asarray(g0[k]).shape).astype(np.float32) for k in keys}
+    g, (sep, fus) = run_fused_and_separate(m0, v0)
     for k in keys:
         np.testing.assert_allclose(fus[k][0], sep[k][0], rtol=1e-6, atol=1e-7, err_msg=k)
         np.testing.assert_allclose(fus[k][1], sep[k][1], rtol=1e-4, atol=1e-12, err_msg=k)
         np.testing.assert_allclose(fus[k][2], sep[k][2], rtol=1e-4, atol=1e-15, err_msg=k)
-    # the regulariser reached every Gaussian, visible or not: the scales' first moment moved from
-    # b1 m0 by (1 - b1) times a gradient that holds w (sign(r) - mean sign(r)) wherever that is non-zero
-    _, g_reg = oracle.loss_reg(np.asarray(g["scales"], np.float32))
-    moved = fus["scales"][1] - np.float32(0.9) * m0["scales"]
-    far = np.abs(g_reg) > 0
-    assert (np.abs(moved[far]) > 0).all()
 
 
 def test_loss_reg_bad_arguments():
