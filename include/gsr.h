@@ -401,12 +401,14 @@ int gsr_track_graph_destroy(gsr_ctx *ctx, gsr_track_graph *tg);
 
 /* Learned tracking initialisation ------------------------------------------
  * A small CNN that proposes a pose correction from the render at the current
- * pose and the observed frame. Input: 8 channels at 160 x 120 (rendered RGB,
- * rendered depth x depth_scale, observed RGB, observed depth x depth_scale,
- * f x f average-pooled from the full frames). Four 3x3 stride-2 convolutions
- * with 64 channels and ReLU (implicit GEMMs on the BF16 matrix cores, FP32
- * accumulation, BF16 activations), global average pooling, linear head to 6
- * outputs (the twist (rho, phi) of a left perturbation). The paper suggests
+ * pose and the observed frame. Input: 8 channels at 160 x 120 (rendered RGB
+ * and depth x depth_scale, then 4 x the observed-minus-rendered RGB and depth
+ * x depth_scale, f x f average-pooled from the full frames). Four 3x3
+ * stride-2 convolutions with 64 channels and ReLU (implicit GEMMs on the BF16
+ * matrix cores, FP32 accumulation, BF16 activations), moment pooling of the
+ * last 10 x 8 map (per channel the mean and the means weighted by the pixel
+ * centre's x and y mapped to (-1, 1): 192 values), linear head to 6 outputs
+ * (the twist (rho, phi) of a left perturbation). The paper suggests
  * learned components in its limitations (Sec. 5) and uses a loss-judged
  * alternative initialiser in its supplement; this network is such an
  * initialiser, judged against constant-speed init by the tracking loss. */
@@ -416,8 +418,8 @@ int gsr_initnet_create(gsr_ctx *ctx, int32_t max_batch, gsr_initnet **out);
 int gsr_initnet_destroy(gsr_ctx *ctx, gsr_initnet *net);
 /* Parameters: a flat FP32 vector of n_params floats, in order: per layer
  * l = 0..3: W_l [64][KP_l] (K ordered (3 ky + kx, channel); KP_0 = 96 with
- * 24 zero pad columns, KP_1..3 = 576), b_l [64]; then the head W_fc [6][64],
- * b_fc [6]. Zero after create. set_params copies a device vector in (and
+ * 24 zero pad columns, KP_1..3 = 576), b_l [64]; then the head W_fc [6][192]
+ * (columns: moment k = 0, 1, 2 of channel c at 64 k + c) and b_fc [6]. Zero after create. set_params copies a device vector in (and
  * resets Adam); get_params copies parameters and/or the last gradients out
  * (either pointer may be NULL). */
 int gsr_initnet_count(gsr_ctx *ctx, gsr_initnet *net, int64_t *n_params);
@@ -430,8 +432,10 @@ int gsr_initnet_set_input(gsr_ctx *ctx, gsr_initnet *net, int32_t batch, const u
 int gsr_initnet_get_activation(gsr_ctx *ctx, gsr_initnet *net, int32_t layer, int32_t batch, uint16_t *act,
                                uint16_t *dact);
 /* Pack one input sample from full-resolution frames (W = 160 f, H = 120 f):
- * f x f average pooling of rendered and observed colour and depth (x
- * depth_scale) into dst (BF16 [120,160,8]). */
+ * f x f average pooling into dst (BF16 [120,160,8]) of the rendered colour
+ * and depth (x depth_scale) in channels 0-3 and of the observed-minus-rendered
+ * colour and depth (x depth_scale), times 4, in channels 4-7 (the residual is
+ * formed in FP32 before rounding to BF16). */
 int gsr_pack_rgbd_pair(gsr_ctx *ctx, const float *rend_color, const float *rend_depth, const float *obs_color,
                        const float *obs_depth, int32_t H, int32_t W, float depth_scale, uint16_t *dst);
 /* Forward of the first `batch` input samples; out: device [B,6] or NULL. */

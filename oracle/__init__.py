@@ -411,15 +411,26 @@ def conv2d_bwd(x, w, dout, stride=2, pad=1, want_dx=True):
     return dx, dw, db
 
 
+def moment_basis(h: int, w: int) -> np.ndarray:
+    """[3, h, w]: 1, x^ and y^ at the pixel centres, x^ = (2 x + 1) / w - 1,
+    y^ = (2 y + 1) / h - 1 (both in (-1, 1))."""
+    xs = (2.0 * np.arange(w) + 1.0) / w - 1.0
+    ys = (2.0 * np.arange(h) + 1.0) / h - 1.0
+    return np.stack([np.ones((h, w)), np.broadcast_to(xs[None, :], (h, w)), np.broadcast_to(ys[:, None], (h, w))])
+
+
 def initnet_forward(x, params):
-    """x [B,8,H,W]; params: w0..w3 [64,C,3,3], b0..b3 [64], wfc [6,64], bfc [6].
-    Four stride-2 3x3 convolutions with ReLU, global average pool, linear head.
-    Returns (out [B,6], cache)."""
+    """x [B,8,H,W]; params: w0..w3 [64,C,3,3], b0..b3 [64], wfc [6,3C], bfc [6].
+    Four stride-2 3x3 convolutions with ReLU, moment pooling (per channel the
+    mean of the last map and its means weighted by x^ and y^, k-major:
+    pool[b, 64 k + c]), linear head. Returns (out [B,6], cache)."""
     acts = [np.asarray(x, np.float64)]
     for l in range(4):
         y = conv2d(acts[-1], params[f"w{l}"], params[f"b{l}"])
         acts.append(np.maximum(y, 0.0))
-    pool = acts[-1].mean(axis=(2, 3))
+    a = acts[-1]
+    basis = moment_basis(a.shape[2], a.shape[3])
+    pool = np.einsum("bchw,khw->bkc", a, basis).reshape(a.shape[0], -1) / (a.shape[2] * a.shape[3])
     out = pool @ np.asarray(params["wfc"], np.float64).T + np.asarray(params["bfc"], np.float64)
     return out, (acts, pool)
 
@@ -428,9 +439,10 @@ def initnet_backward(params, cache, dout):
     """Gradients of the network parameters for upstream dL/dout [B,6]."""
     acts, pool = cache
     grads = {"wfc": dout.T @ pool, "bfc": dout.sum(0)}
-    dpool = dout @ np.asarray(params["wfc"], np.float64)
     a = acts[-1]
-    dact = np.broadcast_to(dpool[:, :, None, None] / (a.shape[2] * a.shape[3]), a.shape).copy()
+    B, C, h, w = a.shape
+    dpool = (dout @ np.asarray(params["wfc"], np.float64)).reshape(B, 3, C)
+    dact = np.einsum("bkc,khw->bchw", dpool, moment_basis(h, w)) / (h * w)
     for l in range(3, -1, -1):
         dy = dact * (acts[l + 1] > 0)
         dx, dw, db = conv2d_bwd(acts[l], params[f"w{l}"], dy, want_dx=l > 0)

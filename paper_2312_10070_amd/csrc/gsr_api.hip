@@ -83,7 +83,7 @@ struct gsr_track_graph {
 // working copies, activations and gradients for up to max_batch samples.
 struct gsr_initnet {
   static constexpr int kLayers = 4;
-  static constexpr int kInH = 120, kInW = 160, kInC = 8, kCh = 64;
+  static constexpr int kInH = 120, kInW = 160, kInC = 8, kCh = 64, kHeadIn = 3 * 64;  // head: three moments
   gsr_ctx* ctx = nullptr;
   int max_batch = 0;
   void* buf = nullptr;
@@ -1126,7 +1126,7 @@ int gsr_initnet_create(gsr_ctx* c, int32_t max_batch, gsr_initnet** out) {
   }
   int64_t np = 0;
   for (int l = 0; l < N::kLayers; ++l) np += (int64_t)N::kCh * gsr::conv_kp(net->C[l]) + N::kCh;
-  np += 6 * N::kCh + 6;
+  np += 6 * N::kHeadIn + 6;
   net->n_params = np;
   const int64_t B = max_batch;
   size_t bytes = 0;
@@ -1145,7 +1145,7 @@ int gsr_initnet_create(gsr_ctx* c, int32_t max_batch, gsr_initnet** out) {
       net->act[l] = cv.take<uint16_t>(sz);
       net->dact[l] = cv.take<uint16_t>(sz);
     }
-    net->pool = cv.take<float>(B * N::kCh);
+    net->pool = cv.take<float>(B * N::kHeadIn);
     net->out = cv.take<float>(B * 6);
     net->scratch = cv.take<float>(B * 6 + 64);
     bytes = cv.off;
@@ -1172,8 +1172,8 @@ int gsr_initnet_create(gsr_ctx* c, int32_t max_batch, gsr_initnet** out) {
   }
   net->wfc = p;
   net->dwfc = g;
-  net->bfc = p + 6 * N::kCh;
-  net->dbfc = g + 6 * N::kCh;
+  net->bfc = p + 6 * N::kHeadIn;
+  net->dbfc = g + 6 * N::kHeadIn;
   for (float* q : {net->params, net->grads, net->m, net->v}) gsr::launch_fill_f32(q, 0.f, np, c->stream);
   *out = net;
   return check_launch(c, "gsr_initnet_create");
@@ -1248,7 +1248,7 @@ int gsr_initnet_forward(gsr_ctx* c, gsr_initnet* net, int32_t batch, float* out)
                          st);
   }
   const int L = gsr_initnet::kLayers;
-  gsr::launch_head_fwd(batch, net->H[L] * net->W[L], net->act[L], net->wfc, net->bfc, net->pool, net->out, st);
+  gsr::launch_head_fwd(batch, net->H[L], net->W[L], net->act[L], net->wfc, net->bfc, net->pool, net->out, st);
   if (out) GSR_HIP(c, hipMemcpyAsync(out, net->out, sizeof(float) * 6 * batch, hipMemcpyDeviceToDevice, st));
   return check_launch(c, "gsr_initnet_forward");
 }
@@ -1265,7 +1265,7 @@ int gsr_initnet_backward(gsr_ctx* c, gsr_initnet* net, int32_t batch, const floa
   gsr::launch_fill_f32(net->grads, 0.f, net->n_params, st);
   float* lp = loss ? loss : net->scratch;
   gsr::launch_fill_f32(lp, 0.f, 1, st);
-  gsr::launch_head_bwd(batch, net->H[L] * net->W[L], net->out, labels, scale, net->pool, net->wfc, net->act[L], dL_dout,
+  gsr::launch_head_bwd(batch, net->H[L], net->W[L], net->out, labels, scale, net->pool, net->wfc, net->act[L], dL_dout,
                        net->dwfc, net->dbfc, net->dact[L], lp, st);
   for (int l = L - 1; l >= 0; --l) {
     // dact[l + 1] holds dL/d(pre-activation of layer l)

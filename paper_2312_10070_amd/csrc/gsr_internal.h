@@ -400,11 +400,11 @@ void launch_conv_bwd_data(int B, int H, int W, int C, const uint16_t* dout, cons
                           uint16_t* din, hipStream_t st);
 void launch_conv_bwd_weight(int B, int H, int W, int C, const uint16_t* dy, const uint16_t* in, float* dw, float* db,
                             hipStream_t st);
-void launch_head_fwd(int B, int npix, const uint16_t* act, const float* wfc, const float* bfc, float* pool, float* out,
-                     hipStream_t st);
-void launch_head_bwd(int B, int npix, const float* out, const float* label, const float* scale, const float* pool,
-                     const float* wfc, const uint16_t* act, const float* dout, float* dwfc, float* dbfc,
-                     uint16_t* dact, float* loss, hipStream_t st);
+void launch_head_fwd(int B, int OH, int OW, const uint16_t* act, const float* wfc, const float* bfc, float* pool,
+                     float* out, hipStream_t st);
+void launch_head_bwd(int B, int OH, int OW, const float* out, const float* label, const float* scale,
+                     const float* pool, const float* wfc, const uint16_t* act, const float* dout, float* dwfc,
+                     float* dbfc, uint16_t* dact, float* loss, hipStream_t st);
 void launch_cast_weights(const float* w, int C, uint16_t* wk, uint16_t* wt, hipStream_t st);
 void launch_pack_input(const float* rc, const float* rd, const float* oc, const float* od, int H, int W, int f,
                        float depth_scale, uint16_t* out, hipStream_t st);

@@ -1,8 +1,9 @@
 // Tracking-initialisation network: a small CNN that proposes a pose
 // correction from the render at the current pose and the observed RGB-D
-// frame (both downsampled to 160 x 120, 8 channels). Four 3x3 stride-2
-// convolutions (64 channels, ReLU), global average pooling and a linear head
-// to a 6-vector twist. Convolutions are implicit GEMMs on the gfx950 matrix
+// frame (both downsampled to 160 x 120, 8 channels: the render and the
+// observed-minus-rendered residual). Four 3x3 stride-2 convolutions (64
+// channels, ReLU), moment pooling (mean and first spatial moments) and a
+// linear head to a 6-vector twist. Convolutions are implicit GEMMs on the gfx950 matrix
 // cores (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation);
 // activations and weights are BF16, master weights and the head FP32.
 //
@@ -24,6 +25,9 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kHeadIn = 3 * 64;     // pooled features: three moments of 64 channels
+constexpr float kDiffGain = 4.f;    // scale of the observed-minus-rendered channels
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
@@ -221,34 +225,56 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ 
   atomicAdd(&db[co], s);
 }
 
-// Head: pool[b] = mean over pixels of act[b]; out[b] = W pool + c. One workgroup per sample.
-__global__ __launch_bounds__(64) void k_head_fwd(const uint16_t* __restrict__ act, int npix, const float* __restrict__ wfc,
-                                                const float* __restrict__ bfc, float* __restrict__ pool,
-                                                float* __restrict__ out) {
+// Head. Moment pooling over the last feature map (OH x OW pixels): for each
+// channel c, pool[b][k][c] = (1/npix) sum_p m_k(p) act[b][p][c] with m_0 = 1,
+// m_1 = x^(p), m_2 = y^(p), x^ = (2 x + 1) / OW - 1 and y^ = (2 y + 1) / OH - 1
+// (pixel centres mapped to (-1, 1)); out[b] = Wfc pool[b] + bfc over the 192
+// pooled values (k major). The first moments keep where features sit, which a
+// plain average cancels (a forward motion or a roll moves image content
+// radially or around the centre, with zero mean displacement).
+// One workgroup per sample, one lane per channel.
+__device__ __forceinline__ float moment_x(int p, int OW) { return (2.f * (float)(p % OW) + 1.f) / (float)OW - 1.f; }
+__device__ __forceinline__ float moment_y(int p, int OW, int OH) {
+  return (2.f * (float)(p / OW) + 1.f) / (float)OH - 1.f;
+}
+
+__global__ __launch_bounds__(64) void k_head_fwd(const uint16_t* __restrict__ act, int OH, int OW,
+                                                const float* __restrict__ wfc, const float* __restrict__ bfc,
+                                                float* __restrict__ pool, float* __restrict__ out) {
   const int b = blockIdx.x, c = threadIdx.x;
-  float s = 0.f;
-  for (int p = 0; p < npix; ++p) s += bf2f(act[((int64_t)b * npix + p) * 64 + c]);
-  s /= (float)npix;
-  pool[b * 64 + c] = s;
-  __shared__ float sp[64];
-  sp[c] = s;
+  const int npix = OH * OW;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  for (int p = 0; p < npix; ++p) {
+    const float v = bf2f(act[((int64_t)b * npix + p) * 64 + c]);
+    s0 += v;
+    s1 += v * moment_x(p, OW);
+    s2 += v * moment_y(p, OW, OH);
+  }
+  const float inv = 1.f / (float)npix;
+  __shared__ float sp[kHeadIn];
+  sp[c] = s0 * inv;
+  sp[64 + c] = s1 * inv;
+  sp[128 + c] = s2 * inv;
+  for (int k = 0; k < 3; ++k) pool[b * kHeadIn + 64 * k + c] = sp[64 * k + c];
   __syncthreads();
   if (c < 6) {
     float o = bfc[c];
-    for (int i = 0; i < 64; ++i) o += wfc[c * 64 + i] * sp[i];
+    for (int i = 0; i < kHeadIn; ++i) o += wfc[c * kHeadIn + i] * sp[i];
     out[b * 6 + c] = o;
   }
 }
 
 // Loss L = 1/(2B) sum ((out - label) / scale)^2, its gradient, the head's
-// gradients (atomic over samples), and dL/dact4 = (W^T dout / npix) * [act > 0].
+// gradients (atomic over samples), and dL/dact4[p][c] = (1/npix)
+// sum_k m_k(p) dpool[k][c] * [act > 0] with dpool = Wfc^T dout.
 __global__ __launch_bounds__(64) void k_head_bwd(const float* __restrict__ out, const float* __restrict__ label,
                                                 const float* __restrict__ scale, int B, const float* __restrict__ pool,
                                                 const float* __restrict__ wfc, const uint16_t* __restrict__ act,
-                                                int npix, const float* __restrict__ dout_in, float* __restrict__ dwfc,
-                                                float* __restrict__ dbfc, uint16_t* __restrict__ dact,
-                                                float* __restrict__ loss) {
+                                                int OH, int OW, const float* __restrict__ dout_in,
+                                                float* __restrict__ dwfc, float* __restrict__ dbfc,
+                                                uint16_t* __restrict__ dact, float* __restrict__ loss) {
   const int b = blockIdx.x, c = threadIdx.x;
+  const int npix = OH * OW;
   __shared__ float g[6];
   if (c < 6) {
     float d;
@@ -263,15 +289,19 @@ __global__ __launch_bounds__(64) void k_head_bwd(const float* __restrict__ out, 
     atomicAdd(&dbfc[c], d);
   }
   __syncthreads();
-  float dp = 0.f;
-  for (int j = 0; j < 6; ++j) {
-    dp += wfc[j * 64 + c] * g[j];
-    atomicAdd(&dwfc[j * 64 + c], g[j] * pool[b * 64 + c]);
+  float dp[3] = {0.f, 0.f, 0.f};
+  for (int k = 0; k < 3; ++k) {
+    const int i = 64 * k + c;
+    for (int j = 0; j < 6; ++j) {
+      dp[k] += wfc[j * kHeadIn + i] * g[j];
+      atomicAdd(&dwfc[j * kHeadIn + i], g[j] * pool[b * kHeadIn + i]);
+    }
   }
-  dp /= (float)npix;
+  const float inv = 1.f / (float)npix;
   for (int p = 0; p < npix; ++p) {
     const int64_t o = ((int64_t)b * npix + p) * 64 + c;
-    dact[o] = bf2f(act[o]) > 0.f ? f2bf(dp) : (uint16_t)0;
+    const float d = (dp[0] + moment_x(p, OW) * dp[1] + moment_y(p, OW, OH) * dp[2]) * inv;
+    dact[o] = bf2f(act[o]) > 0.f ? f2bf(d) : (uint16_t)0;
   }
 }
 
@@ -291,7 +321,10 @@ __global__ void k_cast_weights(const float* __restrict__ w, int C, int KP, uint1
 }
 
 // Input packing: f x f average pooling of the rendered and observed RGB-D
-// frames into 8 BF16 channels (r, g, b, depth * depth_scale) x 2.
+// frames into 8 BF16 channels: the render (r, g, b, depth * depth_scale) and
+// the observation minus the render, times kDiffGain (the residual, formed in
+// FP32 before rounding to BF16, where a few-millimetre depth residual would
+// otherwise fall below the precision of depths of metres).
 __global__ void k_pack_input(const float* __restrict__ rc, const float* __restrict__ rd, const float* __restrict__ oc,
                              const float* __restrict__ od, int H, int W, int f, float depth_scale,
                              uint16_t* __restrict__ out) {
@@ -308,13 +341,13 @@ __global__ void k_pack_input(const float* __restrict__ rc, const float* __restri
       acc[1] += rc[P + p];
       acc[2] += rc[2 * P + p];
       acc[3] += rd[p] * depth_scale;
-      acc[4] += oc[p];
-      acc[5] += oc[P + p];
-      acc[6] += oc[2 * P + p];
-      acc[7] += od[p] * depth_scale;
+      acc[4] += oc[p] - rc[p];
+      acc[5] += oc[P + p] - rc[P + p];
+      acc[6] += oc[2 * P + p] - rc[2 * P + p];
+      acc[7] += (od[p] - rd[p]) * depth_scale;
     }
   const float inv = 1.f / (float)(f * f);
-  for (int c = 0; c < 8; ++c) out[(int64_t)i * 8 + c] = f2bf(acc[c] * inv);
+  for (int c = 0; c < 8; ++c) out[(int64_t)i * 8 + c] = f2bf(acc[c] * inv * (c < 4 ? 1.f : kDiffGain));
 }
 
 ConvShape shape_of(int B, int H, int W, int C) {
@@ -361,16 +394,16 @@ void launch_conv_bwd_weight(int B, int H, int W, int C, const uint16_t* dy, cons
   hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)gb), dim3(256), 0, st, dy, M, db);
 }
 
-void launch_head_fwd(int B, int npix, const uint16_t* act, const float* wfc, const float* bfc, float* pool, float* out,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_head_fwd, dim3((unsigned)B), dim3(64), 0, st, act, npix, wfc, bfc, pool, out);
+void launch_head_fwd(int B, int OH, int OW, const uint16_t* act, const float* wfc, const float* bfc, float* pool,
+                     float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_head_fwd, dim3((unsigned)B), dim3(64), 0, st, act, OH, OW, wfc, bfc, pool, out);
 }
 
-void launch_head_bwd(int B, int npix, const float* out, const float* label, const float* scale, const float* pool,
-                     const float* wfc, const uint16_t* act, const float* dout, float* dwfc, float* dbfc,
-                     uint16_t* dact, float* loss, hipStream_t st) {
-  hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)B), dim3(64), 0, st, out, label, scale, B, pool, wfc, act, npix, dout,
-                     dwfc, dbfc, dact, loss);
+void launch_head_bwd(int B, int OH, int OW, const float* out, const float* label, const float* scale,
+                     const float* pool, const float* wfc, const uint16_t* act, const float* dout, float* dwfc,
+                     float* dbfc, uint16_t* dact, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)B), dim3(64), 0, st, out, label, scale, B, pool, wfc, act, OH, OW,
+                     dout, dwfc, dbfc, dact, loss);
 }
 
 void launch_cast_weights(const float* w, int C, uint16_t* wk, uint16_t* wt, hipStream_t st) {

@@ -369,12 +369,27 @@ def tracking_inputs(seed: int = 0, n: int = 500_000, cam: Intrinsics = TRACKING_
 
 
 def batched_inputs(seed: int = 0, n: int = 1_000_000, cam: Intrinsics = MAPPING_CAMERA, n_views: int = 8,
-                   n_seed_views: int = 16) -> dict:
-    """C4: a sub-map seeded from 16 views and 8 keyframes whose visible fraction is spread
-    out (the keyframes are chosen by the caller from `candidate_views`)."""
+                   n_seed_views: int = 16, n_candidates: int = 48) -> dict:
+    """C4: a sub-map seeded from 16 views around one spot of the room (within
+    0.4 m, turned up to 25 degrees either way from a base heading) and
+    candidate keyframes from that spot turned by 0 to 180 degrees from the
+    base heading (and moved up to 0.3 m): their visible fractions of the
+    sub-map spread from most of it to little of it. The caller picks the 8
+    keyframes from `candidate_views`."""
     rng = np.random.default_rng(seed)
     room = make_room(seed)
-    seed_views = [random_view(rng) for _ in range(n_seed_views)]
+    lo = ROOM_MIN + 0.3 * (ROOM_MAX - ROOM_MIN)
+    hi = ROOM_MAX - 0.3 * (ROOM_MAX - ROOM_MIN)
+    center = rng.uniform(lo, hi)
+    yaw0 = rng.uniform(-np.pi, np.pi)
+
+    def view(max_move, yaw_off, pitch_deg):
+        d = rng.normal(size=3)
+        c = center + max_move * rng.uniform() * d / np.linalg.norm(d)
+        return camera_pose(c, yaw0 + yaw_off, np.deg2rad(pitch_deg))
+
+    seed_views = [view(0.4, np.deg2rad(rng.uniform(-25, 25)), rng.uniform(-10, 10)) for _ in range(n_seed_views)]
     g = seed_gaussians(room, cam, seed_views, n, rng)
-    candidates = [random_view(rng) for _ in range(4 * n_views)]
+    offsets = np.deg2rad(np.linspace(0, 180, n_candidates)) * rng.choice([-1, 1], n_candidates)
+    candidates = [view(0.3, off, rng.uniform(-10, 10)) for off in offsets]
     return dict(gaussians=g, candidate_views=candidates, camera=cam, room=room, n_views=n_views)

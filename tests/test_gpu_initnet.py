@@ -48,11 +48,17 @@ def setup_net(B=3, seed=0):
         if name.startswith("b"):
             flat[off:off + shape[0]] = rng.normal(0, 0.05, shape[0])
         if name == "wfc":
-            flat[off:off + 6 * 64] = rng.normal(0, 0.2, 6 * 64)
+            flat[off:off + 6 * initnet.HEAD_IN] = rng.normal(0, 0.2, 6 * initnet.HEAD_IN)
     net.set_params(torch.from_numpy(flat).cuda())
     x = torch.from_numpy(rng.uniform(0, 1, size=(B, 120, 160, 8)).astype(np.float32)).cuda().to(torch.bfloat16)
     net.set_input(x)
     return net, flat, x
+
+
+def moment_pool(a4):
+    """The head's pooled values from an NHWC last activation [B, 8, 10, 64]."""
+    basis = oracle.moment_basis(a4.shape[1], a4.shape[2])
+    return np.einsum("bhwc,khw->bkc", a4, basis).reshape(a4.shape[0], -1) / (a4.shape[1] * a4.shape[2])
 
 
 def test_layers_forward_match_oracle():
@@ -68,7 +74,7 @@ def test_layers_forward_match_oracle():
     for l in range(4):
         ref = np.maximum(oracle.conv2d(nhwc_to_nchw(acts[l]), Pb[f"w{l}"], P[f"b{l}"]), 0.0)
         close(f"layer{l}", nhwc_to_nchw(acts[l + 1]), ref)
-    pool = acts[4].mean(axis=(1, 2))
+    pool = moment_pool(acts[4])
     ref_out = pool @ P["wfc"].T + P["bfc"]
     np.testing.assert_allclose(out.cpu().numpy(), ref_out, rtol=1e-4, atol=1e-5)
 
@@ -92,14 +98,15 @@ def test_layers_backward_match_oracle():
         a, d = net.activation(l, B, SHAPES[l])
         acts.append(bf16_to_np(a)); dacts.append(bf16_to_np(d))
     # head and loss, from the GPU's own last activation
-    pool = acts[4].mean(axis=(1, 2))
+    pool = moment_pool(acts[4])
     out = pool @ P["wfc"].T + P["bfc"]
     L, dout = oracle.initnet_loss(out, labels.cpu().numpy(), np.array(initnet.LABEL_SCALE))
     assert abs(loss.item() - L) <= 1e-4 * L
     np.testing.assert_allclose(g["wfc"], dout.T @ pool, rtol=1e-4, atol=1e-7)
     np.testing.assert_allclose(g["bfc"], dout.sum(0), rtol=1e-4, atol=1e-7)
-    dpool = dout @ P["wfc"]
-    ref_d4 = np.broadcast_to(dpool[:, None, None, :] / 80.0, acts[4].shape) * (acts[4] > 0)
+    dpool = (dout @ P["wfc"]).reshape(B, 3, 64)
+    basis = oracle.moment_basis(8, 10)
+    ref_d4 = np.einsum("bkc,khw->bhwc", dpool, basis) / 80.0 * (acts[4] > 0)
     close("dact4", dacts[4], ref_d4)
     for l in range(3, -1, -1):
         dy = nhwc_to_nchw(dacts[l + 1])
@@ -119,35 +126,37 @@ def test_pack_input_matches_average_pooling():
     dev = lambda a: torch.from_numpy(a).cuda()
     gsr.pack_rgbd_pair(dev(rc), dev(rd), dev(oc), dev(od), dst, 0.25)
     pool = lambda a: a.reshape(a.shape[:-2] + (120, 2, 160, 2)).mean(axis=(-3, -1))
-    ref = np.concatenate([pool(rc), pool(rd)[None] * 0.25, pool(oc), pool(od)[None] * 0.25], 0).transpose(1, 2, 0)
+    f64 = lambda a: a.astype(np.float64)
+    ref = np.concatenate([pool(f64(rc)), pool(f64(rd))[None] * 0.25, 4 * pool(f64(oc) - f64(rc)),
+                          4 * 0.25 * pool(f64(od) - f64(rd))[None]], 0).transpose(1, 2, 0)
     np.testing.assert_allclose(bf16_to_np(dst), ref, rtol=8e-3, atol=1e-6)
-
-
-CAM = synth.Intrinsics(320, 240, 262.5, 262.5, 160.0, 120.0)
 
 
 @pytest.fixture(scope="module")
 def trained():
+    """The network trained as the benchmark trains it: 50,000 pairs rendered at
+    640 x 480 from procedural scenes built like tracking sub-maps, 15,000 Adam
+    steps of batch 64; 1,024 held-out pairs from other scenes."""
     torch = torch_()
-    x, y = initnet.generate_pairs(32768, seed=11, cam=CAM)
-    xv, yv = initnet.generate_pairs(512, seed=12, cam=CAM)
+    cam = synth.TRACKING_CAMERA
+    x, y = initnet.generate_pairs(50_000, seed=11, cam=cam)
+    xv, yv = initnet.generate_pairs(1024, seed=12, cam=cam)
     net = gsr.InitNet(max_batch=64)
     net.set_params(torch.from_numpy(initnet.init_params(0)).cuda())
-    losses = initnet.train(net, x, y, steps=8000, batch=64, lr=2e-3)
+    losses = initnet.train(net, x, y, steps=15_000, batch=64, lr=2e-3)
     del x, y
     return net, losses, xv, yv
 
 
 def test_training_reduces_loss(trained):
     net, losses, xv, yv = trained
-    assert losses[-100:].mean() < 0.5 * losses[:20].mean(), (losses[:20].mean(), losses[-100:].mean())
+    assert losses[-200:].mean() < 0.2 * losses[:20].mean(), (losses[:20].mean(), losses[-200:].mean())
 
 
 def test_proposals_reduce_held_out_pose_error(trained):
-    """On held-out rooms the predicted twist removes a clear part of the
-    perturbation: its mean squared (scaled) error is below 0.6 of the zero
-    predictor's. A global-average-pooled network cannot undo every
-    rotation/translation ambiguity, so the bar is a clear gain, not a fit."""
+    """On held-out scenes the predicted twist removes most of the perturbation:
+    its mean squared (scaled) error is below 0.45 of the zero predictor's, and
+    the rotation error left is under 0.6 degrees RMS per axis (from up to 3)."""
     torch = torch_()
     net, _, xv, yv = trained
     preds = torch.cat([initnet.predict(net, xv[i:i + 64]) for i in range(0, xv.shape[0], 64)]).cpu().numpy()
@@ -155,24 +164,27 @@ def test_proposals_reduce_held_out_pose_error(trained):
     s = np.array(initnet.LABEL_SCALE)
     mse_pred = np.mean(((preds - y) / s) ** 2)
     mse_zero = np.mean((y / s) ** 2)
-    print("held-out scaled MSE: network", mse_pred, "zero predictor", mse_zero)
-    assert mse_pred < 0.6 * mse_zero, (mse_pred, mse_zero)
+    rms = np.sqrt(np.mean((preds - y) ** 2, 0))
+    print("held-out scaled MSE: network", mse_pred, "zero predictor", mse_zero, "RMS per axis", rms)
+    assert mse_pred < 0.45 * mse_zero, (mse_pred, mse_zero)
+    assert (np.rad2deg(rms[3:]) < 0.6).all(), rms
 
 
 def test_learned_init_gain(trained):
-    """On frames perturbed by 5 cm / 3 degrees (the training range), tracking
-    from the network's proposal (kept only when Eq. 15 prefers it)
-    reaches the accuracy of 100 plain iterations (their final error + 5 %, at
-    least 0.5 mm) in fewer iterations, on average, than plain tracking does."""
+    """Tracking frames at 640 x 480 with 500K Gaussians whose initial pose is
+    off by 5 cm / 3 degrees: tracking from the network's proposal (up to three
+    loss-judged steps) brings the camera within 1 mm / 0.1 degree of the
+    ground truth on more frames than tracking from the initial pose does, and
+    on the frames both reach it needs no more iterations on average."""
     torch = torch_()
     net, _, _, _ = trained
-    budgets = (10, 15, 20, 30, 40, 50, 60, 80, 100)
-    n_plain, n_learned, used = [], [], 0
-    for frame in range(8):
-        inp = synth.tracking_inputs(100 + frame, 60_000, CAM, n_views=3, trans_m=0.05, rot_deg=3.0)
+    budgets = (10, 20, 30, 40, 60, 80, 100)
+    n_plain, n_learned, kept = [], [], []
+    for frame in range(6):
+        inp = synth.tracking_inputs(100 + frame, 500_000, trans_m=0.05, rot_deg=3.0)
         g = {k: torch.from_numpy(v).cuda() for k, v in inp["gaussians"].items()}
         args = (g["means"], g["scales"], g["quats"], g["opacities"], g["colors"])
-        cam = gsr.camera_from(CAM)
+        cam = gsr.camera_from(inp["camera"])
         gt = torch.from_numpy(inp["gt_pose7"]).cuda()
         oc, od, _, st = gsr.render_fwd(*args, gt, cam)
         st.release()
@@ -180,19 +192,25 @@ def test_learned_init_gain(trained):
         kcap = tracking.overlap_capacity(*args, init, cam)
         graphs = {n: gsr.TrackGraph(*args, cam, oc, od, n_iters=n, K_cap=kcap) for n in budgets}
 
-        def err_after(n, start):
+        def reached(n, start):
             q = start.clone()
             graphs[n].run(q)
-            return synth.pose_error(q.cpu().numpy(), inp["gt_pose7"])[0]
+            et, er = synth.pose_error(q.cpu().numpy(), inp["gt_pose7"])
+            return et <= 1e-3 and er <= 0.1
 
-        thr = max(1.05 * err_after(100, init), 5e-4)
-        first = lambda start: next((n for n in budgets if err_after(n, start) <= thr), 101)
+        first = lambda start: next((n for n in budgets if reached(n, start)), None)
         n_plain.append(first(init))
-        start, use, l0, l1 = initnet.propose(net, args, cam, oc, od, init)
-        used += use
+        start, k, l0, l1 = initnet.propose(net, args, cam, oc, od, init, max_steps=3)
+        kept.append(k)
+        assert l1 <= l0
         n_learned.append(first(start))
         for tg in graphs.values():
             tg.close()
-    print("iterations to the target error: plain", n_plain, "learned", n_learned, "proposals used:", used)
-    assert used >= 4, "the proposal should usually beat the initial pose"
-    assert np.mean(n_learned) < np.mean(n_plain), (n_plain, n_learned)
+    print("iterations to 1 mm / 0.1 deg: plain", n_plain, "learned", n_learned, "proposal steps kept:", kept)
+    reach_p = sum(n is not None for n in n_plain)
+    reach_l = sum(n is not None for n in n_learned)
+    assert sum(k > 0 for k in kept) >= 4, "the proposal should usually beat the initial pose"
+    assert reach_l > reach_p, (n_plain, n_learned)
+    both = [(p, l) for p, l in zip(n_plain, n_learned) if p is not None and l is not None]
+    if both:
+        assert np.mean([l for _, l in both]) <= np.mean([p for p, _ in both]), both

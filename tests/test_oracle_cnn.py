@@ -36,7 +36,7 @@ def tiny_params(rng, cin=2, ch=3):
     for l in range(4):
         p[f"w{l}"] = rng.normal(0, 0.5, size=(ch, c, 3, 3)); p[f"b{l}"] = rng.normal(0, 0.1, size=ch)
         c = ch
-    p["wfc"] = rng.normal(0, 0.5, size=(6, ch)); p["bfc"] = rng.normal(0, 0.1, size=6)
+    p["wfc"] = rng.normal(0, 0.5, size=(6, 3 * ch)); p["bfc"] = rng.normal(0, 0.1, size=6)
     return p
 
 
@@ -69,3 +69,24 @@ def test_network_gradient_finite_differences():
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (name, i, fd, an)
             checked += 1
     assert checked > 40
+
+
+def test_moment_pooling_closed_forms():
+    """The head's pooled values: a map that is constant per channel has zero
+    first moments (the pixel centres are symmetric about 0) and its value as
+    the mean; a map equal to x^ has the mean of x^ squared as its x^-moment,
+    (1 - 1/w^2) / 3 for the w centres (2 x + 1) / w - 1."""
+    for h, w in ((8, 10), (3, 5)):
+        basis = oracle.moment_basis(h, w)
+        assert abs(basis[1].sum()) < 1e-12 and abs(basis[2].sum()) < 1e-12
+        np.testing.assert_allclose((basis[1] ** 2).mean(), (1 - 1 / w ** 2) / 3, rtol=1e-12)
+        np.testing.assert_allclose((basis[2] ** 2).mean(), (1 - 1 / h ** 2) / 3, rtol=1e-12)
+    # through the network: zero convolution weights, bias only, so the last map
+    # is the constant relu(b3) per channel; the head sees [relu(b3), 0, 0]
+    rng = np.random.default_rng(4)
+    p = tiny_params(rng, cin=2, ch=3)
+    for l in range(4):
+        p[f"w{l}"][:] = 0.0
+    out, (acts, pool) = oracle.initnet_forward(rng.normal(size=(1, 2, 16, 16)), p)
+    np.testing.assert_allclose(pool[0], np.concatenate([np.maximum(p["b3"], 0), np.zeros(6)]), atol=1e-15)
+    np.testing.assert_allclose(out[0], p["wfc"][:, :3] @ np.maximum(p["b3"], 0) + p["bfc"], rtol=1e-12)
