@@ -119,7 +119,7 @@ def read_traffic(stage: str, workload: str):
 
 # kernels of each stage, as rocprofv3 names them (prefix after the namespace)
 STAGE_KERNELS = {"render_bwd": ["k_render_bwd_block<false>("], "render_fwd": ["k_render_fwd<false>("],
-                 "tile_bins": ["k_tile_init(", "k_bin_place(", "k_tile_sort("],
+                 "tile_bins": ["k_bin_place(", "k_tile_sort("],
                  "bin_count": ["k_bin_count(", "k_scan_reduce(", "k_scan_partials(", "k_scan_down("],
                  "project": ["k_project("], "project_bwd_adam": ["k_project_bwd("],
                  "loss_ssim": ["k_loss_ssim("]}

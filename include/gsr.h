@@ -179,8 +179,9 @@ int gsr_render_bwd_adam(gsr_ctx *ctx, gsr_state *state, const float *dL_dcolor, 
  * 32x8} and blocks_per_cu in {0, 1, 2, 4, 8} with the given upstream
  * gradients, writes the fastest shape into opts->tile_w / tile_h (the other
  * fields are inputs) and the fastest blocks_per_cu into *best_blocks_per_cu.
- * ms_table (may be NULL) receives the 15 mean times, shape-major. Allocates
- * scratch images; synchronises. */
+ * The backward timed is the mapping one (gradients of all five parameter
+ * groups). ms_table (may be NULL) receives the 15 mean times, shape-major.
+ * Allocates scratch images and gradients; synchronises. */
 int gsr_autotune_batch(gsr_ctx *ctx, const gsr_gaussians *g, int32_t n_views, const gsr_camera *cam, gsr_opts *opts,
                        const float *poses7, const float *dL_dcolor, const float *dL_ddepth, int32_t reps,
                        int32_t *best_blocks_per_cu, float *ms_table);

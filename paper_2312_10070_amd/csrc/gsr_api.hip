@@ -398,9 +398,10 @@ void enqueue_back(gsr_ctx* c, gsr_state* s, hipStream_t st, int64_t cap, float* 
 
 // Backward of the compositing and the projection. grads may be NULL (pose only).
 void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, const float* gD, const float* gA,
-                 const gsr_grads* grads, float* dpose7, float* dtwist6, const gsr::AdamFused* adam = nullptr) {
+                 const gsr_grads* grads, float* dpose7, float* dtwist6, const gsr::AdamFused* adam = nullptr,
+                 const gsr::PoseAdam* pose_adam = nullptr) {
   const gsr::Raster& R = s->R;
-  const bool want_pose = dpose7 || dtwist6;
+  const bool want_pose = dpose7 || dtwist6 || pose_adam;
   const int n_items = R.n_tiles * s->n_views;
   // s->g2d is zero here: cleared when allocated, and each projection backward
   // clears the sums it reads
@@ -435,7 +436,7 @@ void enqueue_bwd(gsr_ctx* c, gsr_state* s, hipStream_t st, const float* gC, cons
     gsr::launch_project_bwd(R, pb, st);
     if (want_pose)
       gsr::launch_pose_finalize(s->pose7, s->pose_acc, gsr::project_bwd_blocks(s->n), dpose7, dtwist6, s->n_views,
-                                st);
+                                st, pose_adam);
   }
 }
 
@@ -1035,13 +1036,22 @@ int gsr_autotune_batch(gsr_ctx* c, const gsr_gaussians* g, int32_t n_views, cons
   GSR_HIP(c, hipSetDevice(c->device));
   const int64_t P = (int64_t)cam->width * cam->height;
   if (P <= 0) return fail(c, GSR_EINVAL, "image size must be positive");
+  // images, and the parameter gradients a mapping backward writes (the
+  // configuration is timed on the backward it will run)
+  const int64_t n = g->n > 0 ? g->n : 0;
   float* buf = nullptr;
-  if (hipMalloc((void**)&buf, sizeof(float) * 5 * P * n_views) != hipSuccess) {
+  if (hipMalloc((void**)&buf, sizeof(float) * (5 * P * n_views + 14 * n)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, GSR_ENOMEM, "autotune scratch allocation failed");
   }
-  float* color = buf;
-  float* depth = buf + 3 * P * n_views;
+  gsr_grads grads{};
+  grads.quats = buf;  // 16-byte aligned: the start of the allocation
+  grads.means = buf + 4 * n;
+  grads.scales = grads.means + 3 * n;
+  grads.opacities = grads.scales + 3 * n;
+  grads.colors = grads.opacities + n;
+  float* color = buf + 14 * n;
+  float* depth = color + 3 * P * n_views;
   float* alpha = depth + P * n_views;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
@@ -1066,7 +1076,7 @@ int gsr_autotune_batch(gsr_ctx* c, const gsr_gaussians* g, int32_t n_views, cons
         gsr_state* st = nullptr;
         (void)hipEventRecord(e0, c->stream);
         rc = gsr_render_fwd_batch(c, g, n_views, cam, &o, bpc[bi], poses7, color, depth, alpha, &st);
-        if (rc == GSR_OK) rc = gsr_render_bwd(c, st, dL_dcolor, dL_ddepth, nullptr, nullptr, nullptr, nullptr);
+        if (rc == GSR_OK) rc = gsr_render_bwd(c, st, dL_dcolor, dL_ddepth, nullptr, &grads, nullptr, nullptr);
         (void)hipEventRecord(e1, c->stream);
         if (st) gsr_state_release(c, st);
         if (rc == GSR_OK && hipEventSynchronize(e1) == hipSuccess && r > 0) {
@@ -1534,13 +1544,14 @@ int gsr_track_graph_create(gsr_ctx* c, const gsr_gaussians* g, const gsr_camera*
     if (e == hipSuccess) {
       gsr::launch_fill_f32(tg->adam, 0.f, 20, cap);
       gsr::launch_fill_u32(reinterpret_cast<uint32_t*>(s->d_overflow), 0u, 1, cap);
+      const gsr::PoseAdam pa{tg->adam, to->lr_q, to->lr_t, to->beta1, to->beta2, to->eps};
       for (int it = 0; it < tg->n_iters; ++it) {
         enqueue_front(c, s, cap);
         enqueue_back(c, s, cap, K_cap, tg->color, tg->depth, tg->alpha);
         gsr::launch_loss_track(tg->color, tg->depth, tg->alpha, tg->obs_c, tg->obs_d, P, to->lambda_c,
                                to->inlier_mult, tg->loss + it, tg->gC, tg->gD, tg->median + it, tg->sel_temp, cap);
-        enqueue_bwd(c, s, cap, tg->gC, tg->gD, nullptr, nullptr, tg->dpose, nullptr);
-        gsr::launch_pose_adam(tg->pose, tg->adam, tg->dpose, to->lr_q, to->lr_t, to->beta1, to->beta2, to->eps, cap);
+        // the pose backward's last kernel applies the pose Adam step
+        enqueue_bwd(c, s, cap, tg->gC, tg->gD, nullptr, nullptr, nullptr, nullptr, nullptr, &pa);
       }
       e = hipStreamEndCapture(cap, &tg->graph);
     }

@@ -239,6 +239,7 @@ struct BinArgs {
   int64_t cap;             // positions >= cap are dropped and flagged
   uint64_t* keys;          // [cap] (depth bits << 32 | record index)
   int* overflow;
+  int2* ranges;            // [n_items] written by the placement pass (NULL while counting)
 };
 int bin_workgroups(int64_t n);
 // M from the tile rectangles (LDS histograms, no global atomics).
@@ -337,8 +338,28 @@ struct ProjectBwdArgs {
 int64_t project_bwd_blocks(int64_t n);
 void launch_project_bwd(const Raster& R, const ProjectBwdArgs& a, hipStream_t s);
 // Sums the per-workgroup pose partials in a fixed order and converts them.
+// Adam on the 7 pose parameters (q: lr_q, t: lr_t), bias-corrected with the
+// step count kept in state = [m(8), v(8), step(1)]; element i of a step.
+__device__ __forceinline__ void pose_adam_elem(float* pose, float* state, int i, float gi, float t, float lr_q,
+                                               float lr_t, float b1, float b2, float eps) {
+  const float mi = b1 * state[i] + (1.f - b1) * gi;
+  const float vi = b2 * state[8 + i] + (1.f - b2) * gi * gi;
+  state[i] = mi;
+  state[8 + i] = vi;
+  const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
+  const float lr = i < 4 ? lr_q : lr_t;
+  pose[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+struct PoseAdam {
+  float* state;  // NULL: no step
+  float lr_q, lr_t, b1, b2, eps;
+};
+
+// With adam.state non-NULL (one view), also applies the pose Adam step to
+// pose7 (in place) with the gradient just formed.
 void launch_pose_finalize(const float* pose7, const float* pose_acc, int64_t blocks, float* dL_dpose7,
-                          float* dL_dtwist6, int n_views, hipStream_t s);
+                          float* dL_dtwist6, int n_views, hipStream_t s, const PoseAdam* adam = nullptr);
 // Longest-list-first order of (view, tile) items for the persistent launches
 // (power-of-two length buckets). temp: 64 ints.
 void launch_item_order(const int2* ranges, int n_items, int* order, int* temp, hipStream_t s);
@@ -358,7 +379,7 @@ void launch_loss_reg(const float* scales, int64_t n, float weight, float* loss, 
 // Adds weight (1 - SSIM(X, Y)) to *loss and its gradient to gX ([3,H,W]).
 void launch_loss_ssim(const float* X, const float* Y, int H, int W, float weight, float* loss, float* gX,
                       uint32_t* red, hipStream_t s);
-// temp: track_temp_words() uint32, zero before its first use
+// temp: track_temp_words() uint32, zero before the first call (every call leaves it zero)
 int64_t track_temp_words();
 void launch_loss_track(const float* C, const float* D, const float* A, const float* Ct, const float* Dt, int64_t P,
                        float lambda_c, float inlier_mult, float* loss, float* gC, float* gD, float* median,

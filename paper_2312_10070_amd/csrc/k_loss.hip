@@ -47,9 +47,12 @@ __device__ __forceinline__ bool publish_and_count(float* slot, float value, uint
 // kRedGroup workgroups sums the group's partials and publishes that; the last
 // group sums the group sums. Tickets return to zero. red: kRedWords words,
 // zero before the first launch. With `accumulate`, *out becomes
-// *out + (offset + scale * total) instead.
+// *out + (offset + scale * total) instead. With `clear`, the last workgroup
+// (which runs after every other one has published its partial, so after all
+// their earlier reads) zeroes clear[0, n_clear).
 __device__ __forceinline__ void grid_sum(float v, float* out, uint32_t* red, bool accumulate = false,
-                                         float scale = 1.f, float offset = 0.f) {
+                                         float scale = 1.f, float offset = 0.f, uint32_t* clear = nullptr,
+                                         int n_clear = 0) {
   __shared__ bool go;
   float* f = reinterpret_cast<float*>(red);
   const uint32_t b = blockIdx.x, n = gridDim.x;
@@ -71,6 +74,7 @@ __device__ __forceinline__ void grid_sum(float v, float* out, uint32_t* red, boo
             : 0.f;
   const float total = block_sum(acc);
   if (threadIdx.x == 0) *out = accumulate ? *out + (offset + scale * total) : total;
+  for (int i = threadIdx.x; i < n_clear; i += blockDim.x) clear[i] = 0u;
 }
 
 __device__ __forceinline__ float4 ld4(const float* p, int64_t i) { return reinterpret_cast<const float4*>(p)[i]; }
@@ -183,10 +187,6 @@ __device__ __forceinline__ SelState select_state(const uint32_t* __restrict__ st
   return r;
 }
 
-__global__ void k_select_init(uint32_t* st) {
-  for (int i = threadIdx.x; i < kSelWords; i += blockDim.x) st[i] = 0;
-}
-
 __global__ __launch_bounds__(256) void k_select_hist(const float* __restrict__ D, const float* __restrict__ Dt, int64_t P,
                                                     int pass, uint32_t* __restrict__ st) {
   __shared__ uint32_t h[256];
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_select_hist(const float* __restrict__ D
 __global__ __launch_bounds__(256) void k_loss_track(const float* __restrict__ C, const float* __restrict__ D,
                                                    const float* __restrict__ A, const float* __restrict__ Ct,
                                                    const float* __restrict__ Dt, int64_t P, float lambda_c,
-                                                   float inlier_mult, const uint32_t* __restrict__ st,
+                                                   float inlier_mult, uint32_t* __restrict__ st,
                                                    float* __restrict__ loss, float* __restrict__ gC,
                                                    float* __restrict__ gD, float* __restrict__ median,
                                                    uint32_t* __restrict__ red) {
@@ -234,7 +234,8 @@ __global__ __launch_bounds__(256) void k_loss_track(const float* __restrict__ C,
     gD[i] = w * ld * sgnf(rd);
     acc += w * (lc * l + ld * fabsf(rd));
   }
-  grid_sum(acc, loss, red);
+  // the histograms are read by now: the last workgroup clears them for the next call
+  grid_sum(acc, loss, red, false, 1.f, 0.f, st, kSelWords);
 }
 
 // ---- SSIM term of the mapping colour loss (Eq. 10) ------------------------
@@ -542,16 +543,7 @@ __global__ void k_pose_adam(float* __restrict__ pose, float* __restrict__ state,
   const int i = threadIdx.x;
   const float t = state[16] + 1.f;
   __syncthreads();
-  if (i < 7) {
-    const float gi = g[i];
-    const float mi = b1 * state[i] + (1.f - b1) * gi;
-    const float vi = b2 * state[8 + i] + (1.f - b2) * gi * gi;
-    state[i] = mi;
-    state[8 + i] = vi;
-    const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
-    const float lr = i < 4 ? lr_q : lr_t;
-    pose[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
-  }
+  if (i < 7) pose_adam_elem(pose, state, i, g[i], t, lr_q, lr_t, b1, b2, eps);
   __syncthreads();
   if (i == 0) state[16] = t;
 }
@@ -658,12 +650,13 @@ void launch_loss_track(const float* C, const float* D, const float* A, const flo
     launch_fill_f32(loss, 0.f, 1, s);
     return;
   }
-  hipLaunchKernelGGL(k_select_init, dim3(1), dim3(256), 0, s, temp);
+  // temp's histograms are zero here: cleared when allocated and by the loss
+  // kernel of the previous call, after its last read
   const unsigned g = grid_for(P, 256);
   for (int pass = 0; pass < kSelPasses; ++pass)
     hipLaunchKernelGGL(k_select_hist, dim3(g), dim3(256), 0, s, D, Dt, P, pass, temp);
   hipLaunchKernelGGL(k_loss_track, dim3(grid_for(P, 512)), dim3(256), 0, s, C, D, A, Ct, Dt, P, lambda_c,
-                     inlier_mult, (const uint32_t*)temp, loss, gC, gD, median, temp + kSelWords);
+                     inlier_mult, temp, loss, gC, gD, median, temp + kSelWords);
 }
 
 void launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,

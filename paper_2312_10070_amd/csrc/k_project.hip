@@ -436,10 +436,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a
 // backward's workgroups (fixed order), then dL/d(q, t) and the twist.
 __global__ __launch_bounds__(256) void k_pose_finalize(const float* __restrict__ poses7,
                                                       const float* __restrict__ parts, int64_t blocks,
-                                                      float* __restrict__ dposes7, float* __restrict__ dtwists6) {
+                                                      float* __restrict__ dposes7, float* __restrict__ dtwists6,
+                                                      PoseAdam adam) {
   const int v = blockIdx.x;
   __shared__ float red[4][12];
   __shared__ float acc[12];
+  __shared__ float g7s[7];
   float s[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) s[i] = 0.f;
@@ -456,34 +458,47 @@ __global__ __launch_bounds__(256) void k_pose_finalize(const float* __restrict__
   if (threadIdx.x < 12) acc[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
                                            red[3][threadIdx.x];
   __syncthreads();
-  if (threadIdx.x != 0) return;
   const float* pose7 = poses7 + 7 * v;
-  float* dpose7 = dposes7 ? dposes7 + 7 * v : nullptr;
-  float* dtwist6 = dtwists6 ? dtwists6 + 6 * v : nullptr;
-  const PoseF P = load_pose(pose7);
-  float G[9];
-  for (int i = 0; i < 9; ++i) G[i] = acc[i];
-  const float gt[3] = {acc[9], acc[10], acc[11]};
-  if (dpose7) {
-    float gq[4] = {0, 0, 0, 0};
-    if (P.ok) quat_rot_vjp(P.qh, P.inv_norm, G, gq);
-    for (int i = 0; i < 4; ++i) dpose7[i] = gq[i];
-    for (int i = 0; i < 3; ++i) dpose7[4 + i] = gt[i];
-  }
-  if (dtwist6) {
-    float phi[3] = {P.t[1] * gt[2] - P.t[2] * gt[1], P.t[2] * gt[0] - P.t[0] * gt[2], P.t[0] * gt[1] - P.t[1] * gt[0]};
-    for (int j = 0; j < 3; ++j) {
-      const float r0 = P.R[j], r1 = P.R[3 + j], r2 = P.R[6 + j];
-      const float g0 = G[j], g1 = G[3 + j], g2 = G[6 + j];
-      phi[0] += r1 * g2 - r2 * g1;
-      phi[1] += r2 * g0 - r0 * g2;
-      phi[2] += r0 * g1 - r1 * g0;
+  if (threadIdx.x == 0) {
+    float* dpose7 = dposes7 ? dposes7 + 7 * v : nullptr;
+    float* dtwist6 = dtwists6 ? dtwists6 + 6 * v : nullptr;
+    const PoseF P = load_pose(pose7);
+    float G[9];
+    for (int i = 0; i < 9; ++i) G[i] = acc[i];
+    const float gt[3] = {acc[9], acc[10], acc[11]};
+    if (dpose7 || adam.state) {
+      float gq[4] = {0, 0, 0, 0};
+      if (P.ok) quat_rot_vjp(P.qh, P.inv_norm, G, gq);
+      const float g7[7] = {gq[0], gq[1], gq[2], gq[3], gt[0], gt[1], gt[2]};
+      for (int i = 0; i < 7; ++i) {
+        g7s[i] = g7[i];
+        if (dpose7) dpose7[i] = g7[i];
+      }
     }
-    for (int i = 0; i < 3; ++i) {
-      dtwist6[i] = gt[i];
-      dtwist6[3 + i] = phi[i];
+    if (dtwist6) {
+      float phi[3] = {P.t[1] * gt[2] - P.t[2] * gt[1], P.t[2] * gt[0] - P.t[0] * gt[2], P.t[0] * gt[1] - P.t[1] * gt[0]};
+      for (int j = 0; j < 3; ++j) {
+        const float r0 = P.R[j], r1 = P.R[3 + j], r2 = P.R[6 + j];
+        const float g0 = G[j], g1 = G[3 + j], g2 = G[6 + j];
+        phi[0] += r1 * g2 - r2 * g1;
+        phi[1] += r2 * g0 - r0 * g2;
+        phi[2] += r0 * g1 - r1 * g0;
+      }
+      for (int i = 0; i < 3; ++i) {
+        dtwist6[i] = gt[i];
+        dtwist6[3 + i] = phi[i];
+      }
     }
   }
+  if (!adam.state) return;  // uniform: a kernel argument
+  // the pose Adam step on the gradient just formed (the pose was read above)
+  __syncthreads();
+  const float t = adam.state[16] + 1.f;
+  __syncthreads();
+  if (threadIdx.x < 7)
+    pose_adam_elem(const_cast<float*>(pose7), adam.state, threadIdx.x, g7s[threadIdx.x], t, adam.lr_q, adam.lr_t,
+                   adam.b1, adam.b2, adam.eps);
+  if (threadIdx.x == 0) adam.state[16] = t;
 }
 
 }  // namespace
@@ -502,10 +517,12 @@ void launch_project_bwd(const Raster& R, const ProjectBwdArgs& a, hipStream_t s)
 }
 
 void launch_pose_finalize(const float* pose7, const float* parts, int64_t blocks, float* dpose7, float* dtwist6,
-                          int n_views, hipStream_t s) {
+                          int n_views, hipStream_t s, const PoseAdam* adam) {
   if (n_views <= 0) return;
+  PoseAdam pa{};
+  if (adam && n_views == 1) pa = *adam;
   hipLaunchKernelGGL(k_pose_finalize, dim3((unsigned)n_views), dim3(256), 0, s, pose7, parts, blocks, dpose7,
-                     dtwist6);
+                     dtwist6, pa);
 }
 
 }  // namespace gsr

@@ -160,16 +160,6 @@ __global__ __launch_bounds__(kPlaceThreads) void k_bin_count(Raster Rr, BinArgs 
   for (int i = threadIdx.x; i < c.nt; i += blockDim.x) a.M[(row + i) * a.n_wg + blockIdx.x] = hist[i];
 }
 
-// ranges[t] = [S[t][0], S[t][n_wg - 1] + M[t][n_wg - 1]) clipped to the capacity.
-__global__ __launch_bounds__(256) void k_tile_init(const uint32_t* __restrict__ M, const uint32_t* __restrict__ S,
-                                                  int64_t n_items, int n_wg, int64_t cap, int2* __restrict__ ranges) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_items) return;
-  const int64_t b = t * n_wg;
-  const int64_t s0 = S[b], s1 = (int64_t)S[b + n_wg - 1] + M[b + n_wg - 1];
-  ranges[t] = make_int2((int)(s0 < cap ? s0 : cap), (int)(s1 < cap ? s1 : cap));
-}
-
 // Every (Gaussian, tile) pair of the workgroup takes the next position of its
 // tile's sub-range (LDS counters seeded from S) and writes its key there.
 __global__ __launch_bounds__(kPlaceThreads) void k_bin_place(Raster Rr, BinArgs a) {
@@ -178,6 +168,13 @@ __global__ __launch_bounds__(kPlaceThreads) void k_bin_place(Raster Rr, BinArgs 
   const int64_t view = blockIdx.y;
   const int64_t row = view * Rr.n_tiles + c.t0;
   for (int i = threadIdx.x; i < c.nt; i += blockDim.x) next[i] = a.S[(row + i) * a.n_wg + blockIdx.x];
+  // the chunk's tile ranges [S[t][0], S[t][n_wg - 1] + M[t][n_wg - 1]) clipped
+  // to the capacity, tiles dealt round-robin over the chunk's workgroups
+  for (int i = (int)blockIdx.x + a.n_wg * (int)threadIdx.x; i < c.nt; i += a.n_wg * (int)blockDim.x) {
+    const int64_t b = (row + i) * a.n_wg;
+    const int64_t s0 = a.S[b], s1 = (int64_t)a.S[b + a.n_wg - 1] + a.M[b + a.n_wg - 1];
+    a.ranges[row + i] = make_int2((int)(s0 < a.cap ? s0 : a.cap), (int)(s1 < a.cap ? s1 : a.cap));
+  }
   __syncthreads();
   for (int64_t g = c.g0 + threadIdx.x; g < c.g1; g += blockDim.x) {
     const int64_t o = view * a.n + g;
@@ -413,9 +410,9 @@ void launch_bin_count(const Raster& R, const BinArgs& a, hipStream_t s) {
 void launch_tile_bins(const Raster& R, const BinArgs& a, int64_t n_items, int2* ranges, uint64_t* scratch,
                       uint32_t* ids, hipStream_t s) {
   if (n_items <= 0) return;
-  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, (const uint32_t*)a.M,
-                     (const uint32_t*)a.S, n_items, a.n_wg, a.cap, ranges);
-  hipLaunchKernelGGL(k_bin_place, bin_grid(R, a), dim3(kPlaceThreads), bin_lds(R), s, R, a);
+  BinArgs b = a;
+  b.ranges = ranges;
+  hipLaunchKernelGGL(k_bin_place, bin_grid(R, b), dim3(kPlaceThreads), bin_lds(R), s, R, b);
   hipLaunchKernelGGL(k_tile_sort, dim3((unsigned)((n_items + kBinThreads / 64 - 1) / (kBinThreads / 64))),
                      dim3(kBinThreads), 0, s, (const int2*)ranges, n_items, a.keys, scratch, ids);
 }
