@@ -120,7 +120,7 @@ def read_traffic(stage: str, workload: str):
 # kernels of each stage, as rocprofv3 names them (prefix after the namespace)
 STAGE_KERNELS = {"render_bwd": ["k_render_bwd_block<false>("], "render_fwd": ["k_render_fwd<false>("],
                  "tile_bins": ["k_bin_place(", "k_tile_sort("],
-                 "bin_count": ["k_bin_count(", "k_scan_reduce(", "k_scan_partials(", "k_scan_down("],
+                 "bin_count": ["k_bin_count("],
                  "project": ["k_project("], "project_bwd_adam": ["k_project_bwd("],
                  "loss_ssim": ["k_loss_ssim("]}
 PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {counter} -d <dir> -o run --output-format csv -- python3 bench.py "
@@ -195,7 +195,7 @@ N_CU = 256  # MI355X compute units
 # kernels of the tracking iteration, as rocprofv3 names them
 TRACK_KERNELS = {"render_bwd": ["k_render_bwd_quad<false>("], "render_fwd": ["k_render_fwd<false>("],
                  "project": ["k_project("], "project_bwd": ["k_project_bwd("],
-                 "loss_track": ["k_select_init(", "k_select_hist(", "k_loss_track("]}
+                 "loss_track": ["k_select_hist(", "k_loss_track("]}
 PROFILE_COMMANDS = {
     "H": ("python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-full-loss --no-tracking --no-batched "
           "--no-initnet --no-seed"),

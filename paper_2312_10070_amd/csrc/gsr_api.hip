@@ -32,9 +32,10 @@ struct gsr_state {
   int4* rect = nullptr;
   uint32_t* counts = nullptr;
   int n_wg = 1;                    // binning workgroups per view
-  uint32_t* bin_M = nullptr;       // [items][n_wg]: pairs per (view, tile) and workgroup
-  uint32_t* bin_S = nullptr;       // [items][n_wg]: exclusive scan of bin_M
-  uint32_t* scan_temp = nullptr;
+  uint32_t* bin_M = nullptr;       // [items][n_wg]: a workgroup's offset inside a (view, tile) range
+  uint32_t* bin_T = nullptr;       // [items]: pair totals (zero between forwards)
+  int2* bin_R = nullptr;           // [items]: unclipped ranges
+  uint32_t* bin_ticket = nullptr;  // zero between forwards
   float* g2d = nullptr;
   float* Tfin = nullptr;
   int* last = nullptr;
@@ -172,8 +173,9 @@ void carve_A(gsr_state* s, char* base, int64_t n, int64_t P, int64_t tiles, int6
   s->rect = c.take<int4>(n);
   s->counts = c.take<uint32_t>(n);
   s->bin_M = c.take<uint32_t>(nm);
-  s->bin_S = c.take<uint32_t>(nm);
-  s->scan_temp = c.take<uint32_t>(gsr::scan_temp_words(nm));
+  s->bin_T = c.take<uint32_t>(tiles);
+  s->bin_R = c.take<int2>(tiles);
+  s->bin_ticket = c.take<uint32_t>(4);
   s->g2d = c.take<float>(10 * n);
   s->Tfin = c.take<float>(P);
   s->last = c.take<int>(P);
@@ -219,6 +221,10 @@ int ensure_A(gsr_ctx* c, gsr_state* s, int64_t n, int64_t P, int64_t tiles, int6
   // at zero (the projection backward clears what it reads), so they are
   // cleared only here, when the workspace is allocated.
   gsr::launch_fill_f32(s->g2d, 0.f, 10 * nn, c->stream);
+  // likewise the binning's tile totals and ticket (the counting pass's last
+  // workgroup returns them to zero)
+  gsr::launch_fill_u32(s->bin_T, 0u, tt, c->stream);
+  gsr::launch_fill_u32(s->bin_ticket, 0u, 1, c->stream);
   s->bin_cap = nm;
   s->n_cap = nn;
   s->P_cap = PP;
@@ -353,15 +359,14 @@ struct Stage {
   }
 };
 
-gsr::BinArgs bin_args(gsr_state* s, int64_t cap) {
-  return gsr::BinArgs{s->n, s->n_views, s->n_wg, s->rect, s->bin_M, s->bin_S,
-                      cap, s->keys, s->d_overflow};
+gsr::BinArgs bin_args(gsr_state* s, int64_t cap, uint32_t* K_host = nullptr) {
+  return gsr::BinArgs{s->n,     s->n_views, s->n_wg, s->rect, s->bin_M,    s->bin_T,       s->bin_R,
+                      s->bin_ticket, s->d_K, K_host, cap, s->keys, s->d_overflow};
 }
 
-// Projection, per-(tile, workgroup) pair counts and their scan (the overlap
-// count K lands in s->d_K).
+// Projection, per-(tile, workgroup) pair counts, the tiles' ranges and the
+// overlap count K (in s->d_K, and in *K_host when given).
 void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st, uint32_t* K_host = nullptr) {
-  const int64_t n_items = (int64_t)s->R.n_tiles * s->n_views;
   gsr::ProjectArgs pa{s->n, s->g.means, s->g.scales, s->g.quats, s->g.opacities, s->g.colors, s->pose7,
                       s->rec_uvab, s->rec_cob, s->rec_rgbz, s->rect, s->counts, s->n_views};
   {
@@ -371,8 +376,7 @@ void enqueue_front(gsr_ctx* c, gsr_state* s, hipStream_t st, uint32_t* K_host = 
   {
     Stage t(c, "bin_count");
     s->n_wg = gsr::bin_workgroups(s->n);
-    gsr::launch_bin_count(s->R, bin_args(s, 0), st);
-    gsr::launch_exclusive_scan(s->bin_M, s->bin_S, n_items * s->n_wg, s->d_K, s->scan_temp, st, K_host);
+    gsr::launch_bin_count(s->R, bin_args(s, 0, K_host), st);
   }
 }
 

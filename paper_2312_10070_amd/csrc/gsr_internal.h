@@ -225,8 +225,8 @@ void launch_prune(const PruneArgs& a, int64_t n, float thre, const int32_t* mask
                   hipStream_t s);
 
 // Tile binning (see k_sort.hip). Workgroup w of view v handles the Gaussians
-// [w c, (w + 1) c) with c = ceil(n / n_wg); M[item][w] counts its pairs per
-// (view, tile) item and S = exclusive scan of M in (item, workgroup) order.
+// [w c, (w + 1) c) with c = ceil(n / n_wg); M[item][w] is the offset of its
+// pairs inside the range of the (view, tile) item, R[item] that range.
 // rect[o] = (tx0 | tx1 << 16, ty0 | ty1 << 16, float bits of the camera
 // depth, number of tiles; 0 = not binned): everything binning reads, 16 bytes.
 struct BinArgs {
@@ -235,16 +235,21 @@ struct BinArgs {
   int n_wg;                // workgroups per view
   const int4* rect;
   uint32_t* M;             // [n_items][n_wg]
-  uint32_t* S;             // [n_items][n_wg]
+  uint32_t* T;             // [n_items] pair totals; zero between launches
+  int2* R;                 // [n_items] unclipped ranges
+  uint32_t* ticket;        // zero between launches
+  uint32_t* K;             // overlap count
+  uint32_t* K_host;        // NULL or a device-visible host word that also receives K
   int64_t cap;             // positions >= cap are dropped and flagged
   uint64_t* keys;          // [cap] (depth bits << 32 | record index)
   int* overflow;
   int2* ranges;            // [n_items] written by the placement pass (NULL while counting)
 };
 int bin_workgroups(int64_t n);
-// M from the tile rectangles (LDS histograms, no global atomics).
+// M, R and K from the tile rectangles (LDS histograms, one reservation atomic
+// per (tile, workgroup), the last workgroup scans the tile totals).
 void launch_bin_count(const Raster& R, const BinArgs& a, hipStream_t s);
-// ranges from M and S, slot placement (LDS counters seeded from S), then one
+// ranges from R, slot placement (LDS counters seeded from R and M), then one
 // LDS sort per tile writing ids[cap] (record indices in depth order).
 // scratch: [cap] keys, used by ranges longer than LDS holds.
 void launch_tile_bins(const Raster& R, const BinArgs& a, int64_t n_items, int2* ranges, uint64_t* scratch,

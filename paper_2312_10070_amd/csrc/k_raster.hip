@@ -630,21 +630,23 @@ __device__ __forceinline__ void bwd_item_quad(const Raster& Rr, const BwdArgs& a
       const int myl = q.quad == 0 ? len0 : (q.quad == 1 ? len1 : (q.quad == 2 ? len2 : len3));
       const int maxl = __builtin_amdgcn_readfirstlane(max(max(len0, len1), max(len2, len3)));
       __builtin_amdgcn_wave_barrier();
-      // the next entry is read one step ahead (entry kListCap + 1 exists, so
-      // the read stays inside the row's list)
-      int jn = mylist[0];
+      // the record of step t + 1 is read from LDS during step t, and the list
+      // entry of step t + 2 with it (entries up to kListCap + 1 exist, so the
+      // reads stay inside the row's list; entries past its end are ignored)
+      int jb = 0 < myl ? mylist[0] : 16 * kDummy;
+      int jn = mylist[1];
+      float4 g = lds_at(sm.uvab, jb), cb = lds_at(sm.cob, jb), cz = lds_at(sm.rgbz, jb);
       for (int t = 0; t < maxl; ++t) {
         const bool pend = t < myl;
-        const int jb = pend ? jn : 16 * kDummy;
-        jn = mylist[t + 1];
-        const float4 g = lds_at(sm.uvab, jb);
-        const float4 cb = lds_at(sm.cob, jb);
+        const int jb1 = t + 1 < myl ? jn : 16 * kDummy;
+        jn = mylist[t + 2];
+        const float4 g1 = lds_at(sm.uvab, jb1), cb1 = lds_at(sm.cob, jb1), cz1 = lds_at(sm.rgbz, jb1);
         const float dx = q.fpx - g.x, dy = q.fpy - g.y;
         const PairEval pe = eval_pair(dx, dy, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
         const bool hit = boff + (jb >> 4) < b.last && pe.use;  // the all-zero record never passes `use`
         if (__ballot(hit) != 0) {
           float v[10];
-          bwd_pair(b, pe, hit, dx, dy, lds_at(sm.rgbz, jb), v);
+          bwd_pair(b, pe, hit, dx, dy, cz, v);
           int f;
           const float u = row_reduce6(v, lane, &f);
           if (DET) {
@@ -656,7 +658,10 @@ __device__ __forceinline__ void bwd_item_quad(const Raster& Rr, const BwdArgs& a
             atomicAdd(sm.acc + NF * (jb >> 4) + f, u);
           }
         }
-        asm volatile("" : "+v"(jn));  // keep the read of the next entry in this step
+        jb = jb1;
+        g = g1;
+        cb = cb1;
+        cz = cz1;
       }
       __builtin_amdgcn_wave_barrier();
     }

@@ -1,11 +1,13 @@
-// Tile binning without global atomics. Each binning workgroup owns a
-// contiguous run of Gaussians and counts their (Gaussian, tile) pairs per tile
-// in an LDS histogram, written out as column w of a [tile][workgroup] matrix
-// M. An exclusive scan of M in (tile, workgroup) order gives every workgroup
-// its sub-range inside every tile's [start, end) range (and the overlap count
-// K). The workgroup then walks its Gaussians again, takes positions from LDS
-// counters seeded with its sub-range starts, and writes the keys (float bits
-// of the camera depth << 32 | record index) in arbitrary order. Finally each
+// Tile binning in two passes. Each binning workgroup owns a contiguous run of
+// Gaussians and counts their (Gaussian, tile) pairs per tile in an LDS
+// histogram; for every tile it meets it reserves a sub-range of the tile's
+// range with one atomic on the tile's total and keeps the offset in column w
+// of a [tile][workgroup] matrix M. The last workgroup to finish scans the
+// tile totals into the tiles' [start, end) ranges and the overlap count K
+// (and zeroes the totals for the next launch). The placing workgroup then
+// walks its Gaussians again, takes positions from LDS counters seeded with
+// start + its offset, and writes the keys (float bits of the camera depth <<
+// 32 | record index) in arbitrary order. Finally each
 // tile's range is sorted by key and its record indices written: by one wave
 // in registers (a bitonic network, up to 512 keys), or for longer ranges by a
 // whole workgroup through LDS (runs of 2048 merged pairwise in global
@@ -26,7 +28,9 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;  // 2048
 
 
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* s_wave) {
+// Exclusive scan of v over a workgroup of T threads; *total = the sum.
+template <int T>
+__device__ __forceinline__ uint32_t block_exclusive_scan_t(uint32_t v, uint32_t* total, uint32_t* s_wave) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint32_t x = v;
 #pragma unroll
@@ -38,7 +42,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   __syncthreads();
   uint32_t base = 0, tot = 0;
 #pragma unroll
-  for (int i = 0; i < kScanThreads / 64; ++i) {
+  for (int i = 0; i < T / 64; ++i) {
     if (i < w) base += s_wave[i];
     tot += s_wave[i];
   }
@@ -56,7 +60,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
   for (int i = 0; i < kScanItems; ++i)
     if (base + i < n) s += in[base + i];
   uint32_t tot;
-  block_exclusive_scan(s, &tot, s_wave);
+  block_exclusive_scan_t<kScanThreads>(s, &tot, s_wave);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
@@ -77,7 +81,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(uint32_t* __rest
       s += v[i];
     }
     uint32_t tot;
-    uint32_t ex = block_exclusive_scan(s, &tot, s_wave) + carry;
+    uint32_t ex = block_exclusive_scan_t<kScanThreads>(s, &tot, s_wave) + carry;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
       if (base + i < np) partials[base + i] = ex;
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
     s += v[i];
   }
   uint32_t tot;
-  uint32_t ex = block_exclusive_scan(s, &tot, s_wave) + partials[blockIdx.x];
+  uint32_t ex = block_exclusive_scan_t<kScanThreads>(s, &tot, s_wave) + partials[blockIdx.x];
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     if (base + i < n) out[base + i] = ex;
@@ -137,9 +141,43 @@ __device__ __forceinline__ Chunk bin_chunk(const Raster& Rr, const BinArgs& a) {
   return c;
 }
 
-// M[(v n_tiles + t) n_wg + w] = pairs of workgroup w's Gaussians on tile t of view v.
+// One workgroup: R[i] = (start, start + T[i]) with start the exclusive scan of
+// the tile totals T[0, n) (read at the device-coherent level), T[i] = 0;
+// returns the sum.
+__device__ uint32_t scan_tile_totals(uint32_t* T, int2* R, int64_t n) {
+  __shared__ uint32_t s_wave[kPlaceThreads / 64];
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < n; b0 += (int64_t)kPlaceThreads * kScanItems) {
+    const int64_t base = b0 + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      v[i] = base + i < n ? __hip_atomic_load(T + base + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+      sum += v[i];
+    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan_t<kPlaceThreads>(sum, &tot, s_wave) + carry;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      if (base + i < n) {
+        R[base + i] = make_int2((int)ex, (int)(ex + v[i]));
+        __hip_atomic_store(T + base + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      ex += v[i];
+    }
+    carry += tot;
+  }
+  return carry;
+}
+
+// Pairs per (tile, workgroup) in LDS; M[(v n_tiles + t) n_wg + w] = offset of
+// workgroup w's pairs inside the range of tile t of view v (reserved with an
+// atomic on T, so the order of the workgroups inside a tile is arbitrary).
+// The last workgroup writes the ranges R and K.
 __global__ __launch_bounds__(kPlaceThreads) void k_bin_count(Raster Rr, BinArgs a) {
   extern __shared__ uint32_t hist[];
+  __shared__ bool last;
   const Chunk c = bin_chunk(Rr, a);
   const int64_t view = blockIdx.y;
   for (int i = threadIdx.x; i < c.nt; i += blockDim.x) hist[i] = 0;
@@ -157,23 +195,42 @@ __global__ __launch_bounds__(kPlaceThreads) void k_bin_count(Raster Rr, BinArgs 
   }
   __syncthreads();
   const int64_t row = view * Rr.n_tiles + c.t0;
-  for (int i = threadIdx.x; i < c.nt; i += blockDim.x) a.M[(row + i) * a.n_wg + blockIdx.x] = hist[i];
+  for (int i = threadIdx.x; i < c.nt; i += blockDim.x) {
+    const uint32_t h = hist[i];
+    if (h) a.M[(row + i) * a.n_wg + blockIdx.x] = atomicAdd(a.T + row + i, h);
+  }
+  __syncthreads();  // every reservation of the workgroup has returned
+  if (threadIdx.x == 0) {
+    const uint32_t n_wg_total = gridDim.x * gridDim.y * gridDim.z;
+    const uint32_t t = __hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = t == n_wg_total - 1;
+    if (last) __hip_atomic_store(a.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (!last) return;
+  const uint32_t K = scan_tile_totals(a.T, a.R, (int64_t)Rr.n_tiles * a.n_views);
+  if (threadIdx.x == 0) {
+    *a.K = K;
+    if (a.K_host) *a.K_host = K;
+  }
 }
 
 // Every (Gaussian, tile) pair of the workgroup takes the next position of its
-// tile's sub-range (LDS counters seeded from S) and writes its key there.
+// tile's sub-range (LDS counters seeded with the tile's start + M) and writes
+// its key there. Reads R and M only, so it can be repeated with another
+// capacity.
 __global__ __launch_bounds__(kPlaceThreads) void k_bin_place(Raster Rr, BinArgs a) {
   extern __shared__ uint32_t next[];
   const Chunk c = bin_chunk(Rr, a);
   const int64_t view = blockIdx.y;
   const int64_t row = view * Rr.n_tiles + c.t0;
-  for (int i = threadIdx.x; i < c.nt; i += blockDim.x) next[i] = a.S[(row + i) * a.n_wg + blockIdx.x];
-  // the chunk's tile ranges [S[t][0], S[t][n_wg - 1] + M[t][n_wg - 1]) clipped
-  // to the capacity, tiles dealt round-robin over the chunk's workgroups
+  // (entries of tiles the workgroup has no pair on are not used)
+  for (int i = threadIdx.x; i < c.nt; i += blockDim.x) next[i] = (uint32_t)a.R[row + i].x + a.M[(row + i) * a.n_wg + blockIdx.x];
+  // the chunk's tile ranges clipped to the capacity, tiles dealt round-robin
+  // over the chunk's workgroups
   for (int i = (int)blockIdx.x + a.n_wg * (int)threadIdx.x; i < c.nt; i += a.n_wg * (int)blockDim.x) {
-    const int64_t b = (row + i) * a.n_wg;
-    const int64_t s0 = a.S[b], s1 = (int64_t)a.S[b + a.n_wg - 1] + a.M[b + a.n_wg - 1];
-    a.ranges[row + i] = make_int2((int)(s0 < a.cap ? s0 : a.cap), (int)(s1 < a.cap ? s1 : a.cap));
+    const int2 r = a.R[row + i];
+    a.ranges[row + i] = make_int2((int)(r.x < a.cap ? r.x : a.cap), (int)(r.y < a.cap ? r.y : a.cap));
   }
   __syncthreads();
   for (int64_t g = c.g0 + threadIdx.x; g < c.g1; g += blockDim.x) {
@@ -403,7 +460,11 @@ size_t bin_lds(const Raster& R) { return sizeof(uint32_t) * (size_t)min(R.n_tile
 }  // namespace
 
 void launch_bin_count(const Raster& R, const BinArgs& a, hipStream_t s) {
-  if (R.n_tiles <= 0 || a.n_views <= 0) return;
+  if (R.n_tiles <= 0 || a.n_views <= 0) {
+    launch_fill_u32(a.K, 0u, 1, s);
+    if (a.K_host) launch_fill_u32(a.K_host, 0u, 1, s);
+    return;
+  }
   hipLaunchKernelGGL(k_bin_count, bin_grid(R, a), dim3(kPlaceThreads), bin_lds(R), s, R, a);
 }
 
