@@ -92,7 +92,8 @@ def source_hash(names) -> str:
 
 STAGE_SOURCES = {"render_fwd": ["k_raster.hip", "gsr_internal.h"], "render_bwd": ["k_raster.hip", "gsr_internal.h"],
                  "adam": ["k_loss.hip"], "loss_l1": ["k_loss.hip"],
-                 "tile_bins": ["k_sort.hip"], "bin_count": ["k_sort.hip"], "project": ["k_project.hip", "gsr_internal.h"],
+                 "tile_bins": ["k_sort.hip", "gsr_internal.h"], "bin_count": ["k_sort.hip", "gsr_internal.h"],
+                 "project": ["k_project.hip", "gsr_internal.h"], "loss_track": ["k_loss.hip"],
                  "project_bwd": ["k_project.hip", "gsr_internal.h"],
                  "project_bwd_adam": ["k_project.hip", "gsr_internal.h"],
                  "loss_ssim": ["k_loss.hip", "gsr_internal.h"]}
@@ -123,9 +124,13 @@ STAGE_KERNELS = {"render_bwd": ["k_render_bwd_block<false>("], "render_fwd": ["k
                  "bin_count": ["k_bin_count("],
                  "project": ["k_project("], "project_bwd_adam": ["k_project_bwd("],
                  "loss_ssim": ["k_loss_ssim("]}
-PMC_COMMAND = ("cd /tmp && rocprofv3 --pmc {counter} -d <dir> -o run --output-format csv -- python3 bench.py "
-               "--steps 5 --warmup 2 --no-cpu-baseline --no-tracking --no-batched --no-initnet --no-seed "
-               "--calib-copy-mib {mib}")
+PMC_COMMANDS = {
+    "H": ("cd /tmp && rocprofv3 --pmc {counter} -d <dir> -o run --output-format csv -- python3 bench.py "
+          "--steps 5 --warmup 2 --no-cpu-baseline --no-tracking --no-batched --no-initnet --no-seed --no-c2 "
+          "--calib-copy-mib {mib}"),
+    "C3": ("cd /tmp && rocprofv3 --pmc {counter} -d <dir> -o run --output-format csv -- python3 bench.py "
+           "--profile-tracking 5 --calib-copy-mib {mib}"),
+}
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str, calib_mib: int, workload: str = "H") -> None:
@@ -154,7 +159,13 @@ def summarize_pmc(fetch_csv: str, write_csv: str, calib_mib: int, workload: str 
     write, w_copy = load(write_csv, "WRITE_SIZE")
     nbytes = float(calib_mib << 20)
     sf, sw = nbytes / f_copy, nbytes / w_copy
-    for stage, kernels in STAGE_KERNELS.items():
+    kernels_of = STAGE_KERNELS if workload == "H" else TRACK_KERNELS
+    title = ("mapping iteration 1200x680, 500K Gaussians" if workload == "H"
+             else "tracking iteration 640x480, 500K Gaussians")
+    cmd = PMC_COMMANDS[workload]
+    for stage, kernels in kernels_of.items():
+        if stage not in STAGE_SOURCES:
+            continue
         fb = wb = 0.0
         found = True
         for k in kernels:
@@ -170,10 +181,11 @@ def summarize_pmc(fetch_csv: str, write_csv: str, calib_mib: int, workload: str 
         path = os.path.join(ROOT, "profiles", f"{stage}_{workload}_traffic.txt")
         with open(path, "w") as f:
             f.write(f"# HBM traffic per launch of stage {stage} ({', '.join(k.rstrip('(') for k in kernels)}), "
-                    "mapping iteration 1200x680, 500K Gaussians\n")
-            f.write("# made by: " + PMC_COMMAND.format(counter="FETCH_SIZE", mib=calib_mib) + "\n")
-            f.write("#     and: " + PMC_COMMAND.format(counter="WRITE_SIZE", mib=calib_mib) + "\n")
-            f.write(f"#     then: python bench.py --summarize-pmc <fetch csv> <write csv> --calib-copy-mib {calib_mib}\n")
+                    f"{title}\n")
+            f.write("# made by: " + cmd.format(counter="FETCH_SIZE", mib=calib_mib) + "\n")
+            f.write("#     and: " + cmd.format(counter="WRITE_SIZE", mib=calib_mib) + "\n")
+            f.write(f"#     then: python bench.py --summarize-pmc <fetch csv> <write csv> --pmc-workload {workload} "
+                    f"--calib-copy-mib {calib_mib}\n")
             f.write(f"calibration: copy of {calib_mib} MiB read as FETCH {nbytes / sf / 1024:.0f} KiB, "
                     f"WRITE {nbytes / sw / 1024:.0f} KiB; scale {sf:.4f} / {sw:.4f}\n")
             f.write(f"source_sha1: {source_hash(STAGE_SOURCES[stage])}\n")
@@ -194,11 +206,12 @@ VALU_PASSES = [
 N_CU = 256  # MI355X compute units
 # kernels of the tracking iteration, as rocprofv3 names them
 TRACK_KERNELS = {"render_bwd": ["k_render_bwd_quad<false>("], "render_fwd": ["k_render_fwd<false>("],
-                 "project": ["k_project("], "project_bwd": ["k_project_bwd("],
+                 "project": ["k_project("], "project_bwd": ["k_project_bwd("], "bin_count": ["k_bin_count("],
+                 "tile_bins": ["k_bin_place(", "k_tile_sort("],
                  "loss_track": ["k_select_hist(", "k_loss_track("]}
 PROFILE_COMMANDS = {
-    "H": ("python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-full-loss --no-tracking --no-batched "
-          "--no-initnet --no-seed"),
+    "H": ("python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-tracking --no-batched --no-initnet "
+          "--no-seed --no-c2"),
     "C3": "python3 bench.py --profile-tracking 5",
 }
 
@@ -394,7 +407,8 @@ def bench_tracking(seed: int, n: int, frames: int, seeds: int = 3) -> dict:
             flops = FLOPS_EVAL * work["pairs_bwd"] + FLOPS_COMP_BWD6 * work["pairs_composited"]
             ach = flops / (bwd_ms * 1e-3) / 1e12
             roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": "render_bwd (pose only)",
+                    "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": read_traffic("render_bwd", "C3"),
+                    "kernel": "render_bwd (pose only)",
                     "avg_ms": round(bwd_ms, 4)}
         for f in range(frames):
             tg.set_frame(obs[f][0], obs[f][1])
@@ -421,11 +435,19 @@ def bench_tracking(seed: int, n: int, frames: int, seeds: int = 3) -> dict:
             "roofline": roof}
 
 
-def profile_tracking(seed: int, n: int, iters: int) -> int:
+def profile_tracking(seed: int, n: int, iters: int, calib_mib: int = 0) -> int:
     """A few eager tracking iterations of the C3 frame (the graph's kernels,
-    launched one by one), for counter runs."""
+    launched one by one), for counter runs; with calib_mib, also the plain
+    device copy that calibrates the traffic counters."""
     import torch
     from paper_2312_10070_amd import gsr, synth, tracking
+    if calib_mib > 0:
+        a = torch.empty((calib_mib << 20) // 4, device="cuda", dtype=torch.float32).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     inp = synth.tracking_inputs(seed, n)
     cam = gsr.camera_from(inp["camera"])
     g = {k: torch.from_numpy(v).cuda() for k, v in inp["gaussians"].items()}
@@ -681,7 +703,9 @@ def main() -> int:
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/*_traffic.txt from two rocprofv3 --pmc runs and exit")
+                    help="write profiles/*_<WORKLOAD>_traffic.txt from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-workload", choices=("H", "C3"), default="H",
+                    help="workload of --summarize-pmc: H (mapping, 1200x680) or C3 (tracking, 640x480)")
     ap.add_argument("--summarize-trace", nargs=4, metavar=("STATS_CSV", "NAME", "COMMAND", "TITLE"),
                     help="write profiles/NAME.txt from a rocprofv3 kernel_stats.csv and exit")
     ap.add_argument("--summarize-valu", nargs="+", metavar=("WORKLOAD", "CSV"),
@@ -696,7 +720,7 @@ def main() -> int:
         summarize_valu(args.summarize_valu[1:], args.summarize_valu[0])
         return 0
     if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.calib_copy_mib or 256)
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.calib_copy_mib or 256, args.pmc_workload)
         return 0
     if args.gpus != 1:
         print("bench.py: this benchmark runs on one GPU; multi-GPU runs are not part of it "
@@ -707,7 +731,7 @@ def main() -> int:
     from paper_2312_10070_amd import gsr, synth
 
     if args.profile_tracking:
-        return profile_tracking(args.seed, args.gaussians, args.profile_tracking)
+        return profile_tracking(args.seed, args.gaussians, args.profile_tracking, args.calib_copy_mib)
 
     t_gen = time.perf_counter()
     inp = synth.mapping_inputs(args.seed, args.gaussians)
