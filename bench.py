@@ -607,7 +607,7 @@ def bench_initnet(seed: int, n: int, frames: int, train_pairs: int, train_steps:
     t_train = time.perf_counter() - t0
     del x, y
     print(json.dumps({"initnet_trained": {"pairs": train_pairs, "steps": train_steps, "gen_s": round(t_gen, 1),
-                                          "train_s": round(t_train, 1)}}), flush=True)
+                                          "train_s": round(t_train, 1)}}), file=sys.stderr, flush=True)
     budgets = (10, 20, 30, 40, 60, 80, 100)
     rows = []
     for f in range(frames):
@@ -654,7 +654,8 @@ def bench_initnet(seed: int, n: int, frames: int, train_pairs: int, train_steps:
         rows.append(dict(n_plain=n_plain, ms_plain=ms_plain, kept=kept, e_start=e_start, n_learn=n_learn,
                          ms_learn=(ms_prop + ms_learn) if n_learn else None, ms_prop=ms_prop, e_plain=e_plain,
                          e_learn=e_learn))
-        print(json.dumps({"initnet_frame": f, "iterations_plain": n_plain, "iterations_learned": n_learn}), flush=True)
+        print(json.dumps({"initnet_frame": f, "iterations_plain": n_plain, "iterations_learned": n_learn}),
+              file=sys.stderr, flush=True)
     both = [r for r in rows if r["n_plain"] and r["n_learn"]]
     avg = lambda v: round(float(np.mean(v)), 3) if v else None
     ecm = lambda e: [round(100 * e[0], 3), round(e[1], 3)]
