@@ -271,6 +271,25 @@ int gsr_submap_trigger(const float *pose_first7, const float *pose_cur7, float d
 int gsr_seed_query(gsr_ctx *ctx, const float *means, int64_t n, const float *points, int64_t m, float rho,
                    float r_max, float *nn_d2, int32_t *keep);
 
+/* New Gaussians from the seeding step (Sec. 3.2: the sampled points with no
+ * sub-map Gaussian within rho become new Gaussians; supplement: their
+ * opacity starts at 0.5 and their scale at the nearest-neighbour distance in
+ * the active sub-map). For every j with keep[j] != 0, in order, row r of the
+ * outputs receives mean = points[j], colour = colors[j], scale =
+ * sqrt(nn_d2[j]) (correctly rounded FP32) on all three axes, quaternion
+ * (1, 0, 0, 0) and opacity 0.5 (activated values, as everywhere in this
+ * API). points, colors [m,3], nn_d2 [m] float and keep [m] int32 are device
+ * arrays, as gsr_seed_candidates and gsr_seed_query produce them (a kept
+ * point has nn_d2 >= rho^2 > 0); out[0..4] = means [.,3], scales [.,3], quats
+ * [.,4] (16-byte aligned), opacities [.], colors [.,3]: device buffers with
+ * room for m rows, not aliased with the inputs (append new Gaussians by
+ * passing pointers just past a sub-map's last row). *n_new (host) receives the
+ * count. 0 <= m < 2^31 (m = 0: *n_new = 0, the arrays are not read).
+ * Allocates temporary device memory and synchronises the context's stream.
+ * GSR_EINVAL for NULL arrays (m > 0) or a misaligned quaternion output. */
+int gsr_seed_gaussians(gsr_ctx *ctx, int64_t m, const float *points, const float *colors, const float *nn_d2,
+                       const int32_t *keep, float *const *out, int64_t *n_new);
+
 /* Opacity pruning (supplement, mapping: at the middle and the end of a new
  * keyframe's iterations, Gaussians with opacity below o_thre are removed;
  * o_thre = 0.1 on Replica-like data, 0.5 otherwise). Stable compaction:

@@ -314,6 +314,24 @@ def seed_query(means, points, rho: float, r_max: float, chunk: int = 128):
     return nn, (nn >= rho2).astype(np.int32)
 
 
+def seed_gaussians(points, colors, nn_d2, keep) -> dict:
+    """New Gaussians from the seeding step (Sec. 3.2: the sampled points with
+    no sub-map Gaussian within rho are added; supplement: opacity 0.5, scale =
+    the nearest-neighbour distance in the active sub-map). Every kept point j,
+    in order, gives mean = points[j], colour = colors[j], scale = sqrt(nn_d2[j])
+    on all three axes (binary32, the precision of the stored distance),
+    rotation = identity quaternion (1, 0, 0, 0), opacity 0.5."""
+    idx = np.flatnonzero(np.asarray(keep) != 0)
+    d = np.sqrt(np.asarray(nn_d2, np.float32)[idx])
+    k = idx.shape[0]
+    quats = np.zeros((k, 4), np.float32)
+    quats[:, 0] = 1.0
+    return dict(means=np.asarray(points, np.float32).reshape(-1, 3)[idx],
+                scales=np.repeat(d[:, None], 3, axis=1).astype(np.float32),
+                quats=quats, opacities=np.full(k, 0.5, np.float32),
+                colors=np.asarray(colors, np.float32).reshape(-1, 3)[idx])
+
+
 def prune(groups, o_thre: float):
     """Opacity pruning (supplement, mapping): Gaussian i is kept iff its opacity
     >= o_thre (NaN is not), and the kept rows stay in their order. groups: a

@@ -786,6 +786,43 @@ int gsr_seed_query(gsr_ctx* c, const float* means, int64_t n, const float* point
   return GSR_OK;
 }
 
+int gsr_seed_gaussians(gsr_ctx* c, int64_t m, const float* points, const float* colors, const float* nn_d2,
+                       const int32_t* keep, float* const* out, int64_t* n_new) {
+  if (!c) return GSR_EINVAL;
+  if (m < 0 || m > (int64_t)0x7fffffff || !out || !n_new || (m > 0 && (!points || !colors || !nn_d2 || !keep)))
+    return fail(c, GSR_EINVAL, "bad seed_gaussians arguments");
+  if (m == 0) {
+    *n_new = 0;
+    return GSR_OK;
+  }
+  for (int i = 0; i < 5; ++i)
+    if (!out[i]) return fail(c, GSR_EINVAL, "seed_gaussians: all five output arrays are required");
+  if ((reinterpret_cast<uintptr_t>(out[2]) & 15u) != 0)
+    return fail(c, GSR_EINVAL, "seed_gaussians: the quaternion output must be 16-byte aligned");
+  GSR_HIP(c, hipSetDevice(c->device));
+  uint32_t* temp = nullptr;
+  uint32_t* cnt = nullptr;
+  GSR_HIP(c, hipMalloc((void**)&temp, sizeof(uint32_t) * gsr::seed_init_temp_words(m)));
+  if (hipHostMalloc((void**)&cnt, sizeof(uint32_t), hipHostMallocMapped) != hipSuccess) {
+    (void)hipFree(temp);
+    return fail(c, GSR_ENOMEM, "seed_gaussians: pinned count");
+  }
+  uint32_t* cnt_dev = nullptr;
+  hipError_t e = hipHostGetDevicePointer((void**)&cnt_dev, cnt, 0);
+  if (e == hipSuccess) {
+    Stage t(c, "seed_gaussians");
+    const gsr::SeedInit a{m, points, colors, nn_d2, keep, out[0], out[1], out[2], out[3], out[4]};
+    gsr::launch_seed_init(a, temp, cnt_dev, c->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) *n_new = (int64_t)*(volatile uint32_t*)cnt;
+  (void)hipFree(temp);
+  (void)hipHostFree(cnt);
+  if (e != hipSuccess) return fail(c, GSR_EHIP, hipGetErrorString(e));
+  return GSR_OK;
+}
+
 namespace {
 // Shared body of gsr_prune and gsr_compact: stable compaction of the Gaussians
 // kept by mask (if given) or by opacity >= o_thre.

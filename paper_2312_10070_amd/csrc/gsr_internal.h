@@ -202,6 +202,19 @@ int64_t seed_sample_temp_words(int64_t P);
 void launch_seed_sample(const SeedSample& a, float* points, float* colors, uint32_t* temp, uint32_t* count_host,
                         hipStream_t s);
 
+// New Gaussians from the kept seeding points (k_seed.hip): rows 0..n_new-1 of
+// the outputs, in point order; count_host (pinned, device-visible) receives
+// n_new. temp: seed_init_temp_words(m) uint32.
+struct SeedInit {
+  int64_t m;
+  const float* points;   // [m,3]
+  const float* pcolors;  // [m,3]
+  const float* nn_d2;    // [m]
+  const int32_t* keep;   // [m]
+  float *means, *scales, *quats, *opacities, *colors;
+};
+int64_t seed_init_temp_words(int64_t m);
+void launch_seed_init(const SeedInit& a, uint32_t* temp, uint32_t* count_host, hipStream_t s);
 // Seeding neighbour queries (k_seed.hip): nn_d2[j] = min(r_max^2, min_i |q_j - p_i|^2),
 // keep[j] = nn_d2[j] >= rho^2 (either output may be NULL); rho <= r_max.
 // temp: seed_temp_words(n) uint32, 16-byte aligned.

@@ -137,7 +137,62 @@ __global__ __launch_bounds__(256) void k_seed_emit(SeedSample a, const uint32_t*
   colors[3 * j + 2] = a.color[2 * P + i];
 }
 
+__global__ __launch_bounds__(256) void k_seed_keep_flag(const int32_t* __restrict__ keep, int64_t m,
+                                                       uint32_t* __restrict__ flag) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) flag[j] = keep[j] != 0 ? 1u : 0u;
+}
+
+// Correctly rounded FP32 square root of x: the hardware estimate, then moved
+// to the neighbour whose rounding interval holds sqrt(x). The tests are exact
+// in FP64 (a midpoint between adjacent floats has 25 significant bits, its
+// square at most 50), and sqrt(x) never lies on a midpoint.
+__device__ __forceinline__ float sqrt_rn(float x) {
+  float s = sqrtf(x);
+  if (!(x > 0.f) || !(s < INFINITY)) return s;
+  const double dx = (double)x;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const float up = __uint_as_float(__float_as_uint(s) + 1u), dn = __uint_as_float(__float_as_uint(s) - 1u);
+    const double mhi = 0.5 * ((double)s + (double)up), mlo = 0.5 * ((double)s + (double)dn);
+    if (mhi * mhi < dx) s = up;
+    else if (mlo * mlo > dx) s = dn;
+  }
+  return s;
+}
+
+// New Gaussian at row off[j] for every kept point j: mean = the point, colour
+// = its pixel colour, scale = the nearest-neighbour distance on all three axes
+// (correctly rounded square root of nn_d2), identity rotation, opacity 0.5.
+__global__ __launch_bounds__(256) void k_seed_init(SeedInit a, const uint32_t* __restrict__ flag,
+                                                 const uint32_t* __restrict__ off) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.m || !flag[j]) return;
+  const int64_t r = off[j];
+  const float s = sqrt_rn(a.nn_d2[j]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a.means[3 * r + k] = a.points[3 * j + k];
+    a.scales[3 * r + k] = s;
+    a.colors[3 * r + k] = a.pcolors[3 * j + k];
+  }
+  reinterpret_cast<float4*>(a.quats)[r] = make_float4(1.f, 0.f, 0.f, 0.f);
+  a.opacities[r] = 0.5f;
+}
+
 }  // namespace
+
+int64_t seed_init_temp_words(int64_t m) { return 2 * m + 1 + scan_temp_words(m); }
+
+void launch_seed_init(const SeedInit& a, uint32_t* temp, uint32_t* count_host, hipStream_t s) {
+  uint32_t* flag = temp;
+  uint32_t* off = temp + a.m;
+  uint32_t* total = temp + 2 * a.m;
+  const unsigned g = (unsigned)((a.m + 255) / 256);
+  if (a.m > 0) hipLaunchKernelGGL(k_seed_keep_flag, dim3(g), dim3(256), 0, s, a.keep, a.m, flag);
+  launch_exclusive_scan(flag, off, a.m, total, total + 1, s, count_host);
+  if (a.m > 0) hipLaunchKernelGGL(k_seed_init, dim3(g), dim3(256), 0, s, a, flag, off);
+}
 
 int64_t seed_sample_temp_words(int64_t P) { return 2 * P + 1 + scan_temp_words(P); }
 

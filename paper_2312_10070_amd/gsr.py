@@ -90,6 +90,7 @@ _SIGS = {
                                            ctypes.c_float, ctypes.c_float, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_seed_query": (ctypes.c_int, [P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_float, ctypes.c_float, P, P]),
     "gsr_compact": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_int64)]),
+    "gsr_seed_gaussians": (ctypes.c_int, [P, ctypes.c_int64, P, P, P, P, P, ctypes.POINTER(ctypes.c_int64)]),
     "gsr_submap_offload": (ctypes.c_int, [P, ctypes.c_int64, P, P]),
     "gsr_submap_restore": (ctypes.c_int, [P, ctypes.c_int64, P, P]),
     "gsr_submap_trigger": (ctypes.c_int, [P, P, ctypes.c_float, ctypes.c_float, ctypes.POINTER(ctypes.c_int32)]),
@@ -449,6 +450,25 @@ def seed_query(means, points, rho: float, r_max: float, ctx: Context | None = No
     ctx.check(ctx.lib.gsr_seed_query(ctx.h, _ptr(means), int(means.shape[0]), _ptr(points), m, float(rho),
                                      float(r_max), _ptr(nn), _ptr(keep)))
     return nn, keep
+
+
+def seed_gaussians(points, colors, nn_d2, keep, ctx: Context | None = None) -> dict:
+    """New Gaussians from the kept seeding points (see gsr_seed_gaussians):
+    {means, scales, quats, opacities, colors} with one row per kept point."""
+    ctx = ctx or Context.get(points.device.index or 0)
+    ctx.sync_stream()
+    m = points.shape[0]
+    _f32(points, "points", (m, 3)); _f32(colors, "colors", (m, 3)); _f32(nn_d2, "nn_d2", (m,))
+    if keep.dtype != torch.int32 or keep.shape != (m,) or not keep.is_contiguous():
+        raise ValueError("keep must be a contiguous int32 [m] tensor")
+    dev = points.device
+    out = {k: torch.empty((m,) + sh, device=dev, dtype=torch.float32)
+           for k, sh in (("means", (3,)), ("scales", (3,)), ("quats", (4,)), ("opacities", ()), ("colors", (3,)))}
+    arr = (P * 5)(*[P(out[k].data_ptr()) for k in ("means", "scales", "quats", "opacities", "colors")])
+    n_new = ctypes.c_int64()
+    ctx.check(ctx.lib.gsr_seed_gaussians(ctx.h, m, _ptr(points), _ptr(colors), _ptr(nn_d2), _ptr(keep), arr,
+                                         ctypes.byref(n_new)))
+    return {k: v[:n_new.value] for k, v in out.items()}
 
 
 def _compact_call(params, exp_avg, exp_avg_sq, call):

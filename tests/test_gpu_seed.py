@@ -103,3 +103,46 @@ def test_seed_candidates_match_oracle(W, Hh, first):
     np.testing.assert_allclose(got.reshape(-1, 3), P_ref.reshape(-1, 3), rtol=0, atol=2e-6 * (1 + scale))
     if W * Hh > 1000:
         assert 0 < len(P_ref) < W * Hh
+
+
+@pytest.mark.parametrize("m,frac", [(5003, 0.3), (0, 0.0), (777, 1.0), (64, 0.0), (200000, 0.05)])
+def test_seed_gaussians_match_oracle(m, frac):
+    """New Gaussians (opacity 0.5, scale = the nearest-neighbour distance,
+    identity rotation) from synthetic seeding outputs: bit-exact, including
+    the correctly rounded square root."""
+    torch = torch_()
+    rng = np.random.default_rng(m + 3)
+    pts = rng.uniform(-2, 2, (m, 3)).astype(np.float32)
+    col = rng.uniform(0, 1, (m, 3)).astype(np.float32)
+    nn = rng.uniform(1e-4, 2.5e-3, m).astype(np.float32)
+    nn[: m // 7] = np.float32(0.05) * np.float32(0.05)  # no neighbour within r_max
+    keep = (rng.uniform(size=m) < frac).astype(np.int32)
+    ref = oracle.seed_gaussians(pts, col, nn, keep)
+    got = gsr.seed_gaussians(dev(pts), dev(col), dev(nn), torch.from_numpy(keep).cuda())
+    torch.cuda.synchronize()
+    for k in ("means", "scales", "quats", "opacities", "colors"):
+        np.testing.assert_array_equal(got[k].cpu().numpy(), ref[k], err_msg=k)
+
+
+def test_seed_pipeline_adds_gaussians_where_the_submap_is_empty():
+    """Candidates -> neighbour queries -> new Gaussians, each call checked
+    against the oracle on the same inputs; the new Gaussians sit only where
+    the sub-map had none within rho."""
+    torch = torch_()
+    rng = np.random.default_rng(21)
+    sub = rng.uniform(-0.5, 0.5, (4000, 3)).astype(np.float32)
+    pts = np.concatenate([sub[:1500] + rng.normal(0, 0.002, (1500, 3)),
+                          rng.uniform(-0.6, 0.6, (1500, 3))]).astype(np.float32)
+    col = rng.uniform(0, 1, (3000, 3)).astype(np.float32)
+    rho, r_max = 0.01, 0.05
+    nn, keep = gsr.seed_query(dev(sub), dev(pts), rho, r_max)
+    nn_ref, keep_ref = oracle.seed_query(sub, pts, rho, r_max)
+    np.testing.assert_array_equal(nn.cpu().numpy(), nn_ref)
+    np.testing.assert_array_equal(keep.cpu().numpy(), keep_ref)
+    g = gsr.seed_gaussians(dev(pts), dev(col), nn, keep)
+    ref = oracle.seed_gaussians(pts, col, nn_ref, keep_ref)
+    for k in ref:
+        np.testing.assert_array_equal(g[k].cpu().numpy(), ref[k], err_msg=k)
+    # every new mean is at least rho from every sub-map mean
+    d2, _ = oracle.seed_query(sub, ref["means"], rho, r_max)
+    assert (d2 >= np.float32(rho) * np.float32(rho)).all()

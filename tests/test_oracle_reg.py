@@ -95,6 +95,34 @@ def test_seed_query_matches_kdtree():
     np.testing.assert_array_equal(nn2, nn)
 
 
+def test_seed_gaussians_definition():
+    # supplement: a new Gaussian's opacity starts at 0.5 and its scale at the
+    # nearest-neighbour distance in the active sub-map (checked against a k-d
+    # tree, independent of the oracle's own distance computation); Sec. 3.2:
+    # only the points with no neighbour within rho are added, in their order
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(11)
+    p = rng.uniform(-1, 1, (2000, 3)).astype(np.float32)
+    q = np.concatenate([p[:300] + rng.normal(0, 0.004, (300, 3)), rng.uniform(-1.1, 1.1, (700, 3))]).astype(np.float32)
+    col = rng.uniform(0, 1, (1000, 3)).astype(np.float32)
+    rho, r_max = 0.01, 0.05
+    nn, keep = oracle.seed_query(p, q, rho, r_max)
+    g = oracle.seed_gaussians(q, col, nn, keep)
+    d, _ = cKDTree(p.astype(np.float64)).query(q.astype(np.float64))
+    sel = np.flatnonzero(keep)
+    assert len(sel) == g["means"].shape[0] and 0 < len(sel) < 1000
+    clear = np.abs(d - rho) > 1e-6
+    np.testing.assert_array_equal(keep[clear], (d[clear] >= rho).astype(np.int32))
+    np.testing.assert_allclose(g["scales"], np.repeat(np.minimum(d[sel], r_max)[:, None], 3, 1), rtol=1e-6)
+    assert (g["scales"] >= np.float32(rho) * (1 - 1e-6)).all()
+    np.testing.assert_array_equal(g["opacities"], np.full(len(sel), 0.5, np.float32))
+    np.testing.assert_array_equal(g["quats"], np.tile(np.array([1, 0, 0, 0], np.float32), (len(sel), 1)))
+    np.testing.assert_array_equal(g["means"], q[sel])
+    np.testing.assert_array_equal(g["colors"], col[sel])
+    empty = oracle.seed_gaussians(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0, np.int32))
+    assert all(v.shape[0] == 0 for v in empty.values())
+
+
 def test_seed_candidates_definition():
     from scipy.spatial.transform import Rotation
     cam = oracle.Camera(4, 3, 2.0, 2.5, 1.5, 1.0)
