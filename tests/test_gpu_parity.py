@@ -140,6 +140,40 @@ def test_posed_ragged_forward_backward_and_tiles():
         H.check_grad_ref(k, gp, ref, case=case + " six-field")
 
 
+def test_frame_with_more_tiles_than_one_binning_chunk():
+    """2100 x 2100 = 132 x 132 = 17424 tiles, more than one counting / placing
+    workgroup's LDS tile chunk (16384): binning runs with two tile chunks per
+    workgroup column. Tile lists against the oracle, sampled pixels of the
+    forward and a second forward on the same state (the range scan's tile
+    totals and ticket must have returned to zero)."""
+    rng = np.random.default_rng(8)
+    n = 4000
+    g = dict(means=np.stack([rng.uniform(-1.3, 1.3, n), rng.uniform(-1.3, 1.3, n), rng.uniform(1.5, 4, n)], 1),
+             scales=np.exp(rng.normal(-3.5, 0.5, (n, 3))), quats=rng.normal(size=(n, 4)),
+             opacities=1 / (1 + np.exp(-rng.normal(0, 1, n))), colors=rng.uniform(0, 1, (n, 3)))
+    g["scales"][:3] = 0.8  # a few Gaussians spanning both chunks
+    cam = oracle.Camera(2100, 2100, 1500.0, 1500.0, 1050.3, 1049.7, 0.2, (0.1, 0.2, 0.3))
+    pose = np.array([0.999, 0.02, -0.03, 0.01, 0.02, -0.01, 0.1])
+    pose[:4] /= np.linalg.norm(pose[:4])
+    pose = pose.astype(np.float32).astype(np.float64)
+    g = G.certify(g, pose, cam, 2e-4)
+    tl = oracle.tile_lists(g, pose, cam, oracle.Opts())
+    assert tl["ranges"].shape[0] == 17424
+    rec = oracle.project(g, pose, cam, oracle.Opts())
+    pixels = np.sort(rng.choice(cam.width * cam.height, 3000, replace=False))
+    orc = oracle.render(g, pose, cam, oracle.Opts(amb_rel=1e-4), pixels=pixels, nthreads=8)
+    yy, xx = pixels // cam.width, pixels % cam.width
+    sub_o = {k: (v[:, yy, xx] if v.ndim == 3 else v[yy, xx]) for k, v in orc.items() if k != "hash"}
+    for rep in range(2):
+        out, st, _, _ = run_fwd(g, pose, cam)
+        K, ranges, ids = gsr.tile_lists(st, tl["ranges"].shape[0])
+        assert K == tl["K"]
+        G.compare_tile_lists(ranges.cpu().numpy(), ids.cpu().numpy(), tl, rec["z_cam"], strict=False)
+        sub_g = {k: (v[:, yy, xx] if v.ndim == 3 else v[yy, xx]) for k, v in out.items()}
+        G.compare_images(sub_g, sub_o, TOL)
+        st.release()
+
+
 def test_empty_and_fully_culled_inputs_render_background():
     cam = oracle.Camera(40, 30, 30.0, 30.0, 20.0, 15.0, 0.2, (0.3, 0.6, 0.9))
     pose = np.array([1, 0, 0, 0, 0, 0, 0], np.float64)
