@@ -282,20 +282,11 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
       // (list position + 1) * 16 of slot 0: last16 = code + byte offset
       const int code = 16 * (base - start + 1);
       __builtin_amdgcn_wave_barrier();
-      // the next entry is read one step ahead (entry kListCap + 1 exists, so
-      // the read stays inside the row's list)
-      int jn = mylist[0];
-      // walk while some lane is compositing and its row's list has not ended
-      for (int t = 0; t < maxl && (__ballot(T > 0.f) & __ballot(t < myl)) != 0; ++t) {
-        const bool pend = t < myl;
-        const int jb = pend ? jn : 16 * kDummy;
-        jn = mylist[t + 1];
-        // Every lane runs the same instructions. A skipped pair (alpha <
-        // alpha_min, or the all-zero record) acts as alpha = 0; a stopped lane
-        // has T < 0, so its Tn < T_min and it adds w = 0 and keeps T.
-        const float4 g = lds_at(sm.uvab, jb);
-        const float4 cb = lds_at(sm.cob, jb);
-        const float4 cz = lds_at(sm.rgbz, jb);
+      // One step per record of the row's list. Every lane runs the same
+      // instructions: a skipped pair (alpha < alpha_min, or the all-zero
+      // record) acts as alpha = 0; a stopped lane has T < 0, so its Tn <
+      // T_min and it adds w = 0 and keeps T.
+      auto step = [&](const float4& g, const float4& cb, const float4& cz, int jb) {
         const PairEval pe = eval_pair(q.fpx - g.x, q.fpy - g.y, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
         if (STATS && T > 0.f && jb != 16 * kDummy && box_holds(cb.z, cb.w, q.px, q.py)) ++n_eval;
         const float al = pe.use ? pe.alpha : 0.f;
@@ -309,7 +300,32 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
         last16 = (comp && pe.use) ? code + jb : last16;
         if (STATS && comp && pe.use) ++n_comp;
         T = comp ? Tn : -fabsf(T);
-        asm volatile("" : "+v"(jn));  // keep the read of the next entry in this step
+      };
+      // walk while some lane is compositing and its row's list has not ended
+      auto going = [&](int t) { return t < maxl && (__ballot(T > 0.f) & __ballot(t < myl)) != 0; };
+      // Software pipeline, unrolled by two so that no record is copied
+      // between registers: while step t runs on one record set, the other
+      // set receives the record of step t + 1 from LDS, and the list entry of
+      // step t + 2 is read (entries up to kListCap + 1 exist, so the reads
+      // stay inside the row's list; entries past its end are not used).
+      int jA = 0 < myl ? mylist[0] : 16 * kDummy;
+      int jn = mylist[1];
+      float4 gA = lds_at(sm.uvab, jA), cbA = lds_at(sm.cob, jA), czA = lds_at(sm.rgbz, jA);
+      for (int t = 0;;) {
+        if (!going(t)) break;
+        const int jB = t + 1 < myl ? jn : 16 * kDummy;
+        jn = mylist[t + 2];
+        const float4 gB = lds_at(sm.uvab, jB), cbB = lds_at(sm.cob, jB), czB = lds_at(sm.rgbz, jB);
+        step(gA, cbA, czA, jA);
+        ++t;
+        if (!going(t)) break;
+        jA = t + 1 < myl ? jn : 16 * kDummy;
+        jn = mylist[t + 2];
+        gA = lds_at(sm.uvab, jA);
+        cbA = lds_at(sm.cob, jA);
+        czA = lds_at(sm.rgbz, jA);
+        step(gB, cbB, czB, jB);
+        ++t;
       }
       __builtin_amdgcn_wave_barrier();
     }
@@ -518,19 +534,15 @@ __device__ __forceinline__ void bwd_item_block(const Raster& Rr, const BwdArgs& 
       }
       uint64_t m = __ballot(meets);
       const int cbase = __builtin_amdgcn_readfirstlane(c * kWave);  // keep the index arithmetic scalar
-      while (m) {
-        const int bit = 63 - __builtin_clzll(m);
-        m &= ~(1ull << bit);
-        const int li = cbase + bit;
+      // one visit: the record at slot li (its three float4s already in registers)
+      auto visit = [&](const float4& g, const float4& cb, const float4& cz, int li) {
         const int pos = bstart + li - start;
-        const float4 g = sm.uvab[li];
-        const float4 cb = sm.cob[li];
         const float dx = q.fpx - g.x, dy = q.fpy - g.y;
         const PairEval pe = eval_pair(dx, dy, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
         const bool hit = pos < b.last && pe.use;
-        if (!__any(hit)) continue;
+        if (!__any(hit)) return;
         float v[10];
-        bwd_pair(b, pe, hit, dx, dy, sm.rgbz[li], v);
+        bwd_pair(b, pe, hit, dx, dy, cz, v);
         int f;
         const float u = wave_reduce10(v, lane, &f);
         if (DET) {
@@ -540,6 +552,40 @@ __device__ __forceinline__ void bwd_item_block(const Raster& Rr, const BwdArgs& 
         } else if (f >= 0) {
           atomicAdd(a.g2d + 10 * (int64_t)sm.gid[li] + f, u);
         }
+      };
+      // the highest remaining record of the mask (removed from it)
+      auto take = [&]() {
+        const int bit = 63 - __builtin_clzll(m);
+        m &= ~(1ull << bit);
+        return cbase + bit;
+      };
+      // Software pipeline, unrolled by two: the next visit's record is read
+      // from LDS while the current one is evaluated, into the other register
+      // set, so no record is copied between registers.
+      if (m == 0) continue;
+      int lA = take();
+      float4 gA = sm.uvab[lA], cbA = sm.cob[lA], czA = sm.rgbz[lA];
+      for (;;) {
+        const bool moreB = m != 0;
+        int lB = 0;
+        float4 gB, cbB, czB;
+        if (moreB) {
+          lB = take();
+          gB = sm.uvab[lB];
+          cbB = sm.cob[lB];
+          czB = sm.rgbz[lB];
+        }
+        visit(gA, cbA, czA, lA);
+        if (!moreB) break;
+        const bool moreA = m != 0;
+        if (moreA) {
+          lA = take();
+          gA = sm.uvab[lA];
+          cbA = sm.cob[lA];
+          czA = sm.rgbz[lA];
+        }
+        visit(gB, cbB, czB, lB);
+        if (!moreA) break;
       }
     }
   }
@@ -630,17 +676,8 @@ __device__ __forceinline__ void bwd_item_quad(const Raster& Rr, const BwdArgs& a
       const int myl = q.quad == 0 ? len0 : (q.quad == 1 ? len1 : (q.quad == 2 ? len2 : len3));
       const int maxl = __builtin_amdgcn_readfirstlane(max(max(len0, len1), max(len2, len3)));
       __builtin_amdgcn_wave_barrier();
-      // the record of step t + 1 is read from LDS during step t, and the list
-      // entry of step t + 2 with it (entries up to kListCap + 1 exist, so the
-      // reads stay inside the row's list; entries past its end are ignored)
-      int jb = 0 < myl ? mylist[0] : 16 * kDummy;
-      int jn = mylist[1];
-      float4 g = lds_at(sm.uvab, jb), cb = lds_at(sm.cob, jb), cz = lds_at(sm.rgbz, jb);
-      for (int t = 0; t < maxl; ++t) {
-        const bool pend = t < myl;
-        const int jb1 = t + 1 < myl ? jn : 16 * kDummy;
-        jn = mylist[t + 2];
-        const float4 g1 = lds_at(sm.uvab, jb1), cb1 = lds_at(sm.cob, jb1), cz1 = lds_at(sm.rgbz, jb1);
+      // one step per record of the row's list (pend: the row's list has not ended)
+      auto step = [&](const float4& g, const float4& cb, const float4& cz, int jb, bool pend) {
         const float dx = q.fpx - g.x, dy = q.fpy - g.y;
         const PairEval pe = eval_pair(dx, dy, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
         const bool hit = boff + (jb >> 4) < b.last && pe.use;  // the all-zero record never passes `use`
@@ -658,10 +695,30 @@ __device__ __forceinline__ void bwd_item_quad(const Raster& Rr, const BwdArgs& a
             atomicAdd(sm.acc + NF * (jb >> 4) + f, u);
           }
         }
-        jb = jb1;
-        g = g1;
-        cb = cb1;
-        cz = cz1;
+      };
+      // Software pipeline, unrolled by two so that no record is copied
+      // between registers: while step t runs on one record set, the other
+      // set receives the record of step t + 1 from LDS, and the list entry of
+      // step t + 2 is read (entries up to kListCap + 1 exist, so the reads
+      // stay inside the row's list; entries past its end are not used).
+      int jA = 0 < myl ? mylist[0] : 16 * kDummy;
+      int jn = mylist[1];
+      float4 gA = lds_at(sm.uvab, jA), cbA = lds_at(sm.cob, jA), czA = lds_at(sm.rgbz, jA);
+      for (int t = 0;;) {
+        if (t >= maxl) break;
+        const int jB = t + 1 < myl ? jn : 16 * kDummy;
+        jn = mylist[t + 2];
+        const float4 gB = lds_at(sm.uvab, jB), cbB = lds_at(sm.cob, jB), czB = lds_at(sm.rgbz, jB);
+        step(gA, cbA, czA, jA, t < myl);
+        ++t;
+        if (t >= maxl) break;
+        jA = t + 1 < myl ? jn : 16 * kDummy;
+        jn = mylist[t + 2];
+        gA = lds_at(sm.uvab, jA);
+        cbA = lds_at(sm.cob, jA);
+        czA = lds_at(sm.rgbz, jA);
+        step(gB, cbB, czB, jB, t < myl);
+        ++t;
       }
       __builtin_amdgcn_wave_barrier();
     }
