@@ -340,7 +340,9 @@ __device__ __forceinline__ void adam_range(const AdamFused& A, int grp, int64_t 
 // One thread per Gaussian, looping over the views: parameter gradients are the
 // sum over views; pose partials are reduced per view (workgroup sum + one
 // atomic per value).
-__global__ __launch_bounds__(256) void k_project_bwd(Raster Rr, ProjectBwdArgs a) {
+// At most 128 VGPRs (four waves per SIMD; one register spills): the kernel is
+// bound by memory latency, so resident waves matter more than the spill.
+__global__ __launch_bounds__(256, 4) void k_project_bwd(Raster Rr, ProjectBwdArgs a) {
   __shared__ float red[4][12];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
