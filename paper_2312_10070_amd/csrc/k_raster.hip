@@ -182,7 +182,7 @@ struct FwdSmem {
   float4 uvab[kBatch + 1];
   float4 cob[kBatch + 1];
   float4 rgbz[kBatch + 1];
-  uint16_t list[kWavesPerTile][4][kListCap + 2];
+  uint16_t list[kWavesPerTile][4][kListCap + 4];
 };
 
 // Backward, block walk: the batch's records and their Gaussian ids.
@@ -306,8 +306,11 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
       // Software pipeline, unrolled by two so that no record is copied
       // between registers: while step t runs on one record set, the other
       // set receives the record of step t + 1 from LDS, and the list entry of
-      // step t + 2 is read (entries up to kListCap + 1 exist, so the reads
-      // stay inside the row's list; entries past its end are not used).
+      // step t + 2 is read (entries past the row's list end are not used).
+      // The walk condition is checked before every second step only: a step
+      // after it turned false is a no-op (every lane has stopped, or every
+      // row reads the all-zero record), and entries up to kListCap + 2 exist
+      // for its reads.
       int jA = 0 < myl ? mylist[0] : 16 * kDummy;
       int jn = mylist[1];
       float4 gA = lds_at(sm.uvab, jA), cbA = lds_at(sm.cob, jA), czA = lds_at(sm.rgbz, jA);
@@ -318,7 +321,6 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
         const float4 gB = lds_at(sm.uvab, jB), cbB = lds_at(sm.cob, jB), czB = lds_at(sm.rgbz, jB);
         step(gA, cbA, czA, jA);
         ++t;
-        if (!going(t)) break;
         jA = t + 1 < myl ? jn : 16 * kDummy;
         jn = mylist[t + 2];
         gA = lds_at(sm.uvab, jA);
