@@ -683,19 +683,19 @@ __device__ __forceinline__ void bwd_item_quad(const Raster& Rr, const BwdArgs& a
         const float dx = q.fpx - g.x, dy = q.fpy - g.y;
         const PairEval pe = eval_pair(dx, dy, g.z, g.w, cb.x, cb.y, Rr.amin, Rr.amax);
         const bool hit = boff + (jb >> 4) < b.last && pe.use;  // the all-zero record never passes `use`
-        if (__ballot(hit) != 0) {
-          float v[10];
-          bwd_pair(b, pe, hit, dx, dy, cz, v);
-          int f;
-          const float u = row_reduce6(v, lane, &f);
-          if (DET) {
+        float v[10];
+        bwd_pair(b, pe, hit, dx, dy, cz, v);
+        int f;
+        const float u = row_reduce6(v, lane, &f);
+        if (DET) {
+          if (__ballot(hit) != 0) {
             const int64_t slot = bstart + (jb >> 4);  // position in the ids array
             const int quad = 4 * w + q.quad;          // quadrant of the tile
             if (pend && f >= 0) a.part[(slot * 16 + quad) * NF + f] = u;
             if (pend && (lane & 15) == 0) atomicOr(a.mask + slot, 1u << quad);
-          } else if (pend && f >= 0) {
-            atomicAdd(sm.acc + NF * (jb >> 4) + f, u);
           }
+        } else if (pend && f >= 0) {
+          atomicAdd(sm.acc + NF * (jb >> 4) + f, u);
         }
       };
       // Software pipeline, unrolled by two so that no record is copied
