@@ -28,6 +28,26 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;  // 2048
 
 
+// Gaussians whose rectangles a binning thread loads together (the loads are
+// in flight at once instead of one round trip per Gaussian).
+constexpr int kRectBatch = 4;
+
+// rect of Gaussians g0 + j blockDim.x (j < kRectBatch) of view `view`, zero
+// past g1; every load is issued before any value is used.
+__device__ __forceinline__ void load_rects(const BinArgs& a, int64_t view, int64_t g0, int64_t g1, int4 (&r)[kRectBatch]) {
+  // (indices past g1 load Gaussian g1 - 1 >= g0 and are then zeroed: no branch between the loads)
+#pragma unroll
+  for (int j = 0; j < kRectBatch; ++j) {
+    const int64_t g = g0 + (int64_t)j * blockDim.x;
+    r[j] = a.rect[view * a.n + (g < g1 ? g : g1 - 1)];
+  }
+#pragma unroll
+  for (int j = 0; j < kRectBatch; ++j) {
+    asm volatile("" : "+v"(r[j].x), "+v"(r[j].y), "+v"(r[j].z), "+v"(r[j].w));
+    if (g0 + (int64_t)j * blockDim.x >= g1) r[j] = make_int4(0, 0, 0, 0);
+  }
+}
+
 // Exclusive scan of v over a workgroup of T threads; *total = the sum.
 template <int T>
 __device__ __forceinline__ uint32_t block_exclusive_scan_t(uint32_t v, uint32_t* total, uint32_t* s_wave) {
@@ -182,16 +202,20 @@ __global__ __launch_bounds__(kPlaceThreads) void k_bin_count(Raster Rr, BinArgs 
   const int64_t view = blockIdx.y;
   for (int i = threadIdx.x; i < c.nt; i += blockDim.x) hist[i] = 0;
   __syncthreads();
-  for (int64_t g = c.g0 + threadIdx.x; g < c.g1; g += blockDim.x) {
-    const int64_t o = view * a.n + g;
-    const int4 r = a.rect[o];
-    if (r.w == 0) continue;
-    const int tx0 = r.x & 0xffff, tx1 = (int)((uint32_t)r.x >> 16), ty0 = r.y & 0xffff, ty1 = (int)((uint32_t)r.y >> 16);
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        const int t = ty * Rr.ntx + tx - c.t0;
-        if ((unsigned)t < (unsigned)c.nt) atomicAdd(&hist[t], 1u);
-      }
+  for (int64_t g0 = c.g0 + threadIdx.x; g0 < c.g1; g0 += (int64_t)kRectBatch * blockDim.x) {
+    int4 rr[kRectBatch];
+    load_rects(a, view, g0, c.g1, rr);
+#pragma unroll
+    for (int j = 0; j < kRectBatch; ++j) {
+      const int4 r = rr[j];
+      if (r.w == 0) continue;
+      const int tx0 = r.x & 0xffff, tx1 = (int)((uint32_t)r.x >> 16), ty0 = r.y & 0xffff, ty1 = (int)((uint32_t)r.y >> 16);
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+          const int t = ty * Rr.ntx + tx - c.t0;
+          if ((unsigned)t < (unsigned)c.nt) atomicAdd(&hist[t], 1u);
+        }
+    }
   }
   __syncthreads();
   const int64_t row = view * Rr.n_tiles + c.t0;
@@ -233,23 +257,28 @@ __global__ __launch_bounds__(kPlaceThreads) void k_bin_place(Raster Rr, BinArgs 
     a.ranges[row + i] = make_int2((int)(r.x < a.cap ? r.x : a.cap), (int)(r.y < a.cap ? r.y : a.cap));
   }
   __syncthreads();
-  for (int64_t g = c.g0 + threadIdx.x; g < c.g1; g += blockDim.x) {
-    const int64_t o = view * a.n + g;
-    const int4 r = a.rect[o];
-    if (r.w == 0) continue;
-    const uint64_t key = ((uint64_t)(uint32_t)r.z << 32) | (uint64_t)(uint32_t)o;
-    const int tx0 = r.x & 0xffff, tx1 = (int)((uint32_t)r.x >> 16), ty0 = r.y & 0xffff, ty1 = (int)((uint32_t)r.y >> 16);
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        const int t = ty * Rr.ntx + tx - c.t0;
-        if ((unsigned)t >= (unsigned)c.nt) continue;
-        const uint32_t pos = atomicAdd(&next[t], 1u);
-        if ((int64_t)pos < a.cap) {
-          a.keys[pos] = key;
-        } else {
-          atomicOr(a.overflow, 1);
+  for (int64_t g0 = c.g0 + threadIdx.x; g0 < c.g1; g0 += (int64_t)kRectBatch * blockDim.x) {
+    int4 rr[kRectBatch];
+    load_rects(a, view, g0, c.g1, rr);
+#pragma unroll
+    for (int j = 0; j < kRectBatch; ++j) {
+      const int4 r = rr[j];
+      if (r.w == 0) continue;
+      const int64_t o = view * a.n + g0 + (int64_t)j * blockDim.x;
+      const uint64_t key = ((uint64_t)(uint32_t)r.z << 32) | (uint64_t)(uint32_t)o;
+      const int tx0 = r.x & 0xffff, tx1 = (int)((uint32_t)r.x >> 16), ty0 = r.y & 0xffff, ty1 = (int)((uint32_t)r.y >> 16);
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+          const int t = ty * Rr.ntx + tx - c.t0;
+          if ((unsigned)t >= (unsigned)c.nt) continue;
+          const uint32_t pos = atomicAdd(&next[t], 1u);
+          if ((int64_t)pos < a.cap) {
+            a.keys[pos] = key;
+          } else {
+            atomicOr(a.overflow, 1);
+          }
         }
-      }
+    }
   }
 }
 
