@@ -347,6 +347,41 @@ __device__ void merge_runs(const uint64_t* a, int na, const uint64_t* b, int nb,
 // Keys a single wave sorts in registers (up to 32 per lane).
 constexpr int kWaveSort = 2048;
 
+// The value of lane (lane ^ m) for m in {1, 2, 4, 8, 16, 32}, without LDS:
+// DPP quad_perm for 1 and 2, row_half_mirror then quad_perm [3,2,1,0] for 4
+// ((i ^ 7) ^ 3 = i ^ 4), row_ror:8 for 8 (a rotation by 8 of a 16-lane row is
+// i ^ 8), and v_permlane16_swap / v_permlane32_swap of the value with itself
+// for 16 and 32 (the swap leaves the partner row's or half's values in one
+// of its two results, picked by the lane's row or half).
+__device__ __forceinline__ uint32_t lane_xor32(uint32_t v, int m) {
+  const int lane = threadIdx.x & 63;
+  switch (m) {
+    case 1:
+      return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);
+    case 2:
+      return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);
+    case 4: {
+      const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false);
+      return (uint32_t)__builtin_amdgcn_update_dpp(0, t, 0x1B, 0xf, 0xf, false);
+    }
+    case 8:
+      return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);
+    case 16: {
+      const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+      return ((lane >> 4) & 1) ? p[0] : p[1];
+    }
+    default: {
+      const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+      return (lane & 32) ? p[0] : p[1];
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t v, int m) {
+  const uint32_t lo = lane_xor32((uint32_t)v, m), hi = lane_xor32((uint32_t)(v >> 32), m);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Sorts keys[b, b + len) (0 < len <= 64 E) with one wave: lane l holds
 // elements E l .. E l + E - 1 in registers; a bitonic network whose strides
 // below E are compare-exchanges inside a lane and whose larger strides
@@ -371,7 +406,9 @@ __device__ void wave_sort(const uint64_t* __restrict__ keys, int64_t b, int len,
 #pragma unroll
         for (int r = 0; r < E; ++r) {
           const bool asc = ((E * lane + r) & k) == 0;
-          const uint64_t p = __shfl_xor(e[r], m, 64);
+          // (the 512-key network exchanges through DPP / permlane; the larger
+          // ones through ds_bpermute, whose code stays smaller)
+          const uint64_t p = E == 8 ? lane_xor64(e[r], m) : __shfl_xor(e[r], m, 64);
           // the lower position keeps the minimum of an ascending block, the upper the maximum
           const bool keep_min = asc != upper;
           e[r] = ((e[r] < p) == keep_min) ? e[r] : p;
