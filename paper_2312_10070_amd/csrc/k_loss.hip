@@ -194,10 +194,22 @@ __global__ __launch_bounds__(256) void k_select_hist(const float* __restrict__ D
   const SelState sel = select_state(st, pass);
   const int shift = 24 - 8 * pass;
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
-    if (Dt[i] > 0.f) {
-      const uint32_t b = __float_as_uint(fabsf(D[i] - Dt[i]));
-      if ((b & sel.mask) == sel.prefix) atomicAdd(&h[(b >> shift) & 0xffu], 1u);
+  // four pixels per thread and round: their loads are in flight together
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < P; i0 += 4 * stride) {
+    float d[4], dt[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = min(i0 + u * stride, P - 1);
+      d[u] = D[i];
+      dt[u] = Dt[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + u * stride < P && dt[u] > 0.f) {
+        const uint32_t b = __float_as_uint(fabsf(d[u] - dt[u]));
+        if ((b & sel.mask) == sel.prefix) atomicAdd(&h[(b >> shift) & 0xffu], 1u);
+      }
     }
   }
   __syncthreads();
@@ -655,7 +667,7 @@ void launch_loss_track(const float* C, const float* D, const float* A, const flo
   const unsigned g = grid_for(P, 256);
   for (int pass = 0; pass < kSelPasses; ++pass)
     hipLaunchKernelGGL(k_select_hist, dim3(g), dim3(256), 0, s, D, Dt, P, pass, temp);
-  hipLaunchKernelGGL(k_loss_track, dim3(grid_for(P, 512)), dim3(256), 0, s, C, D, A, Ct, Dt, P, lambda_c,
+  hipLaunchKernelGGL(k_loss_track, dim3(grid_for(P, kRedSlots)), dim3(256), 0, s, C, D, A, Ct, Dt, P, lambda_c,
                      inlier_mult, temp, loss, gC, gD, median, temp + kSelWords);
 }
 
