@@ -72,16 +72,33 @@ __global__ __launch_bounds__(256) void k_seed_query(const float* __restrict__ q,
   const float x = q[3 * j], y = q[3 * j + 1], z = q[3 * j + 2];
   const int cx = cell_of(x, inv_h), cy = cell_of(y, inv_h), cz = cell_of(z, inv_h);
   float best = r2max;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const uint32_t b = bucket_of(cx + dx, cy + dy, cz + dz, mask);
-        const uint32_t s = offsets[b], e = s + counts[b];
-        for (uint32_t k = s; k < e; ++k) {
-          const float4 pk = pts[k];
-          best = fminf(best, dist2(x, y, z, pk.x, pk.y, pk.z));
-        }
+  // a 3x3 slice of cells at a time: its nine bucket ranges are loaded
+  // together, then each bucket's means four per step, so that several loads
+  // are in flight (a step past a bucket's end repeats its first mean of the
+  // step; the minimum is exact, so neither that nor the order matters)
+  for (int dz = -1; dz <= 1; ++dz) {
+    uint32_t s[9], e[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const uint32_t b = bucket_of(cx + t % 3 - 1, cy + t / 3 - 1, cz + dz, mask);
+      s[t] = offsets[b];
+      e[t] = counts[b];
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const uint32_t end = s[t] + e[t];
+      for (uint32_t k = s[t]; k < end; k += 4) {
+        const float4 p0 = pts[k];
+        const float4 p1 = pts[k + 1 < end ? k + 1 : k];
+        const float4 p2 = pts[k + 2 < end ? k + 2 : k];
+        const float4 p3 = pts[k + 3 < end ? k + 3 : k];
+        best = fminf(best, dist2(x, y, z, p0.x, p0.y, p0.z));
+        best = fminf(best, dist2(x, y, z, p1.x, p1.y, p1.z));
+        best = fminf(best, dist2(x, y, z, p2.x, p2.y, p2.z));
+        best = fminf(best, dist2(x, y, z, p3.x, p3.y, p3.z));
       }
+    }
+  }
   if (nn_d2) nn_d2[j] = best;
   if (keep) keep[j] = best < rho2 ? 0 : 1;
 }
