@@ -99,7 +99,7 @@ STAGE_SOURCES = {"render_fwd": ["k_raster.hip", "gsr_internal.h"], "render_bwd":
                  "project": ["k_project.hip", "gsr_internal.h"], "loss_track": ["k_loss.hip"],
                  "project_bwd": ["k_project.hip", "gsr_internal.h"],
                  "project_bwd_adam": ["k_project.hip", "gsr_internal.h"],
-                 "loss_ssim": ["k_loss.hip", "gsr_internal.h"]}
+                 "loss_ssim": ["k_loss.hip", "gsr_internal.h"], "seed_query": ["k_seed.hip"]}
 
 
 def read_traffic(stage: str, workload: str):
@@ -133,7 +133,15 @@ PMC_COMMANDS = {
           "--calib-copy-mib {mib}"),
     "C3": ("cd /tmp && rocprofv3 --pmc {counter} -d <dir> -o run --output-format csv -- python3 bench.py "
            "--profile-tracking 5 --calib-copy-mib {mib}"),
+    "S": ("cd /tmp && rocprofv3 --pmc {counter} -d <dir> -o run --output-format csv -- python3 bench.py "
+          "--steps 1 --warmup 0 --no-cpu-baseline --no-tracking --no-batched --no-initnet --no-c2 --no-full-loss "
+          "--calib-copy-mib {mib}"),
 }
+# kernels of the seeding measurement's neighbour query
+SEED_KERNELS = {"seed_query": ["k_seed_query("]}
+WORKLOAD_TITLES = {"H": "mapping iteration 1200x680, 500K Gaussians",
+                   "C3": "tracking iteration 640x480, 500K Gaussians",
+                   "S": "seeding queries of the 1200x680 keyframe's 650K candidates against the 500K sub-map"}
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str, calib_mib: int, workload: str = "H") -> None:
@@ -162,9 +170,8 @@ def summarize_pmc(fetch_csv: str, write_csv: str, calib_mib: int, workload: str 
     write, w_copy = load(write_csv, "WRITE_SIZE")
     nbytes = float(calib_mib << 20)
     sf, sw = nbytes / f_copy, nbytes / w_copy
-    kernels_of = STAGE_KERNELS if workload == "H" else TRACK_KERNELS
-    title = ("mapping iteration 1200x680, 500K Gaussians" if workload == "H"
-             else "tracking iteration 640x480, 500K Gaussians")
+    kernels_of = {"H": STAGE_KERNELS, "C3": TRACK_KERNELS, "S": SEED_KERNELS}[workload]
+    title = WORKLOAD_TITLES[workload]
     cmd = PMC_COMMANDS[workload]
     for stage, kernels in kernels_of.items():
         if stage not in STAGE_SOURCES:
@@ -710,8 +717,9 @@ def main() -> int:
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/*_<WORKLOAD>_traffic.txt from two rocprofv3 --pmc runs and exit")
-    ap.add_argument("--pmc-workload", choices=("H", "C3"), default="H",
-                    help="workload of --summarize-pmc: H (mapping, 1200x680) or C3 (tracking, 640x480)")
+    ap.add_argument("--pmc-workload", choices=("H", "C3", "S"), default="H",
+                    help="workload of --summarize-pmc: H (mapping, 1200x680), C3 (tracking, 640x480) or S "
+                         "(seeding queries)")
     ap.add_argument("--summarize-trace", nargs=4, metavar=("STATS_CSV", "NAME", "COMMAND", "TITLE"),
                     help="write profiles/NAME.txt from a rocprofv3 kernel_stats.csv and exit")
     ap.add_argument("--summarize-valu", nargs="+", metavar=("WORKLOAD", "CSV"),
@@ -885,23 +893,25 @@ def main() -> int:
         recs = gsr.profile_read()
         m_q = int(cand.shape[0])
         cand_ms = recs["seed_candidates"][0] / recs["seed_candidates"][1]
+        grid_ms = recs["seed_grid"][0] / recs["seed_grid"][1]
         dev_ms = recs["seed_query"][0] / recs["seed_query"][1]
         T = 1024
         while T < 2 * n:
             T *= 2
-        # query: means read twice and written once into the grid (12 + 12 + 16 B), four words per bucket,
-        # candidates read and both outputs written (12 + 8 B)
-        seed_bytes = n * 40.0 + T * 16.0 + m_q * 20.0
+        # the query kernel alone: candidates read and both outputs written (12 + 8 B per query), the grid read
+        # once (offset and count per bucket, one 16-byte point per mean)
+        seed_bytes = m_q * 20.0 + T * 8.0 + n * 16.0
         ach = seed_bytes / (dev_ms * 1e-3) / 1e9
         seed = {"workload": "seeding a new sub-map from the 1200x680 keyframe: M_u = 600,000 uniform + colour-gradient "
                             "candidates, radius test rho 1 cm and nearest-neighbour scale up to 5 cm against the 500K "
                             "sub-map (spatial hash grid built per call)",
                 "candidates": m_q, "kept": int(keep.sum().item()), "candidates_ms": round(cand_ms, 4),
-                "query_ms": round(dev_ms, 4), "call_ms": round((t1 - t0) / reps * 1000.0, 3),
-                "queries_per_s": round(m_q / (dev_ms * 1e-3), 1),
+                "grid_ms": round(grid_ms, 4), "query_ms": round(dev_ms, 4),
+                "call_ms": round((t1 - t0) / reps * 1000.0, 3),
+                "queries_per_s": round(m_q / ((grid_ms + dev_ms) * 1e-3), 1),
                 "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "seed_query",
-                             "avg_ms": round(dev_ms, 4)}}
+                             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": read_traffic("seed_query", "S"),
+                             "kernel": "seed_query", "avg_ms": round(dev_ms, 4)}}
 
     if args.calib_copy_mib > 0:
         nbytes = args.calib_copy_mib << 20

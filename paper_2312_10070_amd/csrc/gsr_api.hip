@@ -776,8 +776,13 @@ int gsr_seed_query(gsr_ctx* c, const float* means, int64_t n, const float* point
   GSR_HIP(c, hipMalloc((void**)&temp, sizeof(uint32_t) * gsr::seed_temp_words(n)));
   hipError_t e;
   {
+    Stage t(c, "seed_grid");
+    gsr::launch_seed_grid(means, n, r_max, temp, c->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
     Stage t(c, "seed_query");
-    gsr::launch_seed_query(means, n, points, m, rho, r_max, nn_d2, keep, temp, c->stream);
+    gsr::launch_seed_query(n, points, m, rho, r_max, nn_d2, keep, temp, c->stream);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

@@ -217,11 +217,13 @@ int64_t seed_init_temp_words(int64_t m);
 void launch_seed_init(const SeedInit& a, uint32_t* temp, uint32_t* count_host, hipStream_t s);
 // Seeding neighbour queries (k_seed.hip): nn_d2[j] = min(r_max^2, min_i |q_j - p_i|^2),
 // keep[j] = nn_d2[j] >= rho^2 (either output may be NULL); rho <= r_max.
-// temp: seed_temp_words(n) uint32, 16-byte aligned.
+// temp: seed_temp_words(n) uint32, 16-byte aligned; launch_seed_grid fills it
+// with the hash grid of the means, launch_seed_query then answers the queries.
 uint32_t seed_buckets(int64_t n);
 int64_t seed_temp_words(int64_t n);
-void launch_seed_query(const float* means, int64_t n, const float* points, int64_t m, float rho, float r_max,
-                       float* nn_d2, int32_t* keep, uint32_t* temp, hipStream_t s);
+void launch_seed_grid(const float* means, int64_t n, float r_max, uint32_t* temp, hipStream_t s);
+void launch_seed_query(int64_t n, const float* points, int64_t m, float rho, float r_max, float* nn_d2,
+                       int32_t* keep, const uint32_t* temp, hipStream_t s);
 
 // Opacity pruning / compaction: in[0..4] = means, scales, quats, opacities,
 // colors (widths 3, 3, 4, 1, 3), in[5..9] / in[10..14] their Adam moments

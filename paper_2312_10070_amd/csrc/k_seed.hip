@@ -62,12 +62,15 @@ __global__ __launch_bounds__(256) void k_grid_fill(const float* __restrict__ p, 
   pts[slot] = make_float4(x, y, z, 0.f);
 }
 
+// offsets: T + 1 words, bucket b's means are pts[offsets[b], offsets[b + 1]).
+// Workgroups are dealt to the 8 XCDs in turn; xcd_tile gives each XCD a
+// contiguous run of queries (candidates come in pixel order, so a run covers a
+// band of the image and its XCD's L2 holds the part of the grid it needs).
 __global__ __launch_bounds__(256) void k_seed_query(const float* __restrict__ q, int64_t m, float inv_h, uint32_t mask,
                                                   const uint32_t* __restrict__ offsets,
-                                                  const uint32_t* __restrict__ counts, const float4* __restrict__ pts,
-                                                  float r2max, float rho2, float* __restrict__ nn_d2,
-                                                  int32_t* __restrict__ keep) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                  const float4* __restrict__ pts, float r2max, float rho2,
+                                                  float* __restrict__ nn_d2, int32_t* __restrict__ keep) {
+  const int64_t j = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const float x = q[3 * j], y = q[3 * j + 1], z = q[3 * j + 2];
   const int cx = cell_of(x, inv_h), cy = cell_of(y, inv_h), cz = cell_of(z, inv_h);
@@ -82,11 +85,11 @@ __global__ __launch_bounds__(256) void k_seed_query(const float* __restrict__ q,
     for (int t = 0; t < 9; ++t) {
       const uint32_t b = bucket_of(cx + t % 3 - 1, cy + t / 3 - 1, cz + dz, mask);
       s[t] = offsets[b];
-      e[t] = counts[b];
+      e[t] = offsets[b + 1];
     }
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const uint32_t end = s[t] + e[t];
+      const uint32_t end = e[t];
       for (uint32_t k = s[t]; k < end; k += 4) {
         const float4 p0 = pts[k];
         const float4 p1 = pts[k + 1 < end ? k + 1 : k];
@@ -236,27 +239,37 @@ static int64_t seed_pts_offset(int64_t T) { return (3 * T + 1 + scan_temp_words(
 
 int64_t seed_temp_words(int64_t n) { return seed_pts_offset(seed_buckets(n)) + 4 * n; }
 
-void launch_seed_query(const float* means, int64_t n, const float* points, int64_t m, float rho, float r_max,
-                       float* nn_d2, int32_t* keep, uint32_t* temp, hipStream_t s) {
+// the cell edge h = r_max (1 + 1e-3) as its reciprocal
+static float seed_inv_h(float r_max) { return (float)(1.0 / ((double)r_max * 1.001)); }
+
+void launch_seed_grid(const float* means, int64_t n, float r_max, uint32_t* temp, hipStream_t s) {
   const uint32_t T = seed_buckets(n);
   uint32_t* counts = temp;
-  uint32_t* offsets = temp + T;
-  uint32_t* cursor = temp + 2 * (int64_t)T;
-  uint32_t* total = temp + 3 * (int64_t)T;
+  uint32_t* cursor = temp + T;
+  uint32_t* offsets = temp + 2 * (int64_t)T;
+  uint32_t* total = offsets + T;  // offsets[T] = n
   uint32_t* scan_tmp = total + 1;
   float4* pts = reinterpret_cast<float4*>(temp + seed_pts_offset(T));
-  const float inv_h = (float)(1.0 / ((double)r_max * 1.001));
+  const float inv_h = seed_inv_h(r_max);
   const uint32_t mask = T - 1;
   launch_fill_u32(counts, 0u, T, s);
   launch_fill_u32(cursor, 0u, T, s);
-  const unsigned gn = (unsigned)((n + 255) / 256), gm = (unsigned)((m + 255) / 256);
+  const unsigned gn = (unsigned)((n + 255) / 256);
   if (n > 0) hipLaunchKernelGGL(k_grid_count, dim3(gn), dim3(256), 0, s, means, n, inv_h, mask, counts);
   launch_exclusive_scan(counts, offsets, T, total, scan_tmp, s);
   if (n > 0) hipLaunchKernelGGL(k_grid_fill, dim3(gn), dim3(256), 0, s, means, n, inv_h, mask, offsets, cursor, pts);
+}
+
+void launch_seed_query(int64_t n, const float* points, int64_t m, float rho, float r_max, float* nn_d2,
+                       int32_t* keep, const uint32_t* temp, hipStream_t s) {
+  const uint32_t T = seed_buckets(n);
+  const uint32_t* offsets = temp + 2 * (int64_t)T;
+  const float4* pts = reinterpret_cast<const float4*>(temp + seed_pts_offset(T));
   const float r2max = r_max * r_max, rho2 = rho * rho;
+  const unsigned gm = (unsigned)((m + 255) / 256);
   if (m > 0)
-    hipLaunchKernelGGL(k_seed_query, dim3(gm), dim3(256), 0, s, points, m, inv_h, mask, offsets, counts,
-                       (const float4*)pts, r2max, rho2, nn_d2, keep);
+    hipLaunchKernelGGL(k_seed_query, dim3(gm), dim3(256), 0, s, points, m, seed_inv_h(r_max), T - 1, offsets, pts,
+                       r2max, rho2, nn_d2, keep);
 }
 
 }  // namespace gsr
