@@ -9,9 +9,9 @@
 // start + its offset, and writes the keys (float bits of the camera depth <<
 // 32 | record index) in arbitrary order. Finally each
 // tile's range is sorted by key and its record indices written: by one wave
-// in registers (a bitonic network, up to 512 keys), or for longer ranges by a
-// whole workgroup through LDS (runs of 2048 merged pairwise in global
-// memory). Keys are unique within a
+// in registers (a bitonic network of up to 2048 keys), or for longer ranges
+// by the waves of a workgroup side by side (runs of 1024 keys, merged
+// pairwise in global memory). Keys are unique within a
 // tile, so the result is the depth order of the "m ordered Gaussians" of
 // Eq. 3 and Eq. 6 with ties broken by index: exactly what a stable sort of
 // (tile, depth) gives. No launch grid depends on K: positions at or beyond
@@ -136,7 +136,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
   }
 }
 
-constexpr int kSortCap = 2048;  // keys a workgroup sorts in LDS (16 KB)
 constexpr int kBinThreads = 256;
 // Threads of a counting / placing workgroup: each walks a few of its
 // workgroup's Gaussians, so more threads hide more of the memory latency.
@@ -282,48 +281,6 @@ __global__ __launch_bounds__(kPlaceThreads) void k_bin_place(Raster Rr, BinArgs 
   }
 }
 
-// Bitonic sort of s[0, n2) ascending (n2 a power of two <= kSortCap), all
-// threads of the workgroup; ends with a barrier.
-__device__ __forceinline__ void lds_bitonic(uint64_t* s, int n2) {
-  const int half = n2 >> 1;
-  for (int k = 2; k <= n2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int p = threadIdx.x; p < half; p += kBinThreads) {
-        const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));  // pairs (i, i + j) with bit j of i clear
-        const int l = i + j;
-        const uint64_t x = s[i], y = s[l];
-        const bool up = (i & k) == 0;
-        if ((x > y) == up) {
-          s[i] = y;
-          s[l] = x;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-__device__ __forceinline__ int pow2_at_least(int v) {
-  int n = 2;
-  while (n < v) n <<= 1;
-  return n;
-}
-
-// Sorts keys[b, b + len) (len <= kSortCap) through LDS; writes the sorted keys
-// to out_keys (may alias keys) and/or their low words to out_ids.
-__device__ void sort_run(const uint64_t* keys, int64_t b, int len, uint64_t* s, uint64_t* out_keys,
-                         uint32_t* out_ids) {
-  const int n2 = pow2_at_least(len);
-  for (int i = threadIdx.x; i < n2; i += kBinThreads) s[i] = i < len ? keys[b + i] : ~0ull;
-  __syncthreads();
-  lds_bitonic(s, n2);
-  for (int i = threadIdx.x; i < len; i += kBinThreads) {
-    if (out_keys) out_keys[b + i] = s[i];
-    if (out_ids) out_ids[b + i] = (uint32_t)s[i];
-  }
-  __syncthreads();
-}
-
 // Merges the sorted runs a[0, na) and b[0, nb) (distinct keys) into out; the
 // output is split evenly over the workgroup's threads by merge-path search.
 __device__ void merge_runs(const uint64_t* a, int na, const uint64_t* b, int nb, uint64_t* out) {
@@ -386,9 +343,10 @@ __device__ __forceinline__ uint64_t lane_xor64(uint64_t v, int m) {
 // elements E l .. E l + E - 1 in registers; a bitonic network whose strides
 // below E are compare-exchanges inside a lane and whose larger strides
 // exchange with lane l ^ (stride / E). Writes the low words (record indices)
-// to ids.
-template <int E>
-__device__ void wave_sort(const uint64_t* __restrict__ keys, int64_t b, int len, uint32_t* __restrict__ ids) {
+// to ids (kKeys false) or the sorted keys to out_keys[b, b + len) (kKeys true).
+template <int E, bool kKeys = false>
+__device__ void wave_sort(const uint64_t* __restrict__ keys, int64_t b, int len, uint32_t* __restrict__ ids,
+                          uint64_t* __restrict__ out_keys = nullptr) {
   const int lane = threadIdx.x & 63;
   uint64_t e[E];
 #pragma unroll
@@ -430,19 +388,23 @@ __device__ void wave_sort(const uint64_t* __restrict__ keys, int64_t b, int len,
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int i = E * lane + r;
-    if (i < len) ids[b + i] = (uint32_t)e[r];
+    if (i < len) {
+      if (kKeys) out_keys[b + i] = e[r];
+      else ids[b + i] = (uint32_t)e[r];
+    }
   }
 }
 
 // Four (view, tile) items per workgroup. Each wave sorts one item of at most
 // kWaveSort keys in registers (the smallest of the 512 / 1024 / 2048-key
-// networks that holds it); longer items are then sorted by the whole
-// workgroup (LDS runs of kSortCap merged pairwise in global memory).
+// networks that holds it). Longer items are cut into runs of kLongRun keys,
+// which the workgroup's waves sort side by side into scratch (the 1024-key
+// network), and pairwise merges (ping-pong between scratch and keys) join.
 __global__ __launch_bounds__(kBinThreads) void k_tile_sort(const int2* __restrict__ ranges, int64_t n_items,
                                                           uint64_t* __restrict__ keys, uint64_t* __restrict__ scratch,
                                                           uint32_t* __restrict__ ids) {
-  __shared__ uint64_t s[kSortCap];
   constexpr int kItems = kBinThreads / 64;
+  constexpr int kLongRun = 1024;
   const int64_t item0 = (int64_t)blockIdx.x * kItems;
   const int w = threadIdx.x >> 6;
   if (item0 + w < n_items) {
@@ -456,16 +418,38 @@ __global__ __launch_bounds__(kBinThreads) void k_tile_sort(const int2* __restric
       wave_sort<32>(keys, rg.x, len, ids);
     }
   }
+  // runs of the long items, dealt to the waves in turn
+  int n_runs = 0;
+  for (int it = 0; it < kItems && item0 + it < n_items; ++it) {
+    const int2 rg = ranges[item0 + it];
+    const int len = rg.y - rg.x;
+    if (len > kWaveSort) n_runs += (len + kLongRun - 1) / kLongRun;
+  }
+  if (n_runs == 0) return;  // uniform across the workgroup
+  for (int j = w; j < n_runs; j += kItems) {
+    int r = j;
+    for (int it = 0; it < kItems && item0 + it < n_items; ++it) {
+      const int2 rg = ranges[item0 + it];
+      const int len = rg.y - rg.x;
+      const int nr = len > kWaveSort ? (len + kLongRun - 1) / kLongRun : 0;
+      if (r < nr) {
+        const int c0 = r * kLongRun;
+        wave_sort<kLongRun / 64, true>(keys, rg.x + c0, min(kLongRun, len - c0), nullptr, scratch);
+        break;
+      }
+      r -= nr;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
   for (int it = 0; it < kItems && item0 + it < n_items; ++it) {
     const int2 rg = ranges[item0 + it];
     const int64_t b = rg.x;
     const int len = rg.y - rg.x;
     if (len <= kWaveSort) continue;  // uniform across the workgroup
-    // long range: sorted runs of kSortCap, then pairwise merges (ping-pong)
-    for (int c0 = 0; c0 < len; c0 += kSortCap) sort_run(keys, b + c0, min(kSortCap, len - c0), s, keys, nullptr);
-    uint64_t* src = keys + b;
-    uint64_t* dst = scratch + b;
-    for (int wd = kSortCap; wd < len; wd <<= 1) {
+    uint64_t* src = scratch + b;
+    uint64_t* dst = keys + b;
+    for (int wd = kLongRun; wd < len; wd <<= 1) {
       for (int lo = 0; lo < len; lo += 2 * wd) {
         const int mid = min(lo + wd, len), hi = min(lo + 2 * wd, len);
         merge_runs(src + lo, mid - lo, src + mid, hi - mid, dst + lo);

@@ -229,10 +229,12 @@ def test_long_lists_and_early_termination():
     G.grads_check({k: v.cpu().numpy().astype(np.float64) for k, v in b.items()}, ref, case="long lists 48x40")
 
 
-def test_tile_ranges_longer_than_lds_are_merged():
-    """Tiles whose lists exceed the 2048 keys one workgroup sorts in LDS
-    (sorted runs merged pairwise in global memory, with a ragged last run):
-    tile lists bit-exact, including depth ties broken by index."""
+def test_tile_ranges_longer_than_one_wave_are_merged():
+    """Tiles whose lists exceed the 2048 keys one wave sorts in registers
+    (runs of 1024 keys sorted by the workgroup's waves side by side, more runs
+    than waves in one workgroup, merged pairwise in global memory, with a
+    ragged last run): tile lists bit-exact, including depth ties broken by
+    index."""
     rng = np.random.default_rng(11)
     n = 7000
     g = dict(means=np.stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.25, 0.25, n), rng.uniform(2, 6, n)], 1),
@@ -245,6 +247,8 @@ def test_tile_ranges_longer_than_lds_are_merged():
     tl = oracle.tile_lists(g, pose, cam, oracle.Opts())
     lens = tl["ranges"][:, 1] - tl["ranges"][:, 0]
     assert lens.max() > 2 * 2048 + 100 and (lens > 2048).sum() >= 2
+    runs = np.where(lens > 2048, (lens + 1023) // 1024, 0)
+    assert max(runs[i:i + 4].sum() for i in range(0, len(runs), 4)) > 4  # four tiles (waves) per workgroup
     out, st, _, _ = run_fwd(g, pose, cam)
     K, ranges, ids = gsr.tile_lists(st, tl["ranges"].shape[0])
     assert K == tl["K"]
