@@ -279,6 +279,46 @@ def test_register_sorts_of_long_tile_lists():
     G.compare_tile_lists(ranges.cpu().numpy(), ids.cpu().numpy(), tl, None)
 
 
+def tile_stacks(lengths, seed=0, tie_every=7):
+    """Gaussians stacked on the centres of the tiles of a 48x48 frame (3 x 3
+    tiles of 16 x 16): lengths[t] small Gaussians (projected radius well under a
+    pixel, centres within 2 px of the tile centre) at random depths in [2, 6],
+    every tie_every-th one sharing the depth of the one before (ties broken by
+    index), so tile t's list has exactly lengths[t] keys."""
+    rng = np.random.default_rng(seed)
+    cam = oracle.Camera(48, 48, 40.0, 40.0, 24.0, 24.0)
+    means = []
+    for t, L in enumerate(lengths):
+        u = 16 * (t % 3) + 7.5 + rng.uniform(-2, 2, L)
+        v = 16 * (t // 3) + 7.5 + rng.uniform(-2, 2, L)
+        z = rng.uniform(2, 6, L)
+        z[tie_every::tie_every] = z[tie_every - 1:-1:tie_every][:len(z[tie_every::tie_every])]
+        means.append(np.stack([(u - cam.cx) / cam.fx * z, (v - cam.cy) / cam.fy * z, z], 1))
+    means = np.concatenate(means)
+    n = len(means)
+    g = dict(means=means, scales=np.full((n, 3), 0.004), quats=rng.normal(size=(n, 4)),
+             opacities=rng.uniform(0.3, 0.9, n), colors=rng.uniform(0, 1, (n, 3)))
+    return g, cam
+
+
+def test_tile_sort_length_boundaries():
+    """Tiles of exactly 0, 1, 512, 513, 1024, 1025, 2048, 2049 and 4097 keys:
+    the edges of the 512 / 1024 / 2048-key register networks and of the runs of
+    1024 keys (a run of one key; five runs in a workgroup of four waves), in
+    one frame; tile lists bit-exact against the oracle, including depth ties."""
+    lengths = [2048, 2049, 1025, 1024, 513, 512, 4097, 1, 0]
+    g, cam = tile_stacks(lengths)
+    pose = np.array([1, 0, 0, 0, 0, 0, 0], np.float64)
+    g = G.certify(g, pose, cam, 1e-4)
+    tl = oracle.tile_lists(g, pose, cam, oracle.Opts())
+    lens = tl["ranges"][:, 1] - tl["ranges"][:, 0]
+    assert lens.tolist() == lengths, lens
+    _, st, _, _ = run_fwd(g, pose, cam)
+    K, ranges, ids = gsr.tile_lists(st, tl["ranges"].shape[0])
+    assert K == tl["K"] == sum(lengths)
+    G.compare_tile_lists(ranges.cpu().numpy(), ids.cpu().numpy(), tl, None)
+
+
 def test_workspace_growth_between_calls():
     """A forward whose overlap count exceeds the tile-list workspace left by the
     previous forward on the same (reused) state: the speculatively queued
