@@ -365,6 +365,59 @@ def test_loss_kernels_match_oracle():
     np.testing.assert_allclose(gD.cpu().numpy(), r["gD"], rtol=1e-5, atol=1e-9)
 
 
+def track_images(rng, h, w, invalid=0.0):
+    C = rng.uniform(0, 1, (3, h, w)).astype(np.float32)
+    Ct = rng.uniform(0, 1, (3, h, w)).astype(np.float32)
+    D = rng.uniform(1, 3, (h, w)).astype(np.float32)
+    Dt = (D + rng.normal(0, 0.05, (h, w))).astype(np.float32)
+    A = rng.uniform(0.3, 1.0, (h, w)).astype(np.float32)
+    Dt[rng.uniform(size=(h, w)) < invalid] = 0.0
+    return C, D, A, Ct, Dt
+
+
+@pytest.mark.parametrize("case", ["one_pixel", "no_valid_pixel", "two_valid_lower_middle", "all_equal",
+                                  "all_zero_error", "six_decades", "ragged_37x23"])
+def test_loss_track_edge_cases(case):
+    """Eq. 15 (with the supplement's masks) on the degenerate inputs of its
+    exact median: a single pixel, no valid observed depth, an even count (the
+    lower middle), every error equal or zero, errors spread over six decades,
+    a ragged frame with invalid pixels. The median is compared bit for bit,
+    the loss and gradients per element."""
+    torch = torch_()
+    rng = np.random.default_rng(sum(map(ord, case)))
+    if case == "one_pixel":
+        C, D, A, Ct, Dt = track_images(rng, 1, 1)
+    elif case == "no_valid_pixel":
+        C, D, A, Ct, Dt = track_images(rng, 4, 6)
+        Dt[:] = 0.0
+    elif case == "two_valid_lower_middle":
+        C, D, A, Ct, Dt = track_images(rng, 3, 5)
+        Dt[:] = 0.0
+        Dt[0, 1], Dt[2, 3] = D[0, 1] + 0.25, D[2, 3] - 0.5
+    elif case == "all_equal":
+        C, D, A, Ct, Dt = track_images(rng, 5, 7)
+        Dt[:] = D + np.float32(0.125)
+    elif case == "all_zero_error":
+        C, D, A, Ct, Dt = track_images(rng, 6, 6)
+        Dt[:] = D
+    elif case == "six_decades":
+        C, D, A, Ct, Dt = track_images(rng, 16, 16)
+        D[:] = np.float32(1e3)
+        Dt[:] = (D - np.exp(rng.uniform(np.log(1e-3), np.log(999.0), D.shape))).astype(np.float32)
+    else:
+        C, D, A, Ct, Dt = track_images(rng, 23, 37, invalid=0.1)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    loss, gC, gD, med = gsr.loss_track(dev(C), dev(D), dev(A), dev(Ct), dev(Dt), 0.5, 50.0)
+    torch.cuda.synchronize()
+    r = oracle.loss_track(C, D, A, Ct, Dt, 0.5, 50.0)
+    if case == "no_valid_pixel":
+        assert r["n_inlier"] == 0 and r["loss"] == 0.0
+    assert med.item() == r["median"]
+    assert abs(loss.item() - r["loss"]) <= 1e-5 * abs(r["loss"]) + 1e-9
+    np.testing.assert_allclose(gC.cpu().numpy(), r["gC"], rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(gD.cpu().numpy(), r["gD"], rtol=1e-5, atol=1e-9)
+
+
 def test_adam_matches_oracle():
     torch = torch_()
     rng = np.random.default_rng(0)
