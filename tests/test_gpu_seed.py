@@ -60,6 +60,32 @@ def test_seed_query_room_scale_sampled():
     assert 0 < keep.sum() < len(q)
 
 
+@pytest.mark.parametrize("offset", [0.0, -37.25, 300.0])
+def test_seed_query_cell_boundaries(offset):
+    """Means on the corners of the hash grid's cells (edge r_max (1 + 1e-3)),
+    queries at just under r_max, exactly r_max and just over r_max from a mean
+    along the axes and diagonals, near the origin and up to 300 m from it (cell
+    coordinates near 6000): every mean within r_max lies in the 27 cells
+    around the query whatever the rounding of the cell index, so the
+    distances are exact."""
+    r_max, rho = 0.05, 0.01
+    h = r_max * 1.001
+    k = np.arange(-3, 4)
+    p = (offset + np.stack(np.meshgrid(k, k, k, indexing="ij"), -1).reshape(-1, 3) * h).astype(np.float32)
+    dirs = np.array([[1, 0, 0], [0, -1, 0], [0, 0, 1], [1, 1, 0], [1, -1, 1], [-1, -1, -1]], np.float64)
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    rng = np.random.default_rng(5)
+    base = p[rng.choice(len(p), 40, replace=False)].astype(np.float64)
+    q = np.concatenate([base[:, None] + s * r_max * dirs[None] for s in (1 - 1e-4, 1.0, 1 + 1e-4, 0.5, 0.1)])
+    q = q.reshape(-1, 3).astype(np.float32)
+    nn_ref, keep_ref = oracle.seed_query(p, q, rho, r_max)
+    nn, keep = run(p, q, rho, r_max)
+    np.testing.assert_array_equal(nn, nn_ref)
+    np.testing.assert_array_equal(keep, keep_ref)
+    cap = np.float32(np.float32(r_max) * np.float32(r_max))  # no mean within r_max
+    assert (nn_ref < cap).any() and (nn_ref == cap).any()
+
+
 def test_seed_query_bad_arguments():
     torch = torch_()
     p = dev(np.zeros((4, 3)))
