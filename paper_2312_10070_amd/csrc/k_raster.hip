@@ -310,24 +310,28 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
       // The walk condition is checked before every second step only: a step
       // after it turned false is a no-op (every lane has stopped, or every
       // row reads the all-zero record), and entries up to kListCap + 2 exist
-      // for its reads.
+      // for its reads. The loop is tested at its end (one exit), which keeps
+      // the carried sums in the same registers around it (a test at the top
+      // cost six register copies per trip).
       int jA = 0 < myl ? mylist[0] : 16 * kDummy;
       int jn = mylist[1];
       float4 gA = lds_at(sm.uvab, jA), cbA = lds_at(sm.cob, jA), czA = lds_at(sm.rgbz, jA);
-      for (int t = 0;;) {
-        if (!going(t)) break;
-        const int jB = t + 1 < myl ? jn : 16 * kDummy;
-        jn = mylist[t + 2];
-        const float4 gB = lds_at(sm.uvab, jB), cbB = lds_at(sm.cob, jB), czB = lds_at(sm.rgbz, jB);
-        step(gA, cbA, czA, jA);
-        ++t;
-        jA = t + 1 < myl ? jn : 16 * kDummy;
-        jn = mylist[t + 2];
-        gA = lds_at(sm.uvab, jA);
-        cbA = lds_at(sm.cob, jA);
-        czA = lds_at(sm.rgbz, jA);
-        step(gB, cbB, czB, jB);
-        ++t;
+      if (going(0)) {
+        int t = 0;
+        do {
+          const int jB = t + 1 < myl ? jn : 16 * kDummy;
+          jn = mylist[t + 2];
+          const float4 gB = lds_at(sm.uvab, jB), cbB = lds_at(sm.cob, jB), czB = lds_at(sm.rgbz, jB);
+          step(gA, cbA, czA, jA);
+          ++t;
+          jA = t + 1 < myl ? jn : 16 * kDummy;
+          jn = mylist[t + 2];
+          gA = lds_at(sm.uvab, jA);
+          cbA = lds_at(sm.cob, jA);
+          czA = lds_at(sm.rgbz, jA);
+          step(gB, cbB, czB, jB);
+          ++t;
+        } while (going(t));
       }
       __builtin_amdgcn_wave_barrier();
     }
