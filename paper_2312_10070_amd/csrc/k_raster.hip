@@ -205,7 +205,7 @@ struct QuadSmem {
   float4 rgbz[kBatch + 1];
   float acc[kBatch * kNF];
   uint32_t gid[kBatch];
-  uint16_t list[kWavesPerTile][4][kListCap + 2];
+  uint16_t list[kWavesPerTile][4][kListCap + 4];
   int max_last;
 };
 
@@ -302,7 +302,7 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
         T = comp ? Tn : -fabsf(T);
       };
       // walk while some lane is compositing and its row's list has not ended
-      auto going = [&](int t) { return t < maxl && (__ballot(T > 0.f) & __ballot(t < myl)) != 0; };
+      auto going = [&](int t) { return (t < maxl) & ((__ballot(T > 0.f) & __ballot(t < myl)) != 0); };
       // Software pipeline, unrolled by two so that no record is copied
       // between registers: while step t runs on one record set, the other
       // set receives the record of step t + 1 from LDS, and the list entry of
@@ -310,9 +310,9 @@ __device__ __forceinline__ void fwd_item(const Raster& Rr, const FwdArgs& a, int
       // The walk condition is checked before every second step only: a step
       // after it turned false is a no-op (every lane has stopped, or every
       // row reads the all-zero record), and entries up to kListCap + 2 exist
-      // for its reads. The loop is tested at its end (one exit), which keeps
-      // the carried sums in the same registers around it (a test at the top
-      // cost six register copies per trip).
+      // for its reads. The loop is tested at its end (one exit) and the test
+      // itself has no branch, so the body is one basic block and the carried
+      // sums stay in the same registers around it.
       int jA = 0 < myl ? mylist[0] : 16 * kDummy;
       int jn = mylist[1];
       float4 gA = lds_at(sm.uvab, jA), cbA = lds_at(sm.cob, jA), czA = lds_at(sm.rgbz, jA);
@@ -705,26 +705,29 @@ __device__ __forceinline__ void bwd_item_quad(const Raster& Rr, const BwdArgs& a
       // Software pipeline, unrolled by two so that no record is copied
       // between registers: while step t runs on one record set, the other
       // set receives the record of step t + 1 from LDS, and the list entry of
-      // step t + 2 is read (entries up to kListCap + 1 exist, so the reads
-      // stay inside the row's list; entries past its end are not used).
+      // step t + 2 is read (entries past the row's list end are not used).
+      // The loop is tested at its end only, so with an odd maxl its last
+      // step runs past every row's list: a no-op (the all-zero record, no
+      // accumulation), and entries up to kListCap + 2 exist for its reads.
       int jA = 0 < myl ? mylist[0] : 16 * kDummy;
       int jn = mylist[1];
       float4 gA = lds_at(sm.uvab, jA), cbA = lds_at(sm.cob, jA), czA = lds_at(sm.rgbz, jA);
-      for (int t = 0;;) {
-        if (t >= maxl) break;
-        const int jB = t + 1 < myl ? jn : 16 * kDummy;
-        jn = mylist[t + 2];
-        const float4 gB = lds_at(sm.uvab, jB), cbB = lds_at(sm.cob, jB), czB = lds_at(sm.rgbz, jB);
-        step(gA, cbA, czA, jA, t < myl);
-        ++t;
-        if (t >= maxl) break;
-        jA = t + 1 < myl ? jn : 16 * kDummy;
-        jn = mylist[t + 2];
-        gA = lds_at(sm.uvab, jA);
-        cbA = lds_at(sm.cob, jA);
-        czA = lds_at(sm.rgbz, jA);
-        step(gB, cbB, czB, jB, t < myl);
-        ++t;
+      if (0 < maxl) {
+        int t = 0;
+        do {
+          const int jB = t + 1 < myl ? jn : 16 * kDummy;
+          jn = mylist[t + 2];
+          const float4 gB = lds_at(sm.uvab, jB), cbB = lds_at(sm.cob, jB), czB = lds_at(sm.rgbz, jB);
+          step(gA, cbA, czA, jA, t < myl);
+          ++t;
+          jA = t + 1 < myl ? jn : 16 * kDummy;
+          jn = mylist[t + 2];
+          gA = lds_at(sm.uvab, jA);
+          cbA = lds_at(sm.cob, jA);
+          czA = lds_at(sm.rgbz, jA);
+          step(gB, cbB, czB, jB, t < myl);
+          ++t;
+        } while (t < maxl);
       }
       __builtin_amdgcn_wave_barrier();
     }
